@@ -1,0 +1,1058 @@
+/*
+ * oracle.c -- plain, serial, slow reference for the structure-adaptive tile
+ * Cholesky (arXiv 2609.29765).  TEST INFRASTRUCTURE ONLY: it is loaded by the
+ * test-suite, by the smoke check and by the CPU-baseline leg of the benchmark,
+ * never by the product library, and it shares no code with it.
+ *
+ * What it computes, and the passage each part follows:
+ *
+ *   pattern check      lower-triangular CSC, rows ascending, diagonal first,
+ *                      no duplicates (input of the element-level graph, Sec. 3)
+ *   dense set-aside    vertices whose degree exceeds max(16, floor(sqrt(100 n)))
+ *                      leave the graph and are ordered last (Sec. 3, "effectively
+ *                      dense rows set aside"; the threshold is our reading)
+ *   orderings          NATURAL, reverse Cuthill-McKee, level-structure nested
+ *                      dissection, AUTO scoring of the three (Sec. 3; the
+ *                      tie-breaks and AUTO constants are our reading)
+ *   symbolic           elimination tree and the exact column structures of L,
+ *                      straight from their definition: struct(L_j) is the lower
+ *                      part of column j of A merged with the structures of the
+ *                      children of j minus the child itself (Sec. 5.4 pipeline)
+ *   tiles              uniform n_b grid, active rows of every off-diagonal tile
+ *                      (the active columns of the stored transpose), full and
+ *                      contiguous flags, diagonal half-width kd (Sec. 4.1-4.3,
+ *                      Sec. 5.2 "Per-tile metadata")
+ *   features, route    fill ratio, mean tile occupancy, degree skew and the
+ *                      fixed precedence of the selector (Sec. 5.1, Table 5)
+ *   task list          the ordered SYRK/POTRF/GEMM/TRSM list (Algorithm 1)
+ *   factor             the Cholesky factor of P A P^T by its definition,
+ *                      column by column, left-looking, no blocking:
+ *                        L_jj = sqrt(A_jj - sum_{k<j} L_jk^2)
+ *                        L_ij = (A_ij - sum_{k<j} L_ik L_jk) / L_jj
+ *   logdet             2 * sum_j log L_jj, compensated (Neumaier) summation
+ *   solve              x = P^T L^-T L^-1 P b
+ *   selected inverse   Z = A^-1 on the pattern of L by the Takahashi
+ *                      recurrence sum_{i>=j} Z_ki L_ij = delta_kj / L_jj
+ *
+ * Parity status: the factor, logdet, solve and selected inverse are pinned by
+ * dense LAPACK, closed forms and spectral identities in the tests; tiles by the
+ * worked examples of Sec. 4.1 and Sec. 4.3; the task list by Algorithm 1 on
+ * hand-built tile patterns.  The orderings and the AUTO winner rule are
+ * PARITY UNPINNED by the paper (it names heuristics without parameters): they
+ * are pinned only by hand-worked small graphs and by agreement with an
+ * independent implementation of the same written rule.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_ERR_ARG (-1)
+#define ORC_ERR_PATTERN (-2)
+#define ORC_ERR_ALLOC (-4)
+
+enum { ORD_NATURAL = 0, ORD_RCM = 1, ORD_ND = 2, ORD_AUTO = 3, ORD_GIVEN = 4 };
+enum { MODE_AUTO = 0, MODE_DENSE = 1, MODE_SEMISPARSE = 2 };
+enum { ROUTE_DENSE = 0, ROUTE_SEMISPARSE = 1, ROUTE_SUPERNODAL = 2 };
+enum { OP_POTRF = 1, OP_SYRK = 2, OP_TRSM = 3, OP_GEMM = 4 };
+
+/* ------------------------------------------------------------------------- */
+/* small utilities                                                           */
+/* ------------------------------------------------------------------------- */
+
+static int cmp_i32(const void* a, const void* b) {
+  int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+  return (x > y) - (x < y);
+}
+
+/* floor(sqrt(v)) for v >= 0, exact in integers */
+static int64_t isqrt64(int64_t v) {
+  int64_t r = (int64_t)sqrt((double)v);
+  while (r * r > v) --r;
+  while ((r + 1) * (r + 1) <= v) ++r;
+  return r;
+}
+
+/* ------------------------------------------------------------------------- */
+/* pattern check                                                             */
+/* ------------------------------------------------------------------------- */
+
+int orc_check_pattern(int64_t n, const int64_t* cp, const int32_t* ri) {
+  if (n <= 0 || !cp || !ri) return ORC_ERR_ARG;
+  if (cp[0] != 0) return ORC_ERR_PATTERN;
+  for (int64_t j = 0; j < n; ++j) {
+    int64_t a = cp[j], b = cp[j + 1];
+    if (b <= a) return ORC_ERR_PATTERN;           /* diagonal missing */
+    if (ri[a] != j) return ORC_ERR_PATTERN;       /* diagonal not first */
+    for (int64_t p = a + 1; p < b; ++p) {
+      if (ri[p] <= ri[p - 1]) return ORC_ERR_PATTERN; /* unsorted/duplicate */
+      if (ri[p] >= n) return ORC_ERR_PATTERN;
+    }
+  }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* graph of A: symmetric adjacency without the diagonal                      */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+  int64_t n;
+  int64_t* xadj;
+  int32_t* adj;
+} graph_t;
+
+static int graph_build(int64_t n, const int64_t* cp, const int32_t* ri, graph_t* g) {
+  int64_t* cnt = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+  if (!cnt) return ORC_ERR_ALLOC;
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t p = cp[j] + 1; p < cp[j + 1]; ++p) {
+      cnt[ri[p] + 1]++;
+      cnt[j + 1]++;
+    }
+  for (int64_t v = 0; v < n; ++v) cnt[v + 1] += cnt[v];
+  int32_t* adj = (int32_t*)malloc(sizeof(int32_t) * (size_t)(cnt[n] + 1));
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  if (!adj || !fill) { free(cnt); free(adj); free(fill); return ORC_ERR_ALLOC; }
+  for (int64_t v = 0; v < n; ++v) fill[v] = cnt[v];
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t p = cp[j] + 1; p < cp[j + 1]; ++p) {
+      int32_t i = ri[p];
+      adj[fill[i]++] = (int32_t)j;
+      adj[fill[j]++] = i;
+    }
+  for (int64_t v = 0; v < n; ++v)
+    qsort(adj + cnt[v], (size_t)(cnt[v + 1] - cnt[v]), sizeof(int32_t), cmp_i32);
+  free(fill);
+  g->n = n;
+  g->xadj = cnt;
+  g->adj = adj;
+  return ORC_OK;
+}
+
+static void graph_free(graph_t* g) {
+  free(g->xadj);
+  free(g->adj);
+}
+
+/* ------------------------------------------------------------------------- */
+/* orderings on a vertex subset.  in_set[v] == tag marks membership.         */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+  const graph_t* g;
+  int32_t* tag;     /* membership tags */
+  int32_t next_tag;
+  int32_t* level;   /* BFS level scratch */
+  int32_t* seen;    /* BFS visit stamps */
+  int32_t stamp;
+  int32_t* queue;
+  int32_t* out;     /* ordering output cursor */
+  int64_t nout;
+} ordctx_t;
+
+static int32_t set_degree(const ordctx_t* c, int32_t v, int32_t t) {
+  int32_t d = 0;
+  for (int64_t p = c->g->xadj[v]; p < c->g->xadj[v + 1]; ++p)
+    if (c->tag[c->g->adj[p]] == t) ++d;
+  return d;
+}
+
+/* BFS inside the set tagged t from root r; fills queue with visit order,
+   level[] for visited vertices; returns the index of the last level. */
+static int32_t bfs_levels(ordctx_t* c, int32_t r, int32_t t, int64_t* nvisit) {
+  c->stamp++;
+  int64_t head = 0, tail = 0;
+  c->queue[tail++] = r;
+  c->seen[r] = c->stamp;
+  c->level[r] = 0;
+  int32_t last = 0;
+  while (head < tail) {
+    int32_t u = c->queue[head++];
+    for (int64_t p = c->g->xadj[u]; p < c->g->xadj[u + 1]; ++p) {
+      int32_t w = c->g->adj[p];
+      if (c->tag[w] != t || c->seen[w] == c->stamp) continue;
+      c->seen[w] = c->stamp;
+      c->level[w] = c->level[u] + 1;
+      if (c->level[w] > last) last = c->level[w];
+      c->queue[tail++] = w;
+    }
+  }
+  *nvisit = tail;
+  return last;
+}
+
+/* George-Liu pseudo-peripheral vertex of the connected set S (sorted list). */
+static int32_t pseudo_peripheral(ordctx_t* c, const int32_t* S, int64_t ns, int32_t t,
+                                 int32_t* ecc_out) {
+  int32_t r = S[0], best = set_degree(c, S[0], t);
+  for (int64_t a = 1; a < ns; ++a) {
+    int32_t d = set_degree(c, S[a], t);
+    if (d < best) { best = d; r = S[a]; }
+  }
+  int64_t nv;
+  int32_t ecc = bfs_levels(c, r, t, &nv);
+  for (;;) {
+    /* minimum-degree vertex of the last level, lowest index on ties */
+    int32_t v = -1, vd = 0;
+    for (int64_t a = 0; a < nv; ++a) {
+      int32_t w = c->queue[a];
+      if (c->level[w] != ecc) continue;
+      int32_t d = set_degree(c, w, t);
+      if (v < 0 || d < vd || (d == vd && w < v)) { v = w; vd = d; }
+    }
+    int64_t nv2;
+    int32_t ecc2 = bfs_levels(c, v, t, &nv2);
+    if (ecc2 > ecc) {
+      r = v;
+      ecc = ecc2;
+      nv = nv2;
+      continue;
+    }
+    /* restore r's level structure for the caller */
+    ecc = bfs_levels(c, r, t, &nv);
+    break;
+  }
+  *ecc_out = ecc;
+  return r;
+}
+
+typedef struct {
+  int32_t v;
+  int32_t d;
+} vd_t;
+
+static int cmp_vd(const void* a, const void* b) {
+  const vd_t* x = (const vd_t*)a;
+  const vd_t* y = (const vd_t*)b;
+  if (x->d != y->d) return (x->d > y->d) - (x->d < y->d);
+  return (x->v > y->v) - (x->v < y->v);
+}
+
+/* reverse Cuthill-McKee of a connected set S tagged t; appends to out */
+static int rcm_component(ordctx_t* c, const int32_t* S, int64_t ns, int32_t t) {
+  int32_t ecc;
+  int32_t r = pseudo_peripheral(c, S, ns, t, &ecc);
+  c->stamp++;
+  int32_t* order = c->out + c->nout;
+  int64_t head = 0, tail = 0;
+  order[tail++] = r;
+  c->seen[r] = c->stamp;
+  vd_t* buf = (vd_t*)malloc(sizeof(vd_t) * (size_t)(ns + 1));
+  if (!buf) return ORC_ERR_ALLOC;
+  while (head < tail) {
+    int32_t u = order[head++];
+    int64_t nb = 0;
+    for (int64_t p = c->g->xadj[u]; p < c->g->xadj[u + 1]; ++p) {
+      int32_t w = c->g->adj[p];
+      if (c->tag[w] != t || c->seen[w] == c->stamp) continue;
+      c->seen[w] = c->stamp;
+      buf[nb].v = w;
+      buf[nb].d = set_degree(c, w, t);
+      nb++;
+    }
+    qsort(buf, (size_t)nb, sizeof(vd_t), cmp_vd);
+    for (int64_t a = 0; a < nb; ++a) order[tail++] = buf[a].v;
+  }
+  free(buf);
+  /* reverse the Cuthill-McKee order of this component */
+  for (int64_t a = 0, b = tail - 1; a < b; ++a, --b) {
+    int32_t tmp = order[a];
+    order[a] = order[b];
+    order[b] = tmp;
+  }
+  c->nout += tail;
+  return ORC_OK;
+}
+
+/* connected components of the set tagged t (members listed ascending in S);
+   writes them consecutively into comp (each sorted ascending) with starts in
+   cstart[0..ncomp]; components come in ascending order of their minimum. */
+static int64_t components(ordctx_t* c, const int32_t* S, int64_t ns, int32_t t, int32_t* comp,
+                          int64_t* cstart) {
+  c->stamp++;
+  int32_t st = c->stamp;
+  int64_t ncomp = 0, w = 0;
+  for (int64_t a = 0; a < ns; ++a) {
+    int32_t s = S[a];
+    if (c->seen[s] == st) continue;
+    cstart[ncomp++] = w;
+    int64_t head = w;
+    comp[w++] = s;
+    c->seen[s] = st;
+    while (head < w) {
+      int32_t u = comp[head++];
+      for (int64_t p = c->g->xadj[u]; p < c->g->xadj[u + 1]; ++p) {
+        int32_t x = c->g->adj[p];
+        if (c->tag[x] != t || c->seen[x] == st) continue;
+        c->seen[x] = st;
+        comp[w++] = x;
+      }
+    }
+    qsort(comp + cstart[ncomp - 1], (size_t)(w - cstart[ncomp - 1]), sizeof(int32_t), cmp_i32);
+  }
+  cstart[ncomp] = w;
+  return ncomp;
+}
+
+/* nested dissection of the connected set S (sorted), current tag t */
+static int nd_rec(ordctx_t* c, const int32_t* S, int64_t ns, int32_t t) {
+  if (ns <= 64) {
+    for (int64_t a = 0; a < ns; ++a) c->out[c->nout++] = S[a];
+    return ORC_OK;
+  }
+  int32_t ecc;
+  (void)pseudo_peripheral(c, S, ns, t, &ecc);
+  if (ecc < 2) {
+    for (int64_t a = 0; a < ns; ++a) c->out[c->nout++] = S[a];
+    return ORC_OK;
+  }
+  int32_t mid = (ecc + 1) / 2; /* ceil(ecc/2) */
+  /* separator: members at level mid (levels are from the root left by
+     pseudo_peripheral); the rest get a fresh tag */
+  int32_t* sep = (int32_t*)malloc(sizeof(int32_t) * (size_t)ns);
+  int32_t* rest = (int32_t*)malloc(sizeof(int32_t) * (size_t)ns);
+  int32_t* comp = (int32_t*)malloc(sizeof(int32_t) * (size_t)ns);
+  int64_t* cstart = (int64_t*)malloc(sizeof(int64_t) * (size_t)(ns + 1));
+  if (!sep || !rest || !comp || !cstart) return ORC_ERR_ALLOC;
+  int64_t nsep = 0, nrest = 0;
+  int32_t t2 = ++c->next_tag;
+  for (int64_t a = 0; a < ns; ++a) {
+    int32_t v = S[a];
+    if (c->level[v] == mid) {
+      sep[nsep++] = v;
+      c->tag[v] = -1;
+    } else {
+      rest[nrest++] = v;
+      c->tag[v] = t2;
+    }
+  }
+  int64_t ncomp = components(c, rest, nrest, t2, comp, cstart);
+  free(rest);
+  for (int64_t q = 0; q < ncomp; ++q) {
+    int64_t a = cstart[q], b = cstart[q + 1];
+    int32_t t3 = ++c->next_tag;
+    for (int64_t x = a; x < b; ++x) c->tag[comp[x]] = t3;
+    int rc = nd_rec(c, comp + a, b - a, t3);
+    if (rc) return rc;
+  }
+  for (int64_t a = 0; a < nsep; ++a) c->out[c->nout++] = sep[a];
+  free(sep);
+  free(comp);
+  free(cstart);
+  return ORC_OK;
+}
+
+/* Ordering of the whole graph by method (NATURAL/RCM/ND); perm[new] = old */
+static int order_fixed(const graph_t* g, int method, int32_t* perm, int32_t* ndense_out) {
+  int64_t n = g->n;
+  int64_t thr = isqrt64(100 * n);
+  if (thr < 16) thr = 16;
+  ordctx_t c;
+  memset(&c, 0, sizeof(c));
+  c.g = g;
+  c.tag = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  c.level = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  c.seen = (int32_t*)calloc((size_t)n, sizeof(int32_t));
+  c.queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  c.out = perm;
+  int32_t* S = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* comp = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int64_t* cstart = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  if (!c.tag || !c.level || !c.seen || !c.queue || !S || !comp || !cstart) return ORC_ERR_ALLOC;
+  c.next_tag = 1;
+  int64_t ns = 0, nd = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    int64_t deg = g->xadj[v + 1] - g->xadj[v];
+    if (deg > thr) {
+      c.tag[v] = -1;
+      nd++;
+    } else {
+      c.tag[v] = 1;
+      S[ns++] = (int32_t)v;
+    }
+  }
+  int rc = ORC_OK;
+  if (method == ORD_NATURAL) {
+    for (int64_t a = 0; a < ns; ++a) c.out[c.nout++] = S[a];
+  } else {
+    int64_t ncomp = components(&c, S, ns, 1, comp, cstart);
+    for (int64_t q = 0; q < ncomp && rc == ORC_OK; ++q) {
+      int64_t a = cstart[q], b = cstart[q + 1];
+      int32_t t = ++c.next_tag;
+      for (int64_t x = a; x < b; ++x) c.tag[comp[x]] = t;
+      if (method == ORD_RCM)
+        rc = rcm_component(&c, comp + a, b - a, t);
+      else
+        rc = nd_rec(&c, comp + a, b - a, t);
+    }
+  }
+  for (int64_t v = 0; v < n; ++v) {
+    int64_t deg = g->xadj[v + 1] - g->xadj[v];
+    if (deg > thr) c.out[c.nout++] = (int32_t)v;
+  }
+  if (rc == ORC_OK && c.nout != n) rc = ORC_ERR_ARG;
+  *ndense_out = (int32_t)nd;
+  free(c.tag);
+  free(c.level);
+  free(c.seen);
+  free(c.queue);
+  free(S);
+  free(comp);
+  free(cstart);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* the analysed state                                                        */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+  int64_t n, qnz;
+  int64_t* qp;
+  int32_t* qi;
+  int32_t* perm;  /* perm[new] = old */
+  int32_t* iperm; /* iperm[old] = new */
+  int32_t ndense;
+  int method_used;
+  /* permuted lower CSC and the map input position -> permuted position */
+  int64_t* cp;
+  int32_t* ci;
+  int64_t* cmap;
+  /* factor structure */
+  int32_t* parent;
+  int64_t* lp;
+  int32_t* li;
+  int64_t lnz;
+  int64_t* cinl; /* permuted entry -> position in L */
+  /* row structure of L (strictly lower part), for the left-looking sweep */
+  int64_t* rp;
+  int32_t* rk;   /* column index k */
+  int64_t* rpos; /* position of L_jk in column k */
+  /* tiles */
+  int nb, NT, mode, route;
+  int64_t ntiles;     /* non-empty off-diagonal tiles */
+  int32_t* tile_m;
+  int32_t* tile_k;
+  int32_t* tile_cnt;  /* |R| as stored (full height in DENSE storage) */
+  int32_t* tile_true; /* |R| from the pattern */
+  int8_t* tile_contig;
+  int64_t* tile_roff; /* offset into rows */
+  int32_t* rows;      /* concatenated active rows, local to block m */
+  int32_t* kd;        /* per diagonal tile */
+  double phi, rho, sigma;
+  int64_t tact;
+  int64_t ntasks;
+  int32_t* tasks; /* 4 ints per task: op, m, k, n (-1 = unused slot) */
+} orc_t;
+
+void orc_free(orc_t* s);
+
+/* symbolic factorization of the permuted matrix, by definition */
+static int symbolic_by_definition(orc_t* s) {
+  int64_t n = s->n;
+  int32_t* head = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* nextc = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* mark = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  s->parent = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  s->lp = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  if (!head || !nextc || !mark || !buf || !s->parent || !s->lp) return ORC_ERR_ALLOC;
+  for (int64_t j = 0; j < n; ++j) { head[j] = -1; mark[j] = -1; }
+  int64_t cap = s->cp[n] * 2 + 16, used = 0;
+  int32_t* li = (int32_t*)malloc(sizeof(int32_t) * (size_t)cap);
+  if (!li) return ORC_ERR_ALLOC;
+  s->lp[0] = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    int64_t cnt = 0;
+    for (int64_t p = s->cp[j]; p < s->cp[j + 1]; ++p) {
+      int32_t i = s->ci[p];
+      if (mark[i] != j) { mark[i] = (int32_t)j; buf[cnt++] = i; }
+    }
+    for (int32_t ch = head[j]; ch >= 0; ch = nextc[ch]) {
+      for (int64_t p = s->lp[ch] + 1; p < s->lp[ch + 1]; ++p) {
+        int32_t i = li[p];
+        if (mark[i] != j) { mark[i] = (int32_t)j; buf[cnt++] = i; }
+      }
+    }
+    qsort(buf, (size_t)cnt, sizeof(int32_t), cmp_i32);
+    if (used + cnt > cap) {
+      while (used + cnt > cap) cap *= 2;
+      int32_t* t = (int32_t*)realloc(li, sizeof(int32_t) * (size_t)cap);
+      if (!t) return ORC_ERR_ALLOC;
+      li = t;
+    }
+    memcpy(li + used, buf, sizeof(int32_t) * (size_t)cnt);
+    used += cnt;
+    s->lp[j + 1] = used;
+    s->parent[j] = cnt > 1 ? buf[1] : -1;
+    if (cnt > 1) {
+      int32_t par = buf[1];
+      nextc[j] = head[par];
+      head[par] = (int32_t)j;
+    }
+  }
+  s->li = li;
+  s->lnz = used;
+  free(head);
+  free(nextc);
+  free(mark);
+  free(buf);
+  return ORC_OK;
+}
+
+static int build_permuted(orc_t* s) {
+  int64_t n = s->n;
+  s->iperm = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  s->cp = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+  s->ci = (int32_t*)malloc(sizeof(int32_t) * (size_t)s->qnz);
+  s->cmap = (int64_t*)malloc(sizeof(int64_t) * (size_t)s->qnz);
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  if (!s->iperm || !s->cp || !s->ci || !s->cmap || !fill) return ORC_ERR_ALLOC;
+  for (int64_t a = 0; a < n; ++a) s->iperm[s->perm[a]] = (int32_t)a;
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t p = s->qp[j]; p < s->qp[j + 1]; ++p) {
+      int32_t a = s->iperm[s->qi[p]], b = s->iperm[j];
+      int32_t col = a < b ? a : b;
+      s->cp[col + 1]++;
+    }
+  for (int64_t j = 0; j < n; ++j) s->cp[j + 1] += s->cp[j];
+  for (int64_t j = 0; j < n; ++j) fill[j] = s->cp[j];
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t p = s->qp[j]; p < s->qp[j + 1]; ++p) {
+      int32_t a = s->iperm[s->qi[p]], b = s->iperm[j];
+      int32_t col = a < b ? a : b, row = a < b ? b : a;
+      s->ci[fill[col]] = row;
+      s->cmap[p] = fill[col];
+      fill[col]++;
+    }
+  /* sort each column by row, carrying the map (insertion sort: columns are
+     short, and this keeps the code obvious) */
+  int64_t* inv = (int64_t*)malloc(sizeof(int64_t) * (size_t)s->qnz);
+  if (!inv) return ORC_ERR_ALLOC;
+  for (int64_t p = 0; p < s->qnz; ++p) inv[s->cmap[p]] = p;
+  for (int64_t j = 0; j < n; ++j) {
+    for (int64_t a = s->cp[j] + 1; a < s->cp[j + 1]; ++a) {
+      int32_t r = s->ci[a];
+      int64_t src = inv[a];
+      int64_t b = a - 1;
+      while (b >= s->cp[j] && s->ci[b] > r) {
+        s->ci[b + 1] = s->ci[b];
+        inv[b + 1] = inv[b];
+        --b;
+      }
+      s->ci[b + 1] = r;
+      inv[b + 1] = src;
+    }
+  }
+  for (int64_t q = 0; q < s->qnz; ++q) s->cmap[inv[q]] = q;
+  free(inv);
+  free(fill);
+  return ORC_OK;
+}
+
+/* tiles, features, route and Algorithm 1 for block size nb */
+static int build_tiles(orc_t* s, int nb, int mode) {
+  int64_t n = s->n;
+  int NT = (int)((n + nb - 1) / nb);
+  s->nb = nb;
+  s->NT = NT;
+  /* active-row bitmaps for every (m,k), m>k, stored as bytes per row */
+  int64_t npairs = (int64_t)NT * (NT - 1) / 2;
+  uint8_t* act = (uint8_t*)calloc((size_t)(npairs > 0 ? npairs : 1) * (size_t)nb, 1);
+  s->kd = (int32_t*)calloc((size_t)NT, sizeof(int32_t));
+  if (!act || !s->kd) return ORC_ERR_ALLOC;
+  /* pair index of (m,k), m>k: column-major over k */
+#define PAIR(m, k) ((int64_t)(k) * (2 * (int64_t)NT - (k)-1) / 2 + ((m) - (k)-1))
+  for (int64_t j = 0; j < n; ++j) {
+    int k = (int)(j / nb);
+    for (int64_t p = s->lp[j]; p < s->lp[j + 1]; ++p) {
+      int64_t i = s->li[p];
+      int m = (int)(i / nb);
+      if (m == k) {
+        if (i - j > s->kd[k]) s->kd[k] = (int32_t)(i - j);
+      } else {
+        act[PAIR(m, k) * nb + (i - (int64_t)m * nb)] = 1;
+      }
+    }
+  }
+  int64_t ntiles = 0, sum_true = 0;
+  for (int k = 0; k < NT; ++k)
+    for (int m = k + 1; m < NT; ++m) {
+      int64_t base = PAIR(m, k) * nb;
+      int cnt = 0;
+      for (int r = 0; r < nb; ++r) cnt += act[base + r];
+      if (cnt) {
+        ntiles++;
+        sum_true += cnt;
+      }
+    }
+  /* features (Sec. 5.1) */
+  int64_t* rowcount = (int64_t*)calloc((size_t)n, sizeof(int64_t));
+  if (!rowcount) return ORC_ERR_ALLOC;
+  for (int64_t p = 0; p < s->lnz; ++p) rowcount[s->li[p]]++;
+  int64_t maxrc = 0;
+  for (int64_t i = 0; i < n; ++i)
+    if (rowcount[i] > maxrc) maxrc = rowcount[i];
+  free(rowcount);
+  s->phi = (double)s->lnz / (double)s->qnz;
+  s->rho = ntiles ? (double)sum_true / ((double)nb * (double)ntiles) : 1.0;
+  s->sigma = ((double)maxrc * (double)n) / (double)s->lnz;
+  s->tact = ntiles + NT;
+  /* fixed precedence of the selector, cut-offs of Table 5 */
+  if (s->rho >= 0.90)
+    s->route = ROUTE_DENSE;
+  else if (s->phi > 2.0 && s->rho < 0.15)
+    s->route = ROUTE_SUPERNODAL;
+  else if (s->rho >= 0.15 || s->sigma >= 20.0)
+    s->route = ROUTE_SEMISPARSE;
+  else
+    s->route = ROUTE_SUPERNODAL;
+  /* the supernodal decision is reported and runs on the active-column tiles */
+  if (mode == MODE_AUTO) mode = (s->route == ROUTE_DENSE) ? MODE_DENSE : MODE_SEMISPARSE;
+  s->mode = mode;
+  int64_t nrows_stored = 0;
+  for (int k = 0; k < NT; ++k)
+    for (int m = k + 1; m < NT; ++m) {
+      int64_t base = PAIR(m, k) * nb;
+      int cnt = 0;
+      for (int r = 0; r < nb; ++r) cnt += act[base + r];
+      int hm = (int)((m == NT - 1) ? n - (int64_t)m * nb : nb);
+      if (cnt) nrows_stored += (mode == MODE_DENSE) ? hm : cnt;
+    }
+  s->ntiles = ntiles;
+  s->tile_m = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ntiles + 1));
+  s->tile_k = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ntiles + 1));
+  s->tile_cnt = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ntiles + 1));
+  s->tile_true = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ntiles + 1));
+  s->tile_contig = (int8_t*)malloc((size_t)(ntiles + 1));
+  s->tile_roff = (int64_t*)malloc(sizeof(int64_t) * (size_t)(ntiles + 1));
+  s->rows = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nrows_stored + 1));
+  if (!s->tile_m || !s->tile_k || !s->tile_cnt || !s->tile_true || !s->tile_contig ||
+      !s->tile_roff || !s->rows)
+    return ORC_ERR_ALLOC;
+  int64_t t = 0, w = 0;
+  for (int k = 0; k < NT; ++k)
+    for (int m = k + 1; m < NT; ++m) {
+      int64_t base = PAIR(m, k) * nb;
+      int cnt = 0, lo = -1, hi = -1;
+      for (int r = 0; r < nb; ++r)
+        if (act[base + r]) {
+          cnt++;
+          if (lo < 0) lo = r;
+          hi = r;
+        }
+      if (!cnt) continue;
+      int hm = (int)((m == NT - 1) ? n - (int64_t)m * nb : nb);
+      s->tile_m[t] = m;
+      s->tile_k[t] = k;
+      s->tile_true[t] = cnt;
+      s->tile_roff[t] = w;
+      if (mode == MODE_DENSE) {
+        s->tile_cnt[t] = hm;
+        s->tile_contig[t] = 1;
+        for (int r = 0; r < hm; ++r) s->rows[w++] = r;
+      } else {
+        s->tile_cnt[t] = cnt;
+        s->tile_contig[t] = (int8_t)(hi - lo + 1 == cnt);
+        for (int r = 0; r < nb; ++r)
+          if (act[base + r]) s->rows[w++] = r;
+      }
+      t++;
+    }
+  s->tile_roff[t] = w;
+#undef PAIR
+  free(act);
+
+  return ORC_OK;
+}
+
+/* Algorithm 1: the ordered task list.  N(k) is the tile neighbourhood. */
+static int build_tasks(orc_t* s) {
+  int NT = s->NT;
+  /* column lists (m>k) are the tile list itself; row lists (n<k) by transpose */
+  int64_t* cstart = (int64_t*)calloc((size_t)NT + 1, sizeof(int64_t));
+  int64_t* rstart = (int64_t*)calloc((size_t)NT + 1, sizeof(int64_t));
+  int32_t* rlist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(s->ntiles + 1));
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(NT + 1));
+  if (!cstart || !rstart || !rlist || !fill) return ORC_ERR_ALLOC;
+  for (int64_t t = 0; t < s->ntiles; ++t) {
+    cstart[s->tile_k[t] + 1]++;
+    rstart[s->tile_m[t] + 1]++;
+  }
+  for (int k = 0; k < NT; ++k) {
+    cstart[k + 1] += cstart[k];
+    rstart[k + 1] += rstart[k];
+  }
+  for (int k = 0; k < NT; ++k) fill[k] = rstart[k];
+  /* tiles are ordered by k then m, so each row list comes out ascending in n */
+  for (int64_t t = 0; t < s->ntiles; ++t) rlist[fill[s->tile_m[t]]++] = s->tile_k[t];
+  free(fill);
+  /* count, then emit */
+  for (int pass = 0; pass < 2; ++pass) {
+    int64_t nt = 0;
+#define EMIT(op, m, k, nn)                \
+  do {                                    \
+    if (pass) {                           \
+      s->tasks[4 * nt + 0] = (op);        \
+      s->tasks[4 * nt + 1] = (m);         \
+      s->tasks[4 * nt + 2] = (k);         \
+      s->tasks[4 * nt + 3] = (nn);        \
+    }                                     \
+    nt++;                                 \
+  } while (0)
+    for (int k = 0; k < NT; ++k) {
+      for (int64_t a = rstart[k]; a < rstart[k + 1]; ++a) EMIT(OP_SYRK, -1, k, rlist[a]);
+      EMIT(OP_POTRF, -1, k, -1);
+      for (int64_t b = cstart[k]; b < cstart[k + 1]; ++b) {
+        int m = s->tile_m[b];
+        /* n in N(k) and N(m), n < k: merge the two ascending row lists */
+        int64_t x = rstart[k], y = rstart[m];
+        while (x < rstart[k + 1] && y < rstart[m + 1]) {
+          int nx = rlist[x], ny = rlist[y];
+          if (nx >= k || ny >= k) break;
+          if (nx == ny) {
+            EMIT(OP_GEMM, m, k, nx);
+            ++x;
+            ++y;
+          } else if (nx < ny) {
+            ++x;
+          } else {
+            ++y;
+          }
+        }
+        EMIT(OP_TRSM, m, k, -1);
+      }
+    }
+#undef EMIT
+    if (!pass) {
+      s->ntasks = nt;
+      s->tasks = (int32_t*)malloc(sizeof(int32_t) * 4 * (size_t)(nt + 1));
+      if (!s->tasks) return ORC_ERR_ALLOC;
+    }
+  }
+  free(cstart);
+  free(rstart);
+  free(rlist);
+  return ORC_OK;
+}
+
+/* L's strictly-lower row structure and the position of each input entry in L */
+static int build_rows_and_cinl(orc_t* s) {
+  int64_t n = s->n;
+  s->rp = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+  s->rk = (int32_t*)malloc(sizeof(int32_t) * (size_t)(s->lnz - n + 1));
+  s->rpos = (int64_t*)malloc(sizeof(int64_t) * (size_t)(s->lnz - n + 1));
+  s->cinl = (int64_t*)malloc(sizeof(int64_t) * (size_t)s->qnz);
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  if (!s->rp || !s->rk || !s->rpos || !s->cinl || !fill) return ORC_ERR_ALLOC;
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t p = s->lp[j] + 1; p < s->lp[j + 1]; ++p) s->rp[s->li[p] + 1]++;
+  for (int64_t i = 0; i < n; ++i) s->rp[i + 1] += s->rp[i];
+  for (int64_t i = 0; i < n; ++i) fill[i] = s->rp[i];
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t p = s->lp[j] + 1; p < s->lp[j + 1]; ++p) {
+      int32_t i = s->li[p];
+      s->rk[fill[i]] = (int32_t)j;
+      s->rpos[fill[i]] = p;
+      fill[i]++;
+    }
+  free(fill);
+  for (int64_t j = 0; j < n; ++j) {
+    int64_t p = s->lp[j];
+    for (int64_t q = s->cp[j]; q < s->cp[j + 1]; ++q) {
+      while (s->li[p] != s->ci[q]) ++p;
+      s->cinl[q] = p;
+    }
+  }
+  return ORC_OK;
+}
+
+/* full symbolic analysis with a fixed permutation */
+static int analyse_with_perm(orc_t* s, int nb, int mode) {
+  int rc = build_permuted(s);
+  if (!rc) rc = symbolic_by_definition(s);
+  if (!rc) rc = build_tiles(s, nb, mode);
+  if (!rc) rc = build_tasks(s);
+  if (!rc) rc = build_rows_and_cinl(s);
+  return rc;
+}
+
+static orc_t* orc_new_copy(int64_t n, const int64_t* cp, const int32_t* ri) {
+  orc_t* s = (orc_t*)calloc(1, sizeof(orc_t));
+  if (!s) return NULL;
+  s->n = n;
+  s->qnz = cp[n];
+  s->qp = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  s->qi = (int32_t*)malloc(sizeof(int32_t) * (size_t)s->qnz);
+  s->perm = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  if (!s->qp || !s->qi || !s->perm) { orc_free(s); return NULL; }
+  memcpy(s->qp, cp, sizeof(int64_t) * (size_t)(n + 1));
+  memcpy(s->qi, ri, sizeof(int32_t) * (size_t)s->qnz);
+  return s;
+}
+
+/* Analyse.  method: NATURAL/RCM/ND/AUTO, or GIVEN with perm_in.  mode:
+   AUTO (route decides storage), DENSE, SEMISPARSE.  Returns NULL on error and
+   sets *err. */
+orc_t* orc_analyse(int64_t n, const int64_t* cp, const int32_t* ri, int method, int nb, int mode,
+                   const int32_t* perm_in, int* err) {
+  *err = orc_check_pattern(n, cp, ri);
+  if (*err) return NULL;
+  if (nb < 1 || method < 0 || method > ORD_GIVEN || mode < 0 || mode > MODE_SEMISPARSE) {
+    *err = ORC_ERR_ARG;
+    return NULL;
+  }
+  if (method == ORD_GIVEN) {
+    if (!perm_in) { *err = ORC_ERR_ARG; return NULL; }
+    orc_t* s = orc_new_copy(n, cp, ri);
+    if (!s) { *err = ORC_ERR_ALLOC; return NULL; }
+    /* must be a permutation */
+    uint8_t* seen = (uint8_t*)calloc((size_t)n, 1);
+    for (int64_t a = 0; a < n; ++a) {
+      if (perm_in[a] < 0 || perm_in[a] >= n || seen[perm_in[a]]) {
+        free(seen);
+        orc_free(s);
+        *err = ORC_ERR_ARG;
+        return NULL;
+      }
+      seen[perm_in[a]] = 1;
+      s->perm[a] = perm_in[a];
+    }
+    free(seen);
+    s->method_used = ORD_GIVEN;
+    *err = analyse_with_perm(s, nb, mode);
+    if (*err) { orc_free(s); return NULL; }
+    return s;
+  }
+  graph_t g;
+  *err = graph_build(n, cp, ri, &g);
+  if (*err) return NULL;
+  if (method != ORD_AUTO) {
+    orc_t* s = orc_new_copy(n, cp, ri);
+    if (!s) { graph_free(&g); *err = ORC_ERR_ALLOC; return NULL; }
+    *err = order_fixed(&g, method, s->perm, &s->ndense);
+    graph_free(&g);
+    if (!*err) *err = analyse_with_perm(s, nb, mode);
+    if (*err) { orc_free(s); return NULL; }
+    s->method_used = method;
+    return s;
+  }
+  /* AUTO: score NATURAL, RCM, ND by (nnz(L), active tiles, occupancy) */
+  orc_t* cand[3] = {NULL, NULL, NULL};
+  for (int m = 0; m < 3; ++m) {
+    cand[m] = orc_new_copy(n, cp, ri);
+    if (!cand[m]) { *err = ORC_ERR_ALLOC; break; }
+    cand[m]->method_used = m;
+    *err = order_fixed(&g, m, cand[m]->perm, &cand[m]->ndense);
+    if (!*err) *err = analyse_with_perm(cand[m], nb, mode);
+    if (*err) break;
+  }
+  graph_free(&g);
+  if (*err) {
+    for (int m = 0; m < 3; ++m)
+      if (cand[m]) orc_free(cand[m]);
+    return NULL;
+  }
+  int win;
+  int minfill = 0;
+  for (int m = 1; m < 3; ++m)
+    if (cand[m]->lnz < cand[minfill]->lnz) minfill = m;
+  if (cand[ORD_NATURAL]->rho < 0.15) {
+    win = minfill; /* sparse graph: fill is a fair proxy for work */
+  } else {
+    int mint = 0;
+    for (int m = 1; m < 3; ++m)
+      if (cand[m]->tact < cand[mint]->tact) mint = m;
+    win = mint;
+    /* a candidate whose fill is lower by enough (at most half) overrides */
+    int low = -1;
+    for (int m = 0; m < 3; ++m)
+      if (2 * cand[m]->lnz <= cand[mint]->lnz && (low < 0 || cand[m]->lnz < cand[low]->lnz)) low = m;
+    if (low >= 0) win = low;
+  }
+  /* nested-dissection allowance on large problems: fill within 1.25x of best */
+  if (n >= 50000 && 4 * cand[ORD_ND]->lnz <= 5 * cand[minfill]->lnz) win = ORD_ND;
+  for (int m = 0; m < 3; ++m)
+    if (m != win) orc_free(cand[m]);
+  return cand[win];
+}
+
+void orc_free(orc_t* s) {
+  if (!s) return;
+  free(s->qp); free(s->qi); free(s->perm); free(s->iperm);
+  free(s->cp); free(s->ci); free(s->cmap);
+  free(s->parent); free(s->lp); free(s->li); free(s->cinl);
+  free(s->rp); free(s->rk); free(s->rpos);
+  free(s->tile_m); free(s->tile_k); free(s->tile_cnt); free(s->tile_true);
+  free(s->tile_contig); free(s->tile_roff); free(s->rows); free(s->kd);
+  free(s->tasks);
+  free(s);
+}
+
+/* ------------------------------------------------------------------------- */
+/* accessors (copy out)                                                      */
+/* ------------------------------------------------------------------------- */
+
+void orc_sizes(const orc_t* s, int64_t* out) {
+  out[0] = s->n;
+  out[1] = s->qnz;
+  out[2] = s->lnz;
+  out[3] = s->nb;
+  out[4] = s->NT;
+  out[5] = s->ntiles;
+  out[6] = s->tile_roff[s->ntiles];
+  out[7] = s->ntasks;
+  out[8] = s->mode;
+  out[9] = s->route;
+  out[10] = s->ndense;
+  out[11] = s->method_used;
+  out[12] = s->tact;
+}
+
+void orc_features(const orc_t* s, double* out) {
+  out[0] = s->phi;
+  out[1] = s->rho;
+  out[2] = s->sigma;
+}
+
+void orc_get_perm(const orc_t* s, int32_t* perm) { memcpy(perm, s->perm, sizeof(int32_t) * (size_t)s->n); }
+void orc_get_etree(const orc_t* s, int32_t* par) { memcpy(par, s->parent, sizeof(int32_t) * (size_t)s->n); }
+void orc_get_L_pattern(const orc_t* s, int64_t* lp, int32_t* li) {
+  memcpy(lp, s->lp, sizeof(int64_t) * (size_t)(s->n + 1));
+  memcpy(li, s->li, sizeof(int32_t) * (size_t)s->lnz);
+}
+void orc_get_value_map(const orc_t* s, int64_t* pos_in_L) {
+  for (int64_t p = 0; p < s->qnz; ++p) pos_in_L[p] = s->cinl[s->cmap[p]];
+}
+void orc_get_tiles(const orc_t* s, int32_t* m, int32_t* k, int32_t* cnt, int32_t* truecnt,
+                   int8_t* contig, int64_t* roff, int32_t* rows, int32_t* kd) {
+  size_t nt = (size_t)s->ntiles;
+  memcpy(m, s->tile_m, sizeof(int32_t) * nt);
+  memcpy(k, s->tile_k, sizeof(int32_t) * nt);
+  memcpy(cnt, s->tile_cnt, sizeof(int32_t) * nt);
+  memcpy(truecnt, s->tile_true, sizeof(int32_t) * nt);
+  memcpy(contig, s->tile_contig, nt);
+  memcpy(roff, s->tile_roff, sizeof(int64_t) * (nt + 1));
+  memcpy(rows, s->rows, sizeof(int32_t) * (size_t)s->tile_roff[nt]);
+  memcpy(kd, s->kd, sizeof(int32_t) * (size_t)s->NT);
+}
+void orc_get_tasks(const orc_t* s, int32_t* tasks) {
+  memcpy(tasks, s->tasks, sizeof(int32_t) * 4 * (size_t)s->ntasks);
+}
+
+/* ------------------------------------------------------------------------- */
+/* numeric phase                                                             */
+/* ------------------------------------------------------------------------- */
+
+/* Cholesky factor of P A P^T.  vals: input values in the analysed CSC order.
+   Lx: output in L's CSC order.  Returns 0, or the 1-based permuted column of
+   the first pivot that is not positive and finite. */
+int64_t orc_factor(const orc_t* s, const double* vals, double* Lx) {
+  int64_t n = s->n;
+  double* x = (double*)calloc((size_t)n, sizeof(double));
+  double* cval = (double*)malloc(sizeof(double) * (size_t)s->qnz);
+  if (!x || !cval) { free(x); free(cval); return -1; }
+  for (int64_t p = 0; p < s->qnz; ++p) cval[s->cmap[p]] = vals[p];
+  int64_t info = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    for (int64_t p = s->lp[j]; p < s->lp[j + 1]; ++p) x[s->li[p]] = 0.0;
+    for (int64_t q = s->cp[j]; q < s->cp[j + 1]; ++q) x[s->ci[q]] += cval[q];
+    /* subtract L_ik L_jk for every k < j with L_jk != 0, k ascending */
+    for (int64_t e = s->rp[j]; e < s->rp[j + 1]; ++e) {
+      int32_t k = s->rk[e];
+      int64_t pjk = s->rpos[e];
+      double ljk = Lx[pjk];
+      for (int64_t p = pjk; p < s->lp[k + 1]; ++p) x[s->li[p]] -= Lx[p] * ljk;
+    }
+    double d = x[j];
+    if (!(d > 0.0) || !isfinite(d)) { info = j + 1; break; }
+    double ljj = sqrt(d);
+    Lx[s->lp[j]] = ljj;
+    for (int64_t p = s->lp[j] + 1; p < s->lp[j + 1]; ++p) Lx[p] = x[s->li[p]] / ljj;
+  }
+  free(x);
+  free(cval);
+  return info;
+}
+
+/* 2 * sum_j log L_jj with Neumaier's compensated summation, j ascending */
+double orc_logdet(const orc_t* s, const double* Lx) {
+  double sum = 0.0, comp = 0.0;
+  for (int64_t j = 0; j < s->n; ++j) {
+    double v = log(Lx[s->lp[j]]);
+    double t = sum + v;
+    if (fabs(sum) >= fabs(v))
+      comp += (sum - t) + v;
+    else
+      comp += (v - t) + sum;
+    sum = t;
+  }
+  return 2.0 * (sum + comp);
+}
+
+/* x = P^T L^-T L^-1 P b for nrhs column-major right-hand sides, in place */
+void orc_solve(const orc_t* s, const double* Lx, double* b, int64_t nrhs) {
+  int64_t n = s->n;
+  double* y = (double*)malloc(sizeof(double) * (size_t)n);
+  for (int64_t r = 0; r < nrhs; ++r) {
+    double* br = b + r * n;
+    for (int64_t a = 0; a < n; ++a) y[a] = br[s->perm[a]];
+    for (int64_t j = 0; j < n; ++j) { /* L z = y */
+      y[j] /= Lx[s->lp[j]];
+      for (int64_t p = s->lp[j] + 1; p < s->lp[j + 1]; ++p) y[s->li[p]] -= Lx[p] * y[j];
+    }
+    for (int64_t j = n - 1; j >= 0; --j) { /* L^T w = z */
+      double acc = y[j];
+      for (int64_t p = s->lp[j] + 1; p < s->lp[j + 1]; ++p) acc -= Lx[p] * y[s->li[p]];
+      y[j] = acc / Lx[s->lp[j]];
+    }
+    for (int64_t a = 0; a < n; ++a) br[s->perm[a]] = y[a];
+  }
+  free(y);
+}
+
+/* Selected inverse Z = (P A P^T)^-1 on the pattern of L (Zx in L's layout),
+   from sum_{i >= j} Z_ki L_ij = delta_kj / L_jj, for j = n-1 down to 0. */
+void orc_selinv(const orc_t* s, const double* Lx, double* Zx) {
+  int64_t n = s->n;
+  double* acc = (double*)calloc((size_t)n, sizeof(double));
+  for (int64_t j = n - 1; j >= 0; --j) {
+    int64_t a0 = s->lp[j], a1 = s->lp[j + 1];
+    for (int64_t a = a0 + 1; a < a1; ++a) acc[s->li[a]] = 0.0;
+    /* acc[k] = sum_{i in struct(L_j), i>j} L_ij Z_ki for k in struct(L_j), k>j */
+    for (int64_t a = a0 + 1; a < a1; ++a) {
+      int32_t i = s->li[a];
+      double lij = Lx[a];
+      /* walk column i of Z; struct(L_j) from i onward lies inside it */
+      int64_t b = a;
+      for (int64_t q = s->lp[i]; q < s->lp[i + 1] && b < a1; ++q) {
+        int32_t k = s->li[q];
+        if (k != s->li[b]) continue;
+        double zki = Zx[q];
+        acc[k] += lij * zki;       /* term i of row k (k >= i)       */
+        if (k != i) acc[i] += Lx[b] * zki; /* mirrored term of row i */
+        ++b;
+      }
+    }
+    double ljj = Lx[a0];
+    double dsum = 0.0;
+    for (int64_t a = a0 + 1; a < a1; ++a) {
+      double z = -acc[s->li[a]] / ljj;
+      Zx[a] = z;
+      dsum += Lx[a] * z;
+    }
+    Zx[a0] = (1.0 / ljj - dsum) / ljj;
+  }
+  free(acc);
+}
+
+/* The selector's fixed precedence (Sec. 5.1) with the cut-offs of Table 5,
+   exposed on its own for boundary tests. */
+int orc_route(double phi, double rho, double sigma) {
+  if (rho >= 0.90) return ROUTE_DENSE;
+  if (phi > 2.0 && rho < 0.15) return ROUTE_SUPERNODAL;
+  if (rho >= 0.15 || sigma >= 20.0) return ROUTE_SEMISPARSE;
+  return ROUTE_SUPERNODAL;
+}
