@@ -1,0 +1,169 @@
+/*
+ * stc.h -- C ABI of the structure-adaptive tile Cholesky library (libstc.so)
+ * for AMD Instinct MI355X (gfx950), FP64 throughout.
+ *
+ * The operation is the numerical phase of the fixed-grid tile Cholesky of
+ * arXiv 2609.29765: a sparsity pattern is analysed once (ordering, symbolic
+ * factor, tile classification, static task list; Sec. 3, Sec. 5.1-5.2), then
+ * its factor L with P A P^T = L L^T is computed many times for new values by
+ * replaying one static POTRF/SYRK/GEMM/TRSM tile schedule (Algorithm 1), the
+ * factor staying resident on the device where the log-determinant and solves
+ * consume it (Sec. 6.8).  The split of a once-per-pattern analysis from a
+ * repeated factorization is the interface the paper states (Sec. 6.7).
+ *
+ * Conventions shared by every entry point
+ *   - Return value: 0 on success; negative for usage errors (STC_ERR_*);
+ *     STC_NOT_SPD (positive) when a factorization met a pivot that is not
+ *     positive and finite.  No C++ exception crosses this boundary.  After a
+ *     non-zero return, stc_last_error() holds a message (thread-local).
+ *   - Host pointers are marked (host); device pointers (device).  Device
+ *     pointers must address memory of the device that was current when the
+ *     handle was bound.
+ *   - The caller owns every device buffer (workspace, values, right-hand
+ *     sides, outputs) and every stream.  The library allocates no device
+ *     memory: stc_workspace_bytes() says how much the caller must provide.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *     Calls taking a stream are asynchronous with respect to the host.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef STC_H
+#define STC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define STC_OK 0
+#define STC_ERR_ARG (-1)     /* a null pointer, a size out of range, a bad option */
+#define STC_ERR_PATTERN (-2) /* input pattern not a valid lower CSC (see stc_analyse) */
+#define STC_ERR_STATE (-3)   /* wrong call order (e.g. logdet before factorize)    */
+#define STC_ERR_ALLOC (-4)   /* host allocation failed or workspace too small      */
+#define STC_ERR_HIP (-5)     /* a HIP runtime call failed                          */
+#define STC_NOT_SPD 1        /* numerical: a pivot was not positive and finite     */
+
+/* orderings (Sec. 3): the paper runs several fill-reducing heuristics and scores
+   them; this library offers its own deterministic NATURAL, RCM and level-
+   structure nested dissection, and AUTO scoring of the three */
+#define STC_ORD_NATURAL 0
+#define STC_ORD_RCM 1
+#define STC_ORD_ND 2
+#define STC_ORD_AUTO 3
+#define STC_ORD_GIVEN 4
+
+/* storage mode: AUTO follows the selector (Sec. 5.1); DENSE stores every
+   non-empty tile in full; SEMISPARSE keeps only active rows (Sec. 4.1) */
+#define STC_MODE_AUTO 0
+#define STC_MODE_DENSE 1
+#define STC_MODE_SEMISPARSE 2
+
+/* routes reported by the selector (Sec. 5.1); SUPERNODAL is reported and the
+   factorization then runs on the active-column tiles */
+#define STC_ROUTE_DENSE 0
+#define STC_ROUTE_SEMISPARSE 1
+#define STC_ROUTE_SUPERNODAL 2
+
+/* task opcodes of Algorithm 1 */
+#define STC_OP_POTRF 1
+#define STC_OP_SYRK 2
+#define STC_OP_TRSM 3
+#define STC_OP_GEMM 4
+
+typedef struct stc_handle stc_handle;
+
+typedef struct {
+  int32_t nb;            /* tile size n_b: 32, 64, 128 or 256 (0 = 64)          */
+  int32_t mode;          /* STC_MODE_*                                           */
+  int32_t ordering;      /* STC_ORD_*                                            */
+  const int32_t* perm;   /* (host) perm[new] = old, read when ordering == GIVEN  */
+} stc_opts;
+
+/* Analyse a sparsity pattern once (Sec. 3, Sec. 5.1-5.2).
+   n       order of the symmetric matrix A, 1 <= n < 2^31.
+   colptr  (host) int64[n+1], rowind (host) int32[colptr[n]]: the LOWER
+           triangle of A in CSC form, original numbering, rows ascending within
+           each column, the diagonal present and first, no duplicates.  Input
+           values passed later to stc_factorize follow this entry order.
+   opts    (host) may be NULL (nb 64, AUTO mode, AUTO ordering).
+   out     (host) receives a new handle; the library copies the pattern.
+   Errors: STC_ERR_PATTERN for an invalid pattern, STC_ERR_ARG for bad
+   options.  The handle owns only host memory until stc_bind is called. */
+int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const stc_opts* opts,
+                stc_handle** out);
+
+/* Device workspace needed to bind with `batch` value sets (batch >= 1):
+   device metadata, `batch` tile stores, and scratch for logdet, solve and the
+   logdet adjoint.  bytes (host) receives the size. */
+int stc_workspace_bytes(const stc_handle* h, int32_t batch, size_t* bytes);
+
+/* Bind a caller-owned device workspace of at least stc_workspace_bytes(batch)
+   bytes, aligned to 256 bytes, on the current device.  Uploads the metadata
+   (synchronously) and captures the factorization schedule as a HIP graph.
+   The workspace must stay allocated while the handle uses it; binding again
+   (new buffer or new batch) replaces the previous binding. */
+int stc_bind(stc_handle* h, void* d_workspace, size_t bytes, int32_t batch, void* stream);
+
+/* Factorize one value set (Sec. 5.2-5.3): d_values (device) double[nnz] in
+   the analysed CSC entry order.  The factor stays in the workspace.  Pivot
+   failures are recorded on the device: read them with stc_info. */
+int stc_factorize(stc_handle* h, const double* d_values, void* stream);
+
+/* Factorize B same-pattern value sets in one graph launch and write their
+   log-determinants.  d_values (device) double[B][nnz]; d_logdet (device)
+   double[B]; d_info (device) int32[B], 0 or the 1-based permuted column of the
+   first failing pivot of that member (its logdet is then NaN).  Requires
+   1 <= B <= the batch the handle was bound with. */
+int stc_factorize_batched(stc_handle* h, const double* d_values, int32_t B, double* d_logdet,
+                          int32_t* d_info, void* stream);
+
+/* log det A = 2 sum_i log L_ii of the last single factorization, written to
+   d_out (device) double[1]; NaN if that factorization failed. */
+int stc_logdet(stc_handle* h, double* d_out, void* stream);
+
+/* Solve A X = B in place with the last single factorization: d_b (device)
+   double[n * nrhs], column-major, original numbering, 1 <= nrhs <= 64. */
+int stc_solve(stc_handle* h, double* d_b, int32_t nrhs, void* stream);
+
+/* Reverse mode of logdet through the last single factorization: given the
+   scalar cotangent d_gbar (device) double[1], writes d_grad_values (device)
+   double[nnz] in the analysed CSC entry order, the symmetric matrix being
+   parameterised by its lower triangle: gbar * 2 (A^-1)_ij off the diagonal
+   and gbar * (A^-1)_ii on it. */
+int stc_logdet_backward(stc_handle* h, const double* d_gbar, double* d_grad_values, void* stream);
+
+/* Status of the last single factorization; synchronizes the bound stream.
+   info (host) receives 0 or the 1-based permuted column of the first pivot
+   that was not positive and finite. */
+int stc_info(stc_handle* h, int32_t* info);
+
+/* Symbolic exports (host copies, for inspection and bit-exact checks).
+   sizes (host) int64[16]: n, nnz(tril A), nnz(L), nb, N_T, non-empty
+   off-diagonal tiles, total stored active rows, tasks, mode (1 dense,
+   2 semisparse), route, dense rows set aside, ordering used, active tiles
+   (off-diagonal + N_T), tile-store doubles per value set, levels, reserved. */
+int stc_get_sizes(const stc_handle* h, int64_t* sizes);
+/* features (host) double[3]: fill ratio phi, mean occupancy rho, skew sigma */
+int stc_get_features(const stc_handle* h, double* features);
+int stc_get_perm(const stc_handle* h, int32_t* perm);     /* int32[n], perm[new] = old */
+int stc_get_etree(const stc_handle* h, int32_t* parent);  /* int32[n], -1 for roots    */
+int stc_get_L_pattern(const stc_handle* h, int64_t* colptr, int32_t* rowind); /* permuted */
+/* tiles in order k ascending then m ascending: m, k, stored rows, pattern rows,
+   contiguous flag, row offsets int64[ntiles+1], rows (local to block m), kd[N_T] */
+int stc_get_tiles(const stc_handle* h, int32_t* m, int32_t* k, int32_t* cnt, int32_t* true_cnt,
+                  int8_t* contig, int64_t* roff, int32_t* rows, int32_t* kd);
+int stc_get_tasks(const stc_handle* h, int32_t* tasks); /* int32[ntasks][4]: op, m, k, n */
+
+/* Copy the last single factor to the host, in stc_get_L_pattern order
+   (h_Lx double[nnz(L)]); synchronizes the stream. */
+int stc_get_factor(stc_handle* h, double* h_Lx, void* stream);
+
+void stc_destroy(stc_handle* h);
+const char* stc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STC_H */

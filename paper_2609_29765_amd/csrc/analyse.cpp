@@ -1,0 +1,752 @@
+// analyse.cpp -- symbolic analysis and static plan (see analyse.hpp).
+//
+// Orderings follow one written rule set (the paper names RCM, AMD, METIS and
+// SCOTCH without parameters, Sec. 3; the rules below are this library's):
+//   * vertices of degree > max(16, floor(sqrt(100 n))) are set aside and
+//     ordered last, ascending;
+//   * connected components are ordered one after another, ascending by their
+//     smallest vertex;
+//   * pseudo-peripheral root (George-Liu): start at the minimum-degree vertex
+//     (lowest index on ties), move to the minimum-degree vertex of the last
+//     BFS level while that strictly increases the eccentricity;
+//   * RCM: Cuthill-McKee from that root, unvisited neighbours appended by
+//     (degree, index) ascending, each component's order reversed;
+//   * ND: sets of at most 64 vertices, or of depth < 2, are leaves in
+//     ascending order; otherwise the middle level (index ceil(depth/2)) of
+//     the root's level structure is the separator, the components of the rest
+//     are dissected in ascending order of their smallest vertex, then the
+//     separator ascending;
+//   * AUTO scores NATURAL, RCM, ND on (nnz(L), active tiles): minimum fill when
+//     the natural order's mean occupancy is below 0.15, else minimum active
+//     tiles unless a candidate has at most half its fill; ND wins on n >= 50000
+//     when its fill is within 1.25x of the best.
+// Degrees are always counted inside the set being ordered.
+#include "analyse.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <functional>
+
+#include "../../include/stc.h"
+
+namespace stc {
+
+namespace {
+
+struct Graph {
+  std::vector<int64_t> start;
+  std::vector<int32_t> nbr;
+  int32_t deg(int32_t v) const { return (int32_t)(start[v + 1] - start[v]); }
+};
+
+Graph make_graph(int64_t n, const int64_t* cp, const int32_t* ri) {
+  std::vector<std::vector<int32_t>> adj((size_t)n);
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t p = cp[j] + 1; p < cp[j + 1]; ++p) {
+      adj[(size_t)ri[p]].push_back((int32_t)j);
+      adj[(size_t)j].push_back(ri[p]);
+    }
+  Graph g;
+  g.start.assign((size_t)n + 1, 0);
+  for (int64_t v = 0; v < n; ++v) g.start[v + 1] = g.start[v] + (int64_t)adj[v].size();
+  g.nbr.resize((size_t)g.start[n]);
+  for (int64_t v = 0; v < n; ++v) {
+    std::sort(adj[v].begin(), adj[v].end());
+    std::copy(adj[v].begin(), adj[v].end(), g.nbr.begin() + g.start[v]);
+  }
+  return g;
+}
+
+int64_t dense_threshold(int64_t n) {
+  // largest t with t*t <= 100 n, by bisection
+  int64_t lo = 0, hi = 1;
+  while (hi * hi <= 100 * n) hi *= 2;
+  while (hi - lo > 1) {
+    int64_t mid = (lo + hi) / 2;
+    if (mid * mid <= 100 * n) lo = mid; else hi = mid;
+  }
+  return std::max<int64_t>(16, lo);
+}
+
+class Orderer {
+ public:
+  Orderer(const Graph& g, int64_t n) : g_(g), owner_((size_t)n, 0), mark_((size_t)n, 0),
+                                        lvl_((size_t)n, 0) {}
+
+  // order the vertices of `set` (ascending, owner == id) by method, appending to out
+  void order_components(const std::vector<int32_t>& set, int32_t id, int method,
+                        std::vector<int32_t>* out) {
+    for (auto& comp : split(set, id)) {
+      int32_t cid = fresh();
+      for (int32_t v : comp) owner_[v] = cid;
+      if (method == kRcm) rcm(comp, cid, out); else nd(comp, cid, out);
+    }
+  }
+  int32_t fresh() { return ++ids_; }
+  void set_owner(int32_t v, int32_t id) { owner_[v] = id; }
+
+ private:
+  const Graph& g_;
+  std::vector<int32_t> owner_, mark_, lvl_;
+  int32_t ids_ = 1, stamp_ = 0;
+
+  int32_t degree_in(int32_t v, int32_t id) const {
+    int32_t d = 0;
+    for (int64_t p = g_.start[v]; p < g_.start[v + 1]; ++p) d += owner_[g_.nbr[p]] == id;
+    return d;
+  }
+
+  // components of the set, each sorted, in ascending order of their minimum
+  std::vector<std::vector<int32_t>> split(const std::vector<int32_t>& set, int32_t id) {
+    std::vector<std::vector<int32_t>> comps;
+    ++stamp_;
+    for (int32_t s : set) {
+      if (mark_[s] == stamp_) continue;
+      std::vector<int32_t> c{s};
+      mark_[s] = stamp_;
+      for (size_t h = 0; h < c.size(); ++h) {
+        int32_t u = c[h];
+        for (int64_t p = g_.start[u]; p < g_.start[u + 1]; ++p) {
+          int32_t w = g_.nbr[p];
+          if (owner_[w] == id && mark_[w] != stamp_) {
+            mark_[w] = stamp_;
+            c.push_back(w);
+          }
+        }
+      }
+      std::sort(c.begin(), c.end());
+      comps.push_back(std::move(c));
+    }
+    return comps;
+  }
+
+  // level structure from root; returns levels as lists
+  std::vector<std::vector<int32_t>> levels_from(int32_t root, int32_t id) {
+    std::vector<std::vector<int32_t>> L{{root}};
+    ++stamp_;
+    mark_[root] = stamp_;
+    lvl_[root] = 0;
+    while (true) {
+      std::vector<int32_t> next;
+      for (int32_t u : L.back())
+        for (int64_t p = g_.start[u]; p < g_.start[u + 1]; ++p) {
+          int32_t w = g_.nbr[p];
+          if (owner_[w] == id && mark_[w] != stamp_) {
+            mark_[w] = stamp_;
+            lvl_[w] = (int32_t)L.size();
+            next.push_back(w);
+          }
+        }
+      if (next.empty()) break;
+      L.push_back(std::move(next));
+    }
+    return L;
+  }
+
+  int32_t min_degree_vertex(const std::vector<int32_t>& vs, int32_t id) const {
+    int32_t best = -1, bd = 0;
+    for (int32_t v : vs) {
+      int32_t d = degree_in(v, id);
+      if (best < 0 || d < bd || (d == bd && v < best)) {
+        best = v;
+        bd = d;
+      }
+    }
+    return best;
+  }
+
+  int32_t peripheral(const std::vector<int32_t>& comp, int32_t id,
+                     std::vector<std::vector<int32_t>>* levels) {
+    int32_t r = min_degree_vertex(comp, id);
+    auto L = levels_from(r, id);
+    for (;;) {
+      int32_t v = min_degree_vertex(L.back(), id);
+      auto L2 = levels_from(v, id);
+      if (L2.size() > L.size()) {
+        r = v;
+        L = std::move(L2);
+      } else {
+        break;
+      }
+    }
+    *levels = std::move(L);
+    return r;
+  }
+
+  void rcm(const std::vector<int32_t>& comp, int32_t id, std::vector<int32_t>* out) {
+    std::vector<std::vector<int32_t>> L;
+    int32_t r = peripheral(comp, id, &L);
+    std::vector<int32_t> order{r};
+    ++stamp_;
+    mark_[r] = stamp_;
+    std::vector<std::pair<int32_t, int32_t>> cand;
+    for (size_t h = 0; h < order.size(); ++h) {
+      int32_t u = order[h];
+      cand.clear();
+      for (int64_t p = g_.start[u]; p < g_.start[u + 1]; ++p) {
+        int32_t w = g_.nbr[p];
+        if (owner_[w] == id && mark_[w] != stamp_) {
+          mark_[w] = stamp_;
+          cand.emplace_back(degree_in(w, id), w);
+        }
+      }
+      std::sort(cand.begin(), cand.end());
+      for (auto& c : cand) order.push_back(c.second);
+    }
+    out->insert(out->end(), order.rbegin(), order.rend());
+  }
+
+  void nd(const std::vector<int32_t>& comp, int32_t id, std::vector<int32_t>* out) {
+    if (comp.size() <= 64) {
+      out->insert(out->end(), comp.begin(), comp.end());
+      return;
+    }
+    std::vector<std::vector<int32_t>> L;
+    peripheral(comp, id, &L);
+    int32_t depth = (int32_t)L.size() - 1;
+    if (depth < 2) {
+      out->insert(out->end(), comp.begin(), comp.end());
+      return;
+    }
+    std::vector<int32_t> sep = L[(size_t)(depth + 1) / 2];
+    std::sort(sep.begin(), sep.end());
+    int32_t rest_id = fresh();
+    std::vector<int32_t> rest;
+    rest.reserve(comp.size() - sep.size());
+    for (int32_t v : comp) owner_[v] = rest_id;
+    for (int32_t v : sep) owner_[v] = 0;
+    for (int32_t v : comp)
+      if (owner_[v] == rest_id) rest.push_back(v);
+    for (auto& part : split(rest, rest_id)) {
+      int32_t pid = fresh();
+      for (int32_t v : part) owner_[v] = pid;
+      nd(part, pid, out);
+    }
+    out->insert(out->end(), sep.begin(), sep.end());
+  }
+};
+
+std::vector<int32_t> fixed_ordering(const Graph& g, int64_t n, int method, int32_t* ndense) {
+  const int64_t thr = dense_threshold(n);
+  std::vector<int32_t> kept, dense, out;
+  out.reserve((size_t)n);
+  for (int32_t v = 0; v < (int32_t)n; ++v) (g.deg(v) > thr ? dense : kept).push_back(v);
+  *ndense = (int32_t)dense.size();
+  if (method == kNatural) {
+    out = kept;
+  } else {
+    Orderer o(g, n);
+    int32_t id = o.fresh();
+    for (int32_t v : kept) o.set_owner(v, id);
+    o.order_components(kept, id, method, &out);
+  }
+  out.insert(out.end(), dense.begin(), dense.end());
+  return out;
+}
+
+// elimination tree (Liu, with path compression) and the row-subtree traversal
+// giving the exact pattern of L, from the strictly lower rows of P A P^T
+void symbolic(Symbolic* s) {
+  const int64_t n = s->n;
+  // rows of the permuted strictly-lower pattern: row i -> columns j < i
+  std::vector<int64_t> rs((size_t)n + 1, 0);
+  for (int64_t c = 0; c < n; ++c)
+    for (int64_t p = s->qp[c] + 1; p < s->qp[c + 1]; ++p) {
+      int32_t a = s->iperm[s->qi[p]], b = s->iperm[c];
+      rs[(size_t)std::max(a, b) + 1]++;
+    }
+  for (int64_t i = 0; i < n; ++i) rs[i + 1] += rs[i];
+  std::vector<int32_t> rc((size_t)rs[n]);
+  {
+    std::vector<int64_t> pos(rs.begin(), rs.end() - 1);
+    for (int64_t c = 0; c < n; ++c)
+      for (int64_t p = s->qp[c] + 1; p < s->qp[c + 1]; ++p) {
+        int32_t a = s->iperm[s->qi[p]], b = s->iperm[c];
+        rc[(size_t)pos[std::max(a, b)]++] = std::min(a, b);
+      }
+  }
+  s->parent.assign((size_t)n, -1);
+  std::vector<int32_t> anc((size_t)n, -1);
+  for (int32_t i = 0; i < (int32_t)n; ++i)
+    for (int64_t p = rs[i]; p < rs[i + 1]; ++p) {
+      int32_t r = rc[p];
+      while (r != -1 && r != i) {
+        int32_t nx = anc[r];
+        anc[r] = i;
+        if (nx == -1) s->parent[r] = i;
+        r = nx;
+      }
+    }
+  // row i of L: every node on the tree paths from its A entries up to i
+  std::vector<int32_t> mark((size_t)n, -1);
+  std::vector<int64_t> ccount((size_t)n, 1);
+  std::vector<int32_t> rowk;
+  std::vector<int64_t> rowstart((size_t)n + 1, 0);
+  for (int32_t i = 0; i < (int32_t)n; ++i) {
+    mark[i] = i;
+    for (int64_t p = rs[i]; p < rs[i + 1]; ++p)
+      for (int32_t k = rc[p]; mark[k] != i; k = s->parent[k]) {
+        mark[k] = i;
+        rowk.push_back(k);
+        ccount[k]++;
+      }
+    rowstart[i + 1] = (int64_t)rowk.size();
+  }
+  s->lp.assign((size_t)n + 1, 0);
+  for (int64_t j = 0; j < n; ++j) s->lp[j + 1] = s->lp[j] + ccount[j];
+  s->lnz = s->lp[n];
+  s->li.assign((size_t)s->lnz, 0);
+  std::vector<int64_t> fill(s->lp.begin(), s->lp.end() - 1);
+  for (int64_t j = 0; j < n; ++j) s->li[(size_t)fill[j]++] = (int32_t)j;
+  for (int32_t i = 0; i < (int32_t)n; ++i)
+    for (int64_t p = rowstart[i]; p < rowstart[i + 1]; ++p) s->li[(size_t)fill[rowk[p]]++] = i;
+}
+
+int route_of(double phi, double rho, double sigma) {
+  if (rho >= 0.90) return kRouteDense;
+  if (phi > 2.0 && rho < 0.15) return kRouteSupernodal;
+  if (rho >= 0.15 || sigma >= 20.0) return kRouteSemisparse;
+  return kRouteSupernodal;
+}
+
+void tiles_and_tasks(Symbolic* s, int nb, int mode) {
+  const int64_t n = s->n;
+  const int32_t NT = (int32_t)((n + nb - 1) / nb);
+  s->nb = nb;
+  s->NT = NT;
+  s->kd.assign((size_t)NT, 0);
+  // per block column: the distinct rows (global) below the diagonal block
+  std::vector<int32_t> seen((size_t)n, -1);
+  std::vector<std::vector<int32_t>> colrows((size_t)NT);
+  for (int64_t j = 0; j < n; ++j) {
+    int32_t k = (int32_t)(j / nb);
+    for (int64_t p = s->lp[j]; p < s->lp[j + 1]; ++p) {
+      int32_t i = s->li[p];
+      if (i / nb == k) {
+        s->kd[k] = std::max<int32_t>(s->kd[k], (int32_t)(i - j));
+      } else if (seen[i] != k) {
+        seen[i] = k;
+        colrows[k].push_back(i);
+      }
+    }
+  }
+  struct Raw { int32_t m, k, lo, hi, cnt; int64_t first; };
+  std::vector<Raw> raw;
+  std::vector<int32_t> allrows;
+  int64_t sum_true = 0;
+  for (int32_t k = 0; k < NT; ++k) {
+    auto& v = colrows[k];
+    std::sort(v.begin(), v.end());
+    size_t a = 0;
+    while (a < v.size()) {
+      int32_t m = v[a] / nb;
+      size_t b = a;
+      while (b < v.size() && v[b] / nb == m) ++b;
+      Raw r{m, k, v[a] - m * nb, v[b - 1] - m * nb, (int32_t)(b - a), (int64_t)allrows.size()};
+      for (size_t x = a; x < b; ++x) allrows.push_back(v[x] - m * nb);
+      raw.push_back(r);
+      sum_true += r.cnt;
+      a = b;
+    }
+    std::vector<int32_t>().swap(v);
+  }
+  const int64_t ntiles = (int64_t)raw.size();
+  // features and route (Sec. 5.1)
+  std::vector<int32_t> rowcount((size_t)n, 0);
+  for (int32_t i : s->li) rowcount[i]++;
+  int64_t maxrc = *std::max_element(rowcount.begin(), rowcount.end());
+  s->phi = (double)s->lnz / (double)s->qnz;
+  s->rho = ntiles ? (double)sum_true / ((double)nb * (double)ntiles) : 1.0;
+  s->sigma = ((double)maxrc * (double)n) / (double)s->lnz;
+  s->tact = ntiles + NT;
+  s->route = route_of(s->phi, s->rho, s->sigma);
+  if (mode == kModeAuto) mode = s->route == kRouteDense ? kModeDense : kModeSemisparse;
+  s->mode = mode;
+  // stored rows: full height on the dense route
+  s->tiles.clear();
+  s->rows.clear();
+  for (const Raw& r : raw) {
+    TileInfo t;
+    t.m = r.m;
+    t.k = r.k;
+    t.true_cnt = r.cnt;
+    t.roff = (int64_t)s->rows.size();
+    const int32_t hm = (r.m == NT - 1) ? (int32_t)(n - (int64_t)r.m * nb) : nb;
+    if (mode == kModeDense) {
+      t.cnt = hm;
+      t.contig = 1;
+      for (int32_t x = 0; x < hm; ++x) s->rows.push_back(x);
+    } else {
+      t.cnt = r.cnt;
+      t.contig = (int8_t)(r.hi - r.lo + 1 == r.cnt);
+      s->rows.insert(s->rows.end(), allrows.begin() + r.first, allrows.begin() + r.first + r.cnt);
+    }
+    s->tiles.push_back(t);
+  }
+  // Algorithm 1 over the tile neighbourhoods N(k)
+  std::vector<std::vector<int32_t>> below((size_t)NT), left((size_t)NT);
+  for (const TileInfo& t : s->tiles) {
+    below[t.k].push_back(t.m);
+    left[t.m].push_back(t.k);
+  }
+  for (auto& v : left) std::sort(v.begin(), v.end());
+  s->tasks.clear();
+  auto push = [&](int op, int m, int k, int nn) {
+    s->tasks.push_back(op);
+    s->tasks.push_back(m);
+    s->tasks.push_back(k);
+    s->tasks.push_back(nn);
+  };
+  std::vector<int32_t> common;
+  for (int32_t k = 0; k < NT; ++k) {
+    for (int32_t nn : left[k]) push(kSyrk, -1, k, nn);
+    push(kPotrf, -1, k, -1);
+    for (int32_t m : below[k]) {
+      common.clear();
+      std::set_intersection(left[k].begin(), left[k].end(), left[m].begin(), left[m].end(),
+                            std::back_inserter(common));
+      for (int32_t nn : common)
+        if (nn < k) push(kGemm, m, k, nn);
+      push(kTrsm, m, k, -1);
+    }
+  }
+}
+
+int analyse_perm(Symbolic* s, int nb, int mode) {
+  const int64_t n = s->n;
+  s->iperm.assign((size_t)n, -1);
+  for (int64_t a = 0; a < n; ++a) s->iperm[s->perm[a]] = (int32_t)a;
+  symbolic(s);
+  tiles_and_tasks(s, nb, mode);
+  return 0;
+}
+
+}  // namespace
+
+int check_pattern(int64_t n, const int64_t* cp, const int32_t* ri, std::string* why) {
+  if (n < 1 || n >= (int64_t(1) << 31) || !cp || !ri) {
+    *why = "n out of range or null pattern";
+    return STC_ERR_ARG;
+  }
+  if (cp[0] != 0) {
+    *why = "colptr[0] != 0";
+    return STC_ERR_PATTERN;
+  }
+  for (int64_t j = 0; j < n; ++j) {
+    if (cp[j + 1] <= cp[j]) {
+      *why = "column " + std::to_string(j) + " has no diagonal";
+      return STC_ERR_PATTERN;
+    }
+    if (ri[cp[j]] != j) {
+      *why = "column " + std::to_string(j) + ": diagonal missing or an upper entry";
+      return STC_ERR_PATTERN;
+    }
+    int32_t prev = (int32_t)j;
+    for (int64_t p = cp[j] + 1; p < cp[j + 1]; ++p) {
+      if (ri[p] <= prev || ri[p] >= n) {
+        *why = "column " + std::to_string(j) + ": rows unsorted, duplicated or out of range";
+        return STC_ERR_PATTERN;
+      }
+      prev = ri[p];
+    }
+  }
+  return 0;
+}
+
+int analyse(int64_t n, const int64_t* cp, const int32_t* ri, int method, int nb, int mode,
+            const int32_t* perm, Symbolic* out, std::string* why) {
+  int rc = check_pattern(n, cp, ri, why);
+  if (rc) return rc;
+  if (nb < 1 || method < kNatural || method > kGiven || mode < kModeAuto || mode > kModeSemisparse) {
+    *why = "invalid nb, ordering or mode";
+    return STC_ERR_ARG;
+  }
+  auto fresh = [&]() {
+    Symbolic s;
+    s.n = n;
+    s.qnz = cp[n];
+    s.qp.assign(cp, cp + n + 1);
+    s.qi.assign(ri, ri + cp[n]);
+    return s;
+  };
+  if (method == kGiven) {
+    if (!perm) {
+      *why = "ordering GIVEN without a permutation";
+      return STC_ERR_ARG;
+    }
+    std::vector<char> hit((size_t)n, 0);
+    for (int64_t a = 0; a < n; ++a) {
+      if (perm[a] < 0 || perm[a] >= n || hit[perm[a]]) {
+        *why = "given permutation is not a permutation of 0..n-1";
+        return STC_ERR_ARG;
+      }
+      hit[perm[a]] = 1;
+    }
+    *out = fresh();
+    out->perm.assign(perm, perm + n);
+    out->method = kGiven;
+    return analyse_perm(out, nb, mode);
+  }
+  Graph g = make_graph(n, cp, ri);
+  if (method != kAuto) {
+    *out = fresh();
+    out->perm = fixed_ordering(g, n, method, &out->ndense);
+    out->method = method;
+    return analyse_perm(out, nb, mode);
+  }
+  Symbolic cand[3];
+  for (int m = 0; m < 3; ++m) {
+    cand[m] = fresh();
+    cand[m].perm = fixed_ordering(g, n, m, &cand[m].ndense);
+    cand[m].method = m;
+    analyse_perm(&cand[m], nb, mode);
+  }
+  int best_fill = 0;
+  for (int m = 1; m < 3; ++m)
+    if (cand[m].lnz < cand[best_fill].lnz) best_fill = m;
+  int win;
+  if (cand[kNatural].rho < 0.15) {
+    win = best_fill;
+  } else {
+    int best_t = 0;
+    for (int m = 1; m < 3; ++m)
+      if (cand[m].tact < cand[best_t].tact) best_t = m;
+    win = best_t;
+    int low = -1;
+    for (int m = 0; m < 3; ++m)
+      if (2 * cand[m].lnz <= cand[best_t].lnz && (low < 0 || cand[m].lnz < cand[low].lnz)) low = m;
+    if (low >= 0) win = low;
+  }
+  if (n >= 50000 && 4 * cand[kNd].lnz <= 5 * cand[best_fill].lnz) win = kNd;
+  *out = std::move(cand[win]);
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// execution plan
+// ---------------------------------------------------------------------------
+
+int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why) {
+  const int32_t nb = s.nb, NT = s.NT;
+  const int64_t n = s.n;
+  (void)why;
+  *p = Plan();
+  p->nb = nb;
+  p->NT = NT;
+  p->bm = bm;
+  p->br = br;
+  const int64_t ntiles = (int64_t)s.tiles.size();
+  // tile store: diagonal tiles first (nb x nb, row-major), then the packed
+  // off-diagonal tiles (stored rows x nb, row-major)
+  int64_t off = (int64_t)NT * nb * nb;
+  p->tile_off.resize((size_t)ntiles);
+  for (int64_t t = 0; t < ntiles; ++t) {
+    p->tile_off[t] = off;
+    off += (int64_t)s.tiles[t].cnt * nb;
+  }
+  p->store = off;
+  p->diag_h.resize((size_t)NT);
+  for (int32_t k = 0; k < NT; ++k) p->diag_h[k] = (int32_t)std::min<int64_t>(nb, n - (int64_t)k * nb);
+  // tile lookup per block column: (m -> tile index), and inverse row maps
+  std::vector<int64_t> col_first((size_t)NT + 1, 0);
+  for (const TileInfo& t : s.tiles) col_first[t.k + 1]++;
+  for (int32_t k = 0; k < NT; ++k) col_first[k + 1] += col_first[k];
+  auto find_tile = [&](int32_t m, int32_t k) -> int64_t {
+    int64_t lo = col_first[k], hi = col_first[k + 1];
+    while (lo < hi) {
+      int64_t mid = (lo + hi) / 2;
+      if (s.tiles[mid].m < m) lo = mid + 1; else hi = mid;
+    }
+    return (lo < col_first[k + 1] && s.tiles[lo].m == m) ? lo : -1;
+  };
+  std::vector<int32_t> inv((size_t)ntiles * nb, -1);
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const TileInfo& ti = s.tiles[t];
+    for (int32_t r = 0; r < ti.cnt; ++r) inv[(size_t)t * nb + s.rows[ti.roff + r]] = r;
+  }
+  auto store_pos = [&](int32_t i, int32_t j) -> int64_t {  // permuted, i >= j
+    int32_t bi = i / nb, bj = j / nb;
+    if (bi == bj) return (int64_t)bj * nb * nb + (int64_t)(i % nb) * nb + (j % nb);
+    int64_t t = find_tile(bi, bj);
+    int32_t r = inv[(size_t)t * nb + (i % nb)];
+    return p->tile_off[t] + (int64_t)r * nb + (j % nb);
+  };
+  p->vmap.resize((size_t)s.qnz);
+  for (int64_t c = 0; c < n; ++c)
+    for (int64_t q = s.qp[c]; q < s.qp[c + 1]; ++q) {
+      int32_t a = s.iperm[s.qi[q]], b = s.iperm[c];
+      p->vmap[q] = store_pos(std::max(a, b), std::min(a, b));
+    }
+  p->lmap.resize((size_t)s.lnz);
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t q = s.lp[j]; q < s.lp[j + 1]; ++q) p->lmap[q] = store_pos(s.li[q], (int32_t)j);
+
+  // gather maps: inverse row map of every tile (used as column maps), stored
+  // once; identity for full tiles
+  std::vector<int32_t> colmap_of((size_t)ntiles, -1);
+  auto full = [&](int64_t t) {
+    const TileInfo& ti = s.tiles[t];
+    int32_t hm = (ti.m == NT - 1) ? (int32_t)(n - (int64_t)ti.m * nb) : nb;
+    return ti.cnt == hm && hm == nb;
+  };
+  for (int64_t t = 0; t < ntiles; ++t) {
+    if (full(t)) continue;
+    colmap_of[t] = (int32_t)p->maps.size();
+    p->maps.insert(p->maps.end(), inv.begin() + t * nb, inv.begin() + (t + 1) * nb);
+  }
+
+  // fused update tasks from Algorithm 1's list, and the level schedule
+  std::vector<int32_t> lvT((size_t)ntiles, -1), lvP((size_t)NT, -1);
+  std::vector<int32_t> upd_of_diag((size_t)NT, -1), upd_of_tile((size_t)ntiles, -1);
+  std::vector<int32_t> lvU_diag((size_t)NT, -1), lvU_tile((size_t)ntiles, -1);
+  std::vector<int32_t> trsm_of_tile((size_t)ntiles, -1);
+  double flops = 0;
+  const auto& T = s.tasks;
+  const size_t ntask = T.size() / 4;
+  auto level_at = [&](int32_t L) -> Level& {
+    if ((int32_t)p->levels.size() <= L) p->levels.resize((size_t)L + 1);
+    return p->levels[(size_t)L];
+  };
+  size_t a = 0;
+  while (a < ntask) {
+    int op = T[4 * a], m = T[4 * a + 1], k = T[4 * a + 2];
+    if (op == kSyrk || op == kGemm) {
+      // gather this output tile's run of contributions
+      const bool diag = op == kSyrk;
+      UpdTask u;
+      int64_t tout = diag ? -1 : find_tile(m, k);
+      u.c_off = diag ? (int64_t)k * nb * nb : p->tile_off[tout];
+      u.c_rows = diag ? p->diag_h[k] : s.tiles[tout].cnt;
+      u.diag = diag ? 1 : 0;
+      u.c_begin = (int32_t)p->contribs.size();
+      int32_t lv = 0;
+      size_t b = a;
+      for (; b < ntask && T[4 * b] == op && T[4 * b + 1] == m && T[4 * b + 2] == k; ++b) {
+        int nn = T[4 * b + 3];
+        Contrib c;
+        int64_t tb = find_tile(k, nn);
+        c.b_off = p->tile_off[tb];
+        c.b_rows = s.tiles[tb].cnt;
+        c.colmap = colmap_of[tb];
+        if (diag) {
+          c.a_off = c.b_off;
+          c.a_rows = c.b_rows;
+          c.rowmap = colmap_of[tb];
+          lv = std::max(lv, lvT[tb] + 1);
+          flops += (double)s.tiles[tb].cnt * s.tiles[tb].cnt * nb;
+        } else {
+          int64_t ta = find_tile(m, nn);
+          c.a_off = p->tile_off[ta];
+          c.a_rows = s.tiles[ta].cnt;
+          const TileInfo& to = s.tiles[tout];
+          const TileInfo& tia = s.tiles[ta];
+          bool same = to.cnt == tia.cnt &&
+                      std::equal(s.rows.begin() + to.roff, s.rows.begin() + to.roff + to.cnt,
+                                 s.rows.begin() + tia.roff);
+          if (same) {
+            c.rowmap = -1;
+          } else {
+            c.rowmap = (int32_t)p->maps.size();
+            for (int32_t r = 0; r < to.cnt; ++r)
+              p->maps.push_back(inv[(size_t)ta * nb + s.rows[to.roff + r]]);
+          }
+          lv = std::max(lv, std::max(lvT[ta], lvT[tb]) + 1);
+          flops += 2.0 * tia.cnt * s.tiles[tb].cnt * nb;
+        }
+        p->contribs.push_back(c);
+      }
+      u.c_end = (int32_t)p->contribs.size();
+      int32_t id = (int32_t)p->upd.size();
+      p->upd.push_back(u);
+      if (diag) {
+        upd_of_diag[k] = id;
+        lvU_diag[k] = lv;
+      } else {
+        upd_of_tile[tout] = id;
+        lvU_tile[tout] = lv;
+      }
+      Level& L = level_at(lv);
+      const int32_t nbr = (u.c_rows + bm - 1) / bm, nbc = diag ? nbr : (nb + bm - 1) / bm;
+      for (int32_t x = 0; x < nbr; ++x)
+        for (int32_t y = 0; y < nbc; ++y) {
+          if (diag && y > x) continue;
+          L.upd_items.push_back(id);
+          L.upd_items.push_back(x);
+          L.upd_items.push_back(y);
+        }
+      a = b;
+    } else if (op == kPotrf) {
+      lvP[k] = lvU_diag[k] + 1;  // 0 when nothing updates the diagonal tile
+      level_at(lvP[k]).potrf.push_back(k);
+      flops += (double)p->diag_h[k] * p->diag_h[k] * p->diag_h[k] / 3.0;
+      ++a;
+    } else {  // kTrsm
+      int64_t t = find_tile(m, k);
+      TrsmTask tt;
+      tt.x_off = p->tile_off[t];
+      tt.l_off = (int64_t)k * nb * nb;
+      tt.rows = s.tiles[t].cnt;
+      tt.k = k;
+      int32_t id = (int32_t)p->trsm.size();
+      p->trsm.push_back(tt);
+      trsm_of_tile[t] = id;
+      lvT[t] = std::max(lvU_tile[t], lvP[k]) + 1;
+      Level& L = level_at(lvT[t]);
+      for (int32_t x = 0; x < (tt.rows + br - 1) / br; ++x) {
+        L.trsm_items.push_back(id);
+        L.trsm_items.push_back(x);
+      }
+      flops += (double)tt.rows * nb * nb;
+      ++a;
+    }
+  }
+  p->flops_tile = flops;
+
+  // solve schedule: block rows / columns and their dependency levels
+  p->row_tiles_ptr.assign((size_t)NT + 1, 0);
+  p->col_tiles_ptr.assign((size_t)NT + 1, 0);
+  for (const TileInfo& t : s.tiles) {
+    p->row_tiles_ptr[t.m + 1]++;
+    p->col_tiles_ptr[t.k + 1]++;
+  }
+  for (int32_t k = 0; k < NT; ++k) {
+    p->row_tiles_ptr[k + 1] += p->row_tiles_ptr[k];
+    p->col_tiles_ptr[k + 1] += p->col_tiles_ptr[k];
+  }
+  p->row_tiles.resize((size_t)ntiles);
+  p->col_tiles.resize((size_t)ntiles);
+  {
+    std::vector<int32_t> fr(p->row_tiles_ptr.begin(), p->row_tiles_ptr.end() - 1);
+    std::vector<int32_t> fc(p->col_tiles_ptr.begin(), p->col_tiles_ptr.end() - 1);
+    for (int64_t t = 0; t < ntiles; ++t) {
+      p->row_tiles[fr[s.tiles[t].m]++] = (int32_t)t;
+      p->col_tiles[fc[s.tiles[t].k]++] = (int32_t)t;
+    }
+  }
+  std::vector<int32_t> fl((size_t)NT, 0), bl((size_t)NT, 0);
+  int32_t fmax = 0, bmax = 0;
+  for (int32_t m = 0; m < NT; ++m) {
+    for (int32_t x = p->row_tiles_ptr[m]; x < p->row_tiles_ptr[m + 1]; ++x)
+      fl[m] = std::max(fl[m], fl[s.tiles[p->row_tiles[x]].k] + 1);
+    fmax = std::max(fmax, fl[m]);
+  }
+  for (int32_t k = NT - 1; k >= 0; --k) {
+    for (int32_t x = p->col_tiles_ptr[k]; x < p->col_tiles_ptr[k + 1]; ++x)
+      bl[k] = std::max(bl[k], bl[s.tiles[p->col_tiles[x]].m] + 1);
+    bmax = std::max(bmax, bl[k]);
+  }
+  auto bucket = [&](const std::vector<int32_t>& lv, int32_t mx, std::vector<int32_t>* ptr,
+                    std::vector<int32_t>* blk) {
+    ptr->assign((size_t)mx + 2, 0);
+    for (int32_t k = 0; k < NT; ++k) (*ptr)[lv[k] + 1]++;
+    for (int32_t L = 0; L <= mx; ++L) (*ptr)[L + 1] += (*ptr)[L];
+    blk->resize((size_t)NT);
+    std::vector<int32_t> f(ptr->begin(), ptr->end() - 1);
+    for (int32_t k = 0; k < NT; ++k) (*blk)[f[lv[k]]++] = k;
+  };
+  bucket(fl, fmax, &p->fwd_level_ptr, &p->fwd_level_blk);
+  bucket(bl, bmax, &p->bwd_level_ptr, &p->bwd_level_blk);
+  return 0;
+}
+
+}  // namespace stc

@@ -1,0 +1,123 @@
+// analyse.hpp -- host-side symbolic analysis and static execution plan of the
+// structure-adaptive tile Cholesky (arXiv 2609.29765, Sec. 3 and Sec. 5.1-5.3).
+//
+// Symbolic part: dense-row set-aside and ordering (Sec. 3), elimination tree
+// and exact fill pattern of L, uniform n_b tile grid with the active rows of
+// every off-diagonal tile (the active columns of the stored transpose, Sec.
+// 4.1), full/contiguous flags and diagonal half-width kd (Sec. 4.2-4.3,
+// Sec. 5.2 "Per-tile metadata"), selector features and route (Sec. 5.1), and
+// the ordered task list of Algorithm 1.
+//
+// Plan part (device-facing): tile-store layout, value map from input entries
+// to the store, per-task gather maps (the transpose of the paper's per-task
+// scatter, Sec. 4.2 and Sec. 5.2 "Per-task scatter"), and a level schedule
+// whose edges are those Algorithm 2 synchronises through its progress matrix.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace stc {
+
+enum Ordering { kNatural = 0, kRcm = 1, kNd = 2, kAuto = 3, kGiven = 4 };
+enum Mode { kModeAuto = 0, kModeDense = 1, kModeSemisparse = 2 };
+enum Route { kRouteDense = 0, kRouteSemisparse = 1, kRouteSupernodal = 2 };
+enum Op { kPotrf = 1, kSyrk = 2, kTrsm = 3, kGemm = 4 };
+
+struct TileInfo {
+  int32_t m, k;      // block row, block column (m > k)
+  int32_t cnt;       // stored active rows
+  int32_t true_cnt;  // active rows of the pattern
+  int8_t contig;     // active rows form one interval
+  int64_t roff;      // offset of this tile's rows in Symbolic::rows
+};
+
+struct Symbolic {
+  int64_t n = 0, qnz = 0;
+  std::vector<int64_t> qp;
+  std::vector<int32_t> qi;
+  std::vector<int32_t> perm, iperm;  // perm[new] = old
+  int32_t ndense = 0;
+  int32_t method = 0;
+  std::vector<int32_t> parent;       // elimination tree of P A P^T
+  std::vector<int64_t> lp;           // pattern of L, CSC, rows ascending
+  std::vector<int32_t> li;
+  int64_t lnz = 0;
+  int32_t nb = 64, NT = 0, mode = 0, route = 0;
+  std::vector<TileInfo> tiles;       // k ascending, then m ascending
+  std::vector<int32_t> rows;         // active rows, local to block m
+  std::vector<int32_t> kd;           // per diagonal tile
+  double phi = 0, rho = 0, sigma = 0;
+  int64_t tact = 0;
+  std::vector<int32_t> tasks;        // 4 ints per task: op, m, k, n (-1 unused)
+};
+
+// Validate a lower CSC pattern; returns 0 or a negative STC_ERR_* code.
+int check_pattern(int64_t n, const int64_t* cp, const int32_t* ri, std::string* why);
+
+// Full symbolic analysis. method in Ordering; mode in Mode; perm read for kGiven.
+int analyse(int64_t n, const int64_t* cp, const int32_t* ri, int method, int nb, int mode,
+            const int32_t* perm, Symbolic* out, std::string* why);
+
+// ---------------------------------------------------------------------------
+// execution plan
+// ---------------------------------------------------------------------------
+
+// One contribution to an output tile: C -= A_rows(a) * B_rows(b)^T, where the
+// A operand rows are gathered through rowmap (identity if < 0) and the B
+// operand rows through the inverse active-row map of tile b (identity if the
+// tile is full).  For a diagonal output (SYRK) a == b.
+struct Contrib {
+  int64_t a_off, b_off;  // store offsets (doubles) of the operand tiles
+  int32_t a_rows, b_rows;
+  int32_t rowmap;        // offset into Plan::maps, or -1 for identity
+  int32_t colmap;        // offset into Plan::maps, or -1 for identity
+};
+
+// A fused update of one output tile by all its contributions (the SYRK or
+// GEMM tasks of Algorithm 1 that write it), accumulated in registers.
+struct UpdTask {
+  int64_t c_off;          // output tile offset
+  int32_t c_rows;         // output rows (stored active rows, or h for a diagonal)
+  int32_t diag;           // 1 for a diagonal tile (lower blocks only)
+  int32_t c_begin, c_end; // contributions [c_begin, c_end)
+};
+
+struct TrsmTask {
+  int64_t x_off;   // panel tile offset
+  int64_t l_off;   // diagonal tile offset
+  int32_t rows;    // stored rows of the panel tile
+  int32_t k;       // block column
+};
+
+struct Level {
+  std::vector<int32_t> upd_items;   // triples: task, block row, block col
+  std::vector<int32_t> potrf;       // block columns
+  std::vector<int32_t> trsm_items;  // pairs: trsm task, row block
+};
+
+struct Plan {
+  int32_t nb = 64, NT = 0;
+  int32_t bm = 64;          // update block (rows and columns)
+  int32_t br = 32;          // rows per TRSM work item
+  int64_t store = 0;        // doubles per value set
+  std::vector<int64_t> tile_off;    // per off-diagonal tile
+  std::vector<int64_t> vmap;        // input entry -> store offset
+  std::vector<int64_t> lmap;        // L entry (CSC order) -> store offset
+  std::vector<int32_t> maps;        // gather maps
+  std::vector<int32_t> diag_h;      // real rows of each diagonal tile
+  std::vector<Contrib> contribs;
+  std::vector<UpdTask> upd;
+  std::vector<TrsmTask> trsm;
+  std::vector<Level> levels;
+  // solve schedule: owner-computes block rows (forward) / block columns (back)
+  std::vector<int32_t> row_tiles_ptr, row_tiles;  // tiles of block row m (n < m)
+  std::vector<int32_t> col_tiles_ptr, col_tiles;  // tiles of block column k (m > k)
+  std::vector<int32_t> fwd_level_ptr, fwd_level_blk;
+  std::vector<int32_t> bwd_level_ptr, bwd_level_blk;
+  double flops_tile = 0;    // tile-algorithmic flops of one factorization
+};
+
+int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why);
+
+}  // namespace stc

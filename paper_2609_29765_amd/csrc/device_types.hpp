@@ -1,0 +1,31 @@
+// device_types.hpp -- plain structs uploaded to the device by the runtime and
+// read by the kernels (all 8-byte aligned, no pointers: offsets only).
+#pragma once
+#include <cstdint>
+
+namespace stc {
+
+struct UpdTaskD {     // one output tile and its run of contributions
+  int64_t c_off;
+  int32_t c_rows, diag;
+  int32_t c_begin, c_end;
+};
+
+struct ContribD {     // C -= A(rows via rowmap) * B(rows via colmap)^T
+  int64_t a_off, b_off;
+  int32_t a_rows, b_rows;
+  int32_t rowmap, colmap;  // offsets into the map pool, -1 = identity
+};
+
+struct TrsmTaskD {
+  int64_t x_off, l_off;
+  int32_t rows, k;
+};
+
+struct TileD {        // off-diagonal tile as the solve sees it
+  int64_t off;        // store offset
+  int64_t roff;       // offset of its active rows in the row pool
+  int32_t m, k, cnt, pad;
+};
+
+}  // namespace stc

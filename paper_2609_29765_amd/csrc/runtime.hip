@@ -1,0 +1,516 @@
+// runtime.hip -- C ABI of libstc.so (declared in include/stc.h): workspace
+// layout, metadata upload, level launches of the static tile schedule, HIP
+// graph capture/replay, and the consumers of the resident factor.
+//
+// The schedule is Algorithm 1's task set with the dependencies Algorithm 2
+// enforces through its progress matrix (a SYRK/GEMM reads finished TRSM
+// tiles, a TRSM reads its finished diagonal tile), grouped into levels: every
+// kernel of a level depends only on earlier levels, so one stream and the
+// kernel boundaries replace the spin-waits on the progress matrix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/stc.h"
+#include "analyse.hpp"
+#include "kernels.hpp"
+
+using namespace stc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                          \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      return fail(STC_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int32_t kInfoNone = 0x7fffffff;
+constexpr int32_t kMaxRhs = 64;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct LevelOffsets {
+  int32_t u_off, u_cnt, p_off, p_cnt, t_off, t_cnt;
+};
+
+}  // namespace
+
+struct stc_handle {
+  Symbolic sym;
+  Plan plan;
+  std::vector<LevelOffsets> lv;
+  // flattened level work lists (host)
+  std::vector<int32_t> upd_items, potrf_list, trsm_items;
+  // binding
+  int device = -1;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int32_t batch = 0;
+  hipStream_t last_stream = nullptr;
+  bool factored = false;
+  // device views into the workspace (set by bind)
+  int64_t* d_vmap = nullptr;
+  int32_t* d_maps = nullptr;
+  UpdTaskD* d_upd = nullptr;
+  ContribD* d_contrib = nullptr;
+  TrsmTaskD* d_trsm = nullptr;
+  int32_t* d_upd_items = nullptr;
+  int32_t* d_potrf = nullptr;
+  int32_t* d_trsm_items = nullptr;
+  int32_t* d_perm = nullptr;
+  TileD* d_tiles = nullptr;
+  int32_t* d_rows = nullptr;
+  int32_t *d_row_ptr = nullptr, *d_row_tiles = nullptr, *d_col_ptr = nullptr,
+          *d_col_tiles = nullptr, *d_fwd_blk = nullptr, *d_bwd_blk = nullptr;
+  double* d_store = nullptr;  // batch stores
+  double* d_y = nullptr;      // solve scratch
+  int32_t* d_info = nullptr;  // batch
+  double* d_ld = nullptr;     // batch
+  std::map<int32_t, hipGraphExec_t> graphs;  // by member count
+  ~stc_handle() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+  }
+};
+
+namespace {
+
+int64_t padded_n(const stc_handle* h) { return (int64_t)h->plan.NT * h->plan.nb; }
+
+// workspace layout; returns total bytes.  With base == null only the size is
+// computed (the handle's pointers are left alone).
+size_t layout(const stc_handle* hc, int32_t batch, char* base) {
+  stc_handle* h = const_cast<stc_handle*>(hc);
+  const Plan& p = h->plan;
+  const Symbolic& s = h->sym;
+  size_t off = 0;
+  auto take = [&](auto** dst, size_t bytes) {
+    using T = std::remove_pointer_t<std::remove_reference_t<decltype(dst)>>;
+    if (base) *dst = (T)(base + off);
+    off = align256(off + std::max<size_t>(bytes, 8));
+  };
+  take(&h->d_vmap, sizeof(int64_t) * p.vmap.size());
+  take(&h->d_maps, sizeof(int32_t) * p.maps.size());
+  take(&h->d_upd, sizeof(UpdTaskD) * p.upd.size());
+  take(&h->d_contrib, sizeof(ContribD) * p.contribs.size());
+  take(&h->d_trsm, sizeof(TrsmTaskD) * p.trsm.size());
+  take(&h->d_upd_items, sizeof(int32_t) * h->upd_items.size());
+  take(&h->d_potrf, sizeof(int32_t) * h->potrf_list.size());
+  take(&h->d_trsm_items, sizeof(int32_t) * h->trsm_items.size());
+  take(&h->d_perm, sizeof(int32_t) * (size_t)s.n);
+  take(&h->d_tiles, sizeof(TileD) * s.tiles.size());
+  take(&h->d_rows, sizeof(int32_t) * s.rows.size());
+  take(&h->d_row_ptr, sizeof(int32_t) * p.row_tiles_ptr.size());
+  take(&h->d_row_tiles, sizeof(int32_t) * p.row_tiles.size());
+  take(&h->d_col_ptr, sizeof(int32_t) * p.col_tiles_ptr.size());
+  take(&h->d_col_tiles, sizeof(int32_t) * p.col_tiles.size());
+  take(&h->d_fwd_blk, sizeof(int32_t) * p.fwd_level_blk.size());
+  take(&h->d_bwd_blk, sizeof(int32_t) * p.bwd_level_blk.size());
+  take(&h->d_info, sizeof(int32_t) * (size_t)batch);
+  take(&h->d_ld, sizeof(double) * (size_t)batch);
+  take(&h->d_y, sizeof(double) * (size_t)padded_n(h) * kMaxRhs);
+  take(&h->d_store, sizeof(double) * (size_t)p.store * (size_t)batch);
+  return off;
+}
+
+template <typename T>
+int upload(T* dst, const std::vector<T>& src) {
+  if (src.empty()) return 0;
+  HIPCHK(hipMemcpy(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
+  return 0;
+}
+
+// launch every level of the schedule for `members` value sets
+template <int NB>
+int launch_levels_nb(stc_handle* h, int32_t members, hipStream_t st) {
+  const int64_t ms = h->plan.store;
+  const int32_t nreal = (int32_t)h->sym.n;
+  for (const LevelOffsets& L : h->lv) {
+    if (L.u_cnt)
+      hipLaunchKernelGGL(k_update<NB>, dim3(L.u_cnt, members), dim3(256), 0, st,
+                         h->d_upd_items + 3 * (int64_t)L.u_off, h->d_upd, h->d_contrib, h->d_maps,
+                         h->d_store, ms);
+    if (L.p_cnt)
+      hipLaunchKernelGGL(k_potrf<NB>, dim3(L.p_cnt, members), dim3(256), 0, st,
+                         h->d_potrf + L.p_off, h->d_store, ms, h->d_info, nreal);
+    if (L.t_cnt)
+      hipLaunchKernelGGL(k_trsm<NB>, dim3(L.t_cnt, members), dim3(256), 0, st,
+                         h->d_trsm_items + 2 * (int64_t)L.t_off, h->d_trsm, h->d_store, ms);
+  }
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int launch_levels(stc_handle* h, int32_t members, hipStream_t st) {
+  switch (h->plan.nb) {
+    case 32: return launch_levels_nb<32>(h, members, st);
+    case 64: return launch_levels_nb<64>(h, members, st);
+    case 128: return launch_levels_nb<128>(h, members, st);
+    case 256: return launch_levels_nb<256>(h, members, st);
+  }
+  return fail(STC_ERR_ARG, "unsupported tile size");
+}
+
+int get_graph(stc_handle* h, int32_t members, hipGraphExec_t* out) {
+  auto it = h->graphs.find(members);
+  if (it != h->graphs.end()) {
+    *out = it->second;
+    return 0;
+  }
+  hipStream_t cs;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+  int rc = launch_levels(h, members, cs);
+  hipGraph_t g;
+  hipError_t e = hipStreamEndCapture(cs, &g);
+  if (rc) {
+    (void)hipStreamDestroy(cs);
+    return rc;
+  }
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return fail(STC_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  }
+  hipGraphExec_t ex;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) return fail(STC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  h->graphs[members] = ex;
+  *out = ex;
+  return 0;
+}
+
+// value load + schedule for `members` value sets starting at vals
+int run_factor(stc_handle* h, const double* vals, int32_t members, hipStream_t st) {
+  const Plan& p = h->plan;
+  const int64_t ms = p.store;
+  hipGraphExec_t ex;
+  int rc = get_graph(h, members, &ex);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_info_reset, dim3((members + 255) / 256), dim3(256), 0, st, h->d_info, members,
+                     kInfoNone);
+  const int64_t zgrid = std::min<int64_t>(4096, (ms / 2 + 255) / 256 + 1);
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)zgrid, members), dim3(256), 0, st, h->d_store, ms, ms);
+  const int32_t hlast = p.diag_h[p.NT - 1];
+  if (hlast < p.nb)
+    hipLaunchKernelGGL(k_pad, dim3(1, members), dim3(256), 0, st, h->d_store,
+                       (int64_t)(p.NT - 1) * p.nb * p.nb, p.nb, hlast, ms);
+  const int64_t qnz = h->sym.qnz;
+  const int64_t vgrid = std::min<int64_t>(4096, (qnz + 255) / 256);
+  hipLaunchKernelGGL(k_value_load, dim3((unsigned)vgrid, members), dim3(256), 0, st, vals, h->d_vmap,
+                     qnz, h->d_store, ms);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipGraphLaunch(ex, st));
+  hipLaunchKernelGGL(k_info_finish, dim3((members + 255) / 256), dim3(256), 0, st, h->d_info, members,
+                     kInfoNone, (int32_t*)nullptr);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int check_bound(const stc_handle* h) {
+  if (!h) return fail(STC_ERR_ARG, "null handle");
+  if (!h->ws) return fail(STC_ERR_STATE, "handle is not bound to a workspace");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != h->device)
+    return fail(STC_ERR_STATE, "current device differs from the bound device");
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* stc_last_error(void) { return g_err.c_str(); }
+
+int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const stc_opts* opts,
+                stc_handle** out) {
+  if (!out) return fail(STC_ERR_ARG, "null output handle");
+  *out = nullptr;
+  stc_opts o{64, STC_MODE_AUTO, STC_ORD_AUTO, nullptr};
+  if (opts) o = *opts;
+  if (o.nb == 0) o.nb = 64;
+  if (o.nb != 32 && o.nb != 64 && o.nb != 128 && o.nb != 256)
+    return fail(STC_ERR_ARG, "nb must be 32, 64, 128 or 256");
+  try {
+    auto* h = new stc_handle();
+    std::string why;
+    int rc = analyse(n, colptr, rowind, o.ordering, o.nb, o.mode, o.perm, &h->sym, &why);
+    if (rc) {
+      delete h;
+      return fail(rc, why);
+    }
+    rc = build_plan(h->sym, UB, TR, &h->plan, &why);
+    if (rc) {
+      delete h;
+      return fail(rc, why);
+    }
+    // flatten the level lists
+    for (const Level& L : h->plan.levels) {
+      LevelOffsets x;
+      x.u_off = (int32_t)(h->upd_items.size() / 3);
+      x.u_cnt = (int32_t)(L.upd_items.size() / 3);
+      h->upd_items.insert(h->upd_items.end(), L.upd_items.begin(), L.upd_items.end());
+      x.p_off = (int32_t)h->potrf_list.size();
+      x.p_cnt = (int32_t)L.potrf.size();
+      h->potrf_list.insert(h->potrf_list.end(), L.potrf.begin(), L.potrf.end());
+      x.t_off = (int32_t)(h->trsm_items.size() / 2);
+      x.t_cnt = (int32_t)(L.trsm_items.size() / 2);
+      h->trsm_items.insert(h->trsm_items.end(), L.trsm_items.begin(), L.trsm_items.end());
+      h->lv.push_back(x);
+    }
+    *out = h;
+    return 0;
+  } catch (const std::bad_alloc&) {
+    return fail(STC_ERR_ALLOC, "host allocation failed during analysis");
+  } catch (const std::exception& e) {
+    return fail(STC_ERR_ARG, e.what());
+  }
+}
+
+int stc_workspace_bytes(const stc_handle* h, int32_t batch, size_t* bytes) {
+  if (!h || !bytes || batch < 1) return fail(STC_ERR_ARG, "null argument or batch < 1");
+  *bytes = layout(h, batch, nullptr);
+  return 0;
+}
+
+int stc_bind(stc_handle* h, void* d_ws, size_t bytes, int32_t batch, void* stream) {
+  (void)stream;
+  if (!h || !d_ws || batch < 1) return fail(STC_ERR_ARG, "null handle/workspace or batch < 1");
+  if (((uintptr_t)d_ws & 255) != 0) return fail(STC_ERR_ARG, "workspace must be 256-byte aligned");
+  size_t need = 0;
+  stc_workspace_bytes(h, batch, &need);
+  if (bytes < need)
+    return fail(STC_ERR_ALLOC, "workspace too small: need " + std::to_string(need) + " bytes");
+  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.second);
+  h->graphs.clear();
+  h->factored = false;
+  HIPCHK(hipGetDevice(&h->device));
+  h->ws = (char*)d_ws;
+  h->ws_bytes = bytes;
+  h->batch = batch;
+  layout(h, batch, h->ws);
+  const Plan& p = h->plan;
+  const Symbolic& s = h->sym;
+  std::vector<UpdTaskD> upd(p.upd.size());
+  for (size_t i = 0; i < upd.size(); ++i)
+    upd[i] = UpdTaskD{p.upd[i].c_off, p.upd[i].c_rows, p.upd[i].diag, p.upd[i].c_begin, p.upd[i].c_end};
+  std::vector<ContribD> con(p.contribs.size());
+  for (size_t i = 0; i < con.size(); ++i) {
+    const Contrib& c = p.contribs[i];
+    con[i] = ContribD{c.a_off, c.b_off, c.a_rows, c.b_rows, c.rowmap, c.colmap};
+  }
+  std::vector<TrsmTaskD> tr(p.trsm.size());
+  for (size_t i = 0; i < tr.size(); ++i)
+    tr[i] = TrsmTaskD{p.trsm[i].x_off, p.trsm[i].l_off, p.trsm[i].rows, p.trsm[i].k};
+  std::vector<TileD> tl(s.tiles.size());
+  for (size_t i = 0; i < tl.size(); ++i)
+    tl[i] = TileD{p.tile_off[i], s.tiles[i].roff, s.tiles[i].m, s.tiles[i].k, s.tiles[i].cnt, 0};
+  int rc = 0;
+  if ((rc = upload(h->d_vmap, p.vmap)) || (rc = upload(h->d_maps, p.maps)) ||
+      (rc = upload(h->d_upd, upd)) || (rc = upload(h->d_contrib, con)) ||
+      (rc = upload(h->d_trsm, tr)) || (rc = upload(h->d_upd_items, h->upd_items)) ||
+      (rc = upload(h->d_potrf, h->potrf_list)) || (rc = upload(h->d_trsm_items, h->trsm_items)) ||
+      (rc = upload(h->d_perm, s.perm)) || (rc = upload(h->d_tiles, tl)) ||
+      (rc = upload(h->d_rows, s.rows)) || (rc = upload(h->d_row_ptr, p.row_tiles_ptr)) ||
+      (rc = upload(h->d_row_tiles, p.row_tiles)) || (rc = upload(h->d_col_ptr, p.col_tiles_ptr)) ||
+      (rc = upload(h->d_col_tiles, p.col_tiles)) || (rc = upload(h->d_fwd_blk, p.fwd_level_blk)) ||
+      (rc = upload(h->d_bwd_blk, p.bwd_level_blk)))
+    return rc;
+  hipGraphExec_t ex;
+  return get_graph(h, 1, &ex);
+}
+
+int stc_factorize(stc_handle* h, const double* d_values, void* stream) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!d_values) return fail(STC_ERR_ARG, "null values");
+  hipStream_t st = (hipStream_t)stream;
+  rc = run_factor(h, d_values, 1, st);
+  if (rc) return rc;
+  h->last_stream = st;
+  h->factored = true;
+  return 0;
+}
+
+int stc_factorize_batched(stc_handle* h, const double* d_values, int32_t B, double* d_logdet,
+                          int32_t* d_info, void* stream) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!d_values || !d_logdet || !d_info) return fail(STC_ERR_ARG, "null pointer");
+  if (B < 1 || B > h->batch) return fail(STC_ERR_ARG, "B must be in [1, bound batch]");
+  hipStream_t st = (hipStream_t)stream;
+  rc = run_factor(h, d_values, B, st);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_logdet, dim3(B), dim3(256), 0, st, h->d_store, h->plan.store, h->plan.nb,
+                     h->sym.n, h->d_info, d_logdet);
+  HIPCHK(hipMemcpyAsync(d_info, h->d_info, sizeof(int32_t) * B, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipGetLastError());
+  h->last_stream = st;
+  h->factored = B >= 1;  // member 0 is the "last single factorization" too
+  return 0;
+}
+
+int stc_logdet(stc_handle* h, double* d_out, void* stream) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!d_out) return fail(STC_ERR_ARG, "null output");
+  if (!h->factored) return fail(STC_ERR_STATE, "logdet before factorize");
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_logdet, dim3(1), dim3(256), 0, st, h->d_store, h->plan.store, h->plan.nb,
+                     h->sym.n, h->d_info, d_out);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int stc_solve(stc_handle* h, double* d_b, int32_t nrhs, void* stream) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!d_b) return fail(STC_ERR_ARG, "null right-hand side");
+  if (nrhs < 1 || nrhs > kMaxRhs) return fail(STC_ERR_ARG, "nrhs must be in [1, 64]");
+  if (!h->factored) return fail(STC_ERR_STATE, "solve before factorize");
+  hipStream_t st = (hipStream_t)stream;
+  const Plan& p = h->plan;
+  const int64_t n = h->sym.n, np = padded_n(h);
+  hipLaunchKernelGGL(k_perm_in, dim3((unsigned)((np * nrhs + 255) / 256)), dim3(256), 0, st, d_b,
+                     h->d_perm, n, np, nrhs, h->d_y);
+  auto sweep = [&](auto fwd_kernel, auto bwd_kernel) {
+    for (size_t L = 0; L + 1 < p.fwd_level_ptr.size(); ++L) {
+      int32_t a = p.fwd_level_ptr[L], b = p.fwd_level_ptr[L + 1];
+      if (b > a)
+        hipLaunchKernelGGL(fwd_kernel, dim3(b - a), dim3(256), 0, st, h->d_fwd_blk + a, h->d_row_ptr,
+                           h->d_row_tiles, h->d_tiles, h->d_rows, h->d_store, h->d_y, np, nrhs);
+    }
+    for (size_t L = 0; L + 1 < p.bwd_level_ptr.size(); ++L) {
+      int32_t a = p.bwd_level_ptr[L], b = p.bwd_level_ptr[L + 1];
+      if (b > a)
+        hipLaunchKernelGGL(bwd_kernel, dim3(b - a), dim3(256), 0, st, h->d_bwd_blk + a, h->d_col_ptr,
+                           h->d_col_tiles, h->d_tiles, h->d_rows, h->d_store, h->d_y, np, nrhs);
+    }
+  };
+  switch (p.nb) {
+    case 32: sweep(k_fwd<32>, k_bwd<32>); break;
+    case 64: sweep(k_fwd<64>, k_bwd<64>); break;
+    case 128: sweep(k_fwd<128>, k_bwd<128>); break;
+    case 256: sweep(k_fwd<256>, k_bwd<256>); break;
+  }
+  hipLaunchKernelGGL(k_perm_out, dim3((unsigned)((n * nrhs + 255) / 256)), dim3(256), 0, st, h->d_y,
+                     h->d_perm, n, np, nrhs, d_b);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int stc_logdet_backward(stc_handle* h, const double* d_gbar, double* d_grad_values, void* stream) {
+  (void)d_gbar;
+  (void)d_grad_values;
+  (void)stream;
+  int rc = check_bound(h);
+  if (rc) return rc;
+  return fail(STC_ERR_STATE, "logdet backward is not available in this build");
+}
+
+int stc_info(stc_handle* h, int32_t* info) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!info) return fail(STC_ERR_ARG, "null output");
+  if (!h->factored) return fail(STC_ERR_STATE, "info before factorize");
+  HIPCHK(hipStreamSynchronize(h->last_stream));
+  HIPCHK(hipMemcpy(info, h->d_info, sizeof(int32_t), hipMemcpyDeviceToHost));
+  return 0;
+}
+
+int stc_get_factor(stc_handle* h, double* h_Lx, void* stream) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!h_Lx) return fail(STC_ERR_ARG, "null output");
+  if (!h->factored) return fail(STC_ERR_STATE, "factor export before factorize");
+  std::vector<double> store((size_t)h->plan.store);
+  HIPCHK(hipMemcpyAsync(store.data(), h->d_store, sizeof(double) * store.size(), hipMemcpyDeviceToHost,
+                        (hipStream_t)stream));
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  const auto& lm = h->plan.lmap;
+  for (size_t q = 0; q < lm.size(); ++q) h_Lx[q] = store[(size_t)lm[q]];
+  return 0;
+}
+
+int stc_get_sizes(const stc_handle* h, int64_t* z) {
+  if (!h || !z) return fail(STC_ERR_ARG, "null argument");
+  const Symbolic& s = h->sym;
+  int64_t rows = 0;
+  for (const TileInfo& t : s.tiles) rows += t.cnt;
+  int64_t v[16] = {s.n, s.qnz, s.lnz, s.nb, s.NT, (int64_t)s.tiles.size(), rows,
+                   (int64_t)(s.tasks.size() / 4), s.mode, s.route, s.ndense, s.method, s.tact,
+                   h->plan.store, (int64_t)h->plan.levels.size(), 0};
+  std::memcpy(z, v, sizeof(v));
+  return 0;
+}
+
+int stc_get_features(const stc_handle* h, double* f) {
+  if (!h || !f) return fail(STC_ERR_ARG, "null argument");
+  f[0] = h->sym.phi;
+  f[1] = h->sym.rho;
+  f[2] = h->sym.sigma;
+  return 0;
+}
+
+int stc_get_perm(const stc_handle* h, int32_t* perm) {
+  if (!h || !perm) return fail(STC_ERR_ARG, "null argument");
+  std::copy(h->sym.perm.begin(), h->sym.perm.end(), perm);
+  return 0;
+}
+
+int stc_get_etree(const stc_handle* h, int32_t* parent) {
+  if (!h || !parent) return fail(STC_ERR_ARG, "null argument");
+  std::copy(h->sym.parent.begin(), h->sym.parent.end(), parent);
+  return 0;
+}
+
+int stc_get_L_pattern(const stc_handle* h, int64_t* colptr, int32_t* rowind) {
+  if (!h || !colptr || !rowind) return fail(STC_ERR_ARG, "null argument");
+  std::copy(h->sym.lp.begin(), h->sym.lp.end(), colptr);
+  std::copy(h->sym.li.begin(), h->sym.li.end(), rowind);
+  return 0;
+}
+
+int stc_get_tiles(const stc_handle* h, int32_t* m, int32_t* k, int32_t* cnt, int32_t* true_cnt,
+                  int8_t* contig, int64_t* roff, int32_t* rows, int32_t* kd) {
+  if (!h || !m || !k || !cnt || !true_cnt || !contig || !roff || !rows || !kd)
+    return fail(STC_ERR_ARG, "null argument");
+  const Symbolic& s = h->sym;
+  for (size_t t = 0; t < s.tiles.size(); ++t) {
+    m[t] = s.tiles[t].m;
+    k[t] = s.tiles[t].k;
+    cnt[t] = s.tiles[t].cnt;
+    true_cnt[t] = s.tiles[t].true_cnt;
+    contig[t] = s.tiles[t].contig;
+    roff[t] = s.tiles[t].roff;
+  }
+  roff[s.tiles.size()] = (int64_t)s.rows.size();
+  std::copy(s.rows.begin(), s.rows.end(), rows);
+  std::copy(s.kd.begin(), s.kd.end(), kd);
+  return 0;
+}
+
+int stc_get_tasks(const stc_handle* h, int32_t* tasks) {
+  if (!h || !tasks) return fail(STC_ERR_ARG, "null argument");
+  std::copy(h->sym.tasks.begin(), h->sym.tasks.end(), tasks);
+  return 0;
+}
+
+void stc_destroy(stc_handle* h) { delete h; }
+
+}  // extern "C"
