@@ -160,6 +160,26 @@ int stc_get_tasks(const stc_handle* h, int32_t* tasks); /* int32[ntasks][4]: op,
    (h_Lx double[nnz(L)]); synchronizes the stream. */
 int stc_get_factor(stc_handle* h, double* h_Lx, void* stream);
 
+/* Static work of one factorization with this plan (host) double[8]:
+   [0] tile-algorithmic flops of the SYRK+GEMM updates: sum |R_kn|^2 n_b over
+       SYRK tasks + sum 2 |R_mn| |R_kn| n_b over GEMM tasks (Algorithm 1's
+       tasks on the stored active rows, Sec. 5.2); [1] POTRF flops sum h^3/3;
+   [2] TRSM flops sum |R_mk| n_b^2; [3] their total; [4] exact Cholesky flops
+   sum_j c_j^2 (c_j = entries of column j of L); [5] update bytes: operand
+   rows read per task plus every output tile read and written once; [6] value
+   load bytes: 20 per input entry plus 8 per stored double; [7] levels. */
+int stc_get_work(const stc_handle* h, double* work);
+
+/* Measurement helper: one factorization of d_values (device) double[nnz]
+   with the same kernels as stc_factorize, launched one by one instead of from
+   the graph, with a HIP event pair around each launch on `stream`;
+   synchronizes the stream.  kind_ms (host) double[4] and kind_launches (host)
+   int64[4] receive total kernel milliseconds and launch counts for: value
+   load (fill + scatter), update, POTRF, TRSM.  Leaves the factor resident
+   like stc_factorize. */
+int stc_profile_factorize(stc_handle* h, const double* d_values, void* stream, double* kind_ms,
+                          int64_t* kind_launches);
+
 void stc_destroy(stc_handle* h);
 const char* stc_last_error(void);
 

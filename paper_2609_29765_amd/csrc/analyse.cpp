@@ -634,6 +634,8 @@ int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why) {
           c.rowmap = colmap_of[tb];
           lv = std::max(lv, lvT[tb] + 1);
           flops += (double)s.tiles[tb].cnt * s.tiles[tb].cnt * nb;
+          p->flops_update += (double)s.tiles[tb].cnt * s.tiles[tb].cnt * nb;
+          p->bytes_update += 8.0 * s.tiles[tb].cnt * nb;
         } else {
           int64_t ta = find_tile(m, nn);
           c.a_off = p->tile_off[ta];
@@ -652,10 +654,13 @@ int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why) {
           }
           lv = std::max(lv, std::max(lvT[ta], lvT[tb]) + 1);
           flops += 2.0 * tia.cnt * s.tiles[tb].cnt * nb;
+          p->flops_update += 2.0 * tia.cnt * s.tiles[tb].cnt * nb;
+          p->bytes_update += 8.0 * (tia.cnt + s.tiles[tb].cnt) * nb;
         }
         p->contribs.push_back(c);
       }
       u.c_end = (int32_t)p->contribs.size();
+      p->bytes_update += 16.0 * u.c_rows * (diag ? u.c_rows : nb);
       int32_t id = (int32_t)p->upd.size();
       p->upd.push_back(u);
       if (diag) {
@@ -679,6 +684,7 @@ int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why) {
       lvP[k] = lvU_diag[k] + 1;  // 0 when nothing updates the diagonal tile
       level_at(lvP[k]).potrf.push_back(k);
       flops += (double)p->diag_h[k] * p->diag_h[k] * p->diag_h[k] / 3.0;
+      p->flops_potrf += (double)p->diag_h[k] * p->diag_h[k] * p->diag_h[k] / 3.0;
       ++a;
     } else {  // kTrsm
       int64_t t = find_tile(m, k);
@@ -697,10 +703,15 @@ int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why) {
         L.trsm_items.push_back(x);
       }
       flops += (double)tt.rows * nb * nb;
+      p->flops_trsm += (double)tt.rows * nb * nb;
       ++a;
     }
   }
   p->flops_tile = flops;
+  for (int64_t j = 0; j < n; ++j) {
+    double c = (double)(s.lp[j + 1] - s.lp[j]);
+    p->flops_exact += c * c;
+  }
 
   // solve schedule: block rows / columns and their dependency levels
   p->row_tiles_ptr.assign((size_t)NT + 1, 0);

@@ -116,6 +116,11 @@ struct Plan {
   std::vector<int32_t> fwd_level_ptr, fwd_level_blk;
   std::vector<int32_t> bwd_level_ptr, bwd_level_blk;
   double flops_tile = 0;    // tile-algorithmic flops of one factorization
+  double flops_update = 0;  // of which SYRK + GEMM contributions
+  double flops_potrf = 0;
+  double flops_trsm = 0;
+  double flops_exact = 0;   // sum_j c_j^2, c_j = entries of column j of L
+  double bytes_update = 0;  // operand rows read + output tiles read and written
 };
 
 int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why);

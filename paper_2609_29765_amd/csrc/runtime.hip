@@ -134,33 +134,62 @@ int upload(T* dst, const std::vector<T>& src) {
   return 0;
 }
 
+// event pairs around individual launches (measurement only)
+struct Prof {
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+  int begin(hipStream_t st, hipEvent_t* a) {
+    HIPCHK(hipEventCreate(a));
+    HIPCHK(hipEventRecord(*a, st));
+    return 0;
+  }
+  int end(int kind, hipStream_t st, hipEvent_t a) {
+    hipEvent_t b;
+    HIPCHK(hipEventCreate(&b));
+    HIPCHK(hipEventRecord(b, st));
+    marks.push_back({kind, {a, b}});
+    return 0;
+  }
+};
+
+enum { kKindLoad = 0, kKindUpdate = 1, kKindPotrf = 2, kKindTrsm = 3 };
+
 // launch every level of the schedule for `members` value sets
 template <int NB>
-int launch_levels_nb(stc_handle* h, int32_t members, hipStream_t st) {
+int launch_levels_nb(stc_handle* h, int32_t members, hipStream_t st, Prof* prof) {
   const int64_t ms = h->plan.store;
   const int32_t nreal = (int32_t)h->sym.n;
+  hipEvent_t ev = nullptr;
   for (const LevelOffsets& L : h->lv) {
-    if (L.u_cnt)
+    if (L.u_cnt) {
+      if (prof && prof->begin(st, &ev)) return STC_ERR_HIP;
       hipLaunchKernelGGL(k_update<NB>, dim3(L.u_cnt, members), dim3(256), 0, st,
                          h->d_upd_items + 3 * (int64_t)L.u_off, h->d_upd, h->d_contrib, h->d_maps,
                          h->d_store, ms);
-    if (L.p_cnt)
+      if (prof && prof->end(kKindUpdate, st, ev)) return STC_ERR_HIP;
+    }
+    if (L.p_cnt) {
+      if (prof && prof->begin(st, &ev)) return STC_ERR_HIP;
       hipLaunchKernelGGL(k_potrf<NB>, dim3(L.p_cnt, members), dim3(256), 0, st,
                          h->d_potrf + L.p_off, h->d_store, ms, h->d_info, nreal);
-    if (L.t_cnt)
+      if (prof && prof->end(kKindPotrf, st, ev)) return STC_ERR_HIP;
+    }
+    if (L.t_cnt) {
+      if (prof && prof->begin(st, &ev)) return STC_ERR_HIP;
       hipLaunchKernelGGL(k_trsm<NB>, dim3(L.t_cnt, members), dim3(256), 0, st,
                          h->d_trsm_items + 2 * (int64_t)L.t_off, h->d_trsm, h->d_store, ms);
+      if (prof && prof->end(kKindTrsm, st, ev)) return STC_ERR_HIP;
+    }
   }
   HIPCHK(hipGetLastError());
   return 0;
 }
 
-int launch_levels(stc_handle* h, int32_t members, hipStream_t st) {
+int launch_levels(stc_handle* h, int32_t members, hipStream_t st, Prof* prof = nullptr) {
   switch (h->plan.nb) {
-    case 32: return launch_levels_nb<32>(h, members, st);
-    case 64: return launch_levels_nb<64>(h, members, st);
-    case 128: return launch_levels_nb<128>(h, members, st);
-    case 256: return launch_levels_nb<256>(h, members, st);
+    case 32: return launch_levels_nb<32>(h, members, st, prof);
+    case 64: return launch_levels_nb<64>(h, members, st, prof);
+    case 128: return launch_levels_nb<128>(h, members, st, prof);
+    case 256: return launch_levels_nb<256>(h, members, st, prof);
   }
   return fail(STC_ERR_ARG, "unsupported tile size");
 }
@@ -195,16 +224,20 @@ int get_graph(stc_handle* h, int32_t members, hipGraphExec_t* out) {
   return 0;
 }
 
-// value load + schedule for `members` value sets starting at vals
-int run_factor(stc_handle* h, const double* vals, int32_t members, hipStream_t st) {
+// value load + schedule for `members` value sets starting at vals; with prof,
+// the schedule is launched kernel by kernel with events instead of the graph
+int run_factor(stc_handle* h, const double* vals, int32_t members, hipStream_t st,
+               Prof* prof = nullptr) {
   const Plan& p = h->plan;
   const int64_t ms = p.store;
-  hipGraphExec_t ex;
-  int rc = get_graph(h, members, &ex);
+  hipGraphExec_t ex = nullptr;
+  int rc = prof ? 0 : get_graph(h, members, &ex);
   if (rc) return rc;
+  hipEvent_t ev = nullptr;
   hipLaunchKernelGGL(k_info_reset, dim3((members + 255) / 256), dim3(256), 0, st, h->d_info, members,
                      kInfoNone);
   const int64_t zgrid = std::min<int64_t>(4096, (ms / 2 + 255) / 256 + 1);
+  if (prof && prof->begin(st, &ev)) return STC_ERR_HIP;
   hipLaunchKernelGGL(k_zero, dim3((unsigned)zgrid, members), dim3(256), 0, st, h->d_store, ms, ms);
   const int32_t hlast = p.diag_h[p.NT - 1];
   if (hlast < p.nb)
@@ -214,8 +247,14 @@ int run_factor(stc_handle* h, const double* vals, int32_t members, hipStream_t s
   const int64_t vgrid = std::min<int64_t>(4096, (qnz + 255) / 256);
   hipLaunchKernelGGL(k_value_load, dim3((unsigned)vgrid, members), dim3(256), 0, st, vals, h->d_vmap,
                      qnz, h->d_store, ms);
+  if (prof && prof->end(kKindLoad, st, ev)) return STC_ERR_HIP;
   HIPCHK(hipGetLastError());
-  HIPCHK(hipGraphLaunch(ex, st));
+  if (prof) {
+    rc = launch_levels(h, members, st, prof);
+    if (rc) return rc;
+  } else {
+    HIPCHK(hipGraphLaunch(ex, st));
+  }
   hipLaunchKernelGGL(k_info_finish, dim3((members + 255) / 256), dim3(256), 0, st, h->d_info, members,
                      kInfoNone, (int32_t*)nullptr);
   HIPCHK(hipGetLastError());
@@ -508,6 +547,52 @@ int stc_get_tiles(const stc_handle* h, int32_t* m, int32_t* k, int32_t* cnt, int
 int stc_get_tasks(const stc_handle* h, int32_t* tasks) {
   if (!h || !tasks) return fail(STC_ERR_ARG, "null argument");
   std::copy(h->sym.tasks.begin(), h->sym.tasks.end(), tasks);
+  return 0;
+}
+
+int stc_get_work(const stc_handle* h, double* w) {
+  if (!h || !w) return fail(STC_ERR_ARG, "null argument");
+  const Plan& p = h->plan;
+  const double q = (double)h->sym.qnz;
+  w[0] = p.flops_update;
+  w[1] = p.flops_potrf;
+  w[2] = p.flops_trsm;
+  w[3] = p.flops_tile;
+  w[4] = p.flops_exact;
+  w[5] = p.bytes_update;
+  w[6] = 20.0 * q + 8.0 * (double)p.store;  // values + map read, value write, store fill
+  w[7] = (double)h->lv.size();
+  return 0;
+}
+
+int stc_profile_factorize(stc_handle* h, const double* d_values, void* stream, double* kind_ms,
+                          int64_t* kind_launches) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!d_values || !kind_ms || !kind_launches) return fail(STC_ERR_ARG, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  Prof prof;
+  rc = run_factor(h, d_values, 1, st, &prof);
+  if (rc == 0) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rc = fail(STC_ERR_HIP, hipGetErrorString(e));
+  }
+  for (int k = 0; k < 4; ++k) {
+    kind_ms[k] = 0.0;
+    kind_launches[k] = 0;
+  }
+  for (auto& m : prof.marks) {
+    float t = 0.f;
+    if (rc == 0 && hipEventElapsedTime(&t, m.second.first, m.second.second) == hipSuccess) {
+      kind_ms[m.first] += t;
+      kind_launches[m.first] += 1;
+    }
+    (void)hipEventDestroy(m.second.first);
+    (void)hipEventDestroy(m.second.second);
+  }
+  if (rc) return rc;
+  h->last_stream = st;
+  h->factored = true;
   return 0;
 }
 

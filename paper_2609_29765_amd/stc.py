@@ -31,7 +31,8 @@ EXPORTS = [
     "stc_analyse", "stc_workspace_bytes", "stc_bind", "stc_factorize", "stc_factorize_batched",
     "stc_logdet", "stc_solve", "stc_logdet_backward", "stc_info", "stc_get_sizes",
     "stc_get_features", "stc_get_perm", "stc_get_etree", "stc_get_L_pattern", "stc_get_tiles",
-    "stc_get_tasks", "stc_get_factor", "stc_destroy", "stc_last_error",
+    "stc_get_tasks", "stc_get_factor", "stc_get_work", "stc_profile_factorize", "stc_destroy",
+    "stc_last_error",
 ]
 
 _LIB = None
@@ -74,6 +75,8 @@ def lib():
     L.stc_get_tiles.argtypes = [vp, _i32p, _i32p, _i32p, _i32p, _i8p, _i64p, _i32p, _i32p]
     L.stc_get_tasks.argtypes = [vp, _i32p]
     L.stc_get_factor.argtypes = [vp, _f64p, vp]
+    L.stc_get_work.argtypes = [vp, _f64p]
+    L.stc_profile_factorize.argtypes = [vp, vp, vp, _f64p, _i64p]
     L.stc_destroy.argtypes = [vp]
     L.stc_destroy.restype = None
     L.stc_last_error.restype = C.c_char_p
@@ -246,6 +249,24 @@ class Analysis:
         out = torch.empty(self.qnz, dtype=torch.float64, device=self._ws.device)
         _check(lib().stc_logdet_backward(self._h, _dptr(g), _dptr(out), _stream_ptr()))
         return out
+
+    def work(self):
+        """Static flop and byte counts of one factorization (see stc_get_work)."""
+        w = np.zeros(8)
+        _check(lib().stc_get_work(self._h, w))
+        keys = ["flops_update", "flops_potrf", "flops_trsm", "flops_tile", "flops_exact",
+                "bytes_update", "bytes_load", "levels"]
+        return dict(zip(keys, (float(x) for x in w)))
+
+    def profile_factorize(self, values):
+        """Per-kernel-kind event timing of one eager factorization."""
+        self._bound()
+        _need_cuda(values)
+        ms = np.zeros(4)
+        cnt = np.zeros(4, np.int64)
+        _check(lib().stc_profile_factorize(self._h, _dptr(values), _stream_ptr(), ms, cnt))
+        kinds = ["load", "update", "potrf", "trsm"]
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(kinds)}
 
     def info(self):
         v = C.c_int32()
