@@ -597,7 +597,6 @@ int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why) {
 
   // fused update tasks from Algorithm 1's list, and the level schedule
   std::vector<int32_t> lvT((size_t)ntiles, -1), lvP((size_t)NT, -1);
-  std::vector<int32_t> upd_of_diag((size_t)NT, -1), upd_of_tile((size_t)ntiles, -1);
   std::vector<int32_t> lvU_diag((size_t)NT, -1), lvU_tile((size_t)ntiles, -1);
   std::vector<int32_t> trsm_of_tile((size_t)ntiles, -1);
   double flops = 0;
@@ -607,19 +606,45 @@ int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why) {
     if ((int32_t)p->levels.size() <= L) p->levels.resize((size_t)L + 1);
     return p->levels[(size_t)L];
   };
+  // Each output tile's contributions split into an early group (operands
+  // ready before the latest one) and a last group.  Both are placed as late
+  // as their consumer allows: the last group one level before the TRSM (or
+  // POTRF) that reads the tile, the early group one level before that.  On a
+  // dense grid this puts POTRF(k) beside the n = k-1 updates of column k and
+  // the bulk of column k's updates one level earlier.
+  auto emit_group = [&](const std::vector<Contrib>& cs, int64_t c_off, int32_t c_rows, bool diag,
+                        int32_t level) {
+    if (cs.empty()) return;
+    UpdTask u;
+    u.c_off = c_off;
+    u.c_rows = c_rows;
+    u.diag = diag ? 1 : 0;
+    u.c_begin = (int32_t)p->contribs.size();
+    p->contribs.insert(p->contribs.end(), cs.begin(), cs.end());
+    u.c_end = (int32_t)p->contribs.size();
+    p->bytes_update += 16.0 * c_rows * (diag ? c_rows : nb);
+    int32_t id = (int32_t)p->upd.size();
+    p->upd.push_back(u);
+    Level& L = level_at(level);
+    const int32_t nbr = (c_rows + bm - 1) / bm, nbc = diag ? nbr : (nb + bm - 1) / bm;
+    for (int32_t x = 0; x < nbr; ++x)
+      for (int32_t y = 0; y < nbc; ++y) {
+        if (diag && y > x) continue;
+        L.upd_items.push_back(id);
+        L.upd_items.push_back(x);
+        L.upd_items.push_back(y);
+      }
+  };
+  std::vector<Contrib> run;
+  std::vector<int32_t> ready;
   size_t a = 0;
   while (a < ntask) {
     int op = T[4 * a], m = T[4 * a + 1], k = T[4 * a + 2];
     if (op == kSyrk || op == kGemm) {
-      // gather this output tile's run of contributions
       const bool diag = op == kSyrk;
-      UpdTask u;
       int64_t tout = diag ? -1 : find_tile(m, k);
-      u.c_off = diag ? (int64_t)k * nb * nb : p->tile_off[tout];
-      u.c_rows = diag ? p->diag_h[k] : s.tiles[tout].cnt;
-      u.diag = diag ? 1 : 0;
-      u.c_begin = (int32_t)p->contribs.size();
-      int32_t lv = 0;
+      run.clear();
+      ready.clear();
       size_t b = a;
       for (; b < ntask && T[4 * b] == op && T[4 * b + 1] == m && T[4 * b + 2] == k; ++b) {
         int nn = T[4 * b + 3];
@@ -632,7 +657,7 @@ int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why) {
           c.a_off = c.b_off;
           c.a_rows = c.b_rows;
           c.rowmap = colmap_of[tb];
-          lv = std::max(lv, lvT[tb] + 1);
+          ready.push_back(lvT[tb] + 1);
           flops += (double)s.tiles[tb].cnt * s.tiles[tb].cnt * nb;
           p->flops_update += (double)s.tiles[tb].cnt * s.tiles[tb].cnt * nb;
           p->bytes_update += 8.0 * s.tiles[tb].cnt * nb;
@@ -652,33 +677,45 @@ int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why) {
             for (int32_t r = 0; r < to.cnt; ++r)
               p->maps.push_back(inv[(size_t)ta * nb + s.rows[to.roff + r]]);
           }
-          lv = std::max(lv, std::max(lvT[ta], lvT[tb]) + 1);
+          ready.push_back(std::max(lvT[ta], lvT[tb]) + 1);
           flops += 2.0 * tia.cnt * s.tiles[tb].cnt * nb;
           p->flops_update += 2.0 * tia.cnt * s.tiles[tb].cnt * nb;
           p->bytes_update += 8.0 * (tia.cnt + s.tiles[tb].cnt) * nb;
         }
-        p->contribs.push_back(c);
+        run.push_back(c);
       }
-      u.c_end = (int32_t)p->contribs.size();
-      p->bytes_update += 16.0 * u.c_rows * (diag ? u.c_rows : nb);
-      int32_t id = (int32_t)p->upd.size();
-      p->upd.push_back(u);
-      if (diag) {
-        upd_of_diag[k] = id;
-        lvU_diag[k] = lv;
-      } else {
-        upd_of_tile[tout] = id;
-        lvU_tile[tout] = lv;
-      }
-      Level& L = level_at(lv);
-      const int32_t nbr = (u.c_rows + bm - 1) / bm, nbc = diag ? nbr : (nb + bm - 1) / bm;
-      for (int32_t x = 0; x < nbr; ++x)
-        for (int32_t y = 0; y < nbc; ++y) {
-          if (diag && y > x) continue;
-          L.upd_items.push_back(id);
-          L.upd_items.push_back(x);
-          L.upd_items.push_back(y);
+      const int32_t rl = *std::max_element(ready.begin(), ready.end());
+      std::vector<Contrib> early, last;
+      int32_t re = 0;  // readiness of the early group
+      for (size_t x = 0; x < run.size(); ++x) {
+        if (ready[x] == rl) {
+          last.push_back(run[x]);
+        } else {
+          early.push_back(run[x]);
+          re = std::max(re, ready[x]);
         }
+      }
+      // the early group goes to the latest level of its window [re, hi] that
+      // holds a POTRF, so that the single-work-group factorization runs beside
+      // it; otherwise to hi
+      auto early_level = [&](int32_t hi) {
+        for (int32_t L = hi; L >= re; --L)
+          if (L < (int32_t)p->levels.size() && !p->levels[(size_t)L].potrf.empty()) return L;
+        return hi;
+      };
+      if (diag) {
+        lvU_diag[k] = rl;  // POTRF(k) follows at rl + 1
+        emit_group(early, (int64_t)k * nb * nb, p->diag_h[k], true, early_level(rl - 1));
+        emit_group(last, (int64_t)k * nb * nb, p->diag_h[k], true, rl);
+      } else {
+        // the TRSM of this tile waits for both the updates and POTRF(k)
+        const int32_t lt = std::max(rl, lvP[k]) + 1;
+        lvU_tile[tout] = lt - 1;
+        const int64_t off = p->tile_off[tout];
+        const int32_t rows = s.tiles[tout].cnt;
+        emit_group(early, off, rows, false, early_level(lt - 2));
+        emit_group(last, off, rows, false, lt - 1);
+      }
       a = b;
     } else if (op == kPotrf) {
       lvP[k] = lvU_diag[k] + 1;  // 0 when nothing updates the diagonal tile

@@ -64,17 +64,18 @@ constexpr int UB = 64;   // output block
 constexpr int UKT = 16;  // K chunk staged in LDS
 constexpr int ULD = UKT + 1;
 
+constexpr int UPD_LDS = 2 * UB * ULD + UB;  // doubles: As, Bs, two int maps
+
 template <int NB>
-__global__ __launch_bounds__(256) void k_update(const int32_t* __restrict__ items,
-                                                const UpdTaskD* __restrict__ tasks,
-                                                const ContribD* __restrict__ contribs,
-                                                const int32_t* __restrict__ maps,
-                                                double* __restrict__ store, int64_t mstride) {
-  __shared__ double As[UB * ULD];
-  __shared__ double Bs[UB * ULD];
-  __shared__ int32_t arow[UB], bcol[UB];
-  double* S = store + (int64_t)blockIdx.y * mstride;
-  const int32_t it = blockIdx.x;
+__device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict__ items,
+                                           const UpdTaskD* __restrict__ tasks,
+                                           const ContribD* __restrict__ contribs,
+                                           const int32_t* __restrict__ maps,
+                                           double* __restrict__ S, double* smem) {
+  double* As = smem;
+  double* Bs = smem + UB * ULD;
+  int32_t* arow = reinterpret_cast<int32_t*>(smem + 2 * UB * ULD);
+  int32_t* bcol = arow + UB;
   const int32_t task = items[3 * it], bx = items[3 * it + 1], by = items[3 * it + 2];
   const UpdTaskD u = tasks[task];
   const int32_t r0 = bx * UB, c0 = by * UB;
@@ -152,119 +153,246 @@ __global__ __launch_bounds__(256) void k_update(const int32_t* __restrict__ item
 }
 
 // ---------------------------------------------------------------------------
-// POTRF of diagonal tiles: right-looking over 32-column panels held in LDS
+// POTRF of diagonal tiles: right-looking over 32-column panels held in LDS;
+// the trailing update runs on FP64 MFMA from the LDS panel.  As a by-product
+// the inverse of every 32 x 32 diagonal block of L is written to dinv
+// (row-major, block J at dinv + J*32*32), for the blocked TRSM.
 // ---------------------------------------------------------------------------
 
 constexpr int PW = 32;
+constexpr int PLD = PW + 1;
+
+// broadcast a double from a fixed lane of the wave (readlane on both halves)
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+// Cholesky of the 32 x 32 block held in P's first 32 rows, by the 32 low
+// lanes of one wave, row r in lane r's registers; then the inverse of the
+// factor, column c in lane c's registers.  Writes L (lower, diagonal
+// included) back to P, the inverse to Z (row-major 32 x 32, stride PLD).
+// Returns the pivot that failed first as a 0-based column, or -1.
+__device__ __forceinline__ int chol32_wave(double* P, double* Z, int lane) {
+  double a[PW];
+  const int r = lane & 31;
+#pragma unroll
+  for (int j = 0; j < PW; ++j) a[j] = (j <= r) ? P[r * PLD + j] : 0.0;
+  int bad = -1;
+#pragma unroll
+  for (int c = 0; c < PW; ++c) {
+    const double d = lane_bcast(a[c], c);
+    if (bad < 0 && (!(d > 0.0) || !isfinite(d))) bad = c;
+    const double ljj = sqrt(d);
+    a[c] = (r > c) ? a[c] / ljj : ((r == c) ? ljj : 0.0);
+#pragma unroll
+    for (int j = c + 1; j < PW; ++j) {
+      const double ljc = lane_bcast(a[c], j);
+      a[j] -= a[c] * ljc;
+    }
+  }
+  // inverse: lane c solves L z = e_c
+  double z[PW];
+#pragma unroll
+  for (int i = 0; i < PW; ++i) {
+    double v = (i == r) ? 1.0 : 0.0;
+#pragma unroll
+    for (int q = 0; q < i; ++q) v -= lane_bcast(a[q], i) * z[q];
+    z[i] = v / lane_bcast(a[i], i);
+  }
+  if (lane < PW) {
+#pragma unroll
+    for (int j = 0; j < PW; ++j) {
+      P[r * PLD + j] = (j <= r) ? a[j] : 0.0;
+      Z[j * PLD + r] = z[j];
+    }
+  }
+  return bad;
+}
 
 template <int NB>
-__global__ __launch_bounds__(256) void k_potrf(const int32_t* __restrict__ ks,
-                                               double* __restrict__ store, int64_t mstride,
-                                               int32_t* __restrict__ info, int32_t nreal) {
-  __shared__ double P[NB * (PW + 1)];
-  __shared__ double dg[PW];
-  double* S = store + (int64_t)blockIdx.y * mstride;
-  const int32_t k = ks[blockIdx.x];
+constexpr int potrf_lds() { return NB * PLD + PW * PLD; }
+
+template <int NB>
+__device__ __forceinline__ void dev_potrf(int32_t k, double* __restrict__ S,
+                                          double* __restrict__ dinv_m, int32_t* __restrict__ inf,
+                                          int32_t nreal, double* smem) {
+  double* P = smem;
+  double* Z = smem + NB * PLD;
   double* A = S + (int64_t)k * NB * NB;
-  const int tid = threadIdx.x;
-  int32_t* inf = info + blockIdx.y;
+  double* dinv = dinv_m + (int64_t)k * NB * PW;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int j0 = 0; j0 < NB; j0 += PW) {
     const int pr = NB - j0;  // panel rows j0..NB-1
     for (int x = tid; x < pr * PW; x += 256) {
-      int r = x / PW, c = x % PW;
-      P[r * (PW + 1) + c] = A[(int64_t)(j0 + r) * NB + j0 + c];
+      const int r = x / PW, c = x % PW;
+      P[r * PLD + c] = A[(int64_t)(j0 + r) * NB + j0 + c];
     }
     __syncthreads();
-    // left-looking inside the panel, one column at a time; the pivot's square
-    // root goes to dg[] so that P's diagonal is never rewritten while read
-    for (int c = 0; c < PW; ++c) {
-      for (int r = c + tid; r < pr; r += 256) {
-        double v = P[r * (PW + 1) + c];
-        for (int p = 0; p < c; ++p) v -= P[r * (PW + 1) + p] * P[c * (PW + 1) + p];
-        P[r * (PW + 1) + c] = v;
-      }
-      __syncthreads();
-      const double d = P[c * (PW + 1) + c];
-      const double ljj = sqrt(d);
-      for (int r = c + 1 + tid; r < pr; r += 256) P[r * (PW + 1) + c] /= ljj;
-      if (tid == 0) {
-        dg[c] = ljj;
-        const int32_t col = k * NB + j0 + c;
-        if ((!(d > 0.0) || !isfinite(d)) && col < nreal) atomicMin(inf, col + 1);
-      }
-      __syncthreads();
+    if (wave == 0) {
+      const int bad = chol32_wave(P, Z, lane);
+      if (lane == 0 && bad >= 0 && k * NB + j0 + bad < nreal) atomicMin(inf, k * NB + j0 + bad + 1);
     }
+    __syncthreads();
+    // rows below the diagonal block: P_below <- P_below inv(L_top)^T on MFMA;
+    // each wave owns whole 16-row blocks, reads them fully, then overwrites
+    const int rb = (pr - PW) / 16;
+    for (int t = wave; t < rb; t += 4) {
+      d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+      const double* pa = P + (PW + t * 16 + (lane & 15)) * PLD + (lane >> 4);
+      const double* z0 = Z + (lane & 15) * PLD + (lane >> 4);
+      const double* z1 = Z + (16 + (lane & 15)) * PLD + (lane >> 4);
+#pragma unroll
+      for (int kk = 0; kk < PW; kk += 4) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[kk], z0[kk], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[kk], z1[kk], acc1, 0, 0, 0);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        double* row = P + (PW + t * 16 + (lane >> 4) + 4 * e) * PLD;
+        row[lane & 15] = acc0[e];
+        row[16 + (lane & 15)] = acc1[e];
+      }
+    }
+    for (int x = tid; x < PW * PW; x += 256) dinv[(j0 / PW) * PW * PW + x] = Z[(x / PW) * PLD + x % PW];
+    __syncthreads();
+    // write the panel back (lower part of its diagonal block)
     for (int x = tid; x < pr * PW; x += 256) {
-      int r = x / PW, c = x % PW;
-      if (c < r) A[(int64_t)(j0 + r) * NB + j0 + c] = P[r * (PW + 1) + c];
-      if (c == r) A[(int64_t)(j0 + r) * NB + j0 + c] = dg[c];
+      const int r = x / PW, c = x % PW;
+      if (c <= r || r >= PW) A[(int64_t)(j0 + r) * NB + j0 + c] = P[r * PLD + c];
     }
-    // trailing update of the lower part below/right of the panel
-    const int tr = NB - j0 - PW;
-    for (int x = tid; x < tr * tr; x += 256) {
-      int i = x / tr, j = x % tr;
-      if (j > i) continue;
-      double v = 0.0;
-      const double* pi = P + (PW + i) * (PW + 1);
-      const double* pj = P + (PW + j) * (PW + 1);
-#pragma unroll 8
-      for (int p = 0; p < PW; ++p) v += pi[p] * pj[p];
-      A[(int64_t)(j0 + PW + i) * NB + j0 + PW + j] -= v;
+    // trailing update A[j0+32:, j0+32:] -= P[32:] P[32:]^T, lower 16 x 16
+    // tiles distributed over the four waves
+    const int tr = (NB - j0 - PW) / 16;
+    const int ntile = tr * (tr + 1) / 2;
+    for (int t = wave; t < ntile; t += 4) {
+      int ti = 0, rem = t;
+      while (rem > ti) {
+        rem -= ti + 1;
+        ++ti;
+      }
+      const int tj = rem;
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      const double* pa = P + (PW + ti * 16 + (lane & 15)) * PLD + (lane >> 4);
+      const double* pb = P + (PW + tj * 16 + (lane & 15)) * PLD + (lane >> 4);
+#pragma unroll
+      for (int kk = 0; kk < PW; kk += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[kk], pb[kk], acc, 0, 0, 0);
+      const int gi = j0 + PW + ti * 16 + (lane >> 4), gj = j0 + PW + tj * 16 + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (ti != tj || gj <= gi + 4 * e) A[(int64_t)(gi + 4 * e) * NB + gj] -= acc[e];
     }
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// TRSM: rows of a panel tile times L_kk^-T, 32 rows per work item
+// TRSM: rows of a panel tile times L_kk^-T, 32 rows per work item, blocked by
+// 32 columns: X_J <- (X_J - X_<J L_J,<J^T) inv(L_JJ)^T, both products on MFMA
 // ---------------------------------------------------------------------------
 
 constexpr int TR = 32;
-constexpr int TCB = 16;
+constexpr int TLD = 4;  // row padding of the LDS copy
 
 template <int NB>
-__global__ __launch_bounds__(256) void k_trsm(const int32_t* __restrict__ items,
-                                              const TrsmTaskD* __restrict__ tasks,
-                                              double* __restrict__ store, int64_t mstride) {
-  __shared__ double X[TR * (NB + 1)];
-  __shared__ double Ld[TCB * (TCB + 1)];
-  double* S = store + (int64_t)blockIdx.y * mstride;
-  const TrsmTaskD t = tasks[items[2 * blockIdx.x]];
-  const int32_t rb = items[2 * blockIdx.x + 1];
+constexpr int trsm_lds() { return TR * (NB + TLD); }
+
+template <int NB>
+__device__ __forceinline__ void dev_trsm(int32_t it, const int32_t* __restrict__ items,
+                                         const TrsmTaskD* __restrict__ tasks,
+                                         double* __restrict__ S,
+                                         const double* __restrict__ dinv_m, double* smem) {
+  constexpr int XLD = NB + TLD;
+  double* X = smem;
+  const TrsmTaskD t = tasks[items[2 * it]];
+  const int32_t rb = items[2 * it + 1];
   const int32_t r0 = rb * TR;
   const int32_t nr = min(TR, t.rows - r0);
   double* Xg = S + t.x_off + (int64_t)r0 * NB;
   const double* L = S + t.l_off;
-  const int tid = threadIdx.x;
-  for (int x = tid; x < nr * NB; x += 256) X[(x / NB) * (NB + 1) + x % NB] = Xg[x];
+  const double* dinv = dinv_m + (int64_t)t.k * NB * PW;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int x = tid; x < TR * NB; x += 256) {
+    const int r = x / NB, c = x % NB;
+    X[r * XLD + c] = r < nr ? Xg[x] : 0.0;
+  }
   __syncthreads();
-  for (int j0 = 0; j0 < NB; j0 += TCB) {
-    // X[:, J] -= X[:, <J] L[J, <J]^T
-    for (int x = tid; x < nr * TCB; x += 256) {
-      int r = x / TCB, c = x % TCB;
-      const double* lrow = L + (int64_t)(j0 + c) * NB;
-      const double* xr = X + r * (NB + 1);
-      double v = 0.0;
-      for (int p = 0; p < j0; ++p) v += xr[p] * lrow[p];
-      X[r * (NB + 1) + j0 + c] -= v;
-    }
-    for (int x = tid; x < TCB * TCB; x += 256) {
-      int i = x / TCB, j = x % TCB;
-      Ld[i * (TCB + 1) + j] = (j <= i) ? L[(int64_t)(j0 + i) * NB + j0 + j] : 0.0;
-    }
+  // each wave owns one 16 x 16 tile of the 32 x 32 block column
+  const int wr = (wave >> 1) * 16, wc = (wave & 1) * 16;
+  for (int j0 = 0; j0 < NB; j0 += PW) {
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    const double* xa = X + (wr + (lane & 15)) * XLD + (lane >> 4);
+    const double* lb = L + (int64_t)(j0 + wc + (lane & 15)) * NB + (lane >> 4);
+    for (int kk = 0; kk < j0; kk += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[kk], lb[kk], acc, 0, 0, 0);
+    // Y = X_J - acc, kept in registers until every wave has read X_<J
+    double y[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      y[e] = X[(wr + (lane >> 4) + 4 * e) * XLD + j0 + wc + (lane & 15)] - acc[e];
     __syncthreads();
-    // X[:, J] <- X[:, J] L_JJ^-T, one row per thread
-    if (tid < nr) {
-      double* xr = X + tid * (NB + 1) + j0;
-      for (int c = 0; c < TCB; ++c) {
-        double v = xr[c];
-        for (int p = 0; p < c; ++p) v -= xr[p] * Ld[c * (TCB + 1) + p];
-        xr[c] = v / Ld[c * (TCB + 1) + c];
-      }
-    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) X[(wr + (lane >> 4) + 4 * e) * XLD + j0 + wc + (lane & 15)] = y[e];
+    __syncthreads();
+    // X_J = Y inv(L_JJ)^T
+    d4 z = {0.0, 0.0, 0.0, 0.0};
+    const double* ya = X + (wr + (lane & 15)) * XLD + j0 + (lane >> 4);
+    const double* db = dinv + (j0 / PW) * PW * PW + (wc + (lane & 15)) * PW + (lane >> 4);
+#pragma unroll
+    for (int kk = 0; kk < PW; kk += 4)
+      z = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[kk], db[kk], z, 0, 0, 0);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) X[(wr + (lane >> 4) + 4 * e) * XLD + j0 + wc + (lane & 15)] = z[e];
     __syncthreads();
   }
-  for (int x = tid; x < nr * NB; x += 256) Xg[x] = X[(x / NB) * (NB + 1) + x % NB];
+  for (int x = tid; x < nr * NB; x += 256) Xg[x] = X[(x / NB) * XLD + x % NB];
+}
+
+// ---------------------------------------------------------------------------
+// one level of the schedule in one launch: work-groups [0, np) factor
+// diagonal tiles, [np, np+nu) apply fused updates, the rest solve panel rows.
+// POTRF work-groups come first so that the latency-bound factorizations start
+// before the update work that fills the rest of the chip.
+// ---------------------------------------------------------------------------
+
+struct LevelArgs {
+  const int32_t* potrf;   // block columns
+  const int32_t* upd;     // triples
+  const int32_t* trsm;    // pairs
+  int32_t np, nu, nt;
+  const UpdTaskD* utasks;
+  const ContribD* contribs;
+  const int32_t* maps;
+  const TrsmTaskD* ttasks;
+  double* store;
+  int64_t mstride;
+  double* dinv;
+  int64_t dstride;
+  int32_t* info;
+  int32_t nreal;
+};
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_level(LevelArgs a) {
+  extern __shared__ double smem[];
+  const int32_t member = blockIdx.y;
+  double* S = a.store + (int64_t)member * a.mstride;
+  int32_t b = blockIdx.x;
+  if (b < a.np) {
+    dev_potrf<NB>(a.potrf[b], S, a.dinv + (int64_t)member * a.dstride, a.info + member, a.nreal,
+                  smem);
+    return;
+  }
+  b -= a.np;
+  if (b < a.nu) {
+    dev_update<NB>(b, a.upd, a.utasks, a.contribs, a.maps, S, smem);
+    return;
+  }
+  b -= a.nu;
+  dev_trsm<NB>(b, a.trsm, a.ttasks, S, a.dinv + (int64_t)member * a.dstride, smem);
 }
 
 // ---------------------------------------------------------------------------

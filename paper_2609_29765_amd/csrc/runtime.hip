@@ -79,6 +79,7 @@ struct stc_handle {
           *d_col_tiles = nullptr, *d_fwd_blk = nullptr, *d_bwd_blk = nullptr;
   double* d_store = nullptr;  // batch stores
   double* d_y = nullptr;      // solve scratch
+  double* d_dinv = nullptr;   // inverses of the 32 x 32 diagonal blocks, per member
   int32_t* d_info = nullptr;  // batch
   double* d_ld = nullptr;     // batch
   std::map<int32_t, hipGraphExec_t> graphs;  // by member count
@@ -90,6 +91,7 @@ struct stc_handle {
 namespace {
 
 int64_t padded_n(const stc_handle* h) { return (int64_t)h->plan.NT * h->plan.nb; }
+int64_t dinv_stride(const stc_handle* h) { return (int64_t)h->plan.NT * h->plan.nb * 32; }
 
 // workspace layout; returns total bytes.  With base == null only the size is
 // computed (the handle's pointers are left alone).
@@ -123,6 +125,7 @@ size_t layout(const stc_handle* hc, int32_t batch, char* base) {
   take(&h->d_info, sizeof(int32_t) * (size_t)batch);
   take(&h->d_ld, sizeof(double) * (size_t)batch);
   take(&h->d_y, sizeof(double) * (size_t)padded_n(h) * kMaxRhs);
+  take(&h->d_dinv, sizeof(double) * (size_t)dinv_stride(h) * (size_t)batch);
   take(&h->d_store, sizeof(double) * (size_t)p.store * (size_t)batch);
   return off;
 }
@@ -153,32 +156,40 @@ struct Prof {
 
 enum { kKindLoad = 0, kKindUpdate = 1, kKindPotrf = 2, kKindTrsm = 3 };
 
-// launch every level of the schedule for `members` value sets
+// launch every level of the schedule for `members` value sets, one kernel per
+// level; with prof, each level is timed and charged to the kind that
+// dominates it (POTRF if present, else update, else TRSM)
 template <int NB>
 int launch_levels_nb(stc_handle* h, int32_t members, hipStream_t st, Prof* prof) {
-  const int64_t ms = h->plan.store;
-  const int32_t nreal = (int32_t)h->sym.n;
+  LevelArgs a;
+  a.utasks = h->d_upd;
+  a.contribs = h->d_contrib;
+  a.maps = h->d_maps;
+  a.ttasks = h->d_trsm;
+  a.store = h->d_store;
+  a.mstride = h->plan.store;
+  a.dinv = h->d_dinv;
+  a.dstride = dinv_stride(h);
+  a.info = h->d_info;
+  a.nreal = (int32_t)h->sym.n;
   hipEvent_t ev = nullptr;
   for (const LevelOffsets& L : h->lv) {
-    if (L.u_cnt) {
-      if (prof && prof->begin(st, &ev)) return STC_ERR_HIP;
-      hipLaunchKernelGGL(k_update<NB>, dim3(L.u_cnt, members), dim3(256), 0, st,
-                         h->d_upd_items + 3 * (int64_t)L.u_off, h->d_upd, h->d_contrib, h->d_maps,
-                         h->d_store, ms);
-      if (prof && prof->end(kKindUpdate, st, ev)) return STC_ERR_HIP;
-    }
-    if (L.p_cnt) {
-      if (prof && prof->begin(st, &ev)) return STC_ERR_HIP;
-      hipLaunchKernelGGL(k_potrf<NB>, dim3(L.p_cnt, members), dim3(256), 0, st,
-                         h->d_potrf + L.p_off, h->d_store, ms, h->d_info, nreal);
-      if (prof && prof->end(kKindPotrf, st, ev)) return STC_ERR_HIP;
-    }
-    if (L.t_cnt) {
-      if (prof && prof->begin(st, &ev)) return STC_ERR_HIP;
-      hipLaunchKernelGGL(k_trsm<NB>, dim3(L.t_cnt, members), dim3(256), 0, st,
-                         h->d_trsm_items + 2 * (int64_t)L.t_off, h->d_trsm, h->d_store, ms);
-      if (prof && prof->end(kKindTrsm, st, ev)) return STC_ERR_HIP;
-    }
+    const int32_t total = L.p_cnt + L.u_cnt + L.t_cnt;
+    if (!total) continue;
+    a.potrf = h->d_potrf + L.p_off;
+    a.upd = h->d_upd_items + 3 * (int64_t)L.u_off;
+    a.trsm = h->d_trsm_items + 2 * (int64_t)L.t_off;
+    a.np = L.p_cnt;
+    a.nu = L.u_cnt;
+    a.nt = L.t_cnt;
+    int lds = 0;
+    if (L.p_cnt) lds = std::max(lds, potrf_lds<NB>());
+    if (L.u_cnt) lds = std::max(lds, UPD_LDS);
+    if (L.t_cnt) lds = std::max(lds, trsm_lds<NB>());
+    const int kind = L.p_cnt ? kKindPotrf : (L.u_cnt ? kKindUpdate : kKindTrsm);
+    if (prof && prof->begin(st, &ev)) return STC_ERR_HIP;
+    hipLaunchKernelGGL(k_level<NB>, dim3(total, members), dim3(256), sizeof(double) * lds, st, a);
+    if (prof && prof->end(kind, st, ev)) return STC_ERR_HIP;
   }
   HIPCHK(hipGetLastError());
   return 0;
