@@ -101,6 +101,24 @@ def main():
     }
     kinds = {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in prof.items()}
 
+    # measured ceilings: MFMA issue microkernel, library DGEMM (rocBLAS via torch)
+    mfma_peak = stc.fp64_mfma_peak()
+    nd = 8192
+    xa = torch.randn(nd, nd, dtype=torch.float64, device="cuda")
+    xb = torch.randn(nd, nd, dtype=torch.float64, device="cuda")
+    torch.matmul(xa, xb)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        torch.matmul(xa, xb)
+    e1.record()
+    torch.cuda.synchronize()
+    dgemm_tf = 3 * 2.0 * nd ** 3 / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    del xa, xb
+    print(f"[bench] measured FP64 MFMA issue {mfma_peak:.1f} TFLOP/s, library DGEMM n={nd} "
+          f"{dgemm_tf:.1f} TFLOP/s", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle
@@ -141,6 +159,7 @@ def main():
         "gflops_tile": round(gflops, 2),
         "frac_peak_whole_factorization": round(gflops / 1e3 / PEAK_FP64_TFLOPS, 4),
         "kernels": kinds,
+        "measured_peaks_tflops": {"mfma_issue": round(mfma_peak, 2), "dgemm_library_8192": round(dgemm_tf, 2)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "logdet": ld,

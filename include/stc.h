@@ -180,6 +180,12 @@ int stc_get_work(const stc_handle* h, double* work);
 int stc_profile_factorize(stc_handle* h, const double* d_values, void* stream, double* kind_ms,
                           int64_t* kind_launches);
 
+/* Measurement helper: FP64 matrix-core (MFMA 16x16x4) issue rate of the
+   current device in TFLOP/s, from a kernel that keeps 16 independent
+   accumulators per wave in registers and touches no memory in its loop
+   (8 work-groups of 4 waves per compute unit).  tflops (host) double[1]. */
+int stc_fp64_mfma_peak(void* stream, double* tflops);
+
 void stc_destroy(stc_handle* h);
 const char* stc_last_error(void);
 

@@ -613,8 +613,8 @@ int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why) {
   // dense grid this puts POTRF(k) beside the n = k-1 updates of column k and
   // the bulk of column k's updates one level earlier.
   auto emit_group = [&](const std::vector<Contrib>& cs, int64_t c_off, int32_t c_rows, bool diag,
-                        int32_t level) {
-    if (cs.empty()) return;
+                        int32_t level) -> int32_t {
+    if (cs.empty()) return -1;
     UpdTask u;
     u.c_off = c_off;
     u.c_rows = c_rows;
@@ -622,18 +622,12 @@ int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why) {
     u.c_begin = (int32_t)p->contribs.size();
     p->contribs.insert(p->contribs.end(), cs.begin(), cs.end());
     u.c_end = (int32_t)p->contribs.size();
+    u.level = level;
+    u.big = (nb >= 128 && c_rows >= 96) ? 1 : 0;
     p->bytes_update += 16.0 * c_rows * (diag ? c_rows : nb);
-    int32_t id = (int32_t)p->upd.size();
+    level_at(level);
     p->upd.push_back(u);
-    Level& L = level_at(level);
-    const int32_t nbr = (c_rows + bm - 1) / bm, nbc = diag ? nbr : (nb + bm - 1) / bm;
-    for (int32_t x = 0; x < nbr; ++x)
-      for (int32_t y = 0; y < nbc; ++y) {
-        if (diag && y > x) continue;
-        L.upd_items.push_back(id);
-        L.upd_items.push_back(x);
-        L.upd_items.push_back(y);
-      }
+    return (int32_t)p->upd.size() - 1;
   };
   std::vector<Contrib> run;
   std::vector<int32_t> ready;
@@ -705,16 +699,18 @@ int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why) {
       };
       if (diag) {
         lvU_diag[k] = rl;  // POTRF(k) follows at rl + 1
-        emit_group(early, (int64_t)k * nb * nb, p->diag_h[k], true, early_level(rl - 1));
-        emit_group(last, (int64_t)k * nb * nb, p->diag_h[k], true, rl);
+        int32_t e = emit_group(early, (int64_t)k * nb * nb, p->diag_h[k], true, early_level(rl - 1));
+        int32_t l = emit_group(last, (int64_t)k * nb * nb, p->diag_h[k], true, rl);
+        if (e >= 0) p->upd[(size_t)e].partner = l;
       } else {
         // the TRSM of this tile waits for both the updates and POTRF(k)
         const int32_t lt = std::max(rl, lvP[k]) + 1;
         lvU_tile[tout] = lt - 1;
         const int64_t off = p->tile_off[tout];
         const int32_t rows = s.tiles[tout].cnt;
-        emit_group(early, off, rows, false, early_level(lt - 2));
-        emit_group(last, off, rows, false, lt - 1);
+        int32_t e = emit_group(early, off, rows, false, early_level(lt - 2));
+        int32_t l = emit_group(last, off, rows, false, lt - 1);
+        if (e >= 0) p->upd[(size_t)e].partner = l;
       }
       a = b;
     } else if (op == kPotrf) {
@@ -742,6 +738,50 @@ int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why) {
       flops += (double)tt.rows * nb * nb;
       p->flops_trsm += (double)tt.rows * nb * nb;
       ++a;
+    }
+  }
+  // work items; early groups of large tiles in under-filled levels split
+  // their contribution range (deterministic: partial slots folded in by the
+  // tile's last group)
+  {
+    const int32_t nlev = (int32_t)p->levels.size();
+    std::vector<int64_t> items((size_t)nlev, 0);
+    auto blocks = [&](const UpdTask& u) -> int64_t {
+      const int32_t b = u.big ? 128 : bm;
+      const int64_t nr = (u.c_rows + b - 1) / b;
+      return u.diag ? nr * (nr + 1) / 2 : nr * ((nb + b - 1) / b);
+    };
+    for (const UpdTask& u : p->upd) items[(size_t)u.level] += blocks(u);
+    const int64_t target = 512;
+    for (UpdTask& u : p->upd) {
+      if (!u.big || u.partner < 0) continue;
+      const int64_t have = items[(size_t)u.level];
+      if (have >= target) continue;
+      const int32_t ncon = u.c_end - u.c_begin;
+      int32_t sp = (int32_t)std::min<int64_t>(8, (target + have - 1) / have);
+      sp = std::min(sp, ncon / 2);
+      if (sp < 2) continue;
+      u.nsplit = sp;
+      u.part_off = p->parts;
+      p->parts += (int64_t)(sp - 1) * u.c_rows * nb;
+      UpdTask& l = p->upd[(size_t)u.partner];
+      l.in_part_off = u.part_off;
+      l.in_npart = sp - 1;
+    }
+    for (int32_t id = 0; id < (int32_t)p->upd.size(); ++id) {
+      const UpdTask& u = p->upd[(size_t)id];
+      const int32_t b = u.big ? 128 : bm;
+      const int32_t nbr = (u.c_rows + b - 1) / b, nbc = u.diag ? nbr : (nb + b - 1) / b;
+      auto& dst = u.big ? p->levels[(size_t)u.level].big_items : p->levels[(size_t)u.level].upd_items;
+      for (int32_t part = 0; part < u.nsplit; ++part)
+        for (int32_t x = 0; x < nbr; ++x)
+          for (int32_t y = 0; y < nbc; ++y) {
+            if (u.diag && y > x) continue;
+            dst.push_back(id);
+            dst.push_back(x);
+            dst.push_back(y);
+            dst.push_back(part);
+          }
     }
   }
   p->flops_tile = flops;

@@ -81,6 +81,13 @@ struct UpdTask {
   int32_t c_rows;         // output rows (stored active rows, or h for a diagonal)
   int32_t diag;           // 1 for a diagonal tile (lower blocks only)
   int32_t c_begin, c_end; // contributions [c_begin, c_end)
+  int32_t level = 0;
+  int32_t big = 0;        // 128 x 128 blocks (else 64 x 64)
+  int32_t partner = -1;   // for an early group: the tile's last group
+  int32_t nsplit = 1;     // contribution range split over this many work-groups
+  int64_t part_off = 0;   // partial slots written when nsplit > 1
+  int64_t in_part_off = 0;
+  int32_t in_npart = 0;   // partial slots folded in by this task
 };
 
 struct TrsmTask {
@@ -91,14 +98,16 @@ struct TrsmTask {
 };
 
 struct Level {
-  std::vector<int32_t> upd_items;   // triples: task, block row, block col
+  std::vector<int32_t> big_items;   // quads: task, block row, block col, part (128 blocks)
+  std::vector<int32_t> upd_items;   // quads: task, block row, block col, part (64 blocks)
   std::vector<int32_t> potrf;       // block columns
   std::vector<int32_t> trsm_items;  // pairs: trsm task, row block
 };
 
 struct Plan {
   int32_t nb = 64, NT = 0;
-  int32_t bm = 64;          // update block (rows and columns)
+  int32_t bm = 64;          // small update block (rows and columns)
+  int64_t parts = 0;        // doubles of partial-sum slots per value set
   int32_t br = 32;          // rows per TRSM work item
   int64_t store = 0;        // doubles per value set
   std::vector<int64_t> tile_off;    // per off-diagonal tile

@@ -71,12 +71,13 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
                                            const UpdTaskD* __restrict__ tasks,
                                            const ContribD* __restrict__ contribs,
                                            const int32_t* __restrict__ maps,
-                                           double* __restrict__ S, double* smem) {
+                                           double* __restrict__ S, const double* __restrict__ parts,
+                                           double* smem) {
   double* As = smem;
   double* Bs = smem + UB * ULD;
   int32_t* arow = reinterpret_cast<int32_t*>(smem + 2 * UB * ULD);
   int32_t* bcol = arow + UB;
-  const int32_t task = items[3 * it], bx = items[3 * it + 1], by = items[3 * it + 2];
+  const int32_t task = items[4 * it], bx = items[4 * it + 1], by = items[4 * it + 2];
   const UpdTaskD u = tasks[task];
   const int32_t r0 = bx * UB, c0 = by * UB;
   const int32_t ncols = u.diag ? u.c_rows : NB;
@@ -143,102 +144,379 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
   }
   // epilogue: lane holds D[i][j] with j = lane % 16, i = lane / 16 + 4 e
   double* C = S + u.c_off;
+  const int64_t slot = (int64_t)u.c_rows * NB;
+  for (int q = 0; q < u.in_npart; ++q) {
+    const double* pq = parts + u.in_part_off + q * slot;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int32_t i = min(r0 + wr + a * 16 + (lane >> 4) + 4 * e, u.c_rows - 1);
+          const int32_t j = min(c0 + wc + b * 16 + (lane & 15), ncols - 1);
+          acc[a][b][e] += pq[(int64_t)i * NB + j];
+        }
+  }
+  double cv[2][2][4];
+#pragma unroll
   for (int a = 0; a < 2; ++a)
+#pragma unroll
     for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int32_t i = min(r0 + wr + a * 16 + (lane >> 4) + 4 * e, u.c_rows - 1);
+        const int32_t j = min(c0 + wc + b * 16 + (lane & 15), ncols - 1);
+        cv[a][b][e] = C[(int64_t)i * NB + j];
+      }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int32_t i = r0 + wr + a * 16 + (lane >> 4) + 4 * e;
         const int32_t j = c0 + wc + b * 16 + (lane & 15);
-        if (i < u.c_rows && j < ncols && (!u.diag || j <= i)) C[(int64_t)i * NB + j] -= acc[a][b][e];
+        if (i < u.c_rows && j < ncols && (!u.diag || j <= i))
+          C[(int64_t)i * NB + j] = cv[a][b][e] - acc[a][b][e];
       }
 }
 
 // ---------------------------------------------------------------------------
-// POTRF of diagonal tiles: right-looking over 32-column panels held in LDS;
-// the trailing update runs on FP64 MFMA from the LDS panel.  As a by-product
-// the inverse of every 32 x 32 diagonal block of L is written to dinv
-// (row-major, block J at dinv + J*32*32), for the blocked TRSM.
+// fused update on a 128 x 128 block (dense or nearly full tiles): four waves
+// of 64 x 64, K staged in LDS in chunks of 16 with two buffers and register
+// prefetch of the next chunk.  A task may split its contribution range over
+// nsplit work-groups: part 0 updates the tile, parts s > 0 write partial
+// sums that the tile's next update task folds in (in_part_off, in_npart).
+// ---------------------------------------------------------------------------
+
+constexpr int UB2 = 128;
+constexpr int UKT2 = 16;
+constexpr int ULD2 = UKT2 + 1;
+constexpr int UPD2_LDS = 4 * UB2 * ULD2;  // two buffers x {A, B}
+
+template <int NB>
+__device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __restrict__ items,
+                                               const UpdTaskD* __restrict__ tasks,
+                                               const ContribD* __restrict__ contribs,
+                                               const int32_t* __restrict__ maps,
+                                               double* __restrict__ S, double* __restrict__ parts,
+                                               double* smem) {
+  const int32_t task = items[4 * it], bx = items[4 * it + 1], by = items[4 * it + 2];
+  const int32_t part = items[4 * it + 3];
+  const UpdTaskD u = tasks[task];
+  const int32_t r0 = bx * UB2, c0 = by * UB2;
+  const int32_t ncols = u.diag ? u.c_rows : NB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  const int lr = tid >> 1, lk = (tid & 1) * 8;  // row and k offset this thread stages
+  const int32_t ncon = u.c_end - u.c_begin;
+  const int32_t cb = u.c_begin + (int32_t)((int64_t)ncon * part / u.nsplit);
+  const int32_t ce = u.c_begin + (int32_t)((int64_t)ncon * (part + 1) / u.nsplit);
+
+  d4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+
+  for (int32_t ci = cb; ci < ce; ++ci) {
+    const ContribD c = contribs[ci];
+    int32_t sa = -1, sb = -1;
+    {
+      const int32_t r = r0 + lr;
+      if (r < u.c_rows) sa = c.rowmap < 0 ? (r < c.a_rows ? r : -1) : maps[c.rowmap + r];
+      const int32_t cc = c0 + lr;
+      if (cc < ncols) sb = c.colmap < 0 ? (cc < c.b_rows ? cc : -1) : maps[c.colmap + cc];
+    }
+    if (!__syncthreads_or(sa >= 0)) continue;
+    if (!__syncthreads_or(sb >= 0)) continue;
+    const double* pa = S + c.a_off + (int64_t)max(sa, 0) * NB + lk;
+    const double* pb = S + c.b_off + (int64_t)max(sb, 0) * NB + lk;
+    double2 ra[4], rb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ra[q] = sa >= 0 ? reinterpret_cast<const double2*>(pa)[q] : make_double2(0.0, 0.0);
+      rb[q] = sb >= 0 ? reinterpret_cast<const double2*>(pb)[q] : make_double2(0.0, 0.0);
+    }
+    for (int k0 = 0; k0 < NB; k0 += UKT2) {
+      double* As = smem + ((k0 / UKT2) & 1) * 2 * UB2 * ULD2;
+      double* Bs = As + UB2 * ULD2;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        As[lr * ULD2 + lk + 2 * q] = ra[q].x;
+        As[lr * ULD2 + lk + 2 * q + 1] = ra[q].y;
+        Bs[lr * ULD2 + lk + 2 * q] = rb[q].x;
+        Bs[lr * ULD2 + lk + 2 * q + 1] = rb[q].y;
+      }
+      __syncthreads();
+      if (k0 + UKT2 < NB) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          ra[q] = sa >= 0 ? reinterpret_cast<const double2*>(pa + k0 + UKT2)[q] : make_double2(0.0, 0.0);
+          rb[q] = sb >= 0 ? reinterpret_cast<const double2*>(pb + k0 + UKT2)[q] : make_double2(0.0, 0.0);
+        }
+      }
+#pragma unroll
+      for (int kk = 0; kk < UKT2; kk += 4) {
+        double af[4], bf[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) af[a] = As[(wr + a * 16 + (lane & 15)) * ULD2 + kk + (lane >> 4)];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bf[b] = Bs[(wc + b * 16 + (lane & 15)) * ULD2 + kk + (lane >> 4)];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+      }
+    }
+  }
+  // epilogue: lane holds D[i][j] with j = lane % 16, i = lane / 16 + 4 e.
+  // Reads are issued unconditionally (addresses clamped into the tile) so
+  // that they are all in flight together; only the stores are masked.
+  double* C = S + u.c_off;
+  const int64_t slot = (int64_t)u.c_rows * NB;
+  if (part > 0) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int32_t i = r0 + wr + a * 16 + (lane >> 4) + 4 * e;
+          const int32_t j = c0 + wc + b * 16 + (lane & 15);
+          if (i < u.c_rows && j < ncols && (!u.diag || j <= i))
+            parts[u.part_off + (part - 1) * slot + (int64_t)i * NB + j] = acc[a][b][e];
+        }
+    return;
+  }
+  for (int q = 0; q < u.in_npart; ++q) {
+    const double* pq = parts + u.in_part_off + q * slot;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int32_t i = min(r0 + wr + a * 16 + (lane >> 4) + 4 * e, u.c_rows - 1);
+          const int32_t j = min(c0 + wc + b * 16 + (lane & 15), ncols - 1);
+          acc[a][b][e] += pq[(int64_t)i * NB + j];
+        }
+  }
+  double cv[4][4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int32_t i = min(r0 + wr + a * 16 + (lane >> 4) + 4 * e, u.c_rows - 1);
+        const int32_t j = min(c0 + wc + b * 16 + (lane & 15), ncols - 1);
+        cv[a][b][e] = C[(int64_t)i * NB + j];
+      }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int32_t i = r0 + wr + a * 16 + (lane >> 4) + 4 * e;
+        const int32_t j = c0 + wc + b * 16 + (lane & 15);
+        if (i < u.c_rows && j < ncols && (!u.diag || j <= i))
+          C[(int64_t)i * NB + j] = cv[a][b][e] - acc[a][b][e];
+      }
+}
+
+// ---------------------------------------------------------------------------
+// POTRF of diagonal tiles.  As a by-product the inverse of every 32 x 32
+// diagonal block of L is written to dinv (row-major, block J at
+// dinv + J*32*32), for the blocked TRSM.
 // ---------------------------------------------------------------------------
 
 constexpr int PW = 32;
 constexpr int PLD = PW + 1;
 
-// broadcast a double from a fixed lane of the wave (readlane on both halves)
-__device__ __forceinline__ double lane_bcast(double v, int src) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
-  return __hiloint2double(hi, lo);
+// Cholesky of the 32 x 32 block held in P's first 32 rows, by one wave,
+// without branches: lane r keeps row r (r = lane mod 32) in registers; at
+// step c every lane publishes its unscaled column-c entry in a 32-entry LDS
+// vector and reads the pivot and the other rows' entries back with uniform
+// addresses (broadcast), so row r's update is a[j] -= (a_rc / d) a_jc.  The
+// wave's LDS operations execute in program order, so the reads see the
+// writes of the same step.  Lanes 32..63 mirror lanes 0..31 and write the
+// same values.  Then the inverse of the factor, column r by lane r, with the
+// rows of L broadcast from P.  Writes L (lower, diagonal included) to P and
+// the inverse to Z (row-major, stride PLD).  Returns the first failing
+// pivot (0-based) or -1; uniform across the wave.
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(fma(-d, r, 1.0), r, r);
+  return fma(fma(-d, r, 1.0), r, r);
 }
 
-// Cholesky of the 32 x 32 block held in P's first 32 rows, by the 32 low
-// lanes of one wave, row r in lane r's registers; then the inverse of the
-// factor, column c in lane c's registers.  Writes L (lower, diagonal
-// included) back to P, the inverse to Z (row-major 32 x 32, stride PLD).
-// Returns the pivot that failed first as a 0-based column, or -1.
-__device__ __forceinline__ int chol32_wave(double* P, double* Z, int lane) {
-  double a[PW];
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  y = y * fma(-0.5 * d * y, y, 1.5);
+  return y * fma(-0.5 * d * y, y, 1.5);
+}
+
+__device__ __forceinline__ int chol32_wave(double* P, double* Z, double* rdiag, int lane) {
+  // row-oriented left-looking (Crout): lane r < 32 owns row r in registers
+  // and at step c computes L_rc = (A_rc - sum_{p<c} L_rp L_cp) / L_cc; row c
+  // of L (written to P by lane c in earlier steps) is read back by broadcast,
+  // and every lane forms the pivot L_cc^2 = A_cc - sum_p L_cp^2 itself.  The
+  // reads of a step precede its write in program order, and the wave's LDS
+  // operations execute in that order.  Lanes 32..63 mirror lanes 0..31.
   const int r = lane & 31;
+  double a[PW];
 #pragma unroll
-  for (int j = 0; j < PW; ++j) a[j] = (j <= r) ? P[r * PLD + j] : 0.0;
+  for (int j = 0; j < PW; ++j) a[j] = P[r * PLD + j];
   int bad = -1;
 #pragma unroll
   for (int c = 0; c < PW; ++c) {
-    const double d = lane_bcast(a[c], c);
-    if (bad < 0 && (!(d > 0.0) || !isfinite(d))) bad = c;
-    const double ljj = sqrt(d);
-    a[c] = (r > c) ? a[c] / ljj : ((r == c) ? ljj : 0.0);
+    double s0 = 0.0, s1 = 0.0, q0 = 0.0, q1 = 0.0;
 #pragma unroll
-    for (int j = c + 1; j < PW; ++j) {
-      const double ljc = lane_bcast(a[c], j);
-      a[j] -= a[c] * ljc;
+    for (int p = 0; p < c; ++p) {
+      const double m = P[c * PLD + p];
+      if (p & 1) {
+        s1 = fma(a[p], m, s1);
+        q1 = fma(m, m, q1);
+      } else {
+        s0 = fma(a[p], m, s0);
+        q0 = fma(m, m, q0);
+      }
     }
+    const double d = P[c * PLD + c] - (q0 + q1);
+    bad = (bad < 0 && (!(d > 0.0) || !isfinite(d))) ? c : bad;
+    const double rs = rsqrt_nr(d);  // 1 / L_cc
+    const double v = (r > c) ? (a[c] - (s0 + s1)) * rs : ((r == c) ? d * rs : 0.0);
+    a[c] = v;
+    __builtin_amdgcn_wave_barrier();
+    P[r * PLD + c] = v;
+    if (r == c) rdiag[c] = rs;
+    __builtin_amdgcn_wave_barrier();
   }
-  // inverse: lane c solves L z = e_c
+  // inverse: lane r solves L z = e_r, rows of L broadcast from P
   double z[PW];
 #pragma unroll
   for (int i = 0; i < PW; ++i) {
     double v = (i == r) ? 1.0 : 0.0;
 #pragma unroll
-    for (int q = 0; q < i; ++q) v -= lane_bcast(a[q], i) * z[q];
-    z[i] = v / lane_bcast(a[i], i);
+    for (int q = 0; q < i; ++q) v -= P[i * PLD + q] * z[q];
+    z[i] = v * rdiag[i];
   }
   if (lane < PW) {
 #pragma unroll
-    for (int j = 0; j < PW; ++j) {
-      P[r * PLD + j] = (j <= r) ? a[j] : 0.0;
-      Z[j * PLD + r] = z[j];
-    }
+    for (int j = 0; j < PW; ++j) Z[j * PLD + r] = z[j];
   }
   return bad;
 }
 
 template <int NB>
-constexpr int potrf_lds() { return NB * PLD + PW * PLD; }
+constexpr int potrf_lds() { return 2 * NB * PLD + PW * PLD + PW; }
 
+// POTRF of one diagonal tile, left-looking over 32-column panels.  A panel
+// (rows j0.., 32 columns) is loaded into LDS in bulk; the columns already
+// factored are streamed in 32-column slabs (bulk load, next slab prefetched
+// in registers) and applied with MFMA, accumulators in registers; the 32 x 32
+// diagonal block is factored and inverted by one wave; the rows below are
+// multiplied by that inverse on MFMA; the panel is written back once.
 template <int NB>
 __device__ __forceinline__ void dev_potrf(int32_t k, double* __restrict__ S,
                                           double* __restrict__ dinv_m, int32_t* __restrict__ inf,
                                           int32_t nreal, double* smem) {
   double* P = smem;
-  double* Z = smem + NB * PLD;
+  double* Sl = smem + NB * PLD;
+  double* Z = Sl + NB * PLD;
+  double* rdiag = Z + PW * PLD;
   double* A = S + (int64_t)k * NB * NB;
   double* dinv = dinv_m + (int64_t)k * NB * PW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int PER = NB * PW / 256;            // elements per thread of a full-height panel
+  constexpr int RBW = NB >= 64 ? NB / 64 : 1;  // row blocks per wave at most
   for (int j0 = 0; j0 < NB; j0 += PW) {
-    const int pr = NB - j0;  // panel rows j0..NB-1
-    for (int x = tid; x < pr * PW; x += 256) {
-      const int r = x / PW, c = x % PW;
-      P[r * PLD + c] = A[(int64_t)(j0 + r) * NB + j0 + c];
+    const int pr = NB - j0;
+    // panel load: every lane loads (clamped rows); rows past pr land in LDS
+    // rows nobody reads
+    {
+      double v[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int x = q * 256 + tid, rr = min(x / PW, pr - 1), c = x % PW;
+        v[q] = A[(int64_t)(j0 + rr) * NB + j0 + c];
+      }
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int x = q * 256 + tid;
+        P[(x / PW) * PLD + x % PW] = v[q];
+      }
+    }
+    if (j0 > 0) {
+      // P -= L[j0:, :j0] L[j0:j0+32, :j0]^T: 32-column slabs of the factored
+      // columns staged through LDS (bulk load, next slab prefetched in
+      // registers), MFMA with accumulators in registers
+      d4 acc[RBW][2];
+#pragma unroll
+      for (int i = 0; i < RBW; ++i) acc[i][0] = acc[i][1] = d4{0.0, 0.0, 0.0, 0.0};
+      double v[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int x = q * 256 + tid, rr = min(x / PW, pr - 1), c = x % PW;
+        v[q] = A[(int64_t)(j0 + rr) * NB + c];
+      }
+      for (int s0 = 0; s0 < j0; s0 += PW) {
+        __syncthreads();  // previous slab fully consumed
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const int x = q * 256 + tid;
+          Sl[(x / PW) * PLD + x % PW] = v[q];
+        }
+        __syncthreads();
+        if (s0 + PW < j0) {
+#pragma unroll
+          for (int q = 0; q < PER; ++q) {
+            const int x = q * 256 + tid, rr = min(x / PW, pr - 1), c = x % PW;
+            v[q] = A[(int64_t)(j0 + rr) * NB + s0 + PW + c];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < RBW; ++i) {
+          const int t = wave + 4 * i;
+          if (t < pr / 16) {
+            const double* pa = Sl + (t * 16 + (lane & 15)) * PLD + (lane >> 4);
+            const double* pb0 = Sl + (lane & 15) * PLD + (lane >> 4);
+            const double* pb1 = Sl + (16 + (lane & 15)) * PLD + (lane >> 4);
+#pragma unroll
+            for (int kk = 0; kk < PW; kk += 4) {
+              acc[i][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[kk], pb0[kk], acc[i][0], 0, 0, 0);
+              acc[i][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[kk], pb1[kk], acc[i][1], 0, 0, 0);
+            }
+          }
+        }
+      }
+      __syncthreads();  // P fully loaded before the accumulated update lands
+#pragma unroll
+      for (int i = 0; i < RBW; ++i) {
+        const int t = wave + 4 * i;
+        if (t < pr / 16) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            double* row = P + (t * 16 + (lane >> 4) + 4 * e) * PLD;
+            row[lane & 15] -= acc[i][0][e];
+            row[16 + (lane & 15)] -= acc[i][1][e];
+          }
+        }
+      }
     }
     __syncthreads();
     if (wave == 0) {
-      const int bad = chol32_wave(P, Z, lane);
+      const int bad = chol32_wave(P, Z, rdiag, lane);
       if (lane == 0 && bad >= 0 && k * NB + j0 + bad < nreal) atomicMin(inf, k * NB + j0 + bad + 1);
     }
     __syncthreads();
     // rows below the diagonal block: P_below <- P_below inv(L_top)^T on MFMA;
     // each wave owns whole 16-row blocks, reads them fully, then overwrites
-    const int rb = (pr - PW) / 16;
-    for (int t = wave; t < rb; t += 4) {
+    for (int t = wave; t < (pr - PW) / 16; t += 4) {
       d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
       const double* pa = P + (PW + t * 16 + (lane & 15)) * PLD + (lane >> 4);
       const double* z0 = Z + (lane & 15) * PLD + (lane >> 4);
@@ -257,32 +535,10 @@ __device__ __forceinline__ void dev_potrf(int32_t k, double* __restrict__ S,
     }
     for (int x = tid; x < PW * PW; x += 256) dinv[(j0 / PW) * PW * PW + x] = Z[(x / PW) * PLD + x % PW];
     __syncthreads();
-    // write the panel back (lower part of its diagonal block)
-    for (int x = tid; x < pr * PW; x += 256) {
-      const int r = x / PW, c = x % PW;
-      if (c <= r || r >= PW) A[(int64_t)(j0 + r) * NB + j0 + c] = P[r * PLD + c];
-    }
-    // trailing update A[j0+32:, j0+32:] -= P[32:] P[32:]^T, lower 16 x 16
-    // tiles distributed over the four waves
-    const int tr = (NB - j0 - PW) / 16;
-    const int ntile = tr * (tr + 1) / 2;
-    for (int t = wave; t < ntile; t += 4) {
-      int ti = 0, rem = t;
-      while (rem > ti) {
-        rem -= ti + 1;
-        ++ti;
-      }
-      const int tj = rem;
-      d4 acc = {0.0, 0.0, 0.0, 0.0};
-      const double* pa = P + (PW + ti * 16 + (lane & 15)) * PLD + (lane >> 4);
-      const double* pb = P + (PW + tj * 16 + (lane & 15)) * PLD + (lane >> 4);
 #pragma unroll
-      for (int kk = 0; kk < PW; kk += 4)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[kk], pb[kk], acc, 0, 0, 0);
-      const int gi = j0 + PW + ti * 16 + (lane >> 4), gj = j0 + PW + tj * 16 + (lane & 15);
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (ti != tj || gj <= gi + 4 * e) A[(int64_t)(gi + 4 * e) * NB + gj] -= acc[e];
+    for (int q = 0; q < PER; ++q) {
+      const int x = q * 256 + tid, r = x / PW, c = x % PW;
+      if (r < pr && (c <= r || r >= PW)) A[(int64_t)(j0 + r) * NB + j0 + c] = P[r * PLD + c];
     }
     __syncthreads();
   }
@@ -294,18 +550,22 @@ __device__ __forceinline__ void dev_potrf(int32_t k, double* __restrict__ S,
 // ---------------------------------------------------------------------------
 
 constexpr int TR = 32;
-constexpr int TLD = 4;  // row padding of the LDS copy
+constexpr int TLD = 4;  // row padding of the LDS copies
 
 template <int NB>
-constexpr int trsm_lds() { return TR * (NB + TLD); }
+constexpr int trsm_lds() { return TR * (NB + TLD) + PW * (NB + TLD); }
 
+// X and the 32 rows of L that a block needs sit in LDS; every global read is
+// issued in bulk with clamped addresses.
 template <int NB>
 __device__ __forceinline__ void dev_trsm(int32_t it, const int32_t* __restrict__ items,
                                          const TrsmTaskD* __restrict__ tasks,
                                          double* __restrict__ S,
                                          const double* __restrict__ dinv_m, double* smem) {
   constexpr int XLD = NB + TLD;
+  constexpr int PER = TR * NB / 256;
   double* X = smem;
+  double* Lr = smem + TR * XLD;
   const TrsmTaskD t = tasks[items[2 * it]];
   const int32_t rb = items[2 * it + 1];
   const int32_t r0 = rb * TR;
@@ -314,17 +574,41 @@ __device__ __forceinline__ void dev_trsm(int32_t it, const int32_t* __restrict__
   const double* L = S + t.l_off;
   const double* dinv = dinv_m + (int64_t)t.k * NB * PW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int x = tid; x < TR * NB; x += 256) {
-    const int r = x / NB, c = x % NB;
-    X[r * XLD + c] = r < nr ? Xg[x] : 0.0;
+  {
+    double v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int x = q * 256 + tid, rr = min(x / NB, nr - 1);
+      v[q] = Xg[(int64_t)rr * NB + x % NB];
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int x = q * 256 + tid;
+      X[(x / NB) * XLD + x % NB] = (x / NB) < nr ? v[q] : 0.0;
+    }
   }
-  __syncthreads();
   // each wave owns one 16 x 16 tile of the 32 x 32 block column
   const int wr = (wave >> 1) * 16, wc = (wave & 1) * 16;
   for (int j0 = 0; j0 < NB; j0 += PW) {
+    // rows j0..j0+31 of L, columns 0..j0-1, staged in LDS (columns past j0
+    // are loaded clamped and never read)
+    if (j0 > 0) {
+      double v[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int x = q * 256 + tid, r = x / NB, c = min(x % NB, j0 - 1);
+        v[q] = L[(int64_t)(j0 + r) * NB + c];
+      }
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int x = q * 256 + tid;
+        Lr[(x / NB) * XLD + x % NB] = v[q];
+      }
+    }
+    __syncthreads();
     d4 acc = {0.0, 0.0, 0.0, 0.0};
     const double* xa = X + (wr + (lane & 15)) * XLD + (lane >> 4);
-    const double* lb = L + (int64_t)(j0 + wc + (lane & 15)) * NB + (lane >> 4);
+    const double* lb = Lr + (wc + (lane & 15)) * XLD + (lane >> 4);
     for (int kk = 0; kk < j0; kk += 4)
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[kk], lb[kk], acc, 0, 0, 0);
     // Y = X_J - acc, kept in registers until every wave has read X_<J
@@ -340,15 +624,22 @@ __device__ __forceinline__ void dev_trsm(int32_t it, const int32_t* __restrict__
     d4 z = {0.0, 0.0, 0.0, 0.0};
     const double* ya = X + (wr + (lane & 15)) * XLD + j0 + (lane >> 4);
     const double* db = dinv + (j0 / PW) * PW * PW + (wc + (lane & 15)) * PW + (lane >> 4);
+    double dz[PW / 4];
 #pragma unroll
-    for (int kk = 0; kk < PW; kk += 4)
-      z = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[kk], db[kk], z, 0, 0, 0);
+    for (int q = 0; q < PW / 4; ++q) dz[q] = db[4 * q];
+#pragma unroll
+    for (int q = 0; q < PW / 4; ++q)
+      z = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[4 * q], dz[q], z, 0, 0, 0);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 4; ++e) X[(wr + (lane >> 4) + 4 * e) * XLD + j0 + wc + (lane & 15)] = z[e];
     __syncthreads();
   }
-  for (int x = tid; x < nr * NB; x += 256) Xg[x] = X[(x / NB) * XLD + x % NB];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int x = q * 256 + tid;
+    if ((x / NB) < nr) Xg[x] = X[(x / NB) * XLD + x % NB];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -360,9 +651,12 @@ __device__ __forceinline__ void dev_trsm(int32_t it, const int32_t* __restrict__
 
 struct LevelArgs {
   const int32_t* potrf;   // block columns
-  const int32_t* upd;     // triples
+  const int32_t* big;     // quads: task, block row, block col, part (128 blocks)
+  const int32_t* upd;     // quads (64 blocks)
   const int32_t* trsm;    // pairs
-  int32_t np, nu, nt;
+  int32_t np, nbig, nu, nt;
+  double* parts;          // partial-sum slots
+  int64_t pstride;
   const UpdTaskD* utasks;
   const ContribD* contribs;
   const int32_t* maps;
@@ -375,24 +669,53 @@ struct LevelArgs {
   int32_t nreal;
 };
 
-template <int NB>
+// HAS_P / HAS_G compile the POTRF and 128-block paths in or out, so a level
+// without them keeps the smaller register footprint of the remaining paths
+template <int NB, bool HAS_P, bool HAS_G>
 __global__ __launch_bounds__(256) void k_level(LevelArgs a) {
   extern __shared__ double smem[];
   const int32_t member = blockIdx.y;
   double* S = a.store + (int64_t)member * a.mstride;
   int32_t b = blockIdx.x;
-  if (b < a.np) {
+  if (HAS_P && b < a.np) {
     dev_potrf<NB>(a.potrf[b], S, a.dinv + (int64_t)member * a.dstride, a.info + member, a.nreal,
                   smem);
     return;
   }
   b -= a.np;
+  double* parts = a.parts + (int64_t)member * a.pstride;
+  if (HAS_G && b < a.nbig) {
+    if constexpr (NB >= UB2 && HAS_G) dev_update_big<NB>(b, a.big, a.utasks, a.contribs, a.maps, S, parts, smem);
+    return;
+  }
+  b -= a.nbig;
   if (b < a.nu) {
-    dev_update<NB>(b, a.upd, a.utasks, a.contribs, a.maps, S, smem);
+    dev_update<NB>(b, a.upd, a.utasks, a.contribs, a.maps, S, parts, smem);
     return;
   }
   b -= a.nu;
   dev_trsm<NB>(b, a.trsm, a.ttasks, S, a.dinv + (int64_t)member * a.dstride, smem);
+}
+
+// ---------------------------------------------------------------------------
+// measurement: FP64 MFMA issue rate with operands in registers, 16
+// independent accumulators per wave, no memory traffic in the loop
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_mfma_issue(double* __restrict__ out, int32_t iters, double seed) {
+  const int lane = threadIdx.x & 63;
+  double a = seed + lane * 1e-3, b = seed - lane * 1e-3;
+  d4 acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int32_t it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) s += acc[q][0] + acc[q][1] + acc[q][2] + acc[q][3];
+  if (s == 12345.678) out[blockIdx.x] = s;  // keeps the loop alive
 }
 
 // ---------------------------------------------------------------------------

@@ -45,7 +45,7 @@ constexpr int32_t kMaxRhs = 64;
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct LevelOffsets {
-  int32_t u_off, u_cnt, p_off, p_cnt, t_off, t_cnt;
+  int32_t u_off, u_cnt, g_off, g_cnt, p_off, p_cnt, t_off, t_cnt;
 };
 
 }  // namespace
@@ -55,7 +55,7 @@ struct stc_handle {
   Plan plan;
   std::vector<LevelOffsets> lv;
   // flattened level work lists (host)
-  std::vector<int32_t> upd_items, potrf_list, trsm_items;
+  std::vector<int32_t> upd_items, big_items, potrf_list, trsm_items;
   // binding
   int device = -1;
   char* ws = nullptr;
@@ -70,6 +70,8 @@ struct stc_handle {
   ContribD* d_contrib = nullptr;
   TrsmTaskD* d_trsm = nullptr;
   int32_t* d_upd_items = nullptr;
+  int32_t* d_big_items = nullptr;
+  double* d_parts = nullptr;  // partial-sum slots, per member
   int32_t* d_potrf = nullptr;
   int32_t* d_trsm_items = nullptr;
   int32_t* d_perm = nullptr;
@@ -111,6 +113,7 @@ size_t layout(const stc_handle* hc, int32_t batch, char* base) {
   take(&h->d_contrib, sizeof(ContribD) * p.contribs.size());
   take(&h->d_trsm, sizeof(TrsmTaskD) * p.trsm.size());
   take(&h->d_upd_items, sizeof(int32_t) * h->upd_items.size());
+  take(&h->d_big_items, sizeof(int32_t) * h->big_items.size());
   take(&h->d_potrf, sizeof(int32_t) * h->potrf_list.size());
   take(&h->d_trsm_items, sizeof(int32_t) * h->trsm_items.size());
   take(&h->d_perm, sizeof(int32_t) * (size_t)s.n);
@@ -126,6 +129,7 @@ size_t layout(const stc_handle* hc, int32_t batch, char* base) {
   take(&h->d_ld, sizeof(double) * (size_t)batch);
   take(&h->d_y, sizeof(double) * (size_t)padded_n(h) * kMaxRhs);
   take(&h->d_dinv, sizeof(double) * (size_t)dinv_stride(h) * (size_t)batch);
+  take(&h->d_parts, sizeof(double) * (size_t)p.parts * (size_t)batch);
   take(&h->d_store, sizeof(double) * (size_t)p.store * (size_t)batch);
   return off;
 }
@@ -172,23 +176,37 @@ int launch_levels_nb(stc_handle* h, int32_t members, hipStream_t st, Prof* prof)
   a.dstride = dinv_stride(h);
   a.info = h->d_info;
   a.nreal = (int32_t)h->sym.n;
+  a.parts = h->d_parts;
+  a.pstride = h->plan.parts;
   hipEvent_t ev = nullptr;
   for (const LevelOffsets& L : h->lv) {
-    const int32_t total = L.p_cnt + L.u_cnt + L.t_cnt;
+    const int32_t total = L.p_cnt + L.g_cnt + L.u_cnt + L.t_cnt;
     if (!total) continue;
     a.potrf = h->d_potrf + L.p_off;
-    a.upd = h->d_upd_items + 3 * (int64_t)L.u_off;
+    a.big = h->d_big_items + 4 * (int64_t)L.g_off;
+    a.upd = h->d_upd_items + 4 * (int64_t)L.u_off;
     a.trsm = h->d_trsm_items + 2 * (int64_t)L.t_off;
     a.np = L.p_cnt;
+    a.nbig = L.g_cnt;
     a.nu = L.u_cnt;
     a.nt = L.t_cnt;
     int lds = 0;
     if (L.p_cnt) lds = std::max(lds, potrf_lds<NB>());
+    if (L.g_cnt) lds = std::max(lds, UPD2_LDS);
     if (L.u_cnt) lds = std::max(lds, UPD_LDS);
     if (L.t_cnt) lds = std::max(lds, trsm_lds<NB>());
-    const int kind = L.p_cnt ? kKindPotrf : (L.u_cnt ? kKindUpdate : kKindTrsm);
+    const int kind = L.p_cnt ? kKindPotrf : ((L.u_cnt || L.g_cnt) ? kKindUpdate : kKindTrsm);
     if (prof && prof->begin(st, &ev)) return STC_ERR_HIP;
-    hipLaunchKernelGGL(k_level<NB>, dim3(total, members), dim3(256), sizeof(double) * lds, st, a);
+    const dim3 grid(total, members);
+    const size_t shm = sizeof(double) * lds;
+    if (L.p_cnt && L.g_cnt)
+      hipLaunchKernelGGL((k_level<NB, true, true>), grid, dim3(256), shm, st, a);
+    else if (L.p_cnt)
+      hipLaunchKernelGGL((k_level<NB, true, false>), grid, dim3(256), shm, st, a);
+    else if (L.g_cnt)
+      hipLaunchKernelGGL((k_level<NB, false, true>), grid, dim3(256), shm, st, a);
+    else
+      hipLaunchKernelGGL((k_level<NB, false, false>), grid, dim3(256), shm, st, a);
     if (prof && prof->end(kind, st, ev)) return STC_ERR_HIP;
   }
   HIPCHK(hipGetLastError());
@@ -312,9 +330,12 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
     // flatten the level lists
     for (const Level& L : h->plan.levels) {
       LevelOffsets x;
-      x.u_off = (int32_t)(h->upd_items.size() / 3);
-      x.u_cnt = (int32_t)(L.upd_items.size() / 3);
+      x.u_off = (int32_t)(h->upd_items.size() / 4);
+      x.u_cnt = (int32_t)(L.upd_items.size() / 4);
       h->upd_items.insert(h->upd_items.end(), L.upd_items.begin(), L.upd_items.end());
+      x.g_off = (int32_t)(h->big_items.size() / 4);
+      x.g_cnt = (int32_t)(L.big_items.size() / 4);
+      h->big_items.insert(h->big_items.end(), L.big_items.begin(), L.big_items.end());
       x.p_off = (int32_t)h->potrf_list.size();
       x.p_cnt = (int32_t)L.potrf.size();
       h->potrf_list.insert(h->potrf_list.end(), L.potrf.begin(), L.potrf.end());
@@ -357,8 +378,11 @@ int stc_bind(stc_handle* h, void* d_ws, size_t bytes, int32_t batch, void* strea
   const Plan& p = h->plan;
   const Symbolic& s = h->sym;
   std::vector<UpdTaskD> upd(p.upd.size());
-  for (size_t i = 0; i < upd.size(); ++i)
-    upd[i] = UpdTaskD{p.upd[i].c_off, p.upd[i].c_rows, p.upd[i].diag, p.upd[i].c_begin, p.upd[i].c_end};
+  for (size_t i = 0; i < upd.size(); ++i) {
+    const UpdTask& u = p.upd[i];
+    upd[i] = UpdTaskD{u.c_off, u.part_off, u.in_part_off, u.c_rows, u.diag, u.c_begin, u.c_end,
+                      u.nsplit, u.in_npart};
+  }
   std::vector<ContribD> con(p.contribs.size());
   for (size_t i = 0; i < con.size(); ++i) {
     const Contrib& c = p.contribs[i];
@@ -374,6 +398,7 @@ int stc_bind(stc_handle* h, void* d_ws, size_t bytes, int32_t batch, void* strea
   if ((rc = upload(h->d_vmap, p.vmap)) || (rc = upload(h->d_maps, p.maps)) ||
       (rc = upload(h->d_upd, upd)) || (rc = upload(h->d_contrib, con)) ||
       (rc = upload(h->d_trsm, tr)) || (rc = upload(h->d_upd_items, h->upd_items)) ||
+      (rc = upload(h->d_big_items, h->big_items)) ||
       (rc = upload(h->d_potrf, h->potrf_list)) || (rc = upload(h->d_trsm_items, h->trsm_items)) ||
       (rc = upload(h->d_perm, s.perm)) || (rc = upload(h->d_tiles, tl)) ||
       (rc = upload(h->d_rows, s.rows)) || (rc = upload(h->d_row_ptr, p.row_tiles_ptr)) ||
@@ -604,6 +629,32 @@ int stc_profile_factorize(stc_handle* h, const double* d_values, void* stream, d
   if (rc) return rc;
   h->last_stream = st;
   h->factored = true;
+  return 0;
+}
+
+int stc_fp64_mfma_peak(void* stream, double* tflops) {
+  if (!tflops) return fail(STC_ERR_ARG, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  int dev = 0, cus = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int blocks = cus * 8;
+  const int32_t iters = 2000;
+  double* scratch = nullptr;  // never written (the guard in the kernel is false)
+  hipEvent_t a, b;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  hipLaunchKernelGGL(k_mfma_issue, dim3(blocks), dim3(256), 0, st, scratch, iters, 1.0);
+  HIPCHK(hipEventRecord(a, st));
+  hipLaunchKernelGGL(k_mfma_issue, dim3(blocks), dim3(256), 0, st, scratch, iters, 1.0);
+  HIPCHK(hipEventRecord(b, st));
+  HIPCHK(hipEventSynchronize(b));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  const double flops = (double)blocks * 4 /* waves */ * iters * 16 * (16.0 * 16 * 4 * 2);
+  *tflops = flops / (ms * 1e-3) / 1e12;
   return 0;
 }
 

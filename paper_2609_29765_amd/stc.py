@@ -31,7 +31,7 @@ EXPORTS = [
     "stc_analyse", "stc_workspace_bytes", "stc_bind", "stc_factorize", "stc_factorize_batched",
     "stc_logdet", "stc_solve", "stc_logdet_backward", "stc_info", "stc_get_sizes",
     "stc_get_features", "stc_get_perm", "stc_get_etree", "stc_get_L_pattern", "stc_get_tiles",
-    "stc_get_tasks", "stc_get_factor", "stc_get_work", "stc_profile_factorize", "stc_destroy",
+    "stc_get_tasks", "stc_get_factor", "stc_get_work", "stc_profile_factorize", "stc_fp64_mfma_peak", "stc_destroy",
     "stc_last_error",
 ]
 
@@ -77,6 +77,7 @@ def lib():
     L.stc_get_factor.argtypes = [vp, _f64p, vp]
     L.stc_get_work.argtypes = [vp, _f64p]
     L.stc_profile_factorize.argtypes = [vp, vp, vp, _f64p, _i64p]
+    L.stc_fp64_mfma_peak.argtypes = [vp, _f64p]
     L.stc_destroy.argtypes = [vp]
     L.stc_destroy.restype = None
     L.stc_last_error.restype = C.c_char_p
@@ -278,6 +279,13 @@ class Analysis:
         Lx = np.zeros(self.lnz)
         _check(lib().stc_get_factor(self._h, Lx, _stream_ptr()))
         return Lx
+
+
+def fp64_mfma_peak():
+    """Measured FP64 MFMA issue rate of the current device, TFLOP/s."""
+    out = np.zeros(1)
+    _check(lib().stc_fp64_mfma_peak(_stream_ptr(), out))
+    return float(out[0])
 
 
 def _make_logdet_function():

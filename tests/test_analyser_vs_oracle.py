@@ -93,7 +93,7 @@ def test_bad_options():
 
 def test_abi_exports_every_declared_symbol():
     hdr = open(os.path.join(ROOT, "include", "stc.h")).read()
-    declared = set(re.findall(r"\b(stc_[A-Za-z_]+)\s*\(", hdr))
+    declared = set(re.findall(r"\b(stc_[A-Za-z0-9_]+)\s*\(", hdr))
     lib = S.lib()
     for name in declared:
         assert hasattr(lib, name), name
