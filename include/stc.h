@@ -127,11 +127,18 @@ int stc_logdet(stc_handle* h, double* d_out, void* stream);
    double[n * nrhs], column-major, original numbering, 1 <= nrhs <= 64. */
 int stc_solve(stc_handle* h, double* d_b, int32_t nrhs, void* stream);
 
-/* Reverse mode of logdet through the last single factorization: given the
-   scalar cotangent d_gbar (device) double[1], writes d_grad_values (device)
-   double[nnz] in the analysed CSC entry order, the symmetric matrix being
-   parameterised by its lower triangle: gbar * 2 (A^-1)_ij off the diagonal
-   and gbar * (A^-1)_ii on it. */
+/* Reverse mode of logdet through the last single factorization (the
+   differentiable factorization of Sec. 6.8): given the scalar cotangent d_gbar
+   (device) double[1], writes d_grad_values (device) double[nnz] in the
+   analysed CSC entry order, the symmetric matrix being parameterised by its
+   lower triangle: gbar * 2 (A^-1)_ij off the diagonal and gbar * (A^-1)_ii on
+   it.  For this cotangent the adjoint of the tile Cholesky restricted to the
+   pattern of L is the selected inverse Z = A^-1 on that pattern, computed on
+   the device by the blocked Takahashi recurrence over the tile DAG in reverse
+   order (one graph launch), from the factor and the 32 x 32 diagonal-block
+   inverses the factorization left in the workspace.  Writes NaN everywhere
+   when that factorization failed (stc_info != 0).  Overwrites the workspace's
+   selected-inverse scratch; the factor is left intact. */
 int stc_logdet_backward(stc_handle* h, const double* d_gbar, double* d_grad_values, void* stream);
 
 /* Status of the last single factorization; synchronizes the bound stream.
@@ -160,14 +167,17 @@ int stc_get_tasks(const stc_handle* h, int32_t* tasks); /* int32[ntasks][4]: op,
    (h_Lx double[nnz(L)]); synchronizes the stream. */
 int stc_get_factor(stc_handle* h, double* h_Lx, void* stream);
 
-/* Static work of one factorization with this plan (host) double[8]:
+/* Static work of one factorization with this plan (host) double[10]:
    [0] tile-algorithmic flops of the SYRK+GEMM updates: sum |R_kn|^2 n_b over
        SYRK tasks + sum 2 |R_mn| |R_kn| n_b over GEMM tasks (Algorithm 1's
        tasks on the stored active rows, Sec. 5.2); [1] POTRF flops sum h^3/3;
    [2] TRSM flops sum |R_mk| n_b^2; [3] their total; [4] exact Cholesky flops
    sum_j c_j^2 (c_j = entries of column j of L); [5] update bytes: operand
    rows read per task plus every output tile read and written once; [6] value
-   load bytes: 20 per input entry plus 8 per stored double; [7] levels. */
+   load bytes: 20 per input entry plus 8 per stored double; [7] levels;
+   [8] flops of stc_logdet_backward (tile products of the selected-inverse
+   recurrence, 2 per multiply-add); [9] its levels (kernel launches after the
+   diagonal-tile inverses). */
 int stc_get_work(const stc_handle* h, double* work);
 
 /* Measurement helper: one factorization of d_values (device) double[nnz]

@@ -837,4 +837,169 @@ int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why) {
   return 0;
 }
 
+
+// ---------------------------------------------------------------------------
+// backward plan
+// ---------------------------------------------------------------------------
+
+int build_backward(const Symbolic& s, Plan* p, BackPlan* b, std::string* why) {
+  (void)why;
+  *b = BackPlan();
+  const int32_t nb = s.nb, NT = s.NT;
+  const int64_t ntiles = (int64_t)s.tiles.size();
+  enum { BUF_L = 0, BUF_Z = 1, BUF_G = 2, BUF_M = 3 };
+  enum { NORMAL = 0, TRANS = 1, SYM = 2 };
+  std::vector<int64_t> col_first((size_t)NT + 1, 0);
+  for (const TileInfo& t : s.tiles) col_first[t.k + 1]++;
+  for (int32_t k = 0; k < NT; ++k) col_first[k + 1] += col_first[k];
+  auto find_tile = [&](int32_t m, int32_t k) -> int64_t {
+    int64_t lo = col_first[k], hi = col_first[k + 1];
+    while (lo < hi) {
+      int64_t mid = (lo + hi) / 2;
+      if (s.tiles[mid].m < m) lo = mid + 1; else hi = mid;
+    }
+    return (lo < col_first[k + 1] && s.tiles[lo].m == m) ? lo : -1;
+  };
+  // per tile: its active rows (local to block m) in the map pool, or -1 when
+  // they are 0..n_b-1
+  std::vector<int32_t> rows_of((size_t)ntiles, -1);
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const TileInfo& ti = s.tiles[t];
+    if (ti.cnt == nb) continue;
+    rows_of[t] = (int32_t)p->maps.size();
+    p->maps.insert(p->maps.end(), s.rows.begin() + ti.roff, s.rows.begin() + ti.roff + ti.cnt);
+  }
+  std::vector<int32_t> pos((size_t)nb);
+  auto set_pos = [&](int64_t t) {  // pos[local row] = position in tile t, or -1
+    std::fill(pos.begin(), pos.end(), -1);
+    const TileInfo& ti = s.tiles[t];
+    for (int32_t r = 0; r < ti.cnt; ++r) pos[s.rows[ti.roff + r]] = r;
+  };
+  auto diag_off = [&](int32_t k) { return (int64_t)k * nb * nb; };
+  int32_t nlev = 2;
+  b->level_items.resize(2);
+  auto add_task = [&](int32_t level, const ConTask& t) {
+    if ((int32_t)b->level_items.size() <= level) b->level_items.resize((size_t)level + 1);
+    nlev = std::max(nlev, level + 1);
+    const int32_t id = (int32_t)b->tasks.size();
+    b->tasks.push_back(t);
+    const int32_t nbr = (t.c_rows + 63) / 64, nbc = (t.ncols + 63) / 64;
+    for (int32_t x = 0; x < nbr; ++x)
+      for (int32_t y = 0; y < nbc; ++y) {
+        if (t.diag && y > x) continue;
+        b->level_items[(size_t)level].push_back(id);
+        b->level_items[(size_t)level].push_back(x);
+        b->level_items[(size_t)level].push_back(y);
+      }
+  };
+  auto new_task = [&](int64_t c_off, int32_t c_buf, int32_t rows, int32_t cols, int32_t diag,
+                      int32_t beta, double alpha) {
+    ConTask t{c_off, c_buf, rows, cols, diag, (int32_t)b->terms.size(), 0, beta, alpha};
+    return t;
+  };
+  // level 0: G_k = L_kk^-1 by block columns of 32
+  for (int32_t k = 0; k < NT; ++k)
+    for (int32_t J = 0; J < nb / 32; ++J) {
+      b->trtri_items.push_back(k);
+      b->trtri_items.push_back(J);
+    }
+  // level 1: M_mk = L_mk G_k, and H_k = G_k^T G_k into the diagonal Z tiles
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const TileInfo& ti = s.tiles[t];
+    ConTask task = new_task(p->tile_off[t], BUF_M, ti.cnt, nb, 0, 0, 1.0);
+    b->terms.push_back(ConTerm{p->tile_off[t], diag_off(ti.k), BUF_L, NORMAL, -1, -1, BUF_G, -1, nb});
+    task.t_end = (int32_t)b->terms.size();
+    add_task(1, task);
+    b->flops += 2.0 * ti.cnt * nb * nb;
+  }
+  for (int32_t k = 0; k < NT; ++k) {
+    ConTask task = new_task(diag_off(k), BUF_Z, p->diag_h[k], p->diag_h[k], 1, 0, 1.0);
+    b->terms.push_back(ConTerm{diag_off(k), diag_off(k), BUF_G, TRANS, -1, -1, BUF_G, -1, nb});
+    task.t_end = (int32_t)b->terms.size();
+    add_task(1, task);
+    b->flops += (double)nb * nb * nb;
+  }
+  // block columns in descending order; a task's level follows the Z tiles it
+  // reads
+  std::vector<int32_t> zlev_tile((size_t)ntiles, 1), zlev_diag((size_t)NT, 1);
+  for (int32_t k = NT - 1; k >= 0; --k) {
+    const int64_t c0 = col_first[k], c1 = col_first[k + 1];
+    for (int64_t ti = c0; ti < c1; ++ti) {
+      const TileInfo& to = s.tiles[ti];
+      const int32_t i = to.m;
+      ConTask task = new_task(p->tile_off[ti], BUF_Z, to.cnt, nb, 0, 0, -1.0);
+      int32_t lv = 2;
+      for (int64_t tm = c0; tm < c1; ++tm) {
+        const TileInfo& tb = s.tiles[tm];
+        const int32_t m = tb.m;
+        // contraction index: the K = cnt(m,k) active rows q of tile (m,k)
+        ConTerm c{};
+        c.b_buf = BUF_M;
+        c.b_off = p->tile_off[tm];
+        c.b_qmap = -1;
+        c.K = tb.cnt;
+        c.a_buf = BUF_Z;
+        if (m < i) {  // Z_im = stored tile (i,m): [row of (i,m), q]
+          const int64_t tim = find_tile(i, m);
+          if (tim < 0) continue;  // no entry of L couples the two blocks
+          const TileInfo& ta = s.tiles[tim];
+          c.a_off = p->tile_off[tim];
+          c.a_mode = NORMAL;
+          c.a_qmap = rows_of[tm];
+          const bool same = to.cnt == ta.cnt &&
+                            std::equal(s.rows.begin() + to.roff,
+                                       s.rows.begin() + to.roff + to.cnt, s.rows.begin() + ta.roff);
+          if (same) {
+            c.a_rmap = -1;
+          } else {
+            set_pos(tim);
+            c.a_rmap = (int32_t)p->maps.size();
+            for (int32_t r = 0; r < to.cnt; ++r) p->maps.push_back(pos[s.rows[to.roff + r]]);
+          }
+          lv = std::max(lv, zlev_tile[tim] + 1);
+        } else if (m == i) {  // Z_ii, symmetric, lower triangle stored
+          c.a_off = diag_off(i);
+          c.a_mode = SYM;
+          c.a_rmap = rows_of[ti];
+          c.a_qmap = rows_of[tm];
+          lv = std::max(lv, zlev_diag[i] + 1);
+        } else {  // Z_im = (stored tile (m,i))^T: [row of (m,i) for q, column r]
+          const int64_t tmi = find_tile(m, i);
+          if (tmi < 0) continue;
+          c.a_off = p->tile_off[tmi];
+          c.a_mode = TRANS;
+          c.a_rmap = rows_of[ti];
+          set_pos(tmi);
+          c.a_qmap = (int32_t)p->maps.size();
+          for (int32_t q = 0; q < tb.cnt; ++q) p->maps.push_back(pos[s.rows[tb.roff + q]]);
+          lv = std::max(lv, zlev_tile[tmi] + 1);
+        }
+        b->terms.push_back(c);
+        b->flops += 2.0 * to.cnt * tb.cnt * nb;
+      }
+      task.t_end = (int32_t)b->terms.size();
+      zlev_tile[ti] = lv;
+      add_task(lv, task);
+    }
+    if (c1 == c0) continue;  // Z_kk = H_k
+    ConTask dtask = new_task(diag_off(k), BUF_Z, p->diag_h[k], p->diag_h[k], 1, 1, -1.0);
+    int32_t lv = 2;
+    for (int64_t tm = c0; tm < c1; ++tm) {
+      // sum over the active rows q of tile (m,k): M[q, r] Z[q, c]
+      b->terms.push_back(ConTerm{p->tile_off[tm], p->tile_off[tm], BUF_M, TRANS, -1, -1, BUF_Z, -1,
+                                 s.tiles[tm].cnt});
+      lv = std::max(lv, zlev_tile[tm] + 1);
+      b->flops += 2.0 * s.tiles[tm].cnt * nb * nb;
+    }
+    dtask.t_end = (int32_t)b->terms.size();
+    zlev_diag[k] = lv;
+    add_task(lv, dtask);
+  }
+  b->level_items.resize((size_t)nlev);
+  // input entries on the diagonal: the first entry of each column
+  b->diagflag.assign((size_t)s.qnz, 0);
+  for (int64_t j = 0; j < s.n; ++j) b->diagflag[(size_t)s.qp[j]] = 1;
+  return 0;
+}
+
 }  // namespace stc

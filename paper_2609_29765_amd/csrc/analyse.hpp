@@ -134,4 +134,37 @@ struct Plan {
 
 int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why);
 
+// Reverse mode of log det through the factorization.  For the logdet
+// cotangent the adjoint of the blocked Cholesky restricted to pattern(L) is
+// the selected inverse Z = (P A P^T)^-1 on pattern(L); it is computed by the
+// blocked Takahashi recurrence over the tile DAG in reverse:
+//   G_k = L_kk^-1, M_mk = L_mk G_k, H_k = G_k^T G_k,
+//   Z_ik = - sum_{m in C_k} Z_im M_mk          (i in C_k, rows R_ik)
+//   Z_kk = H_k - sum_{m in C_k} M_mk^T Z_mk
+// with C_k the non-empty tiles below diagonal tile k.
+struct ConTerm {
+  int64_t a_off, b_off;
+  int32_t a_buf, a_mode, a_rmap, a_qmap;
+  int32_t b_buf, b_qmap, K;
+};
+
+struct ConTask {
+  int64_t c_off;
+  int32_t c_buf, c_rows, ncols, diag;
+  int32_t t_begin, t_end;
+  int32_t beta;
+  double alpha;
+};
+
+struct BackPlan {
+  std::vector<ConTerm> terms;
+  std::vector<ConTask> tasks;
+  std::vector<std::vector<int32_t>> level_items;  // per level: task, block row, block col
+  std::vector<int32_t> trtri_items;               // level 0: pairs (k, block column)
+  std::vector<int8_t> diagflag;                   // input entry is a diagonal entry
+  double flops = 0;
+};
+
+int build_backward(const Symbolic& s, Plan* p, BackPlan* b, std::string* why);
+
 }  // namespace stc

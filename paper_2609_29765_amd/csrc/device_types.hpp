@@ -26,6 +26,27 @@ struct TrsmTaskD {
   int32_t rows, k;
 };
 
+// C (+)= alpha * sum_q A(r, q) B(q, j), operands read through index maps
+// (offsets into the map pool, -1 = identity; a map entry -1 = structural
+// zero).  Buffers: 0 factor store, 1 selected-inverse store, 2 inverses of
+// the diagonal tiles, 3 products L_mk inv(L_kk).
+enum { CA_NORMAL = 0, CA_TRANS = 1, CA_SYM = 2 };
+
+struct ConTermD {
+  int64_t a_off, b_off;
+  int32_t a_buf, a_mode, a_rmap, a_qmap;
+  int32_t b_buf, b_qmap, K, pad;
+};
+
+struct ConTaskD {
+  int64_t c_off;
+  int32_t c_buf, c_rows, ncols, diag;
+  int32_t t_begin, t_end;
+  int32_t beta;     // 1: accumulate into C, 0: overwrite
+  int32_t pad;
+  double alpha;
+};
+
 struct TileD {        // off-diagonal tile as the solve sees it
   int64_t off;        // store offset
   int64_t roff;       // offset of its active rows in the row pool

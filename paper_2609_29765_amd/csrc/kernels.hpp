@@ -702,6 +702,212 @@ __global__ __launch_bounds__(256) void k_level(LevelArgs a) {
 // independent accumulators per wave, no memory traffic in the loop
 // ---------------------------------------------------------------------------
 
+// ---------------------------------------------------------------------------
+// reverse mode of log det: selected inverse by the blocked Takahashi
+// recurrence (tile DAG in reverse)
+// ---------------------------------------------------------------------------
+
+// G_k = L_kk^-1, one 32-column block J per work-group: G_JJ = D_J (the 32 x 32
+// inverse the factorization kept) and, down the block column,
+// G_IJ = -D_I sum_{J <= P < I} L_IP G_PJ, both products on MFMA; the block
+// column of G sits in LDS and is written out in full (zeros above).
+constexpr int GLD = 33;
+
+template <int NB>
+constexpr int trtri_lds() { return NB * GLD + 32 * GLD; }
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_trtri(const int32_t* __restrict__ items,
+                                               const double* __restrict__ S,
+                                               const double* __restrict__ dinv,
+                                               double* __restrict__ G) {
+  extern __shared__ double smem[];
+  double* Gc = smem;            // NB x 32 block column
+  double* T = smem + NB * GLD;  // 32 x 32
+  const int32_t k = items[2 * blockIdx.x], J = items[2 * blockIdx.x + 1];
+  const double* L = S + (int64_t)k * NB * NB;
+  const double* D = dinv + (int64_t)k * NB * 32;
+  double* Gk = G + (int64_t)k * NB * NB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tr = (wave >> 1) * 16, tc = (wave & 1) * 16;
+  for (int x = tid; x < 32 * 32; x += 256) Gc[(J * 32 + x / 32) * GLD + x % 32] = D[J * 1024 + x];
+  __syncthreads();
+  for (int I = J + 1; I < NB / 32; ++I) {
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int kk = J * 32; kk < I * 32; kk += 4) {
+      const double a = L[(int64_t)(I * 32 + tr + (lane & 15)) * NB + kk + (lane >> 4)];
+      const double b = Gc[(kk + (lane >> 4)) * GLD + tc + (lane & 15)];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) T[(tr + (lane >> 4) + 4 * e) * GLD + tc + (lane & 15)] = acc[e];
+    __syncthreads();
+    acc = d4{0.0, 0.0, 0.0, 0.0};
+    for (int kk = 0; kk < 32; kk += 4) {
+      const double a = D[I * 1024 + (tr + (lane & 15)) * 32 + kk + (lane >> 4)];
+      const double b = T[(kk + (lane >> 4)) * GLD + tc + (lane & 15)];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Gc[(I * 32 + tr + (lane >> 4) + 4 * e) * GLD + tc + (lane & 15)] = -acc[e];
+    __syncthreads();
+  }
+  for (int x = tid; x < NB * 32; x += 256) {
+    const int r = x / 32, c = x % 32;
+    Gk[(int64_t)r * NB + J * 32 + c] = (r >= J * 32) ? Gc[r * GLD + c] : 0.0;
+  }
+}
+
+// One 64 x 64 block of C = beta C + alpha sum_t A_t B_t over the terms of a
+// task.  A_t(r, p) is read through the term's row map and contraction map in
+// one of three forms (stored tile, transposed tile, symmetric diagonal tile
+// with its lower triangle stored); B_t(p, j) is row p of a tile (through an
+// optional map), j the output column.  K is staged in LDS in chunks of 16.
+constexpr int CB = 64;
+constexpr int CKT = 16;
+constexpr int CLD = CKT + 1;
+constexpr int CON_LDS = 2 * CB * CLD + CB / 2 + CKT;  // As, Bs, row map, two chunk maps
+
+struct BackArgs {
+  const int32_t* items;  // triples: task, block row, block column
+  const ConTaskD* tasks;
+  const ConTermD* terms;
+  const int32_t* maps;
+  const double* L;  // factor store
+  double* Z;        // selected-inverse store (same layout)
+  double* M;        // L_mk G_k in the off-diagonal slots, G_k in the diagonal slots
+};
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_backcon(BackArgs g) {
+  extern __shared__ double smem[];
+  double* As = smem;
+  double* Bs = smem + CB * CLD;
+  int32_t* arow = reinterpret_cast<int32_t*>(smem + 2 * CB * CLD);
+  int32_t* aq = arow + CB;
+  int32_t* bq = aq + CKT;
+  const int32_t task = g.items[3 * blockIdx.x], bx = g.items[3 * blockIdx.x + 1],
+                by = g.items[3 * blockIdx.x + 2];
+  const ConTaskD u = g.tasks[task];
+  const int32_t r0 = bx * CB, c0 = by * CB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  d4 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int32_t t = u.t_begin; t < u.t_end; ++t) {
+    const ConTermD c = g.terms[t];
+    const double* A = (c.a_buf == 0 ? g.L : (c.a_buf == 1 ? g.Z : g.M)) + c.a_off;
+    const double* B = (c.b_buf == 0 ? g.L : (c.b_buf == 1 ? g.Z : g.M)) + c.b_off;
+    __syncthreads();  // previous term's maps consumed
+    if (tid < CB) {
+      const int32_t r = r0 + tid;
+      int32_t v = -1;
+      if (r < u.c_rows) v = c.a_rmap < 0 ? r : g.maps[c.a_rmap + r];
+      arow[tid] = v;
+    }
+    for (int32_t k0 = 0; k0 < c.K; k0 += CKT) {
+      if (tid < CKT) {
+        const int32_t p = k0 + tid;
+        aq[tid] = p < c.K ? (c.a_qmap < 0 ? p : g.maps[c.a_qmap + p]) : -1;
+      } else if (tid < 2 * CKT) {
+        const int32_t p = k0 + tid - CKT;
+        bq[tid - CKT] = p < c.K ? (c.b_qmap < 0 ? p : g.maps[c.b_qmap + p]) : -1;
+      }
+      __syncthreads();
+      // A chunk: 64 rows x 16; B chunk: 16 x 64 columns; 4 elements per thread
+      double av[4], bv[4];
+      int arr[4], apq[4];
+      if (c.a_mode == CA_TRANS) {
+        const int p = tid >> 4, rb = (tid & 15) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          arr[e] = rb + e;
+          apq[e] = p;
+        }
+      } else {
+        const int row = tid >> 2, pb = (tid & 3) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          arr[e] = row;
+          apq[e] = pb + e;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int32_t rr = arow[arr[e]], qq = aq[apq[e]];
+        const int32_t rc = max(rr, 0), qc = max(qq, 0);
+        int64_t off;
+        if (c.a_mode == CA_NORMAL) off = (int64_t)rc * NB + qc;
+        else if (c.a_mode == CA_TRANS) off = (int64_t)qc * NB + rc;
+        else off = (int64_t)max(rc, qc) * NB + min(rc, qc);
+        const double v = A[off];
+        av[e] = (rr >= 0 && qq >= 0) ? v : 0.0;
+      }
+      {
+        const int p = tid >> 4, jb = (tid & 15) * 4;
+        const int32_t qb = bq[p];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int32_t j = c0 + jb + e;
+          const double v = B[(int64_t)max(qb, 0) * NB + min(j, NB - 1)];
+          bv[e] = (qb >= 0 && j < NB) ? v : 0.0;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) As[arr[e] * CLD + apq[e]] = av[e];
+      {
+        const int p = tid >> 4, jb = (tid & 15) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Bs[(jb + e) * CLD + p] = bv[e];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < CKT; kk += 4) {
+        double af[2], bf[2];
+        for (int a = 0; a < 2; ++a) af[a] = As[(wr + a * 16 + (lane & 15)) * CLD + kk + (lane >> 4)];
+        for (int b = 0; b < 2; ++b) bf[b] = Bs[(wc + b * 16 + (lane & 15)) * CLD + kk + (lane >> 4)];
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+  }
+  double* C = (u.c_buf == 0 ? nullptr : (u.c_buf == 1 ? g.Z : g.M)) + u.c_off;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int32_t i = r0 + wr + a * 16 + (lane >> 4) + 4 * e;
+        const int32_t j = c0 + wc + b * 16 + (lane & 15);
+        if (i < u.c_rows && j < u.ncols && (!u.diag || j <= i)) {
+          double* cp = C + (int64_t)i * NB + j;
+          const double v = u.alpha * acc[a][b][e];
+          *cp = u.beta ? *cp + v : v;
+        }
+      }
+}
+
+// gradient of log det with respect to the input values (lower triangle of a
+// symmetric matrix): gbar * Z_ij, doubled off the diagonal; NaN when the
+// factorization failed
+__global__ void k_logdet_grad(const double* __restrict__ Z, const int64_t* __restrict__ vmap,
+                              const int8_t* __restrict__ diag, const double* __restrict__ gbar,
+                              const int32_t* __restrict__ info, int64_t qnz,
+                              double* __restrict__ out) {
+  const double gb = gbar[0];
+  const bool ok = info[0] == 0;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (; i < qnz; i += step) {
+    const double z = Z[vmap[i]];
+    out[i] = ok ? gb * (diag[i] ? z : 2.0 * z) : __builtin_nan("");
+  }
+}
+
 __global__ __launch_bounds__(256) void k_mfma_issue(double* __restrict__ out, int32_t iters, double seed) {
   const int lane = threadIdx.x & 63;
   double a = seed + lane * 1e-3, b = seed - lane * 1e-3;

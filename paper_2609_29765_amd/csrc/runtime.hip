@@ -85,8 +85,21 @@ struct stc_handle {
   int32_t* d_info = nullptr;  // batch
   double* d_ld = nullptr;     // batch
   std::map<int32_t, hipGraphExec_t> graphs;  // by member count
+  // reverse mode of log det
+  BackPlan back;
+  std::vector<int32_t> back_items;       // flattened per level
+  std::vector<int32_t> back_level_ptr;   // items of level L: [ptr[L], ptr[L+1])
+  ConTermD* d_bterms = nullptr;
+  ConTaskD* d_btasks = nullptr;
+  int32_t* d_bitems = nullptr;
+  int32_t* d_trtri = nullptr;
+  int8_t* d_bdiag = nullptr;
+  double* d_zs = nullptr;  // selected inverse, store layout
+  double* d_ms = nullptr;  // G_k (diagonal slots) and L_mk G_k (off-diagonal slots)
+  hipGraphExec_t back_graph = nullptr;
   ~stc_handle() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    if (back_graph) (void)hipGraphExecDestroy(back_graph);
   }
 };
 
@@ -130,6 +143,13 @@ size_t layout(const stc_handle* hc, int32_t batch, char* base) {
   take(&h->d_y, sizeof(double) * (size_t)padded_n(h) * kMaxRhs);
   take(&h->d_dinv, sizeof(double) * (size_t)dinv_stride(h) * (size_t)batch);
   take(&h->d_parts, sizeof(double) * (size_t)p.parts * (size_t)batch);
+  take(&h->d_bterms, sizeof(ConTermD) * h->back.terms.size());
+  take(&h->d_btasks, sizeof(ConTaskD) * h->back.tasks.size());
+  take(&h->d_bitems, sizeof(int32_t) * h->back_items.size());
+  take(&h->d_trtri, sizeof(int32_t) * h->back.trtri_items.size());
+  take(&h->d_bdiag, sizeof(int8_t) * h->back.diagflag.size());
+  take(&h->d_zs, sizeof(double) * (size_t)p.store);
+  take(&h->d_ms, sizeof(double) * (size_t)p.store);
   take(&h->d_store, sizeof(double) * (size_t)p.store * (size_t)batch);
   return off;
 }
@@ -290,6 +310,63 @@ int run_factor(stc_handle* h, const double* vals, int32_t members, hipStream_t s
   return 0;
 }
 
+// selected inverse of the last single factorization into d_zs: the G_k
+// level, then one contraction kernel per level of the reverse tile DAG
+template <int NB>
+int launch_backward_nb(stc_handle* h, hipStream_t st) {
+  const int32_t ntr = (int32_t)(h->back.trtri_items.size() / 2);
+  hipLaunchKernelGGL((k_trtri<NB>), dim3(ntr), dim3(256), sizeof(double) * trtri_lds<NB>(), st,
+                     h->d_trtri, h->d_store, h->d_dinv, h->d_ms);
+  BackArgs g;
+  g.tasks = h->d_btasks;
+  g.terms = h->d_bterms;
+  g.maps = h->d_maps;
+  g.L = h->d_store;
+  g.Z = h->d_zs;
+  g.M = h->d_ms;
+  for (size_t L = 0; L + 1 < h->back_level_ptr.size(); ++L) {
+    const int32_t a = h->back_level_ptr[L], b = h->back_level_ptr[L + 1];
+    if (b == a) continue;
+    g.items = h->d_bitems + 3 * (int64_t)a;
+    hipLaunchKernelGGL((k_backcon<NB>), dim3(b - a), dim3(256), sizeof(double) * CON_LDS, st, g);
+  }
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int launch_backward(stc_handle* h, hipStream_t st) {
+  switch (h->plan.nb) {
+    case 32: return launch_backward_nb<32>(h, st);
+    case 64: return launch_backward_nb<64>(h, st);
+    case 128: return launch_backward_nb<128>(h, st);
+    case 256: return launch_backward_nb<256>(h, st);
+  }
+  return fail(STC_ERR_ARG, "unsupported tile size");
+}
+
+int get_back_graph(stc_handle* h, hipGraphExec_t* out) {
+  if (h->back_graph) {
+    *out = h->back_graph;
+    return 0;
+  }
+  hipStream_t cs;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+  int rc = launch_backward(h, cs);
+  hipGraph_t g;
+  hipError_t e = hipStreamEndCapture(cs, &g);
+  (void)hipStreamDestroy(cs);
+  if (rc) return rc;
+  if (e != hipSuccess) return fail(STC_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  hipGraphExec_t ex;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(STC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  h->back_graph = ex;
+  *out = ex;
+  return 0;
+}
+
 int check_bound(const stc_handle* h) {
   if (!h) return fail(STC_ERR_ARG, "null handle");
   if (!h->ws) return fail(STC_ERR_STATE, "handle is not bound to a workspace");
@@ -323,9 +400,15 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
       return fail(rc, why);
     }
     rc = build_plan(h->sym, UB, TR, &h->plan, &why);
+    if (rc == 0) rc = build_backward(h->sym, &h->plan, &h->back, &why);
     if (rc) {
       delete h;
       return fail(rc, why);
+    }
+    h->back_level_ptr.push_back(0);
+    for (const auto& li : h->back.level_items) {
+      h->back_items.insert(h->back_items.end(), li.begin(), li.end());
+      h->back_level_ptr.push_back((int32_t)(h->back_items.size() / 3));
     }
     // flatten the level lists
     for (const Level& L : h->plan.levels) {
@@ -369,6 +452,8 @@ int stc_bind(stc_handle* h, void* d_ws, size_t bytes, int32_t batch, void* strea
     return fail(STC_ERR_ALLOC, "workspace too small: need " + std::to_string(need) + " bytes");
   for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.second);
   h->graphs.clear();
+  if (h->back_graph) (void)hipGraphExecDestroy(h->back_graph);
+  h->back_graph = nullptr;
   h->factored = false;
   HIPCHK(hipGetDevice(&h->device));
   h->ws = (char*)d_ws;
@@ -405,6 +490,21 @@ int stc_bind(stc_handle* h, void* d_ws, size_t bytes, int32_t batch, void* strea
       (rc = upload(h->d_row_tiles, p.row_tiles)) || (rc = upload(h->d_col_ptr, p.col_tiles_ptr)) ||
       (rc = upload(h->d_col_tiles, p.col_tiles)) || (rc = upload(h->d_fwd_blk, p.fwd_level_blk)) ||
       (rc = upload(h->d_bwd_blk, p.bwd_level_blk)))
+    return rc;
+  const BackPlan& bp = h->back;
+  std::vector<ConTermD> bt(bp.terms.size());
+  for (size_t i = 0; i < bt.size(); ++i) {
+    const ConTerm& c = bp.terms[i];
+    bt[i] = ConTermD{c.a_off, c.b_off, c.a_buf, c.a_mode, c.a_rmap, c.a_qmap, c.b_buf, c.b_qmap, c.K, 0};
+  }
+  std::vector<ConTaskD> bk(bp.tasks.size());
+  for (size_t i = 0; i < bk.size(); ++i) {
+    const ConTask& t = bp.tasks[i];
+    bk[i] = ConTaskD{t.c_off, t.c_buf, t.c_rows, t.ncols, t.diag, t.t_begin, t.t_end, t.beta, 0, t.alpha};
+  }
+  if ((rc = upload(h->d_bterms, bt)) || (rc = upload(h->d_btasks, bk)) ||
+      (rc = upload(h->d_bitems, h->back_items)) || (rc = upload(h->d_trtri, bp.trtri_items)) ||
+      (rc = upload(h->d_bdiag, bp.diagflag)))
     return rc;
   hipGraphExec_t ex;
   return get_graph(h, 1, &ex);
@@ -490,12 +590,21 @@ int stc_solve(stc_handle* h, double* d_b, int32_t nrhs, void* stream) {
 }
 
 int stc_logdet_backward(stc_handle* h, const double* d_gbar, double* d_grad_values, void* stream) {
-  (void)d_gbar;
-  (void)d_grad_values;
-  (void)stream;
   int rc = check_bound(h);
   if (rc) return rc;
-  return fail(STC_ERR_STATE, "logdet backward is not available in this build");
+  if (!d_gbar || !d_grad_values) return fail(STC_ERR_ARG, "null pointer");
+  if (!h->factored) return fail(STC_ERR_STATE, "logdet backward before factorize");
+  hipStream_t st = (hipStream_t)stream;
+  hipGraphExec_t ex;
+  rc = get_back_graph(h, &ex);
+  if (rc) return rc;
+  HIPCHK(hipGraphLaunch(ex, st));
+  const int64_t qnz = h->sym.qnz;
+  const int64_t grid = std::min<int64_t>(4096, (qnz + 255) / 256);
+  hipLaunchKernelGGL(k_logdet_grad, dim3((unsigned)grid), dim3(256), 0, st, h->d_zs, h->d_vmap,
+                     h->d_bdiag, d_gbar, h->d_info, qnz, d_grad_values);
+  HIPCHK(hipGetLastError());
+  return 0;
 }
 
 int stc_info(stc_handle* h, int32_t* info) {
@@ -598,6 +707,8 @@ int stc_get_work(const stc_handle* h, double* w) {
   w[5] = p.bytes_update;
   w[6] = 20.0 * q + 8.0 * (double)p.store;  // values + map read, value write, store fill
   w[7] = (double)h->lv.size();
+  w[8] = h->back.flops;
+  w[9] = (double)(h->back_level_ptr.size() - 1);
   return 0;
 }
 

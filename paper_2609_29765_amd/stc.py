@@ -210,6 +210,7 @@ class Analysis:
         assert values.numel() == self.qnz
         self._values = values  # keep alive until the stream has consumed it
         _check(lib().stc_factorize(self._h, _dptr(values), _stream_ptr()))
+        self._fact_id = getattr(self, "_fact_id", 0) + 1
         return self
 
     def factorize_batched(self, values):
@@ -225,6 +226,7 @@ class Analysis:
         self._values = values
         _check(lib().stc_factorize_batched(self._h, _dptr(values), int(B), _dptr(ld), _dptr(info),
                                            _stream_ptr()))
+        self._fact_id = getattr(self, "_fact_id", 0) + 1
         return ld, info
 
     def logdet(self):
@@ -253,10 +255,10 @@ class Analysis:
 
     def work(self):
         """Static flop and byte counts of one factorization (see stc_get_work)."""
-        w = np.zeros(8)
+        w = np.zeros(10)
         _check(lib().stc_get_work(self._h, w))
         keys = ["flops_update", "flops_potrf", "flops_trsm", "flops_tile", "flops_exact",
-                "bytes_update", "bytes_load", "levels"]
+                "bytes_update", "bytes_load", "levels", "flops_backward", "levels_backward"]
         return dict(zip(keys, (float(x) for x in w)))
 
     def profile_factorize(self, values):
@@ -298,11 +300,17 @@ def _make_logdet_function():
         def forward(ctx, values, analysis):
             analysis.factorize(values)
             ctx.analysis = analysis
+            ctx.fact_id = analysis._fact_id
+            ctx.save_for_backward(values)
             return analysis.logdet().clone()
 
         @staticmethod
         def backward(ctx, g):
-            return ctx.analysis.logdet_backward(g), None
+            a = ctx.analysis
+            if a._fact_id != ctx.fact_id:  # another factorization ran since: redo this one
+                (values,) = ctx.saved_tensors
+                a.factorize(values.detach())
+            return a.logdet_backward(g), None
 
     return LogDet
 
