@@ -1,56 +1,95 @@
 """Benchmark: FP64 tile-Cholesky factorizations per second on one MI355X.
 
-Workload: the dense-route matrix -- random SPD of order 12288 with ~20%
-off-diagonal density (uniform pattern, N(0,1) entries, diagonal = row
-absolute sum + 1), tile 256, every tile dense.  One step = value load +
-the whole POTRF/SYRK/GEMM/TRSM tile schedule (one HIP-graph replay), values
+Headline workload: the dense-route matrix -- random SPD of order 12288 with
+~20% off-diagonal density (uniform pattern, N(0,1) entries, diagonal = row
+absolute sum + 1), tile 256, every tile dense.  One step = value load + the
+whole POTRF/SYRK/GEMM/TRSM tile schedule (one HIP-graph replay), values
 already resident in HBM.
 
 Prints one JSON line.  Besides the headline value it carries:
-  roofline      the update kernel (SYRK+GEMM contributions on FP64 MFMA),
-                algorithmic flops / event-timed kernel time against the FP64
-                matrix peak of 78.6 TFLOP/s;
+  roofline      the level kernel form that takes most of the factorization
+                time: tile-algorithmic flops of the tasks it runs per launch /
+                its event-timed average launch duration, against the FP64
+                matrix peak of 78.6 TFLOP/s; HBM traffic per launch from the
+                committed counter summary when it matches the current kernels;
   cpu_baseline  the oracle (plain serial C, one core) timed on a smaller
                 instance of the same generator, scaled to this order by the
-                flop ratio.
+                flop ratio;
+  extras        the other forms of the metric, measured in a child process
+                (so the headline process's kernel statistics cover the
+                headline only): batched factorization of 128 value sets
+                against the plain path, logdet backward against the forward
+                and against central differences, the semisparse
+                spatio-temporal matrix, and the small 2-D GMRF.
 """
 import argparse
+import hashlib
 import json
 import os
+import subprocess
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6
+PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 matrix peak (published)
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E (published)
+KERNEL_SOURCES = ["paper_2609_29765_amd/csrc/kernels.hpp", "paper_2609_29765_amd/csrc/device_types.hpp",
+                  "paper_2609_29765_amd/csrc/runtime.hip", "paper_2609_29765_amd/csrc/analyse.cpp"]
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=12288)
-    ap.add_argument("--nb", type=int, default=256)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-n", type=int, default=4096)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(run with --gpus 1)", file=sys.stderr)
-        sys.exit(2)
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
-    import numpy as np
+
+def load_lib():
     import torch
-    from paper_2609_29765_amd import stc, workloads
-
+    from paper_2609_29765_amd import stc
     if not os.path.exists(stc.LIB_PATH):
         from paper_2609_29765_amd import build as pb
         pb.build()
     if not torch.cuda.is_available():
         print("no HIP device visible", file=sys.stderr)
         sys.exit(1)
+    return stc
+
+
+def events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def timed(fn, reps):
+    """Milliseconds per call of fn over reps calls, bracketed by syncs."""
+    import torch
+    torch.cuda.synchronize()
+    e0, e1 = events()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# headline: dense route, n = 12288, tile 256
+# ---------------------------------------------------------------------------
+
+def headline(args):
+    import torch
+    stc = load_lib()
+    from paper_2609_29765_amd import workloads
 
     t0 = time.time()
     w = workloads.dense_spd(args.n, 0.2, 0)
@@ -61,45 +100,67 @@ def main():
     a.bind()
     work = a.work()
     vals = torch.from_numpy(w.values).cuda()
-    print(f"[bench] n={w.n} nnz={w.nnz} nb={a.nb} mode={a.mode} route={a.route} "
-          f"levels={a.nlevels} analyse={t_analyse:.2f}s gen={t_gen:.2f}s", file=sys.stderr, flush=True)
+    log(f"n={w.n} nnz={w.nnz} nb={a.nb} mode={a.mode} route={a.route} levels={a.nlevels} "
+        f"analyse={t_analyse:.2f}s gen={t_gen:.2f}s")
 
     for _ in range(args.warmup):
         a.factorize(vals)
     torch.cuda.synchronize()
     assert a.info() == 0, "warm-up factorization failed"
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    start.record()
+    e0, e1 = events()
+    e0.record()
     for _ in range(args.steps):
         a.factorize(vals)
-    stop.record()
+    e1.record()
     torch.cuda.synchronize()
-    ms_total = start.elapsed_time(stop)
-    ms_step = ms_total / args.steps
+    ms_step = e0.elapsed_time(e1) / args.steps
     ld = float(a.logdet().item())
-    info = a.info()
-    print(f"[bench] {args.steps} steps {ms_step:.3f} ms/step logdet={ld:.6f} info={info}",
-          file=sys.stderr, flush=True)
+    assert a.info() == 0
+    log(f"{args.steps} steps {ms_step:.3f} ms/step logdet={ld:.6f}")
 
-    # per-kernel-kind event timing of one eager factorization (same kernels)
-    prof = a.profile_factorize(vals)
-    upd_ms, upd_launches = prof["update"]
-    achieved = work["flops_update"] / (upd_ms * 1e-3) / 1e12
+    # per-launch event timing of eager factorizations (same kernels, same
+    # stream), charged to the level-kernel form each launch uses
+    agg = {}
+    for _ in range(args.prof_reps):
+        for k, (ms, cnt, fl) in a.profile_factorize(vals).items():
+            m0, c0, f0 = agg.get(k, (0.0, 0, 0.0))
+            agg[k] = (m0 + ms, c0 + cnt, f0 + fl)
+    level_kinds = [k for k in agg if k != "load" and agg[k][1] > 0]
+    dom = max(level_kinds, key=lambda k: agg[k][0])
+    ms_d, cnt_d, fl_d = agg[dom]
+    avg_ms = ms_d / cnt_d
+    flops_per_launch = fl_d / cnt_d
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    symbol = {"k_level<P,G>": f"k_level<{a.nb}, true, true>", "k_level<P>": f"k_level<{a.nb}, true, false>",
+              "k_level<G>": f"k_level<{a.nb}, false, true>", "k_level": f"k_level<{a.nb}, false, false>"}[dom]
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic_dense12288_nb256.json")
+    if os.path.exists(tfile):
+        with open(tfile) as fh:
+            tr = json.load(fh)
+        if tr.get("source_hash") == kernel_source_hash() and symbol in tr.get("kernels", {}):
+            traffic = tr["kernels"][symbol]["bytes_per_launch"]
     roofline = {
         "bound": "mfma",
         "achieved": round(achieved, 3),
         "peak": PEAK_FP64_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-        "traffic": None,
-        "kernel": f"k_update<{a.nb}>",
-        "launches": upd_launches,
-        "avg_launch_ms": round(upd_ms / max(upd_launches, 1), 4),
-        "flops_per_launch": work["flops_update"] / max(upd_launches, 1),
+        "traffic": traffic,
+        "kernel": symbol,
+        "launches": cnt_d // args.prof_reps,
+        "avg_launch_ms": round(avg_ms, 5),
+        "flops_per_launch": flops_per_launch,
     }
-    kinds = {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in prof.items()}
+    fam_ms = sum(agg[k][0] for k in level_kinds)
+    fam_fl = sum(agg[k][2] for k in level_kinds)
+    kinds = {k: {"ms_per_factorization": round(v[0] / args.prof_reps, 4), "launches": v[1] // args.prof_reps,
+                 "avg_launch_ms": round(v[0] / max(v[1], 1), 5),
+                 "tflops": round(v[2] / (v[0] * 1e-3) / 1e12, 3) if v[0] > 0 and v[2] > 0 else None}
+             for k, v in agg.items()}
+    log(f"roofline {symbol}: {achieved:.2f} TFLOP/s over {cnt_d // args.prof_reps} launches; "
+        f"all level kernels {fam_fl / (fam_ms * 1e-3) / 1e12:.2f} TFLOP/s")
 
     # measured ceilings: MFMA issue microkernel, library DGEMM (rocBLAS via torch)
     mfma_peak = stc.fp64_mfma_peak()
@@ -107,39 +168,261 @@ def main():
     xa = torch.randn(nd, nd, dtype=torch.float64, device="cuda")
     xb = torch.randn(nd, nd, dtype=torch.float64, device="cuda")
     torch.matmul(xa, xb)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(3):
-        torch.matmul(xa, xb)
-    e1.record()
-    torch.cuda.synchronize()
-    dgemm_tf = 3 * 2.0 * nd ** 3 / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    dgemm_ms = timed(lambda: torch.matmul(xa, xb), 3)
+    dgemm_tf = 2.0 * nd ** 3 / (dgemm_ms * 1e-3) / 1e12
     del xa, xb
-    print(f"[bench] measured FP64 MFMA issue {mfma_peak:.1f} TFLOP/s, library DGEMM n={nd} "
-          f"{dgemm_tf:.1f} TFLOP/s", file=sys.stderr, flush=True)
+    log(f"measured FP64 MFMA issue {mfma_peak:.1f} TFLOP/s, library DGEMM n={nd} {dgemm_tf:.1f} TFLOP/s")
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import oracle
-        ns = args.cpu_sample_n
-        ws = workloads.dense_spd(ns, 0.2, 0)
-        o = oracle.Analysis(ws.n, ws.colptr, ws.rowind, "natural", nb=args.nb)
+    return dict(
+        ms_step=ms_step, logdet=ld, analyse_s=t_analyse, a=a, w=w, work=work, roofline=roofline,
+        kinds=kinds, level_family_tflops=round(fam_fl / (fam_ms * 1e-3) / 1e12, 3),
+        peaks={"mfma_issue": round(mfma_peak, 2), "dgemm_library_8192": round(dgemm_tf, 2)})
+
+
+# ---------------------------------------------------------------------------
+# extras (child process)
+# ---------------------------------------------------------------------------
+
+def extra_gmrf():
+    """Small 2-D GMRF (n = 1024, tile 64, ND): factorize + logdet + solve."""
+    import torch
+    from paper_2609_29765_amd import stc, workloads
+    w = workloads.gmrf_grid2d(32, 32, 0.1, 0)
+    a = stc.Analysis(w.n, w.colptr, w.rowind, nb=64, ordering="nd").bind()
+    v = torch.from_numpy(w.values).cuda()
+    b = torch.from_numpy(w.b).cuda()
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+
+    def step():
+        a.factorize(v)
+        a.logdet()
+        a.solve(b)
+
+    step()
+    us_f = timed(lambda: a.factorize(v), 200) * 1e3
+    us = timed(step, 200) * 1e3
+    del out
+    return {"workload": "2-D GMRF 32x32 grid, Laplacian + 0.1 I, n=1024, tile 64, ND",
+            "us_per_factorization": round(us_f, 2), "us_per_factorize_logdet_solve": round(us, 2),
+            "levels": a.nlevels, "mode": a.mode}
+
+
+def extra_semisparse():
+    """Spatio-temporal arrowhead, n = 101,258: tile size tuned over 128/256."""
+    import torch
+    from paper_2609_29765_amd import workloads
+    from paper_2609_29765_amd.autotune import autotune
+    w = workloads.spatiotemporal_arrowhead()
+    v = torch.from_numpy(w.values).cuda()
+    t0 = time.time()
+    a, table = autotune(w.n, w.colptr, w.rowind, v, nbs=(128, 256), ordering="nd", trials=3)
+    t_tune = time.time() - t0
+    ms = timed(lambda: a.factorize(v), 10)
+    assert a.info() == 0
+    wk = a.work()
+    prof = a.profile_factorize(v)
+    return {"workload": "spatio-temporal arrowhead n=101258 (50 steps x 45x45 grid, AR1 0.9, kappa 0.5, "
+                        "8 dense border rows), ND ordering",
+            "nb": a.nb, "mode": a.mode, "route": a.route, "levels": a.nlevels,
+            "factorizations_per_s": round(1000.0 / ms, 3), "ms_per_factorization": round(ms, 3),
+            "gflops_tile": round(wk["flops_tile"] / (ms * 1e-3) / 1e9, 1),
+            "gflops_exact": round(wk["flops_exact"] / (ms * 1e-3) / 1e9, 1),
+            "tile_gflop": round(wk["flops_tile"] / 1e9, 2), "exact_gflop": round(wk["flops_exact"] / 1e9, 2),
+            "autotune": table, "autotune_s": round(t_tune, 1),
+            "kernels": {k: {"ms": round(x[0], 3), "launches": x[1]} for k, x in prof.items()},
+            "logdet": float(a.logdet().item())}
+
+
+def extra_batched(B):
+    """3-D Laplacian 24^3 + 0.05 I, B value sets: one batched call vs B plain calls."""
+    import torch
+    from paper_2609_29765_amd import workloads
+    from paper_2609_29765_amd.autotune import autotune
+    w = workloads.batched_laplacian3d(m=24, B=B, seed=0)
+    V = torch.from_numpy(w.values).cuda()
+    a, table = autotune(w.n, w.colptr, w.rowind, V, nbs=(64, 128), ordering="nd", batched=True, trials=2)
+    ms_batched = timed(lambda: a.factorize_batched(V), 3)
+    ld_b, info = a.factorize_batched(V)
+    assert int(info.abs().sum().item()) == 0
+    ld_s = torch.empty(B, dtype=torch.float64, device="cuda")
+
+    def plain():
+        for i in range(B):
+            a.factorize(V[i])
+            ld_s[i:i + 1].copy_(a.logdet().reshape(1))
+
+    plain()
+    ms_plain = timed(plain, 2)
+    dev = float(((ld_s - ld_b).abs() / ld_b.abs()).max().item())
+    return {"workload": f"3-D Laplacian 24^3 + 0.05 I, n=13824, B={B} hyperparameter value sets, ND",
+            "nb": a.nb, "mode": a.mode, "levels": a.nlevels, "B": B,
+            "ms_batched": round(ms_batched, 3), "ms_plain_loop": round(ms_plain, 3),
+            "batched_speedup": round(ms_plain / ms_batched, 3),
+            "factorizations_per_s_batched": round(B * 1000.0 / ms_batched, 1),
+            "factorizations_per_s_plain": round(B * 1000.0 / ms_plain, 1),
+            "max_rel_logdet_batched_vs_plain": dev, "autotune": table}
+
+
+def extra_backward():
+    """Differentiable arrowhead n = 12,508: logdet + gradient vs forward and FD."""
+    import numpy as np
+    import torch
+    from paper_2609_29765_amd import workloads
+    from paper_2609_29765_amd.autotune import autotune
+    w = workloads.differentiable_arrowhead(20, 25, 8, 0)
+    v = torch.from_numpy(w.values).cuda()
+    a, table = autotune(w.n, w.colptr, w.rowind, v, nbs=(32, 64, 128), ordering="nd", trials=3)
+    one = torch.ones(1, dtype=torch.float64, device="cuda")
+    dv = torch.from_numpy(w.dvalues).cuda()
+
+    def fwd():
+        a.factorize(v)
+        return a.logdet()
+
+    def fwd_bwd():
+        a.factorize(v)
+        a.logdet()
+        return dv @ a.logdet_backward(one)
+
+    fwd_bwd()
+    ms_f = timed(fwd, 20)
+    ms_fb = timed(fwd_bwd, 20)
+    g = fwd_bwd().cpu().numpy()
+    th = w.meta["theta"]
+    h = 1e-5
+    plus_minus = []
+    for i in range(3):
+        for s in (+1, -1):
+            t2 = th.copy()
+            t2[i] += s * h
+            plus_minus.append(torch.from_numpy(workloads.differentiable_arrowhead(20, 25, 8, 0, theta=t2).values).cuda())
+    lds = torch.empty(6, dtype=torch.float64, device="cuda")
+
+    def fd():
+        for j, vv in enumerate(plus_minus):
+            a.factorize(vv)
+            lds[j:j + 1].copy_(a.logdet().reshape(1))
+
+    fd()
+    ms_fd = timed(fd, 5)
+    l6 = lds.cpu().numpy()
+    gfd = (l6[0::2] - l6[1::2]) / (2 * h)
+    wk = a.work()
+    return {"workload": "differentiable arrowhead n=12508 (20 steps x 25x25 grid + 8 border rows), "
+                        "theta=(log tau, log kappa, atanh rho) seed 0, ND",
+            "nb": a.nb, "levels_forward": a.nlevels, "levels_backward": int(wk["levels_backward"]),
+            "ms_forward": round(ms_f, 4), "ms_forward_backward": round(ms_fb, 4),
+            "backward_ratio": round(ms_fb / ms_f, 3),
+            "ms_fd_gradient": round(ms_fd, 4), "speedup_vs_fd": round(ms_fd / ms_fb, 3),
+            "grad": [float(x) for x in g], "grad_fd": [float(x) for x in gfd],
+            "max_rel_grad_vs_fd": float(np.max(np.abs(g - gfd) / np.abs(gfd))),
+            "backward_gflop": round(wk["flops_backward"] / 1e9, 3), "autotune": table}
+
+
+def run_extras(path, batch):
+    load_lib()
+    out = {}
+    for name, fn in [("gmrf_2d", extra_gmrf), ("backward", extra_backward),
+                     ("batched", lambda: extra_batched(batch)), ("semisparse", extra_semisparse)]:
         t0 = time.time()
-        Lx, oinfo = o.factor(ws.values)
-        t_cpu = time.time() - t0
-        assert oinfo == 0
-        scale = (args.n / ns) ** 3
-        cpu = {
-            "value": round(1.0 / (t_cpu * scale), 6),
-            "unit": "factorizations/s",
-            "cores": 1,
-            "kind": "oracle",
-            "sample": f"oracle factor of the same generator at n={ns} (seed 0) took {t_cpu:.2f} s; "
-                      f"scaled by (n/{ns})^3 = {scale:.1f} to n={args.n}",
-        }
+        log(f"extra {name} ...")
+        out[name] = fn()
+        out[name]["wall_s"] = round(time.time() - t0, 1)
+        log(f"extra {name}: {json.dumps(out[name])[:300]}")
+        import torch
+        torch.cuda.empty_cache()
+    with open(path, "w") as fh:
+        json.dump(out, fh)
 
-    gflops = work["flops_tile"] / (ms_step * 1e-3) / 1e9
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle on a bounded sample
+# ---------------------------------------------------------------------------
+
+def cpu_baseline(args):
+    from oracle import oracle
+    from paper_2609_29765_amd import workloads
+    ns = args.cpu_sample_n
+    ws = workloads.dense_spd(ns, 0.2, 0)
+    o = oracle.Analysis(ws.n, ws.colptr, ws.rowind, "natural", nb=args.nb)
+    t0 = time.time()
+    Lx, oinfo = o.factor(ws.values)
+    t_cpu = time.time() - t0
+    assert oinfo == 0
+    scale = (args.n / ns) ** 3
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {
+        "value": round(1.0 / (t_cpu * scale), 6),
+        "unit": "factorizations/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"oracle factorization (serial C, one thread) of the same generator at n={ns} (seed 0) "
+                  f"took {t_cpu:.2f} s on {model or 'the host'} ({os.cpu_count()} logical CPUs visible); "
+                  f"scaled by the flop ratio (n/{ns})^3 = {scale:.2f} to n={args.n}",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=12288)
+    ap.add_argument("--nb", type=int, default=256)
+    ap.add_argument("--prof-reps", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--cpu-sample-n", type=int, default=5120)
+    ap.add_argument("--extras-out", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device copy (counter calibration runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.extras_out:
+        run_extras(args.extras_out, args.batch)
+        return
+
+    import torch
+    hl = headline(args)
+    if args.copy_calibration:
+        x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        x.fill_(1.0)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+    a, w, work = hl["a"], hl["w"], hl["work"]
+    a.release()
+    torch.cuda.empty_cache()
+
+    extras = None
+    if not args.no_extras:
+        fd, path = tempfile.mkstemp(suffix=".json")
+        os.close(fd)
+        cmd = [sys.executable, os.path.abspath(__file__), "--extras-out", path, "--batch", str(args.batch)]
+        rc = subprocess.run(cmd).returncode
+        if rc != 0:
+            print(f"extras child failed with status {rc}", file=sys.stderr)
+            sys.exit(rc)
+        with open(path) as fh:
+            extras = json.load(fh)
+        os.unlink(path)
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args)
+
+    ms_step = hl["ms_step"]
     line = {
         "metric": "FP64 factorizations/s + % FP64 MFMA peak; batched & backward vs plain path",
         "value": round(1000.0 / ms_step, 4),
@@ -154,16 +437,18 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"dense-route random SPD n={args.n}, 20% off-diagonal density, "
-                               f"tile {a.nb}, natural order (every row dense)",
-                   "n": args.n, "nb": a.nb, "nnz_lower": w.nnz, "route": a.route},
-        "gflops_tile": round(gflops, 2),
-        "frac_peak_whole_factorization": round(gflops / 1e3 / PEAK_FP64_TFLOPS, 4),
-        "kernels": kinds,
-        "measured_peaks_tflops": {"mfma_issue": round(mfma_peak, 2), "dgemm_library_8192": round(dgemm_tf, 2)},
-        "roofline": roofline,
+                               f"tile {a.nb}, natural order (every tile dense)",
+                   "n": args.n, "nb": a.nb, "nnz_lower": w.nnz, "route": a.route, "levels": a.nlevels},
+        "gflops_tile": round(work["flops_tile"] / (ms_step * 1e-3) / 1e9, 2),
+        "frac_peak_whole_factorization": round(work["flops_tile"] / (ms_step * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+        "roofline": hl["roofline"],
+        "level_kernels_tflops": hl["level_family_tflops"],
+        "kernels": hl["kinds"],
+        "measured_peaks_tflops": hl["peaks"],
         "cpu_baseline": cpu,
-        "logdet": ld,
-        "analyse_s": round(t_analyse, 3),
+        "extras": extras,
+        "logdet": hl["logdet"],
+        "analyse_s": round(hl["analyse_s"], 3),
     }
     print(json.dumps(line), flush=True)
 

@@ -183,12 +183,15 @@ int stc_get_work(const stc_handle* h, double* work);
 /* Measurement helper: one factorization of d_values (device) double[nnz]
    with the same kernels as stc_factorize, launched one by one instead of from
    the graph, with a HIP event pair around each launch on `stream`;
-   synchronizes the stream.  kind_ms (host) double[4] and kind_launches (host)
-   int64[4] receive total kernel milliseconds and launch counts for: value
-   load (fill + scatter), update, POTRF, TRSM.  Leaves the factor resident
-   like stc_factorize. */
+   synchronizes the stream.  kind_ms (host) double[5], kind_launches (host)
+   int64[5] and kind_flops (host) double[5] receive total kernel milliseconds,
+   launch counts and tile-algorithmic flops (the stc_get_work [3] terms of the
+   tasks each launch runs) for: [0] value load (fill + scatter, no flops);
+   [1..4] the level kernel in its four forms: with POTRF work-groups and
+   128 x 128 update blocks, POTRF only, 128 x 128 blocks only, neither.
+   Leaves the factor resident like stc_factorize. */
 int stc_profile_factorize(stc_handle* h, const double* d_values, void* stream, double* kind_ms,
-                          int64_t* kind_launches);
+                          int64_t* kind_launches, double* kind_flops);
 
 /* Measurement helper: FP64 matrix-core (MFMA 16x16x4) issue rate of the
    current device in TFLOP/s, from a kernel that keeps 16 independent

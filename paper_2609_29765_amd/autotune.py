@@ -1,0 +1,62 @@
+"""Tile-size / storage-mode autotuner.
+
+The paper fixes n_b per regime by hand (80 by default, 120 for structured
+sparse problems on its CPU nodes; 512 and beyond on its GPU, Sec. 6.1 and
+Sec. 6.8) and leaves the choice open.  Here the choice is measured: the
+pattern is analysed at every candidate (n_b, storage mode), each candidate's
+captured schedule is replayed on the caller's own values (one value set, or
+the whole batch), and the fastest is kept.  The ordering is computed once, at
+the first candidate, and handed to the others as a given permutation, so the
+candidates differ only in their tiling and schedule.
+"""
+from . import stc
+
+
+def autotune(n, colptr, rowind, values, nbs=(64, 128, 256), modes=("auto",), ordering="auto",
+             batched=False, trials=3, warmup=1):
+    """Return (best Analysis, bound; table of every candidate).
+
+    values: device float64 [nnz] (batched=False) or [B, nnz] (batched=True).
+    Each table row: nb, mode, ms per factorization call, levels, tile flops.
+    Candidates that lose release their workspace.
+    """
+    import torch
+
+    perm = None
+    best = None
+    table = []
+    for nb in nbs:
+        for mode in modes:
+            if perm is None:
+                a = stc.Analysis(n, colptr, rowind, nb=nb, mode=mode, ordering=ordering)
+                perm = a.perm()
+            else:
+                a = stc.Analysis(n, colptr, rowind, nb=nb, mode=mode, ordering="given", perm=perm)
+            a.bind(batch=values.shape[0] if batched else 1)
+
+            def run():
+                if batched:
+                    a.factorize_batched(values)
+                else:
+                    a.factorize(values)
+
+            for _ in range(warmup):
+                run()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(trials):
+                run()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / trials
+            table.append(dict(nb=a.nb, mode=a.mode, ms=round(ms, 4), levels=a.nlevels,
+                              tile_gflop=round(a.work()["flops_tile"] / 1e9, 3)))
+            if best is None or ms < best[0]:
+                if best is not None:
+                    best[1].release()
+                best = (ms, a)
+            else:
+                a.release()
+    return best[1], table

@@ -625,7 +625,9 @@ int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why) {
     u.level = level;
     u.big = (nb >= 128 && c_rows >= 96) ? 1 : 0;
     p->bytes_update += 16.0 * c_rows * (diag ? c_rows : nb);
-    level_at(level);
+    Level& lv = level_at(level);
+    for (const Contrib& c : cs)
+      lv.flops += diag ? (double)c.b_rows * c.b_rows * nb : 2.0 * c.a_rows * c.b_rows * nb;
     p->upd.push_back(u);
     return (int32_t)p->upd.size() - 1;
   };
@@ -716,6 +718,7 @@ int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why) {
     } else if (op == kPotrf) {
       lvP[k] = lvU_diag[k] + 1;  // 0 when nothing updates the diagonal tile
       level_at(lvP[k]).potrf.push_back(k);
+      level_at(lvP[k]).flops += (double)p->diag_h[k] * p->diag_h[k] * p->diag_h[k] / 3.0;
       flops += (double)p->diag_h[k] * p->diag_h[k] * p->diag_h[k] / 3.0;
       p->flops_potrf += (double)p->diag_h[k] * p->diag_h[k] * p->diag_h[k] / 3.0;
       ++a;
@@ -731,6 +734,7 @@ int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why) {
       trsm_of_tile[t] = id;
       lvT[t] = std::max(lvU_tile[t], lvP[k]) + 1;
       Level& L = level_at(lvT[t]);
+      L.flops += (double)tt.rows * nb * nb;
       for (int32_t x = 0; x < (tt.rows + br - 1) / br; ++x) {
         L.trsm_items.push_back(id);
         L.trsm_items.push_back(x);

@@ -102,6 +102,7 @@ struct Level {
   std::vector<int32_t> upd_items;   // quads: task, block row, block col, part (64 blocks)
   std::vector<int32_t> potrf;       // block columns
   std::vector<int32_t> trsm_items;  // pairs: trsm task, row block
+  double flops = 0;                 // tile-algorithmic flops of the level's tasks
 };
 
 struct Plan {

@@ -163,26 +163,32 @@ int upload(T* dst, const std::vector<T>& src) {
 
 // event pairs around individual launches (measurement only)
 struct Prof {
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+  struct Mark {
+    int kind;
+    double flops;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
   int begin(hipStream_t st, hipEvent_t* a) {
     HIPCHK(hipEventCreate(a));
     HIPCHK(hipEventRecord(*a, st));
     return 0;
   }
-  int end(int kind, hipStream_t st, hipEvent_t a) {
+  int end(int kind, double flops, hipStream_t st, hipEvent_t a) {
     hipEvent_t b;
     HIPCHK(hipEventCreate(&b));
     HIPCHK(hipEventRecord(b, st));
-    marks.push_back({kind, {a, b}});
+    marks.push_back({kind, flops, a, b});
     return 0;
   }
 };
 
-enum { kKindLoad = 0, kKindUpdate = 1, kKindPotrf = 2, kKindTrsm = 3 };
+// measurement kinds: the value load, and the four instantiations of the
+// level kernel (with/without POTRF work-groups, with/without 128-blocks)
+enum { kKindLoad = 0, kKindLevelPG = 1, kKindLevelP = 2, kKindLevelG = 3, kKindLevel = 4, kKinds = 5 };
 
 // launch every level of the schedule for `members` value sets, one kernel per
-// level; with prof, each level is timed and charged to the kind that
-// dominates it (POTRF if present, else update, else TRSM)
+// level; with prof, each launch is timed and charged to its instantiation
 template <int NB>
 int launch_levels_nb(stc_handle* h, int32_t members, hipStream_t st, Prof* prof) {
   LevelArgs a;
@@ -199,7 +205,8 @@ int launch_levels_nb(stc_handle* h, int32_t members, hipStream_t st, Prof* prof)
   a.parts = h->d_parts;
   a.pstride = h->plan.parts;
   hipEvent_t ev = nullptr;
-  for (const LevelOffsets& L : h->lv) {
+  for (size_t li = 0; li < h->lv.size(); ++li) {
+    const LevelOffsets& L = h->lv[li];
     const int32_t total = L.p_cnt + L.g_cnt + L.u_cnt + L.t_cnt;
     if (!total) continue;
     a.potrf = h->d_potrf + L.p_off;
@@ -215,7 +222,7 @@ int launch_levels_nb(stc_handle* h, int32_t members, hipStream_t st, Prof* prof)
     if (L.g_cnt) lds = std::max(lds, UPD2_LDS);
     if (L.u_cnt) lds = std::max(lds, UPD_LDS);
     if (L.t_cnt) lds = std::max(lds, trsm_lds<NB>());
-    const int kind = L.p_cnt ? kKindPotrf : ((L.u_cnt || L.g_cnt) ? kKindUpdate : kKindTrsm);
+    const int kind = L.p_cnt ? (L.g_cnt ? kKindLevelPG : kKindLevelP) : (L.g_cnt ? kKindLevelG : kKindLevel);
     if (prof && prof->begin(st, &ev)) return STC_ERR_HIP;
     const dim3 grid(total, members);
     const size_t shm = sizeof(double) * lds;
@@ -227,7 +234,7 @@ int launch_levels_nb(stc_handle* h, int32_t members, hipStream_t st, Prof* prof)
       hipLaunchKernelGGL((k_level<NB, false, true>), grid, dim3(256), shm, st, a);
     else
       hipLaunchKernelGGL((k_level<NB, false, false>), grid, dim3(256), shm, st, a);
-    if (prof && prof->end(kind, st, ev)) return STC_ERR_HIP;
+    if (prof && prof->end(kind, h->plan.levels[li].flops * members, st, ev)) return STC_ERR_HIP;
   }
   HIPCHK(hipGetLastError());
   return 0;
@@ -296,7 +303,7 @@ int run_factor(stc_handle* h, const double* vals, int32_t members, hipStream_t s
   const int64_t vgrid = std::min<int64_t>(4096, (qnz + 255) / 256);
   hipLaunchKernelGGL(k_value_load, dim3((unsigned)vgrid, members), dim3(256), 0, st, vals, h->d_vmap,
                      qnz, h->d_store, ms);
-  if (prof && prof->end(kKindLoad, st, ev)) return STC_ERR_HIP;
+  if (prof && prof->end(kKindLoad, 0.0, st, ev)) return STC_ERR_HIP;
   HIPCHK(hipGetLastError());
   if (prof) {
     rc = launch_levels(h, members, st, prof);
@@ -713,10 +720,10 @@ int stc_get_work(const stc_handle* h, double* w) {
 }
 
 int stc_profile_factorize(stc_handle* h, const double* d_values, void* stream, double* kind_ms,
-                          int64_t* kind_launches) {
+                          int64_t* kind_launches, double* kind_flops) {
   int rc = check_bound(h);
   if (rc) return rc;
-  if (!d_values || !kind_ms || !kind_launches) return fail(STC_ERR_ARG, "null argument");
+  if (!d_values || !kind_ms || !kind_launches || !kind_flops) return fail(STC_ERR_ARG, "null argument");
   hipStream_t st = (hipStream_t)stream;
   Prof prof;
   rc = run_factor(h, d_values, 1, st, &prof);
@@ -724,18 +731,20 @@ int stc_profile_factorize(stc_handle* h, const double* d_values, void* stream, d
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) rc = fail(STC_ERR_HIP, hipGetErrorString(e));
   }
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < kKinds; ++k) {
     kind_ms[k] = 0.0;
     kind_launches[k] = 0;
+    kind_flops[k] = 0.0;
   }
   for (auto& m : prof.marks) {
     float t = 0.f;
-    if (rc == 0 && hipEventElapsedTime(&t, m.second.first, m.second.second) == hipSuccess) {
-      kind_ms[m.first] += t;
-      kind_launches[m.first] += 1;
+    if (rc == 0 && hipEventElapsedTime(&t, m.a, m.b) == hipSuccess) {
+      kind_ms[m.kind] += t;
+      kind_launches[m.kind] += 1;
+      kind_flops[m.kind] += m.flops;
     }
-    (void)hipEventDestroy(m.second.first);
-    (void)hipEventDestroy(m.second.second);
+    (void)hipEventDestroy(m.a);
+    (void)hipEventDestroy(m.b);
   }
   if (rc) return rc;
   h->last_stream = st;

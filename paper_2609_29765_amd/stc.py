@@ -76,7 +76,7 @@ def lib():
     L.stc_get_tasks.argtypes = [vp, _i32p]
     L.stc_get_factor.argtypes = [vp, _f64p, vp]
     L.stc_get_work.argtypes = [vp, _f64p]
-    L.stc_profile_factorize.argtypes = [vp, vp, vp, _f64p, _i64p]
+    L.stc_profile_factorize.argtypes = [vp, vp, vp, _f64p, _i64p, _f64p]
     L.stc_fp64_mfma_peak.argtypes = [vp, _f64p]
     L.stc_destroy.argtypes = [vp]
     L.stc_destroy.restype = None
@@ -202,6 +202,16 @@ class Analysis:
         if self._ws is None:
             self.bind()
 
+    def release(self):
+        """Drop the workspace; the next factorize binds a new one."""
+        self._ws = None
+        self.batch = 0
+
+    def _ws_device(self):
+        if self._ws is None:
+            raise RuntimeError("the analysis is not bound to a workspace (factorize first)")
+        return self._ws.device
+
     # ---------------------------------------------------------------- numeric
     def factorize(self, values):
         """values: device float64 tensor [nnz] in the analysed CSC entry order."""
@@ -231,13 +241,14 @@ class Analysis:
 
     def logdet(self):
         import torch
-        out = torch.empty(1, dtype=torch.float64, device=self._ws.device)
+        out = torch.empty(1, dtype=torch.float64, device=self._ws_device())
         _check(lib().stc_logdet(self._h, _dptr(out), _stream_ptr()))
         return out[0]
 
     def solve(self, b):
         """Solve A x = b; b device float64 [n] or [n, nrhs] (column-major copy made)."""
         _need_cuda(b)
+        self._ws_device()
         one = b.dim() == 1
         B = b.reshape(self.n, -1)
         nrhs = B.shape[1]
@@ -249,7 +260,7 @@ class Analysis:
     def logdet_backward(self, gbar):
         import torch
         g = gbar.reshape(1).to(torch.float64).contiguous()
-        out = torch.empty(self.qnz, dtype=torch.float64, device=self._ws.device)
+        out = torch.empty(self.qnz, dtype=torch.float64, device=self._ws_device())
         _check(lib().stc_logdet_backward(self._h, _dptr(g), _dptr(out), _stream_ptr()))
         return out
 
@@ -261,23 +272,29 @@ class Analysis:
                 "bytes_update", "bytes_load", "levels", "flops_backward", "levels_backward"]
         return dict(zip(keys, (float(x) for x in w)))
 
+    KERNEL_KINDS = ["load", "k_level<P,G>", "k_level<P>", "k_level<G>", "k_level"]
+
     def profile_factorize(self, values):
-        """Per-kernel-kind event timing of one eager factorization."""
+        """Event timing of one eager factorization, per kernel form:
+        {kind: (ms, launches, flops)} (see stc_profile_factorize)."""
         self._bound()
         _need_cuda(values)
-        ms = np.zeros(4)
-        cnt = np.zeros(4, np.int64)
-        _check(lib().stc_profile_factorize(self._h, _dptr(values), _stream_ptr(), ms, cnt))
-        kinds = ["load", "update", "potrf", "trsm"]
-        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(kinds)}
+        ms = np.zeros(5)
+        cnt = np.zeros(5, np.int64)
+        fl = np.zeros(5)
+        _check(lib().stc_profile_factorize(self._h, _dptr(values), _stream_ptr(), ms, cnt, fl))
+        self._fact_id = getattr(self, "_fact_id", 0) + 1
+        return {k: (float(ms[i]), int(cnt[i]), float(fl[i])) for i, k in enumerate(self.KERNEL_KINDS)}
 
     def info(self):
+        self._ws_device()
         v = C.c_int32()
         _check(lib().stc_info(self._h, C.byref(v)))
         return int(v.value)
 
     def factor(self):
         """Host copy of L in L_pattern() order."""
+        self._ws_device()
         Lx = np.zeros(self.lnz)
         _check(lib().stc_get_factor(self._h, Lx, _stream_ptr()))
         return Lx
