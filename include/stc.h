@@ -79,6 +79,9 @@ typedef struct {
   int32_t mode;          /* STC_MODE_*                                           */
   int32_t ordering;      /* STC_ORD_*                                            */
   const int32_t* perm;   /* (host) perm[new] = old, read when ordering == GIVEN  */
+  int32_t split_target;  /* schedule: work items per level that splitting long
+                            update chains (deterministic split-K) aims for;
+                            0 = 1024.  Changes timing only, not results.      */
 } stc_opts;
 
 /* Analyse a sparsity pattern once (Sec. 3, Sec. 5.1-5.2).

@@ -526,11 +526,12 @@ int analyse(int64_t n, const int64_t* cp, const int32_t* ri, int method, int nb,
 // execution plan
 // ---------------------------------------------------------------------------
 
-int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why) {
+int build_plan(const Symbolic& s, int bm, int br, int64_t split_target, Plan* p, std::string* why) {
   const int32_t nb = s.nb, NT = s.NT;
   const int64_t n = s.n;
   (void)why;
   *p = Plan();
+  if (split_target > 0) p->split_target = split_target;
   p->nb = nb;
   p->NT = NT;
   p->bm = bm;
@@ -755,14 +756,21 @@ int build_plan(const Symbolic& s, int bm, int br, Plan* p, std::string* why) {
       const int64_t nr = (u.c_rows + b - 1) / b;
       return u.diag ? nr * (nr + 1) / 2 : nr * ((nb + b - 1) / b);
     };
+    // a level with few 128-blocks runs them as 64-blocks: four times the
+    // work-groups for the same work
+    std::vector<int64_t> bigblocks((size_t)nlev, 0);
+    for (const UpdTask& u : p->upd)
+      if (u.big) bigblocks[(size_t)u.level] += blocks(u);
+    for (UpdTask& u : p->upd)
+      if (u.big && bigblocks[(size_t)u.level] < 64 && u.c_end - u.c_begin <= 2) u.big = 0;
     for (const UpdTask& u : p->upd) items[(size_t)u.level] += blocks(u);
-    const int64_t target = 512;
+    const int64_t target = p->split_target;
     for (UpdTask& u : p->upd) {
       if (!u.big || u.partner < 0) continue;
       const int64_t have = items[(size_t)u.level];
       if (have >= target) continue;
       const int32_t ncon = u.c_end - u.c_begin;
-      int32_t sp = (int32_t)std::min<int64_t>(8, (target + have - 1) / have);
+      int32_t sp = (int32_t)std::min<int64_t>(16, (target + have - 1) / have);
       sp = std::min(sp, ncon / 2);
       if (sp < 2) continue;
       u.nsplit = sp;

@@ -337,17 +337,18 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
 constexpr int PW = 32;
 constexpr int PLD = PW + 1;
 
-// Cholesky of the 32 x 32 block held in P's first 32 rows, by one wave,
-// without branches: lane r keeps row r (r = lane mod 32) in registers; at
-// step c every lane publishes its unscaled column-c entry in a 32-entry LDS
-// vector and reads the pivot and the other rows' entries back with uniform
-// addresses (broadcast), so row r's update is a[j] -= (a_rc / d) a_jc.  The
-// wave's LDS operations execute in program order, so the reads see the
-// writes of the same step.  Lanes 32..63 mirror lanes 0..31 and write the
-// same values.  Then the inverse of the factor, column r by lane r, with the
-// rows of L broadcast from P.  Writes L (lower, diagonal included) to P and
-// the inverse to Z (row-major, stride PLD).  Returns the first failing
-// pivot (0-based) or -1; uniform across the wave.
+// Cholesky of the 32 x 32 block held in P's first 32 rows and the inverse of
+// the factor, by one wave.  Lanes 0..31 hold row r of A in registers and run
+// the left-looking (Crout) recurrence L_rc = (A_rc - sum_{p<c} L_rp L_cp) / L_cc;
+// lanes 32..63 hold the unit vector e_r and run forward substitution for
+// column r of L^-1, z_c = (e_rc - sum_{p<c} L_cp z_p) / L_cc -- the same
+// expression on different registers, so one instruction stream serves both
+// and both read row c of L by LDS broadcast.  The pivot L_cc^2 is lane c's
+// value of that expression, taken by readlane.  The reads of a step precede
+// its write in program order, and a wave's LDS operations execute in that
+// order.  Writes L (lower, diagonal included, zeros above) to P, the inverse
+// (row-major, stride PLD) to Z and 1 / L_cc to rdiag.  Returns the first
+// failing pivot (0-based) or -1; uniform across the wave.
 __device__ __forceinline__ double rcp_nr(double d) {
   double r = __builtin_amdgcn_rcp(d);
   r = fma(fma(-d, r, 1.0), r, r);
@@ -361,53 +362,39 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
 }
 
 __device__ __forceinline__ int chol32_wave(double* P, double* Z, double* rdiag, int lane) {
-  // row-oriented left-looking (Crout): lane r < 32 owns row r in registers
-  // and at step c computes L_rc = (A_rc - sum_{p<c} L_rp L_cp) / L_cc; row c
-  // of L (written to P by lane c in earlier steps) is read back by broadcast,
-  // and every lane forms the pivot L_cc^2 = A_cc - sum_p L_cp^2 itself.  The
-  // reads of a step precede its write in program order, and the wave's LDS
-  // operations execute in that order.  Lanes 32..63 mirror lanes 0..31.
   const int r = lane & 31;
-  double a[PW];
+  const bool lo = lane < 32;
+  double x[PW];
 #pragma unroll
-  for (int j = 0; j < PW; ++j) a[j] = P[r * PLD + j];
+  for (int j = 0; j < PW; ++j) {
+    const double a = P[r * PLD + j];
+    x[j] = lo ? a : (j == r ? 1.0 : 0.0);
+  }
   int bad = -1;
 #pragma unroll
   for (int c = 0; c < PW; ++c) {
-    double s0 = 0.0, s1 = 0.0, q0 = 0.0, q1 = 0.0;
+    double s0 = 0.0, s1 = 0.0;
 #pragma unroll
     for (int p = 0; p < c; ++p) {
-      const double m = P[c * PLD + p];
-      if (p & 1) {
-        s1 = fma(a[p], m, s1);
-        q1 = fma(m, m, q1);
-      } else {
-        s0 = fma(a[p], m, s0);
-        q0 = fma(m, m, q0);
-      }
+      if (p & 1) s1 = fma(x[p], P[c * PLD + p], s1);
+      else s0 = fma(x[p], P[c * PLD + p], s0);
     }
-    const double d = P[c * PLD + c] - (q0 + q1);
+    const double t = x[c] - (s0 + s1);
+    const int dlo = __builtin_amdgcn_readlane(__double2loint(t), c);
+    const int dhi = __builtin_amdgcn_readlane(__double2hiint(t), c);
+    const double d = __hiloint2double(dhi, dlo);
     bad = (bad < 0 && (!(d > 0.0) || !isfinite(d))) ? c : bad;
     const double rs = rsqrt_nr(d);  // 1 / L_cc
-    const double v = (r > c) ? (a[c] - (s0 + s1)) * rs : ((r == c) ? d * rs : 0.0);
-    a[c] = v;
+    const double v = (lo && r < c) ? 0.0 : t * rs;
+    x[c] = v;
     __builtin_amdgcn_wave_barrier();
-    P[r * PLD + c] = v;
-    if (r == c) rdiag[c] = rs;
+    if (lo) P[r * PLD + c] = v;
+    if (lane == c) rdiag[c] = rs;
     __builtin_amdgcn_wave_barrier();
   }
-  // inverse: lane r solves L z = e_r, rows of L broadcast from P
-  double z[PW];
+  if (!lo) {
 #pragma unroll
-  for (int i = 0; i < PW; ++i) {
-    double v = (i == r) ? 1.0 : 0.0;
-#pragma unroll
-    for (int q = 0; q < i; ++q) v -= P[i * PLD + q] * z[q];
-    z[i] = v * rdiag[i];
-  }
-  if (lane < PW) {
-#pragma unroll
-    for (int j = 0; j < PW; ++j) Z[j * PLD + r] = z[j];
+    for (int j = 0; j < PW; ++j) Z[j * PLD + r] = x[j];
   }
   return bad;
 }

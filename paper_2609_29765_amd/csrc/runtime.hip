@@ -393,11 +393,12 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
                 stc_handle** out) {
   if (!out) return fail(STC_ERR_ARG, "null output handle");
   *out = nullptr;
-  stc_opts o{64, STC_MODE_AUTO, STC_ORD_AUTO, nullptr};
+  stc_opts o{64, STC_MODE_AUTO, STC_ORD_AUTO, nullptr, 0};
   if (opts) o = *opts;
   if (o.nb == 0) o.nb = 64;
   if (o.nb != 32 && o.nb != 64 && o.nb != 128 && o.nb != 256)
     return fail(STC_ERR_ARG, "nb must be 32, 64, 128 or 256");
+  if (o.split_target < 0) return fail(STC_ERR_ARG, "split_target must be >= 0");
   try {
     auto* h = new stc_handle();
     std::string why;
@@ -406,7 +407,7 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
       delete h;
       return fail(rc, why);
     }
-    rc = build_plan(h->sym, UB, TR, &h->plan, &why);
+    rc = build_plan(h->sym, UB, TR, o.split_target, &h->plan, &why);
     if (rc == 0) rc = build_backward(h->sym, &h->plan, &h->back, &why);
     if (rc) {
       delete h;
