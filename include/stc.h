@@ -8,8 +8,8 @@
  * its factor L with P A P^T = L L^T is computed many times for new values by
  * replaying one static POTRF/SYRK/GEMM/TRSM tile schedule (Algorithm 1), the
  * factor staying resident on the device where the log-determinant and solves
- * consume it (Sec. 6.8).  The split of a once-per-pattern analysis from a
- * repeated factorization is the interface the paper states (Sec. 6.7).
+ * consume it (Sec. 6.7).  The split of a once-per-pattern analysis from a
+ * repeated factorization is the interface the paper states (Sec. 6.6).
  *
  * Conventions shared by every entry point
  *   - Return value: 0 on success; negative for usage errors (STC_ERR_*);
@@ -130,18 +130,18 @@ int stc_logdet(stc_handle* h, double* d_out, void* stream);
    double[n * nrhs], column-major, original numbering, 1 <= nrhs <= 64. */
 int stc_solve(stc_handle* h, double* d_b, int32_t nrhs, void* stream);
 
-/* Reverse mode of logdet through the last single factorization (the
-   differentiable factorization of Sec. 6.8): given the scalar cotangent d_gbar
-   (device) double[1], writes d_grad_values (device) double[nnz] in the
-   analysed CSC entry order, the symmetric matrix being parameterised by its
-   lower triangle: gbar * 2 (A^-1)_ij off the diagonal and gbar * (A^-1)_ii on
-   it.  For this cotangent the adjoint of the tile Cholesky restricted to the
-   pattern of L is the selected inverse Z = A^-1 on that pattern, computed on
-   the device by the blocked Takahashi recurrence over the tile DAG in reverse
-   order (one graph launch), from the factor and the 32 x 32 diagonal-block
-   inverses the factorization left in the workspace.  Writes NaN everywhere
-   when that factorization failed (stc_info != 0).  Overwrites the workspace's
-   selected-inverse scratch; the factor is left intact. */
+/* Reverse mode of logdet through the last single factorization: given the
+   scalar cotangent d_gbar (device) double[1], writes d_grad_values (device)
+   double[nnz] in the analysed CSC entry order, the symmetric matrix being
+   parameterised by its lower triangle: gbar * 2 (A^-1)_ij off the diagonal and
+   gbar * (A^-1)_ii on it.  For this cotangent the adjoint of the tile Cholesky
+   restricted to the pattern of L is the selected inverse Z = A^-1 on that
+   pattern (the selected inversion that consumes the resident factor, Sec.
+   6.7), computed on the device by the blocked Takahashi recurrence over the
+   tile DAG in reverse order (one graph launch), from the factor and the 32 x
+   32 diagonal-block inverses the factorization left in the workspace.  Writes
+   NaN everywhere when that factorization failed (stc_info != 0).  Overwrites
+   the workspace's selected-inverse scratch; the factor is left intact. */
 int stc_logdet_backward(stc_handle* h, const double* d_gbar, double* d_grad_values, void* stream);
 
 /* Status of the last single factorization; synchronizes the bound stream.

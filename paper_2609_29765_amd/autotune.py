@@ -2,7 +2,7 @@
 
 The paper fixes n_b per regime by hand (80 by default, 120 for structured
 sparse problems on its CPU nodes; 512 and beyond on its GPU, Sec. 6.1 and
-Sec. 6.8) and leaves the choice open.  Here the choice is measured: the
+Sec. 6.7) and leaves the choice open.  Here the choice is measured: the
 pattern is analysed at every candidate (n_b, storage mode), each candidate's
 captured schedule is replayed on the caller's own values (one value set, or
 the whole batch), and the fastest is kept.  The ordering is computed once, at

@@ -1,8 +1,9 @@
-"""GPU parity of the logdet reverse mode (the differentiable factorization of
-Sec. 6.8): library gradient values against the oracle's selected inverse, the
-parameter gradient of the differentiable arrowhead against the oracle's trace
-tr(Q^-1 dQ/dtheta) and against central finite differences of the library's
-own logdet, and the autograd wiring.
+"""GPU parity of the logdet reverse mode.  Its gradient is the selected
+inverse on the pattern of L, one of the consumers of the resident factor the
+paper lists (Sec. 6.7).  Checked here: library gradient values against the
+oracle's selected inverse; the parameter gradient of the differentiable
+arrowhead against the oracle's trace tr(Q^-1 dQ/dtheta) and against central
+finite differences of the library's own logdet; the autograd wiring.
 
 Tolerances: gradient values ||g - g_o||_inf <= 1e-10 ||g_o||_inf (the
 selected inverse reuses the factor, whose entries agree to 1e-10 relative);
