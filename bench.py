@@ -7,8 +7,9 @@ whole POTRF/SYRK/GEMM/TRSM tile schedule (one HIP-graph replay), values
 already resident in HBM.
 
 Prints one JSON line.  Besides the headline value it carries:
-  roofline      the level kernel form that takes most of the factorization
-                time: tile-algorithmic flops of the tasks it runs per launch /
+  roofline      the level kernel (POTRF, updates with or without 128-blocks,
+                TRSM) that takes most of the factorization time:
+                tile-algorithmic flops of the tasks it runs per launch /
                 its event-timed average launch duration, against the FP64
                 matrix peak of 78.6 TFLOP/s; HBM traffic per launch from the
                 committed counter summary when it matches the current kernels;
@@ -119,8 +120,8 @@ def headline(args):
     assert a.info() == 0
     log(f"{args.steps} steps {ms_step:.3f} ms/step logdet={ld:.6f}")
 
-    # per-launch event timing of eager factorizations (same kernels, same
-    # stream), charged to the level-kernel form each launch uses
+    # per-launch event timing of eager factorizations (same kernels, one
+    # stream), charged to the kernel each launch uses
     agg = {}
     for _ in range(args.prof_reps):
         for k, (ms, cnt, fl) in a.profile_factorize(vals).items():
@@ -132,8 +133,8 @@ def headline(args):
     avg_ms = ms_d / cnt_d
     flops_per_launch = fl_d / cnt_d
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
-    symbol = {"k_level<P,G>": f"k_level<{a.nb}, true, true>", "k_level<P>": f"k_level<{a.nb}, true, false>",
-              "k_level<G>": f"k_level<{a.nb}, false, true>", "k_level": f"k_level<{a.nb}, false, false>"}[dom]
+    symbol = {"k_potrf": f"k_potrf<{a.nb}>", "k_upd<G>": f"k_upd<{a.nb}, true>",
+              "k_upd": f"k_upd<{a.nb}, false>", "k_trsm": f"k_trsm<{a.nb}>"}[dom]
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "traffic_dense12288_nb256.json")
     if os.path.exists(tfile):

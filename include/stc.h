@@ -190,9 +190,10 @@ int stc_get_work(const stc_handle* h, double* work);
    int64[5] and kind_flops (host) double[5] receive total kernel milliseconds,
    launch counts and tile-algorithmic flops (the stc_get_work [3] terms of the
    tasks each launch runs) for: [0] value load (fill + scatter, no flops);
-   [1..4] the level kernel in its four forms: with POTRF work-groups and
-   128 x 128 update blocks, POTRF only, 128 x 128 blocks only, neither.
-   Leaves the factor resident like stc_factorize. */
+   [1] POTRF; [2] updates with 128 x 128 blocks; [3] updates with 64 x 64
+   blocks only; [4] TRSM.  In the graph the kernels of one level run
+   concurrently; here they run one after the other.  Leaves the factor
+   resident like stc_factorize. */
 int stc_profile_factorize(stc_handle* h, const double* d_values, void* stream, double* kind_ms,
                           int64_t* kind_launches, double* kind_flops);
 

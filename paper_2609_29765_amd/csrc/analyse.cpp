@@ -627,8 +627,11 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t split_target, Plan* p,
     u.big = (nb >= 128 && c_rows >= 96) ? 1 : 0;
     p->bytes_update += 16.0 * c_rows * (diag ? c_rows : nb);
     Level& lv = level_at(level);
-    for (const Contrib& c : cs)
-      lv.flops += diag ? (double)c.b_rows * c.b_rows * nb : 2.0 * c.a_rows * c.b_rows * nb;
+    for (const Contrib& c : cs) {
+      const double f = diag ? (double)c.b_rows * c.b_rows * nb : 2.0 * c.a_rows * c.b_rows * nb;
+      lv.flops += f;
+      lv.flops_upd += f;
+    }
     p->upd.push_back(u);
     return (int32_t)p->upd.size() - 1;
   };
@@ -720,6 +723,7 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t split_target, Plan* p,
       lvP[k] = lvU_diag[k] + 1;  // 0 when nothing updates the diagonal tile
       level_at(lvP[k]).potrf.push_back(k);
       level_at(lvP[k]).flops += (double)p->diag_h[k] * p->diag_h[k] * p->diag_h[k] / 3.0;
+      level_at(lvP[k]).flops_potrf += (double)p->diag_h[k] * p->diag_h[k] * p->diag_h[k] / 3.0;
       flops += (double)p->diag_h[k] * p->diag_h[k] * p->diag_h[k] / 3.0;
       p->flops_potrf += (double)p->diag_h[k] * p->diag_h[k] * p->diag_h[k] / 3.0;
       ++a;
@@ -736,6 +740,7 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t split_target, Plan* p,
       lvT[t] = std::max(lvU_tile[t], lvP[k]) + 1;
       Level& L = level_at(lvT[t]);
       L.flops += (double)tt.rows * nb * nb;
+      L.flops_trsm += (double)tt.rows * nb * nb;
       for (int32_t x = 0; x < (tt.rows + br - 1) / br; ++x) {
         L.trsm_items.push_back(id);
         L.trsm_items.push_back(x);

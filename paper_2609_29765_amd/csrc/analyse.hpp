@@ -103,6 +103,7 @@ struct Level {
   std::vector<int32_t> potrf;       // block columns
   std::vector<int32_t> trsm_items;  // pairs: trsm task, row block
   double flops = 0;                 // tile-algorithmic flops of the level's tasks
+  double flops_potrf = 0, flops_upd = 0, flops_trsm = 0;  // the same, by kernel
 };
 
 struct Plan {

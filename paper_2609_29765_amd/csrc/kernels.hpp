@@ -291,10 +291,12 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
         }
     return;
   }
-  for (int q = 0; q < u.in_npart; ++q) {
-    const double* pq = parts + u.in_part_off + q * slot;
+  // one 16-row block at a time: its partial slots and C values are read
+  // together (addresses clamped into the tile), then the stores are masked
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 4; ++a) {
+    for (int q = 0; q < u.in_npart; ++q) {
+      const double* pq = parts + u.in_part_off + q * slot;
 #pragma unroll
       for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -303,20 +305,16 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
           const int32_t j = min(c0 + wc + b * 16 + (lane & 15), ncols - 1);
           acc[a][b][e] += pq[(int64_t)i * NB + j];
         }
-  }
-  double cv[4][4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
+    }
+    double cv[4][4];
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int32_t i = min(r0 + wr + a * 16 + (lane >> 4) + 4 * e, u.c_rows - 1);
         const int32_t j = min(c0 + wc + b * 16 + (lane & 15), ncols - 1);
-        cv[a][b][e] = C[(int64_t)i * NB + j];
+        cv[b][e] = C[(int64_t)i * NB + j];
       }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -324,8 +322,9 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
         const int32_t i = r0 + wr + a * 16 + (lane >> 4) + 4 * e;
         const int32_t j = c0 + wc + b * 16 + (lane & 15);
         if (i < u.c_rows && j < ncols && (!u.diag || j <= i))
-          C[(int64_t)i * NB + j] = cv[a][b][e] - acc[a][b][e];
+          C[(int64_t)i * NB + j] = cv[b][e] - acc[a][b][e];
       }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -420,23 +419,22 @@ __device__ __forceinline__ void dev_potrf(int32_t k, double* __restrict__ S,
   double* dinv = dinv_m + (int64_t)k * NB * PW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int PER = NB * PW / 256;            // elements per thread of a full-height panel
+  const int trow = tid >> 5, tcol = tid & 31;   // 8 rows x 32 columns per pass
   constexpr int RBW = NB >= 64 ? NB / 64 : 1;  // row blocks per wave at most
   for (int j0 = 0; j0 < NB; j0 += PW) {
     const int pr = NB - j0;
-    // panel load: every lane loads (clamped rows); rows past pr land in LDS
-    // rows nobody reads
+    // panel load: thread (trow, tcol) takes rows q*8 + trow; pr is a
+    // multiple of 32, so a whole group of 8 rows is in or out (uniform skip)
+    // and every address is one base plus a uniform offset
     {
       double v[PER];
+      const double* src = A + (int64_t)(j0 + trow) * NB + j0 + tcol;
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int x = q * 256 + tid, rr = min(x / PW, pr - 1), c = x % PW;
-        v[q] = A[(int64_t)(j0 + rr) * NB + j0 + c];
-      }
+      for (int q = 0; q < PER; ++q)
+        if (q * 8 < pr) v[q] = src[(int64_t)q * 8 * NB];
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int x = q * 256 + tid;
-        P[(x / PW) * PLD + x % PW] = v[q];
-      }
+      for (int q = 0; q < PER; ++q)
+        if (q * 8 < pr) P[(q * 8 + trow) * PLD + tcol] = v[q];
     }
     if (j0 > 0) {
       // P -= L[j0:, :j0] L[j0:j0+32, :j0]^T: 32-column slabs of the factored
@@ -446,25 +444,20 @@ __device__ __forceinline__ void dev_potrf(int32_t k, double* __restrict__ S,
 #pragma unroll
       for (int i = 0; i < RBW; ++i) acc[i][0] = acc[i][1] = d4{0.0, 0.0, 0.0, 0.0};
       double v[PER];
+      const double* src = A + (int64_t)(j0 + trow) * NB + tcol;
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int x = q * 256 + tid, rr = min(x / PW, pr - 1), c = x % PW;
-        v[q] = A[(int64_t)(j0 + rr) * NB + c];
-      }
+      for (int q = 0; q < PER; ++q)
+        if (q * 8 < pr) v[q] = src[(int64_t)q * 8 * NB];
       for (int s0 = 0; s0 < j0; s0 += PW) {
         __syncthreads();  // previous slab fully consumed
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-          const int x = q * 256 + tid;
-          Sl[(x / PW) * PLD + x % PW] = v[q];
-        }
+        for (int q = 0; q < PER; ++q)
+          if (q * 8 < pr) Sl[(q * 8 + trow) * PLD + tcol] = v[q];
         __syncthreads();
         if (s0 + PW < j0) {
 #pragma unroll
-          for (int q = 0; q < PER; ++q) {
-            const int x = q * 256 + tid, rr = min(x / PW, pr - 1), c = x % PW;
-            v[q] = A[(int64_t)(j0 + rr) * NB + s0 + PW + c];
-          }
+          for (int q = 0; q < PER; ++q)
+            if (q * 8 < pr) v[q] = src[(int64_t)q * 8 * NB + s0 + PW];
         }
 #pragma unroll
         for (int i = 0; i < RBW; ++i) {
@@ -473,7 +466,7 @@ __device__ __forceinline__ void dev_potrf(int32_t k, double* __restrict__ S,
             const double* pa = Sl + (t * 16 + (lane & 15)) * PLD + (lane >> 4);
             const double* pb0 = Sl + (lane & 15) * PLD + (lane >> 4);
             const double* pb1 = Sl + (16 + (lane & 15)) * PLD + (lane >> 4);
-#pragma unroll
+#pragma unroll 2
             for (int kk = 0; kk < PW; kk += 4) {
               acc[i][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[kk], pb0[kk], acc[i][0], 0, 0, 0);
               acc[i][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[kk], pb1[kk], acc[i][1], 0, 0, 0);
@@ -522,10 +515,13 @@ __device__ __forceinline__ void dev_potrf(int32_t k, double* __restrict__ S,
     }
     for (int x = tid; x < PW * PW; x += 256) dinv[(j0 / PW) * PW * PW + x] = Z[(x / PW) * PLD + x % PW];
     __syncthreads();
+    {
+      double* dst = A + (int64_t)(j0 + trow) * NB + j0 + tcol;
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int x = q * 256 + tid, r = x / PW, c = x % PW;
-      if (r < pr && (c <= r || r >= PW)) A[(int64_t)(j0 + r) * NB + j0 + c] = P[r * PLD + c];
+      for (int q = 0; q < PER; ++q) {
+        const int r = q * 8 + trow;
+        if (q * 8 < pr && (tcol <= r || r >= PW)) dst[(int64_t)q * 8 * NB] = P[r * PLD + tcol];
+      }
     }
     __syncthreads();
   }
@@ -656,32 +652,41 @@ struct LevelArgs {
   int32_t nreal;
 };
 
-// HAS_P / HAS_G compile the POTRF and 128-block paths in or out, so a level
-// without them keeps the smaller register footprint of the remaining paths
-template <int NB, bool HAS_P, bool HAS_G>
-__global__ __launch_bounds__(256) void k_level(LevelArgs a) {
+// The kernels of one level.  POTRF, the update blocks and the TRSM items of a
+// level are independent of each other, so they are separate kernels (each
+// with its own LDS and register budget, which sets how many work-groups share
+// a compute unit) that the runtime runs concurrently on forked graph branches.
+template <int NB>
+__global__ __launch_bounds__(256) void k_potrf(LevelArgs a) {
+  extern __shared__ double smem[];
+  const int32_t member = blockIdx.y;
+  dev_potrf<NB>(a.potrf[blockIdx.x], a.store + (int64_t)member * a.mstride,
+                a.dinv + (int64_t)member * a.dstride, a.info + member, a.nreal, smem);
+}
+
+// HAS_G compiles the 128-block path in or out, so a level without it keeps
+// the smaller register footprint of the 64-block path
+template <int NB, bool HAS_G>
+__global__ __launch_bounds__(256, 2) void k_upd(LevelArgs a) {
   extern __shared__ double smem[];
   const int32_t member = blockIdx.y;
   double* S = a.store + (int64_t)member * a.mstride;
-  int32_t b = blockIdx.x;
-  if (HAS_P && b < a.np) {
-    dev_potrf<NB>(a.potrf[b], S, a.dinv + (int64_t)member * a.dstride, a.info + member, a.nreal,
-                  smem);
-    return;
-  }
-  b -= a.np;
   double* parts = a.parts + (int64_t)member * a.pstride;
+  int32_t b = blockIdx.x;
   if (HAS_G && b < a.nbig) {
     if constexpr (NB >= UB2 && HAS_G) dev_update_big<NB>(b, a.big, a.utasks, a.contribs, a.maps, S, parts, smem);
     return;
   }
   b -= a.nbig;
-  if (b < a.nu) {
-    dev_update<NB>(b, a.upd, a.utasks, a.contribs, a.maps, S, parts, smem);
-    return;
-  }
-  b -= a.nu;
-  dev_trsm<NB>(b, a.trsm, a.ttasks, S, a.dinv + (int64_t)member * a.dstride, smem);
+  dev_update<NB>(b, a.upd, a.utasks, a.contribs, a.maps, S, parts, smem);
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_trsm(LevelArgs a) {
+  extern __shared__ double smem[];
+  const int32_t member = blockIdx.y;
+  dev_trsm<NB>(blockIdx.x, a.trsm, a.ttasks, a.store + (int64_t)member * a.mstride,
+               a.dinv + (int64_t)member * a.dstride, smem);
 }
 
 // ---------------------------------------------------------------------------

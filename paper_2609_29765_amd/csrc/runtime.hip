@@ -183,14 +183,36 @@ struct Prof {
   }
 };
 
-// measurement kinds: the value load, and the four instantiations of the
-// level kernel (with/without POTRF work-groups, with/without 128-blocks)
-enum { kKindLoad = 0, kKindLevelPG = 1, kKindLevelP = 2, kKindLevelG = 3, kKindLevel = 4, kKinds = 5 };
+// measurement kinds: the value load and the level kernels
+enum { kKindLoad = 0, kKindPotrf = 1, kKindUpdBig = 2, kKindUpd = 3, kKindTrsm = 4, kKinds = 5 };
 
-// launch every level of the schedule for `members` value sets, one kernel per
-// level; with prof, each launch is timed and charged to its instantiation
+// side streams and events for forking the kernels of a level onto concurrent
+// graph branches during capture (default priority, non-blocking)
+struct Fork {
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+  int make() {
+    for (int i = 0; i < 2; ++i) HIPCHK(hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    for (int i = 0; i < 2; ++i) HIPCHK(hipEventCreateWithFlags(&join[i], hipEventDisableTiming));
+    return 0;
+  }
+  ~Fork() {
+    for (int i = 0; i < 2; ++i) {
+      if (side[i]) (void)hipStreamDestroy(side[i]);
+      if (join[i]) (void)hipEventDestroy(join[i]);
+    }
+    if (fork) (void)hipEventDestroy(fork);
+  }
+};
+
+// launch every level of the schedule for `members` value sets.  A level runs
+// up to three kernels (POTRF, updates, TRSM), which touch disjoint tiles:
+// with `fork` they go on concurrent branches joined before the next level,
+// otherwise one after the other on `st`; with prof, each launch is timed and
+// charged to its kernel with the tile-algorithmic flops of its tasks
 template <int NB>
-int launch_levels_nb(stc_handle* h, int32_t members, hipStream_t st, Prof* prof) {
+int launch_levels_nb(stc_handle* h, int32_t members, hipStream_t st, Prof* prof, Fork* fork) {
   LevelArgs a;
   a.utasks = h->d_upd;
   a.contribs = h->d_contrib;
@@ -207,8 +229,7 @@ int launch_levels_nb(stc_handle* h, int32_t members, hipStream_t st, Prof* prof)
   hipEvent_t ev = nullptr;
   for (size_t li = 0; li < h->lv.size(); ++li) {
     const LevelOffsets& L = h->lv[li];
-    const int32_t total = L.p_cnt + L.g_cnt + L.u_cnt + L.t_cnt;
-    if (!total) continue;
+    const Level& PL = h->plan.levels[li];
     a.potrf = h->d_potrf + L.p_off;
     a.big = h->d_big_items + 4 * (int64_t)L.g_off;
     a.upd = h->d_upd_items + 4 * (int64_t)L.u_off;
@@ -217,35 +238,61 @@ int launch_levels_nb(stc_handle* h, int32_t members, hipStream_t st, Prof* prof)
     a.nbig = L.g_cnt;
     a.nu = L.u_cnt;
     a.nt = L.t_cnt;
-    int lds = 0;
-    if (L.p_cnt) lds = std::max(lds, potrf_lds<NB>());
-    if (L.g_cnt) lds = std::max(lds, UPD2_LDS);
-    if (L.u_cnt) lds = std::max(lds, UPD_LDS);
-    if (L.t_cnt) lds = std::max(lds, trsm_lds<NB>());
-    const int kind = L.p_cnt ? (L.g_cnt ? kKindLevelPG : kKindLevelP) : (L.g_cnt ? kKindLevelG : kKindLevel);
-    if (prof && prof->begin(st, &ev)) return STC_ERR_HIP;
-    const dim3 grid(total, members);
-    const size_t shm = sizeof(double) * lds;
-    if (L.p_cnt && L.g_cnt)
-      hipLaunchKernelGGL((k_level<NB, true, true>), grid, dim3(256), shm, st, a);
-    else if (L.p_cnt)
-      hipLaunchKernelGGL((k_level<NB, true, false>), grid, dim3(256), shm, st, a);
-    else if (L.g_cnt)
-      hipLaunchKernelGGL((k_level<NB, false, true>), grid, dim3(256), shm, st, a);
-    else
-      hipLaunchKernelGGL((k_level<NB, false, false>), grid, dim3(256), shm, st, a);
-    if (prof && prof->end(kind, h->plan.levels[li].flops * members, st, ev)) return STC_ERR_HIP;
+    const bool has_u = L.u_cnt + L.g_cnt > 0;
+    const int nk = (L.p_cnt > 0) + has_u + (L.t_cnt > 0);
+    if (nk == 0) continue;
+    // the update kernel (the largest) stays on st; the others may fork
+    const bool forking = fork && !prof && nk > 1;
+    int nside = 0;
+    if (forking) HIPCHK(hipEventRecord(fork->fork, st));
+    if (L.p_cnt) {
+      hipStream_t s = st;
+      if (forking && (has_u || L.t_cnt)) {
+        s = fork->side[nside];
+        HIPCHK(hipStreamWaitEvent(s, fork->fork, 0));
+      }
+      if (prof && prof->begin(s, &ev)) return STC_ERR_HIP;
+      hipLaunchKernelGGL((k_potrf<NB>), dim3(L.p_cnt, members), dim3(256), sizeof(double) * potrf_lds<NB>(),
+                         s, a);
+      if (prof && prof->end(kKindPotrf, PL.flops_potrf * members, s, ev)) return STC_ERR_HIP;
+      if (s != st) HIPCHK(hipEventRecord(fork->join[nside++], s));
+    }
+    if (L.t_cnt) {
+      hipStream_t s = st;
+      if (forking && has_u) {
+        s = fork->side[nside];
+        HIPCHK(hipStreamWaitEvent(s, fork->fork, 0));
+      }
+      if (prof && prof->begin(s, &ev)) return STC_ERR_HIP;
+      hipLaunchKernelGGL((k_trsm<NB>), dim3(L.t_cnt, members), dim3(256), sizeof(double) * trsm_lds<NB>(), s,
+                         a);
+      if (prof && prof->end(kKindTrsm, PL.flops_trsm * members, s, ev)) return STC_ERR_HIP;
+      if (s != st) HIPCHK(hipEventRecord(fork->join[nside++], s));
+    }
+    if (has_u) {
+      const int lds = std::max(L.g_cnt ? UPD2_LDS : 0, L.u_cnt ? UPD_LDS : 0);
+      const dim3 grid(L.g_cnt + L.u_cnt, members);
+      if (prof && prof->begin(st, &ev)) return STC_ERR_HIP;
+      if (L.g_cnt)
+        hipLaunchKernelGGL((k_upd<NB, true>), grid, dim3(256), sizeof(double) * lds, st, a);
+      else
+        hipLaunchKernelGGL((k_upd<NB, false>), grid, dim3(256), sizeof(double) * lds, st, a);
+      if (prof && prof->end(L.g_cnt ? kKindUpdBig : kKindUpd, PL.flops_upd * members, st, ev))
+        return STC_ERR_HIP;
+    }
+    for (int i = 0; i < nside; ++i) HIPCHK(hipStreamWaitEvent(st, fork->join[i], 0));
   }
   HIPCHK(hipGetLastError());
   return 0;
 }
 
-int launch_levels(stc_handle* h, int32_t members, hipStream_t st, Prof* prof = nullptr) {
+int launch_levels(stc_handle* h, int32_t members, hipStream_t st, Prof* prof = nullptr,
+                  Fork* fork = nullptr) {
   switch (h->plan.nb) {
-    case 32: return launch_levels_nb<32>(h, members, st, prof);
-    case 64: return launch_levels_nb<64>(h, members, st, prof);
-    case 128: return launch_levels_nb<128>(h, members, st, prof);
-    case 256: return launch_levels_nb<256>(h, members, st, prof);
+    case 32: return launch_levels_nb<32>(h, members, st, prof, fork);
+    case 64: return launch_levels_nb<64>(h, members, st, prof, fork);
+    case 128: return launch_levels_nb<128>(h, members, st, prof, fork);
+    case 256: return launch_levels_nb<256>(h, members, st, prof, fork);
   }
   return fail(STC_ERR_ARG, "unsupported tile size");
 }
@@ -258,8 +305,13 @@ int get_graph(stc_handle* h, int32_t members, hipGraphExec_t* out) {
   }
   hipStream_t cs;
   HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  Fork fork;
+  if (fork.make()) {
+    (void)hipStreamDestroy(cs);
+    return STC_ERR_HIP;
+  }
   HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
-  int rc = launch_levels(h, members, cs);
+  int rc = launch_levels(h, members, cs, nullptr, &fork);
   hipGraph_t g;
   hipError_t e = hipStreamEndCapture(cs, &g);
   if (rc) {

@@ -273,7 +273,7 @@ class Analysis:
                 "bytes_update", "bytes_load", "levels", "flops_backward", "levels_backward"]
         return dict(zip(keys, (float(x) for x in w)))
 
-    KERNEL_KINDS = ["load", "k_level<P,G>", "k_level<P>", "k_level<G>", "k_level"]
+    KERNEL_KINDS = ["load", "k_potrf", "k_upd<G>", "k_upd", "k_trsm"]
 
     def profile_factorize(self, values):
         """Event timing of one eager factorization, per kernel form:
