@@ -79,9 +79,10 @@ typedef struct {
   int32_t mode;          /* STC_MODE_*                                           */
   int32_t ordering;      /* STC_ORD_*                                            */
   const int32_t* perm;   /* (host) perm[new] = old, read when ordering == GIVEN  */
-  int32_t split_target;  /* schedule: work items per level that splitting long
-                            update chains (deterministic split-K) aims for;
-                            0 = 1024.  Changes timing only, not results.      */
+  int32_t wg_slots;      /* schedule: concurrent update work-groups the per-
+                            level split of long update chains (deterministic
+                            split-K) is balanced for; 0 = 384 (the best of a
+                            sweep on MI355X).  Changes timing only.            */
 } stc_opts;
 
 /* Analyse a sparsity pattern once (Sec. 3, Sec. 5.1-5.2).

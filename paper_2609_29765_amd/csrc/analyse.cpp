@@ -24,6 +24,7 @@
 #include "analyse.hpp"
 
 #include <algorithm>
+#include <queue>
 #include <cmath>
 #include <functional>
 
@@ -526,12 +527,12 @@ int analyse(int64_t n, const int64_t* cp, const int32_t* ri, int method, int nb,
 // execution plan
 // ---------------------------------------------------------------------------
 
-int build_plan(const Symbolic& s, int bm, int br, int64_t split_target, Plan* p, std::string* why) {
+int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std::string* why) {
   const int32_t nb = s.nb, NT = s.NT;
   const int64_t n = s.n;
   (void)why;
   *p = Plan();
-  if (split_target > 0) p->split_target = split_target;
+  if (wg_slots > 0) p->wg_slots = wg_slots;
   p->nb = nb;
   p->NT = NT;
   p->bm = bm;
@@ -768,22 +769,70 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t split_target, Plan* p,
       if (u.big) bigblocks[(size_t)u.level] += blocks(u);
     for (UpdTask& u : p->upd)
       if (u.big && bigblocks[(size_t)u.level] < 64 && u.c_end - u.c_begin <= 2) u.big = 0;
-    for (const UpdTask& u : p->upd) items[(size_t)u.level] += blocks(u);
-    const int64_t target = p->split_target;
-    for (UpdTask& u : p->upd) {
-      if (!u.big || u.partner < 0) continue;
-      const int64_t have = items[(size_t)u.level];
-      if (have >= target) continue;
-      const int32_t ncon = u.c_end - u.c_begin;
-      int32_t sp = (int32_t)std::min<int64_t>(16, (target + have - 1) / have);
-      sp = std::min(sp, ncon / 2);
-      if (sp < 2) continue;
-      u.nsplit = sp;
-      u.part_off = p->parts;
-      p->parts += (int64_t)(sp - 1) * u.c_rows * nb;
-      UpdTask& l = p->upd[(size_t)u.partner];
-      l.in_part_off = u.part_off;
-      l.in_npart = sp - 1;
+    // Split of the early groups' contribution ranges, chosen per level: every
+    // split s in 1..16 is tried by simulating longest-first list scheduling of
+    // the level's update items on wg_slots concurrent work-groups, and the
+    // split with the shortest estimated makespan is kept (ties: fewer parts).
+    // Item durations are in units of one 128-block contribution; a 64-block
+    // contribution is a quarter; the epilogue costs a quarter plus a tenth per
+    // folded partial slot.
+    (void)items;
+    auto dur = [&](const UpdTask& u, int64_t ncon_part) {
+      return (u.big ? 1.0 : 0.25) * (double)ncon_part + 0.25 + 0.1 * u.in_npart;
+    };
+    std::vector<std::vector<int32_t>> lev_tasks((size_t)nlev);
+    for (int32_t id = 0; id < (int32_t)p->upd.size(); ++id) lev_tasks[(size_t)p->upd[(size_t)id].level].push_back(id);
+    const int64_t slots = p->wg_slots;
+    std::vector<double> durs;
+    for (int32_t L = 0; L < nlev; ++L) {
+      bool any = false;
+      for (int32_t id : lev_tasks[(size_t)L]) {
+        const UpdTask& u = p->upd[(size_t)id];
+        any |= u.big && u.partner >= 0 && u.c_end - u.c_begin >= 2;
+      }
+      if (!any) continue;
+      int32_t best_sp = 1;
+      double best = 1e300;
+      for (int32_t sp = 1; sp <= 16; ++sp) {
+        durs.clear();
+        for (int32_t id : lev_tasks[(size_t)L]) {
+          const UpdTask& u = p->upd[(size_t)id];
+          const int64_t ncon = u.c_end - u.c_begin;
+          const int32_t s_u = (u.big && u.partner >= 0) ? (int32_t)std::max<int64_t>(1, std::min<int64_t>(sp, ncon / 2)) : 1;
+          const int64_t nblk = blocks(u);
+          for (int32_t part = 0; part < s_u; ++part) {
+            const double d = dur(u, ncon * (part + 1) / s_u - ncon * part / s_u);
+            for (int64_t x = 0; x < nblk; ++x) durs.push_back(d);
+          }
+        }
+        std::sort(durs.begin(), durs.end(), std::greater<double>());
+        std::priority_queue<double, std::vector<double>, std::greater<double>> q;
+        for (int64_t x = 0; x < slots; ++x) q.push(0.0);
+        double mk = 0;
+        for (double d : durs) {
+          const double t = q.top() + d;
+          q.pop();
+          q.push(t);
+          mk = std::max(mk, t);
+        }
+        if (mk < best - 1e-9) {
+          best = mk;
+          best_sp = sp;
+        }
+      }
+      for (int32_t id : lev_tasks[(size_t)L]) {
+        UpdTask& u = p->upd[(size_t)id];
+        if (!u.big || u.partner < 0) continue;
+        const int32_t ncon = u.c_end - u.c_begin;
+        const int32_t sp = std::min(best_sp, ncon / 2);
+        if (sp < 2) continue;
+        u.nsplit = sp;
+        u.part_off = p->parts;
+        p->parts += (int64_t)(sp - 1) * u.c_rows * nb;
+        UpdTask& l = p->upd[(size_t)u.partner];
+        l.in_part_off = u.part_off;
+        l.in_npart = sp - 1;
+      }
     }
     for (int32_t id = 0; id < (int32_t)p->upd.size(); ++id) {
       const UpdTask& u = p->upd[(size_t)id];
@@ -800,6 +849,26 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t split_target, Plan* p,
             dst.push_back(part);
           }
     }
+    // longest items first: work-groups are dispatched in index order, so a
+    // level runs as a longest-processing-time-first list schedule
+    auto item_dur = [&](const int32_t* q) {
+      const UpdTask& u = p->upd[(size_t)q[0]];
+      const int64_t ncon = u.c_end - u.c_begin;
+      return dur(u, ncon * (q[3] + 1) / u.nsplit - ncon * q[3] / u.nsplit);
+    };
+    for (Level& L : p->levels)
+      for (std::vector<int32_t>* v : {&L.big_items, &L.upd_items}) {
+        const size_t cnt = v->size() / 4;
+        std::vector<size_t> order(cnt);
+        for (size_t x = 0; x < cnt; ++x) order[x] = x;
+        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+          return item_dur(&(*v)[4 * a]) > item_dur(&(*v)[4 * b]);
+        });
+        std::vector<int32_t> out(v->size());
+        for (size_t x = 0; x < cnt; ++x)
+          std::copy(v->begin() + 4 * order[x], v->begin() + 4 * order[x] + 4, out.begin() + 4 * x);
+        v->swap(out);
+      }
   }
   p->flops_tile = flops;
   for (int64_t j = 0; j < n; ++j) {

@@ -108,7 +108,7 @@ struct Level {
 
 struct Plan {
   int32_t nb = 64, NT = 0;
-  int64_t split_target = 1024;  // work items a level's split-K aims for
+  int64_t wg_slots = 384;  // concurrent update work-groups the split balances for
   int32_t bm = 64;          // small update block (rows and columns)
   int64_t parts = 0;        // doubles of partial-sum slots per value set
   int32_t br = 32;          // rows per TRSM work item
@@ -135,9 +135,9 @@ struct Plan {
   double bytes_update = 0;  // operand rows read + output tiles read and written
 };
 
-// split_target: work items per level that the split of long contribution
-// ranges aims for (0 = 1024)
-int build_plan(const Symbolic& s, int bm, int br, int64_t split_target, Plan* p, std::string* why);
+// wg_slots: concurrent update work-groups the per-level split of long
+// contribution ranges is balanced for (0 = 384, measured best on MI355X)
+int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std::string* why);
 
 // Reverse mode of log det through the factorization.  For the logdet
 // cotangent the adjoint of the blocked Cholesky restricted to pattern(L) is

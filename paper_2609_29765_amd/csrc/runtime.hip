@@ -450,7 +450,7 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
   if (o.nb == 0) o.nb = 64;
   if (o.nb != 32 && o.nb != 64 && o.nb != 128 && o.nb != 256)
     return fail(STC_ERR_ARG, "nb must be 32, 64, 128 or 256");
-  if (o.split_target < 0) return fail(STC_ERR_ARG, "split_target must be >= 0");
+  if (o.wg_slots < 0) return fail(STC_ERR_ARG, "wg_slots must be >= 0");
   try {
     auto* h = new stc_handle();
     std::string why;
@@ -459,7 +459,7 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
       delete h;
       return fail(rc, why);
     }
-    rc = build_plan(h->sym, UB, TR, o.split_target, &h->plan, &why);
+    rc = build_plan(h->sym, UB, TR, o.wg_slots, &h->plan, &why);
     if (rc == 0) rc = build_backward(h->sym, &h->plan, &h->back, &why);
     if (rc) {
       delete h;

@@ -46,7 +46,7 @@ class STCError(RuntimeError):
 
 class _opts(C.Structure):
     _fields_ = [("nb", C.c_int32), ("mode", C.c_int32), ("ordering", C.c_int32),
-                ("perm", C.c_void_p), ("split_target", C.c_int32)]
+                ("perm", C.c_void_p), ("wg_slots", C.c_int32)]
 
 
 def lib():
@@ -118,13 +118,13 @@ class Analysis:
     """Once-per-pattern analysis; factorize / logdet / solve many times."""
 
     def __init__(self, n, colptr, rowind, nb=64, mode="auto", ordering="auto", perm=None,
-                 split_target=0):
+                 wg_slots=0):
         L = lib()
         self.colptr = np.ascontiguousarray(colptr, np.int64)
         self.rowind = np.ascontiguousarray(rowind, np.int32)
         self._perm_in = None if perm is None else np.ascontiguousarray(perm, np.int32)
         o = _opts(int(nb), MODES[mode], ORDERINGS[ordering],
-                  None if self._perm_in is None else self._perm_in.ctypes.data, int(split_target))
+                  None if self._perm_in is None else self._perm_in.ctypes.data, int(wg_slots))
         h = C.c_void_p()
         _check(L.stc_analyse(int(n), self.colptr, self.rowind, C.byref(o), C.byref(h)))
         self._h = h
