@@ -527,6 +527,179 @@ __device__ __forceinline__ void dev_potrf(int32_t k, double* __restrict__ S,
   }
 }
 
+// POTRF with one panel of look-ahead (tiles of 128 and 256).  While wave 0
+// factors and inverts the diagonal block of panel j, waves 1..3 accumulate
+// the update of panel j+1 from the columns factored before panel j (read back
+// from the tile, staged through LDS areas private to each wave, so no
+// barrier involves wave 0); after panel j's rows below the diagonal block are
+// solved, they add panel j's own contribution straight from LDS and subtract
+// the total from panel j+1's freshly loaded values.  Same arithmetic as the
+// left-looking dev_potrf, with the update of each panel taken in two parts.
+constexpr int LKC = 16;          // K chunk of the look-ahead staging
+constexpr int LKLD = LKC + 1;
+
+template <int NB>
+constexpr int la_rbw() { return ((NB - PW) / 16 + 2) / 3; }  // row blocks per waves 1..3
+
+template <int NB>
+constexpr int potrf_la_lds() { return NB * PLD + PW * PLD + PW + 3 * (la_rbw<NB>() * 16 + PW) * LKLD; }
+
+template <int NB>
+__device__ __forceinline__ void dev_potrf_la(int32_t k, double* __restrict__ S,
+                                             double* __restrict__ dinv_m, int32_t* __restrict__ inf,
+                                             int32_t nreal, double* smem) {
+  constexpr int RB3 = la_rbw<NB>();
+  constexpr int WROWS = RB3 * 16 + PW;  // staged rows per wave: its A rows, then the B rows
+  double* P = smem;
+  double* Z = P + NB * PLD;
+  double* rdiag = Z + PW * PLD;
+  double* Wall = rdiag + PW;
+  double* A = S + (int64_t)k * NB * NB;
+  double* dinv = dinv_m + (int64_t)k * NB * PW;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int PER = NB * PW / 256;
+  const int trow = tid >> 5, tcol = tid & 31;
+  // rows [j0, NB) x columns [j0, j0 + 32) of the tile into P (pr = NB - j0 is a
+  // multiple of 32, so groups of 8 rows are wholly in or out)
+  auto load_panel = [&](int j0) {
+    const int pr = NB - j0;
+    double v[PER];
+    const double* src = A + (int64_t)(j0 + trow) * NB + j0 + tcol;
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+      if (q * 8 < pr) v[q] = src[(int64_t)q * 8 * NB];
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+      if (q * 8 < pr) P[(q * 8 + trow) * PLD + tcol] = v[q];
+  };
+  load_panel(0);
+  for (int j0 = 0; j0 < NB; j0 += PW) {
+    const int pr = NB - j0, pr1 = pr - PW;  // rows of this panel and of the next
+    const int nrb = pr1 / 16;               // 16-row blocks of the next panel
+    d4 acc[RB3][2];
+#pragma unroll
+    for (int b = 0; b < RB3; ++b) acc[b][0] = acc[b][1] = d4{0.0, 0.0, 0.0, 0.0};
+    __syncthreads();  // P holds this panel, fully updated
+    if (wave == 0) {
+      const int bad = chol32_wave(P, Z, rdiag, lane);
+      if (lane == 0 && bad >= 0 && k * NB + j0 + bad < nreal) atomicMin(inf, k * NB + j0 + bad + 1);
+    } else if (pr1 > 0 && j0 > 0) {
+      const int w = wave - 1;
+      double* WA = Wall + w * WROWS * LKLD;
+      double* WB = WA + RB3 * 16 * LKLD;
+      for (int s0 = 0; s0 < j0; s0 += LKC) {
+        // stage 16 columns of this wave's rows of the next panel, and of the
+        // next panel's first 32 rows, as 4-double segments
+        for (int x = lane; x < WROWS * 4; x += 64) {
+          const int rl = x >> 2, seg = (x & 3) * 4;
+          int grow;  // row of the tile, or -1 for a row block past the panel
+          if (rl < RB3 * 16) {
+            const int t = w + 3 * (rl >> 4);
+            grow = t < nrb ? j0 + PW + t * 16 + (rl & 15) : -1;
+          } else {
+            grow = j0 + PW + (rl - RB3 * 16);
+          }
+          double2 v0 = make_double2(0.0, 0.0), v1 = v0;
+          if (grow >= 0) {
+            const double2* src = reinterpret_cast<const double2*>(A + (int64_t)grow * NB + s0 + seg);
+            v0 = src[0];
+            v1 = src[1];
+          }
+          double* d = (rl < RB3 * 16 ? WA + rl * LKLD : WB + (rl - RB3 * 16) * LKLD) + seg;
+          d[0] = v0.x;
+          d[1] = v0.y;
+          d[2] = v1.x;
+          d[3] = v1.y;
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int b = 0; b < RB3; ++b) {
+          if (w + 3 * b < nrb) {
+#pragma unroll
+            for (int kk = 0; kk < LKC; kk += 4) {
+              const double af = WA[(b * 16 + (lane & 15)) * LKLD + kk + (lane >> 4)];
+              const double b0 = WB[(lane & 15) * LKLD + kk + (lane >> 4)];
+              const double b1 = WB[(16 + (lane & 15)) * LKLD + kk + (lane >> 4)];
+              acc[b][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, b0, acc[b][0], 0, 0, 0);
+              acc[b][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, b1, acc[b][1], 0, 0, 0);
+            }
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __syncthreads();
+    // rows below the diagonal block: P_below <- P_below inv(L_top)^T on MFMA;
+    // each wave owns whole 16-row blocks, reads them fully, then overwrites
+    for (int t = wave; t < pr1 / 16; t += 4) {
+      d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+      const double* pa = P + (PW + t * 16 + (lane & 15)) * PLD + (lane >> 4);
+      const double* z0 = Z + (lane & 15) * PLD + (lane >> 4);
+      const double* z1 = Z + (16 + (lane & 15)) * PLD + (lane >> 4);
+#pragma unroll
+      for (int kk = 0; kk < PW; kk += 4) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[kk], z0[kk], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[kk], z1[kk], acc1, 0, 0, 0);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        double* row = P + (PW + t * 16 + (lane >> 4) + 4 * e) * PLD;
+        row[lane & 15] = acc0[e];
+        row[16 + (lane & 15)] = acc1[e];
+      }
+    }
+    for (int x = tid; x < PW * PW; x += 256) dinv[(j0 / PW) * PW * PW + x] = Z[(x / PW) * PLD + x % PW];
+    __syncthreads();
+    {
+      double* dst = A + (int64_t)(j0 + trow) * NB + j0 + tcol;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int r = q * 8 + trow;
+        if (q * 8 < pr && (tcol <= r || r >= PW)) dst[(int64_t)q * 8 * NB] = P[r * PLD + tcol];
+      }
+    }
+    if (pr1 > 0) {
+      // this panel's contribution to the next one, from LDS
+      if (wave > 0) {
+        const int w = wave - 1;
+#pragma unroll
+        for (int b = 0; b < RB3; ++b) {
+          const int t = w + 3 * b;
+          if (t < nrb) {
+            const double* pa = P + (PW + t * 16 + (lane & 15)) * PLD + (lane >> 4);
+            const double* pb0 = P + (PW + (lane & 15)) * PLD + (lane >> 4);
+            const double* pb1 = P + (PW + 16 + (lane & 15)) * PLD + (lane >> 4);
+#pragma unroll
+            for (int kk = 0; kk < PW; kk += 4) {
+              acc[b][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[kk], pb0[kk], acc[b][0], 0, 0, 0);
+              acc[b][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[kk], pb1[kk], acc[b][1], 0, 0, 0);
+            }
+          }
+        }
+      }
+      __syncthreads();  // P is no longer read as this panel
+      load_panel(j0 + PW);
+      __syncthreads();
+      if (wave > 0) {
+        const int w = wave - 1;
+#pragma unroll
+        for (int b = 0; b < RB3; ++b) {
+          const int t = w + 3 * b;
+          if (t < nrb) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              double* row = P + (t * 16 + (lane >> 4) + 4 * e) * PLD;
+              row[lane & 15] -= acc[b][0][e];
+              row[16 + (lane & 15)] -= acc[b][1][e];
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // TRSM: rows of a panel tile times L_kk^-T, 32 rows per work item, blocked by
 // 32 columns: X_J <- (X_J - X_<J L_J,<J^T) inv(L_JJ)^T, both products on MFMA
@@ -657,11 +830,18 @@ struct LevelArgs {
 // with its own LDS and register budget, which sets how many work-groups share
 // a compute unit) that the runtime runs concurrently on forked graph branches.
 template <int NB>
+constexpr int k_potrf_lds() { return NB >= 128 ? potrf_la_lds<NB>() : potrf_lds<NB>(); }
+
+template <int NB>
 __global__ __launch_bounds__(256) void k_potrf(LevelArgs a) {
   extern __shared__ double smem[];
   const int32_t member = blockIdx.y;
-  dev_potrf<NB>(a.potrf[blockIdx.x], a.store + (int64_t)member * a.mstride,
-                a.dinv + (int64_t)member * a.dstride, a.info + member, a.nreal, smem);
+  if constexpr (NB >= 128)
+    dev_potrf_la<NB>(a.potrf[blockIdx.x], a.store + (int64_t)member * a.mstride,
+                     a.dinv + (int64_t)member * a.dstride, a.info + member, a.nreal, smem);
+  else
+    dev_potrf<NB>(a.potrf[blockIdx.x], a.store + (int64_t)member * a.mstride,
+                  a.dinv + (int64_t)member * a.dstride, a.info + member, a.nreal, smem);
 }
 
 // HAS_G compiles the 128-block path in or out, so a level without it keeps

@@ -252,7 +252,7 @@ int launch_levels_nb(stc_handle* h, int32_t members, hipStream_t st, Prof* prof,
         HIPCHK(hipStreamWaitEvent(s, fork->fork, 0));
       }
       if (prof && prof->begin(s, &ev)) return STC_ERR_HIP;
-      hipLaunchKernelGGL((k_potrf<NB>), dim3(L.p_cnt, members), dim3(256), sizeof(double) * potrf_lds<NB>(),
+      hipLaunchKernelGGL((k_potrf<NB>), dim3(L.p_cnt, members), dim3(256), sizeof(double) * k_potrf_lds<NB>(),
                          s, a);
       if (prof && prof->end(kKindPotrf, PL.flops_potrf * members, s, ev)) return STC_ERR_HIP;
       if (s != st) HIPCHK(hipEventRecord(fork->join[nside++], s));
