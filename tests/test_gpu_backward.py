@@ -85,13 +85,13 @@ def _theta_grad(a, w):
     return w.dvalues @ gv
 
 
-@pytest.mark.parametrize("T,m", [(4, 6), (20, 25)])
-def test_theta_gradient_vs_trace_and_fd(T, m):
+@pytest.mark.parametrize("T,m,nb", [(4, 6, 64), (20, 25, 64), (20, 25, 128)])
+def test_theta_gradient_vs_trace_and_fd(T, m, nb):
     w = W.differentiable_arrowhead(T, m, 8, 0)
-    a = S.Analysis(w.n, w.colptr, w.rowind, nb=64, ordering="nd").bind()
+    a = S.Analysis(w.n, w.colptr, w.rowind, nb=nb, ordering="nd").bind()
     print(f"[gpu] theta gradient n={w.n}", flush=True)
     g = _theta_grad(a, w)
-    o = O.Analysis(w.n, w.colptr, w.rowind, "nd", nb=64)
+    o = O.Analysis(w.n, w.colptr, w.rowind, "nd", nb=nb)
     Lo, _ = o.factor(w.values)
     gt = w.dvalues @ o.logdet_grad_values(Lo)
     assert np.all(np.abs(g - gt) <= 1e-8 * np.abs(gt)), (g, gt)

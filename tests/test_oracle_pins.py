@@ -14,6 +14,7 @@ import scipy.sparse as sp
 
 from oracle import oracle as O
 from paper_2609_29765_amd import workloads as W
+from tests import closed_forms as CF
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -166,16 +167,12 @@ def test_ar1_closed_form(rho):
 # spectral identities
 # ---------------------------------------------------------------------------
 
-def _lam(m):
-    return 2 - 2 * np.cos(np.pi * np.arange(m) / m)
-
-
 def test_gmrf32_spectral_logdet_and_solve():
     w = W.gmrf_grid2d(32, 32, 0.1, 0)
     a = O.Analysis(w.n, w.colptr, w.rowind, "nd", nb=64)
     Lx, info = a.factor(w.values)
     assert info == 0
-    lam = _lam(32)
+    lam = CF.lam(32)
     ld = np.log(lam[:, None] + lam[None, :] + 0.1).sum()
     assert abs(a.logdet(Lx) - ld) <= 1e-12 * abs(ld)
     # exact solve in the DCT eigenbasis of the path Laplacian
@@ -194,27 +191,9 @@ def test_lap3d_member_spectral_logdet(member):
     Lx, info = a.factor(w.values[member])
     assert info == 0
     wb, sb = w.meta["hyper"][member]
-    lam = _lam(6)
+    lam = CF.lam(6)
     ld = np.log(wb * (lam[:, None, None] + lam[None, :, None] + lam[None, None, :]) + 0.05 * sb).sum()
     assert abs(a.logdet(Lx) - ld) <= 1e-12 * abs(ld)
-
-
-def _bordered_logdet(T, m, tau, kappa, rho, Bc, D):
-    """logdet of [[tau kron(AR1, kappa^2 I + L), B], [B^T, D]] through the
-    Kronecker eigenbasis and the Schur complement of the border."""
-    av = np.linalg.eigvalsh(W.ar1_precision(T, rho).toarray())
-    au, U = np.linalg.eigh(W.ar1_precision(T, rho).toarray())
-    ev, V1 = np.linalg.eigh(W.path_laplacian(m).toarray())
-    mu = kappa * kappa + ev[:, None] + ev[None, :]
-    G = m * m
-    ld_field = T * G * np.log(tau) + G * np.log(av).sum() + T * np.log(mu).sum()
-    nb = Bc.shape[1]
-    X = Bc.T.reshape(nb, T, m, m)
-    Y = np.einsum("st,bsij,ip,jq->btpq", U, X, V1, V1, optimize=True)
-    S = np.einsum("btpq,ctpq,t,pq->bc", Y, Y, 1.0 / au, 1.0 / mu, optimize=True) / tau
-    sign, ld_s = np.linalg.slogdet(D - S)
-    assert sign > 0
-    return ld_field + ld_s
 
 
 def test_small_spatiotemporal_closed_form():
@@ -222,7 +201,7 @@ def test_small_spatiotemporal_closed_form():
     a = O.Analysis(w.n, w.colptr, w.rowind, "nd", nb=32)
     Lx, info = a.factor(w.values)
     assert info == 0
-    ld = _bordered_logdet(6, 8, 1.0, 0.5, 0.9, w.meta["Bc"], w.meta["D"])
+    ld = CF.bordered_logdet(6, 8, 1.0, 0.5, 0.9, w.meta["Bc"], w.meta["D"])
     assert abs(a.logdet(Lx) - ld) <= 1e-12 * abs(ld)
 
 
@@ -232,7 +211,7 @@ def test_differentiable_arrowhead_closed_form_full_size():
     Lx, info = a.factor(w.values)
     assert info == 0
     mt = w.meta
-    ld = _bordered_logdet(20, 25, mt["tau"], mt["kappa"], mt["rho"], mt["Bc"], mt["D"])
+    ld = CF.bordered_logdet(20, 25, mt["tau"], mt["kappa"], mt["rho"], mt["Bc"], mt["D"])
     assert abs(a.logdet(Lx) - ld) <= 1e-12 * abs(ld)
 
 
@@ -271,7 +250,7 @@ def test_gradient_trace_vs_closed_form_fd():
             t2[i] += s * h
             w2 = W.differentiable_arrowhead(T, m, 8, seed=3, theta=t2)
             mt = w2.meta
-            vals.append(_bordered_logdet(T, m, mt["tau"], mt["kappa"], mt["rho"], mt["Bc"], mt["D"]))
+            vals.append(CF.bordered_logdet(T, m, mt["tau"], mt["kappa"], mt["rho"], mt["Bc"], mt["D"]))
         fd[i] = (vals[0] - vals[1]) / (2 * h)
     assert np.all(np.abs(g - fd) <= 1e-7 * np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max()))
 
