@@ -743,35 +743,56 @@ __device__ __forceinline__ void dev_trsm(int32_t it, const int32_t* __restrict__
       X[(x / NB) * XLD + x % NB] = (x / NB) < nr ? v[q] : 0.0;
     }
   }
-  // each wave owns one 16 x 16 tile of the 32 x 32 block column
+  // each wave owns one 16 x 16 tile of the 32 x 32 block column.  The rows
+  // of L for the next block column (columns before it only) and the next
+  // 32 x 32 inverse are loaded into registers while the current one is
+  // computed; the K loop runs four independent accumulators.
   const int wr = (wave >> 1) * 16, wc = (wave & 1) * 16;
-  for (int j0 = 0; j0 < NB; j0 += PW) {
-    // rows j0..j0+31 of L, columns 0..j0-1, staged in LDS (columns past j0
-    // are loaded clamped and never read)
+  constexpr int NJ = NB / PW;
+  constexpr int LPER = PW * (NB - PW) / 256;  // L values per thread, largest block column
+  double lv[LPER > 0 ? LPER : 1];
+  double dz[PW / 4];
+  auto fetch = [&](int j0n) {  // rows j0n..j0n+31 of L, columns < j0n; inverse of block j0n
+#pragma unroll
+    for (int q = 0; q < LPER; ++q) {
+      const int x = q * 256 + tid;  // 32 x 32 groups: group x >> 10, row (x >> 5) & 31, column x & 31
+      if (x < PW * j0n) lv[q] = L[(int64_t)(j0n + ((x >> 5) & 31)) * NB + (x >> 10) * PW + (x & 31)];
+    }
+    const double* db = dinv + (j0n / PW) * PW * PW + (wc + (lane & 15)) * PW + (lane >> 4);
+#pragma unroll
+    for (int q = 0; q < PW / 4; ++q) dz[q] = db[4 * q];
+  };
+  fetch(0);
+  for (int J = 0; J < NJ; ++J) {
+    const int j0 = J * PW;
     if (j0 > 0) {
-      double v[PER];
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int x = q * 256 + tid, r = x / NB, c = min(x % NB, j0 - 1);
-        v[q] = L[(int64_t)(j0 + r) * NB + c];
-      }
-#pragma unroll
-      for (int q = 0; q < PER; ++q) {
+      for (int q = 0; q < LPER; ++q) {
         const int x = q * 256 + tid;
-        Lr[(x / NB) * XLD + x % NB] = v[q];
+        if (x < PW * j0) Lr[((x >> 5) & 31) * XLD + (x >> 10) * PW + (x & 31)] = lv[q];
       }
     }
+    double dzc[PW / 4];
+#pragma unroll
+    for (int q = 0; q < PW / 4; ++q) dzc[q] = dz[q];
     __syncthreads();
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    if (J + 1 < NJ) fetch(j0 + PW);
+    d4 acc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
     const double* xa = X + (wr + (lane & 15)) * XLD + (lane >> 4);
     const double* lb = Lr + (wc + (lane & 15)) * XLD + (lane >> 4);
-    for (int kk = 0; kk < j0; kk += 4)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[kk], lb[kk], acc, 0, 0, 0);
+    for (int kk = 0; kk < j0; kk += 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[kk + 4 * u], lb[kk + 4 * u], acc[u], 0, 0, 0);
+    }
     // Y = X_J - acc, kept in registers until every wave has read X_<J
     double y[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e)
-      y[e] = X[(wr + (lane >> 4) + 4 * e) * XLD + j0 + wc + (lane & 15)] - acc[e];
+      y[e] = X[(wr + (lane >> 4) + 4 * e) * XLD + j0 + wc + (lane & 15)] -
+             ((acc[0][e] + acc[1][e]) + (acc[2][e] + acc[3][e]));
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 4; ++e) X[(wr + (lane >> 4) + 4 * e) * XLD + j0 + wc + (lane & 15)] = y[e];
@@ -779,18 +800,14 @@ __device__ __forceinline__ void dev_trsm(int32_t it, const int32_t* __restrict__
     // X_J = Y inv(L_JJ)^T
     d4 z = {0.0, 0.0, 0.0, 0.0};
     const double* ya = X + (wr + (lane & 15)) * XLD + j0 + (lane >> 4);
-    const double* db = dinv + (j0 / PW) * PW * PW + (wc + (lane & 15)) * PW + (lane >> 4);
-    double dz[PW / 4];
-#pragma unroll
-    for (int q = 0; q < PW / 4; ++q) dz[q] = db[4 * q];
 #pragma unroll
     for (int q = 0; q < PW / 4; ++q)
-      z = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[4 * q], dz[q], z, 0, 0, 0);
+      z = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[4 * q], dzc[q], z, 0, 0, 0);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 4; ++e) X[(wr + (lane >> 4) + 4 * e) * XLD + j0 + wc + (lane & 15)] = z[e];
-    __syncthreads();
   }
+  __syncthreads();
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int x = q * 256 + tid;

@@ -143,8 +143,8 @@ class Analysis:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().stc_destroy(h)
+        if h is not None and h.value and _LIB is not None:  # _LIB is None at interpreter exit
+            _LIB.stc_destroy(h)
             self._h = None
 
     # ---------------------------------------------------------------- symbolic
