@@ -341,13 +341,16 @@ constexpr int PLD = PW + 1;
 // the left-looking (Crout) recurrence L_rc = (A_rc - sum_{p<c} L_rp L_cp) / L_cc;
 // lanes 32..63 hold the unit vector e_r and run forward substitution for
 // column r of L^-1, z_c = (e_rc - sum_{p<c} L_cp z_p) / L_cc -- the same
-// expression on different registers, so one instruction stream serves both
-// and both read row c of L by LDS broadcast.  The pivot L_cc^2 is lane c's
-// value of that expression, taken by readlane.  The reads of a step precede
-// its write in program order, and a wave's LDS operations execute in that
-// order.  Writes L (lower, diagonal included, zeros above) to P, the inverse
-// (row-major, stride PLD) to Z and 1 / L_cc to rdiag.  Returns the first
-// failing pivot (0-based) or -1; uniform across the wave.
+// expression on different registers, so one instruction stream serves both.
+// Columns go four at a time: every lane forms its four partial sums t_q
+// (rows c0..c0+3 of L read by LDS broadcast), the 4 x 4 pivot block (t of
+// lanes c0..c0+3, by readlane) is factored with uniform scalar arithmetic,
+// and each lane finishes its four entries by a 4-term forward substitution.
+// The reads of a step precede its writes in program order, and a wave's LDS
+// operations execute in that order.  Writes L (lower, diagonal included,
+// zeros above) to P, the inverse (row-major, stride PLD) to Z and 1 / L_cc to
+// rdiag.  Returns the first failing pivot (0-based) or -1; uniform across the
+// wave.
 __device__ __forceinline__ double rcp_nr(double d) {
   double r = __builtin_amdgcn_rcp(d);
   r = fma(fma(-d, r, 1.0), r, r);
@@ -360,6 +363,12 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
   return y * fma(-0.5 * d * y, y, 1.5);
 }
 
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ int chol32_wave(double* P, double* Z, double* rdiag, int lane) {
   const int r = lane & 31;
   const bool lo = lane < 32;
@@ -369,33 +378,68 @@ __device__ __forceinline__ int chol32_wave(double* P, double* Z, double* rdiag, 
     const double a = P[r * PLD + j];
     x[j] = lo ? a : (j == r ? 1.0 : 0.0);
   }
-  int bad = -1;
+  double myd = 1.0, myrs = 1.0;  // lane r < 32 keeps pivot r and its 1 / L_rr
 #pragma unroll
-  for (int c = 0; c < PW; ++c) {
-    double s0 = 0.0, s1 = 0.0;
+  for (int c0 = 0; c0 < PW; c0 += 4) {
+    double t[4];
 #pragma unroll
-    for (int p = 0; p < c; ++p) {
-      if (p & 1) s1 = fma(x[p], P[c * PLD + p], s1);
-      else s0 = fma(x[p], P[c * PLD + p], s0);
+    for (int q = 0; q < 4; ++q) {
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int p = 0; p < c0; ++p) {
+        if (p & 1) s1 = fma(x[p], P[(c0 + q) * PLD + p], s1);
+        else s0 = fma(x[p], P[(c0 + q) * PLD + p], s0);
+      }
+      t[q] = x[c0 + q] - (s0 + s1);
     }
-    const double t = x[c] - (s0 + s1);
-    const int dlo = __builtin_amdgcn_readlane(__double2loint(t), c);
-    const int dhi = __builtin_amdgcn_readlane(__double2hiint(t), c);
-    const double d = __hiloint2double(dhi, dlo);
-    bad = (bad < 0 && (!(d > 0.0) || !isfinite(d))) ? c : bad;
-    const double rs = rsqrt_nr(d);  // 1 / L_cc
-    const double v = (lo && r < c) ? 0.0 : t * rs;
-    x[c] = v;
+    // pivot block T_iq = t_q of lane c0 + i (i >= q), factored uniformly
+    double T[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q <= i; ++q) T[i][q] = readlane_f64(t[q], c0 + i);
+    double Lb[4][4], rs[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double d = T[q][q];
+#pragma unroll
+      for (int p = 0; p < q; ++p) d = fma(-Lb[q][p], Lb[q][p], d);
+      rs[q] = rsqrt_nr(d);
+      Lb[q][q] = d * rs[q];
+#pragma unroll
+      for (int i = q + 1; i < 4; ++i) {
+        double v = T[i][q];
+#pragma unroll
+        for (int p = 0; p < q; ++p) v = fma(-Lb[i][p], Lb[q][p], v);
+        Lb[i][q] = v * rs[q];
+      }
+      myd = (r == c0 + q) ? d : myd;
+      myrs = (r == c0 + q) ? rs[q] : myrs;
+    }
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double u = t[q];
+#pragma unroll
+      for (int p = 0; p < q; ++p) u = fma(-v[p], Lb[q][p], u);
+      v[q] = (lo && r < c0 + q) ? 0.0 : u * rs[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[c0 + q] = v[q];
     __builtin_amdgcn_wave_barrier();
-    if (lo) P[r * PLD + c] = v;
-    if (lane == c) rdiag[c] = rs;
+    if (lo) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) P[r * PLD + c0 + q] = v[q];
+    }
     __builtin_amdgcn_wave_barrier();
   }
+  if (lo) rdiag[r] = myrs;
   if (!lo) {
 #pragma unroll
     for (int j = 0; j < PW; ++j) Z[j * PLD + r] = x[j];
   }
-  return bad;
+  const unsigned long long m = __ballot(lo && (!(myd > 0.0) || !isfinite(myd)));
+  return m ? (int)__builtin_ctzll(m) : -1;
 }
 
 template <int NB>
