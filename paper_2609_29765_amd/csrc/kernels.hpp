@@ -220,56 +220,66 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-  for (int32_t ci = cb; ci < ce; ++ci) {
+  // One stream of (contribution, 16-wide K chunk) steps: the next step's
+  // operand rows (and, at a contribution boundary, its row maps) are fetched
+  // into registers while the current step runs on MFMA, so contribution
+  // boundaries cost no extra latency.  Rows a map leaves out load as zeros.
+  constexpr int KSTEPS = NB / UKT2;
+  const int32_t nsteps = (ce - cb) * KSTEPS;
+  int32_t sa = -1, sb = -1;
+  const double* pa = S;
+  const double* pb = S;
+  auto open_contrib = [&](int32_t ci) {
     const ContribD c = contribs[ci];
-    int32_t sa = -1, sb = -1;
-    {
-      const int32_t r = r0 + lr;
-      if (r < u.c_rows) sa = c.rowmap < 0 ? (r < c.a_rows ? r : -1) : maps[c.rowmap + r];
-      const int32_t cc = c0 + lr;
-      if (cc < ncols) sb = c.colmap < 0 ? (cc < c.b_rows ? cc : -1) : maps[c.colmap + cc];
-    }
-    if (!__syncthreads_or(sa >= 0)) continue;
-    if (!__syncthreads_or(sb >= 0)) continue;
-    const double* pa = S + c.a_off + (int64_t)max(sa, 0) * NB + lk;
-    const double* pb = S + c.b_off + (int64_t)max(sb, 0) * NB + lk;
-    double2 ra[4], rb[4];
+    const int32_t r = r0 + lr;
+    sa = -1;
+    sb = -1;
+    if (r < u.c_rows) sa = c.rowmap < 0 ? (r < c.a_rows ? r : -1) : maps[c.rowmap + r];
+    const int32_t cc = c0 + lr;
+    if (cc < ncols) sb = c.colmap < 0 ? (cc < c.b_rows ? cc : -1) : maps[c.colmap + cc];
+    pa = S + c.a_off + (int64_t)max(sa, 0) * NB + lk;
+    pb = S + c.b_off + (int64_t)max(sb, 0) * NB + lk;
+  };
+  double2 ra[4], rb[4];
+  auto fetch = [&](int32_t k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      ra[q] = sa >= 0 ? reinterpret_cast<const double2*>(pa)[q] : make_double2(0.0, 0.0);
-      rb[q] = sb >= 0 ? reinterpret_cast<const double2*>(pb)[q] : make_double2(0.0, 0.0);
+      ra[q] = sa >= 0 ? reinterpret_cast<const double2*>(pa + k0)[q] : make_double2(0.0, 0.0);
+      rb[q] = sb >= 0 ? reinterpret_cast<const double2*>(pb + k0)[q] : make_double2(0.0, 0.0);
     }
-    for (int k0 = 0; k0 < NB; k0 += UKT2) {
-      double* As = smem + ((k0 / UKT2) & 1) * 2 * UB2 * ULD2;
-      double* Bs = As + UB2 * ULD2;
+  };
+  if (nsteps > 0) {
+    open_contrib(cb);
+    fetch(0);
+  }
+  for (int32_t st = 0; st < nsteps; ++st) {
+    double* As = smem + (st & 1) * 2 * UB2 * ULD2;
+    double* Bs = As + UB2 * ULD2;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        As[lr * ULD2 + lk + 2 * q] = ra[q].x;
-        As[lr * ULD2 + lk + 2 * q + 1] = ra[q].y;
-        Bs[lr * ULD2 + lk + 2 * q] = rb[q].x;
-        Bs[lr * ULD2 + lk + 2 * q + 1] = rb[q].y;
-      }
-      __syncthreads();
-      if (k0 + UKT2 < NB) {
+    for (int q = 0; q < 4; ++q) {
+      As[lr * ULD2 + lk + 2 * q] = ra[q].x;
+      As[lr * ULD2 + lk + 2 * q + 1] = ra[q].y;
+      Bs[lr * ULD2 + lk + 2 * q] = rb[q].x;
+      Bs[lr * ULD2 + lk + 2 * q + 1] = rb[q].y;
+    }
+    __syncthreads();
+    if (st + 1 < nsteps) {
+      const int32_t kn = (st + 1) % KSTEPS;
+      if (kn == 0) open_contrib(cb + (st + 1) / KSTEPS);
+      fetch(kn * UKT2);
+    }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          ra[q] = sa >= 0 ? reinterpret_cast<const double2*>(pa + k0 + UKT2)[q] : make_double2(0.0, 0.0);
-          rb[q] = sb >= 0 ? reinterpret_cast<const double2*>(pb + k0 + UKT2)[q] : make_double2(0.0, 0.0);
-        }
-      }
+    for (int kk = 0; kk < UKT2; kk += 4) {
+      double af[4], bf[4];
 #pragma unroll
-      for (int kk = 0; kk < UKT2; kk += 4) {
-        double af[4], bf[4];
+      for (int a = 0; a < 4; ++a) af[a] = As[(wr + a * 16 + (lane & 15)) * ULD2 + kk + (lane >> 4)];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) af[a] = As[(wr + a * 16 + (lane & 15)) * ULD2 + kk + (lane >> 4)];
+      for (int b = 0; b < 4; ++b) bf[b] = Bs[(wc + b * 16 + (lane & 15)) * ULD2 + kk + (lane >> 4)];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) bf[b] = Bs[(wc + b * 16 + (lane & 15)) * ULD2 + kk + (lane >> 4)];
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
-      }
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
     }
   }
   // epilogue: lane holds D[i][j] with j = lane % 16, i = lane / 16 + 4 e.
