@@ -64,7 +64,7 @@ constexpr int UB = 64;   // output block
 constexpr int UKT = 16;  // K chunk staged in LDS
 constexpr int ULD = UKT + 1;
 
-constexpr int UPD_LDS = 2 * UB * ULD + UB;  // doubles: As, Bs, two int maps
+constexpr int UPD_LDS = 2 * UB * ULD;  // doubles: As, Bs
 
 template <int NB>
 __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict__ items,
@@ -73,74 +73,75 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
                                            const int32_t* __restrict__ maps,
                                            double* __restrict__ S, const double* __restrict__ parts,
                                            double* smem) {
-  double* As = smem;
-  double* Bs = smem + UB * ULD;
-  int32_t* arow = reinterpret_cast<int32_t*>(smem + 2 * UB * ULD);
-  int32_t* bcol = arow + UB;
   const int32_t task = items[4 * it], bx = items[4 * it + 1], by = items[4 * it + 2];
   const UpdTaskD u = tasks[task];
   const int32_t r0 = bx * UB, c0 = by * UB;
   const int32_t ncols = u.diag ? u.c_rows : NB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int srow = tid >> 2, skq = (tid & 3) * 4;  // row and 4 columns this thread stages
 
   d4 acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-  for (int32_t ci = u.c_begin; ci < u.c_end; ++ci) {
+  // one stream of (contribution, 16-wide K chunk) steps, the next step's
+  // operand rows (and at a contribution boundary its row maps) fetched into
+  // registers while the current one runs; absent rows load as zeros
+  constexpr int KSTEPS = NB / UKT;
+  const int32_t nsteps = (u.c_end - u.c_begin) * KSTEPS;
+  int32_t sa = -1, sb = -1;
+  const double* pa = S;
+  const double* pb = S;
+  auto open_contrib = [&](int32_t ci) {
     const ContribD c = contribs[ci];
-    int32_t src = -1;
-    if (tid < UB) {
-      int32_t r = r0 + tid;
-      if (r < u.c_rows) src = c.rowmap < 0 ? (r < c.a_rows ? r : -1) : maps[c.rowmap + r];
-      arow[tid] = src;
-    } else if (tid < 2 * UB) {
-      int32_t cc = c0 + tid - UB;
-      if (cc < ncols) src = c.colmap < 0 ? (cc < c.b_rows ? cc : -1) : maps[c.colmap + cc];
-      bcol[tid - UB] = src;
+    const int32_t r = r0 + srow, cc = c0 + srow;
+    sa = -1;
+    sb = -1;
+    if (r < u.c_rows) sa = c.rowmap < 0 ? (r < c.a_rows ? r : -1) : maps[c.rowmap + r];
+    if (cc < ncols) sb = c.colmap < 0 ? (cc < c.b_rows ? cc : -1) : maps[c.colmap + cc];
+    pa = S + c.a_off + (int64_t)max(sa, 0) * NB + skq;
+    pb = S + c.b_off + (int64_t)max(sb, 0) * NB + skq;
+  };
+  double2 a0, a1, b0, b1;
+  auto fetch = [&](int32_t k0) {
+    const double2 z = make_double2(0.0, 0.0);
+    a0 = sa >= 0 ? reinterpret_cast<const double2*>(pa + k0)[0] : z;
+    a1 = sa >= 0 ? reinterpret_cast<const double2*>(pa + k0)[1] : z;
+    b0 = sb >= 0 ? reinterpret_cast<const double2*>(pb + k0)[0] : z;
+    b1 = sb >= 0 ? reinterpret_cast<const double2*>(pb + k0)[1] : z;
+  };
+  if (nsteps > 0) {
+    open_contrib(u.c_begin);
+    fetch(0);
+  }
+  double* As = smem;
+  double* Bs = smem + UB * ULD;
+  for (int32_t st = 0; st < nsteps; ++st) {
+    {
+      double* da = As + srow * ULD + skq;
+      double* db = Bs + srow * ULD + skq;
+      da[0] = a0.x; da[1] = a0.y; da[2] = a1.x; da[3] = a1.y;
+      db[0] = b0.x; db[1] = b0.y; db[2] = b1.x; db[3] = b1.y;
     }
-    // block-wide: does any gathered A row and any gathered B row land here?
-    const int anyA = __syncthreads_or(tid < UB && src >= 0);
-    const int anyB = __syncthreads_or(tid >= UB && tid < 2 * UB && src >= 0);
-    if (!(anyA && anyB)) continue;
-    const double* A = S + c.a_off;
-    const double* B = S + c.b_off;
-    for (int k0 = 0; k0 < NB; k0 += UKT) {
-      // 64 rows x 16 columns per operand: 4 consecutive doubles per thread
-      {
-        const int row = tid >> 2, kq = (tid & 3) * 4;
-        const int32_t sa = arow[row], sb = bcol[row];
-        double2 a0 = make_double2(0.0, 0.0), a1 = a0, b0 = a0, b1 = a0;
-        if (sa >= 0) {
-          const double2* pa = reinterpret_cast<const double2*>(A + (int64_t)sa * NB + k0 + kq);
-          a0 = pa[0];
-          a1 = pa[1];
-        }
-        if (sb >= 0) {
-          const double2* pb = reinterpret_cast<const double2*>(B + (int64_t)sb * NB + k0 + kq);
-          b0 = pb[0];
-          b1 = pb[1];
-        }
-        double* da = As + row * ULD + kq;
-        double* db = Bs + row * ULD + kq;
-        da[0] = a0.x; da[1] = a0.y; da[2] = a1.x; da[3] = a1.y;
-        db[0] = b0.x; db[1] = b0.y; db[2] = b1.x; db[3] = b1.y;
-      }
-      __syncthreads();
+    __syncthreads();
+    if (st + 1 < nsteps) {
+      const int32_t kn = (st + 1) % KSTEPS;
+      if (kn == 0) open_contrib(u.c_begin + (st + 1) / KSTEPS);
+      fetch(kn * UKT);
+    }
 #pragma unroll
-      for (int kk = 0; kk < UKT; kk += 4) {
-        // A fragment: lane holds A[i = lane % 16][k = lane / 16]
-        // B fragment: lane holds B[k = lane / 16][j = lane % 16] = Bop[j][k]
-        double af[2], bf[2];
-        for (int a = 0; a < 2; ++a) af[a] = As[(wr + a * 16 + (lane & 15)) * ULD + kk + (lane >> 4)];
-        for (int b = 0; b < 2; ++b) bf[b] = Bs[(wc + b * 16 + (lane & 15)) * ULD + kk + (lane >> 4)];
-        for (int a = 0; a < 2; ++a)
-          for (int b = 0; b < 2; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
-      }
-      __syncthreads();
+    for (int kk = 0; kk < UKT; kk += 4) {
+      // A fragment: lane holds A[i = lane % 16][k = lane / 16]
+      // B fragment: lane holds B[k = lane / 16][j = lane % 16] = Bop[j][k]
+      double af[2], bf[2];
+      for (int a = 0; a < 2; ++a) af[a] = As[(wr + a * 16 + (lane & 15)) * ULD + kk + (lane >> 4)];
+      for (int b = 0; b < 2; ++b) bf[b] = Bs[(wc + b * 16 + (lane & 15)) * ULD + kk + (lane >> 4)];
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
     }
+    __syncthreads();
   }
   // epilogue: lane holds D[i][j] with j = lane % 16, i = lane / 16 + 4 e
   double* C = S + u.c_off;
