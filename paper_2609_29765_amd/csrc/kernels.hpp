@@ -1010,7 +1010,8 @@ __global__ __launch_bounds__(256) void k_trtri(const int32_t* __restrict__ items
 constexpr int CB = 64;
 constexpr int CKT = 16;
 constexpr int CLD = CKT + 1;
-constexpr int CON_LDS = 2 * CB * CLD + CB / 2 + CKT;  // As, Bs, row map, two chunk maps
+template <int NB>
+constexpr int con_lds() { return 2 * CB * CLD + (CB + 2 * NB + 1) / 2; }  // As, Bs, row map, two K maps
 
 struct BackArgs {
   const int32_t* items;  // triples: task, block row, block column
@@ -1027,9 +1028,9 @@ __global__ __launch_bounds__(256) void k_backcon(BackArgs g) {
   extern __shared__ double smem[];
   double* As = smem;
   double* Bs = smem + CB * CLD;
-  int32_t* arow = reinterpret_cast<int32_t*>(smem + 2 * CB * CLD);
-  int32_t* aq = arow + CB;
-  int32_t* bq = aq + CKT;
+  int32_t* arow = reinterpret_cast<int32_t*>(smem + 2 * CB * CLD);  // CB
+  int32_t* aq = arow + CB;                                           // NB
+  int32_t* bq = aq + NB;                                             // NB
   const int32_t task = g.items[3 * blockIdx.x], bx = g.items[3 * blockIdx.x + 1],
                 by = g.items[3 * blockIdx.x + 2];
   const ConTaskD u = g.tasks[task];
@@ -1039,73 +1040,63 @@ __global__ __launch_bounds__(256) void k_backcon(BackArgs g) {
   d4 acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  // Per term, its row map and both contraction maps go to LDS once; then the
+  // 16-wide chunks of K run with the next chunk's values read into registers
+  // while the current one is on MFMA.  Each thread stages four A elements --
+  // (row tid/4, p = 4 (tid%4) .. +3) for a stored or symmetric A, (rows
+  // 4 (tid%16) .. +3, p = tid/16) for a transposed one -- and four B elements
+  // (p = tid/16, columns c0 + 4 (tid%16) .. +3).
+  const int arow_n = tid >> 2, apq_n = (tid & 3) * 4;
+  const int arow_t = (tid & 15) * 4, apq_t = tid >> 4;
+  const int bp = tid >> 4, bj = (tid & 15) * 4;
   for (int32_t t = u.t_begin; t < u.t_end; ++t) {
     const ConTermD c = g.terms[t];
     const double* A = (c.a_buf == 0 ? g.L : (c.a_buf == 1 ? g.Z : g.M)) + c.a_off;
     const double* B = (c.b_buf == 0 ? g.L : (c.b_buf == 1 ? g.Z : g.M)) + c.b_off;
-    __syncthreads();  // previous term's maps consumed
+    const bool tr = c.a_mode == CA_TRANS;
+    __syncthreads();  // previous term's maps and chunks consumed
     if (tid < CB) {
       const int32_t r = r0 + tid;
-      int32_t v = -1;
-      if (r < u.c_rows) v = c.a_rmap < 0 ? r : g.maps[c.a_rmap + r];
-      arow[tid] = v;
+      arow[tid] = r < u.c_rows ? (c.a_rmap < 0 ? r : g.maps[c.a_rmap + r]) : -1;
     }
-    for (int32_t k0 = 0; k0 < c.K; k0 += CKT) {
-      if (tid < CKT) {
-        const int32_t p = k0 + tid;
-        aq[tid] = p < c.K ? (c.a_qmap < 0 ? p : g.maps[c.a_qmap + p]) : -1;
-      } else if (tid < 2 * CKT) {
-        const int32_t p = k0 + tid - CKT;
-        bq[tid - CKT] = p < c.K ? (c.b_qmap < 0 ? p : g.maps[c.b_qmap + p]) : -1;
-      }
-      __syncthreads();
-      // A chunk: 64 rows x 16; B chunk: 16 x 64 columns; 4 elements per thread
-      double av[4], bv[4];
-      int arr[4], apq[4];
-      if (c.a_mode == CA_TRANS) {
-        const int p = tid >> 4, rb = (tid & 15) * 4;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          arr[e] = rb + e;
-          apq[e] = p;
-        }
-      } else {
-        const int row = tid >> 2, pb = (tid & 3) * 4;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          arr[e] = row;
-          apq[e] = pb + e;
-        }
-      }
+    for (int p = tid; p < c.K; p += 256) {
+      aq[p] = c.a_qmap < 0 ? p : g.maps[c.a_qmap + p];
+      bq[p] = c.b_qmap < 0 ? p : g.maps[c.b_qmap + p];
+    }
+    __syncthreads();
+    double av[4], bv[4];
+    auto fetch = [&](int32_t k0) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int32_t rr = arow[arr[e]], qq = aq[apq[e]];
+        const int32_t rl = tr ? arow_t + e : arow_n;
+        const int32_t pl = k0 + (tr ? apq_t : apq_n + e);
+        const int32_t rr = arow[rl], qq = pl < c.K ? aq[pl] : -1;
         const int32_t rc = max(rr, 0), qc = max(qq, 0);
         int64_t off;
         if (c.a_mode == CA_NORMAL) off = (int64_t)rc * NB + qc;
-        else if (c.a_mode == CA_TRANS) off = (int64_t)qc * NB + rc;
+        else if (tr) off = (int64_t)qc * NB + rc;
         else off = (int64_t)max(rc, qc) * NB + min(rc, qc);
         const double v = A[off];
         av[e] = (rr >= 0 && qq >= 0) ? v : 0.0;
       }
-      {
-        const int p = tid >> 4, jb = (tid & 15) * 4;
-        const int32_t qb = bq[p];
+      const int32_t pb = k0 + bp;
+      const int32_t qb = pb < c.K ? bq[pb] : -1;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int32_t j = c0 + jb + e;
-          const double v = B[(int64_t)max(qb, 0) * NB + min(j, NB - 1)];
-          bv[e] = (qb >= 0 && j < NB) ? v : 0.0;
-        }
+      for (int e = 0; e < 4; ++e) {
+        const int32_t j = c0 + bj + e;
+        const double v = B[(int64_t)max(qb, 0) * NB + min(j, NB - 1)];
+        bv[e] = (qb >= 0 && j < NB) ? v : 0.0;
       }
+    };
+    fetch(0);
+    for (int32_t k0 = 0; k0 < c.K; k0 += CKT) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) As[arr[e] * CLD + apq[e]] = av[e];
-      {
-        const int p = tid >> 4, jb = (tid & 15) * 4;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) Bs[(jb + e) * CLD + p] = bv[e];
+      for (int e = 0; e < 4; ++e) {
+        As[(tr ? arow_t + e : arow_n) * CLD + (tr ? apq_t : apq_n + e)] = av[e];
+        Bs[(bj + e) * CLD + bp] = bv[e];
       }
       __syncthreads();
+      if (k0 + CKT < c.K) fetch(k0 + CKT);
 #pragma unroll
       for (int kk = 0; kk < CKT; kk += 4) {
         double af[2], bf[2];

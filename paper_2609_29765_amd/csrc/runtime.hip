@@ -387,7 +387,7 @@ int launch_backward_nb(stc_handle* h, hipStream_t st) {
     const int32_t a = h->back_level_ptr[L], b = h->back_level_ptr[L + 1];
     if (b == a) continue;
     g.items = h->d_bitems + 3 * (int64_t)a;
-    hipLaunchKernelGGL((k_backcon<NB>), dim3(b - a), dim3(256), sizeof(double) * CON_LDS, st, g);
+    hipLaunchKernelGGL((k_backcon<NB>), dim3(b - a), dim3(256), sizeof(double) * con_lds<NB>(), st, g);
   }
   HIPCHK(hipGetLastError());
   return 0;
