@@ -764,19 +764,22 @@ constexpr int TR = 32;
 constexpr int TLD = 4;  // row padding of the LDS copies
 
 template <int NB>
-constexpr int trsm_lds() { return TR * (NB + TLD) + PW * (NB + TLD); }
+constexpr int trsm_lds() { return TR * (NB + TLD) + PW * (PW + 1); }
 
-// X and the 32 rows of L that a block needs sit in LDS; every global read is
-// issued in bulk with clamped addresses.
+// X (the panel rows) sits in LDS; the rows of L a block column needs stream
+// through one 32 x 32 LDS chunk, the next chunk and the next 32 x 32 inverse
+// read into registers while the current one is used.  Keeping only X
+// resident lets two work-groups share a compute unit.
 template <int NB>
 __device__ __forceinline__ void dev_trsm(int32_t it, const int32_t* __restrict__ items,
                                          const TrsmTaskD* __restrict__ tasks,
                                          double* __restrict__ S,
                                          const double* __restrict__ dinv_m, double* smem) {
   constexpr int XLD = NB + TLD;
+  constexpr int CLDT = PW + 1;
   constexpr int PER = TR * NB / 256;
   double* X = smem;
-  double* Lr = smem + TR * XLD;
+  double* Lc = smem + TR * XLD;  // 32 x 32 chunk of L
   const TrsmTaskD t = tasks[items[2 * it]];
   const int32_t rb = items[2 * it + 1];
   const int32_t r0 = rb * TR;
@@ -798,56 +801,58 @@ __device__ __forceinline__ void dev_trsm(int32_t it, const int32_t* __restrict__
       X[(x / NB) * XLD + x % NB] = (x / NB) < nr ? v[q] : 0.0;
     }
   }
-  // each wave owns one 16 x 16 tile of the 32 x 32 block column.  The rows
-  // of L for the next block column (columns before it only) and the next
-  // 32 x 32 inverse are loaded into registers while the current one is
-  // computed; the K loop runs four independent accumulators.
+  __syncthreads();  // X staged before block column 0 reads it
+  // each wave owns one 16 x 16 tile of the 32 x 32 block column
   const int wr = (wave >> 1) * 16, wc = (wave & 1) * 16;
+  const int crow = tid >> 3, ccol = (tid & 7) * 4;  // this thread's 4 values of a chunk
   constexpr int NJ = NB / PW;
-  constexpr int LPER = PW * (NB - PW) / 256;  // L values per thread, largest block column
-  double lv[LPER > 0 ? LPER : 1];
+  // the chunks in use order: block column J needs rows J*32.. of L, column
+  // chunks g = 0..J-1; chunk index s runs over all (J, g) pairs
+  double cv[4];
+  auto fetch_chunk = [&](int J, int g) {
+    const double* src = L + (int64_t)(J * PW + crow) * NB + g * PW + ccol;
+    const double2 a = reinterpret_cast<const double2*>(src)[0];
+    const double2 b = reinterpret_cast<const double2*>(src)[1];
+    cv[0] = a.x;
+    cv[1] = a.y;
+    cv[2] = b.x;
+    cv[3] = b.y;
+  };
   double dz[PW / 4];
-  auto fetch = [&](int j0n) {  // rows j0n..j0n+31 of L, columns < j0n; inverse of block j0n
-#pragma unroll
-    for (int q = 0; q < LPER; ++q) {
-      const int x = q * 256 + tid;  // 32 x 32 groups: group x >> 10, row (x >> 5) & 31, column x & 31
-      if (x < PW * j0n) lv[q] = L[(int64_t)(j0n + ((x >> 5) & 31)) * NB + (x >> 10) * PW + (x & 31)];
-    }
-    const double* db = dinv + (j0n / PW) * PW * PW + (wc + (lane & 15)) * PW + (lane >> 4);
+  auto fetch_inv = [&](int J) {
+    const double* db = dinv + J * PW * PW + (wc + (lane & 15)) * PW + (lane >> 4);
 #pragma unroll
     for (int q = 0; q < PW / 4; ++q) dz[q] = db[4 * q];
   };
-  fetch(0);
+  fetch_inv(0);
+  if (NJ > 1) fetch_chunk(1, 0);
   for (int J = 0; J < NJ; ++J) {
     const int j0 = J * PW;
-    if (j0 > 0) {
+    d4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = acc;
+    const double* xa = X + (wr + (lane & 15)) * XLD + (lane >> 4);
+    const double* lb = Lc + (wc + (lane & 15)) * CLDT + (lane >> 4);
+    for (int g = 0; g < J; ++g) {
+      __syncthreads();  // previous chunk consumed
 #pragma unroll
-      for (int q = 0; q < LPER; ++q) {
-        const int x = q * 256 + tid;
-        if (x < PW * j0) Lr[((x >> 5) & 31) * XLD + (x >> 10) * PW + (x & 31)] = lv[q];
+      for (int e = 0; e < 4; ++e) Lc[crow * CLDT + ccol + e] = cv[e];
+      __syncthreads();
+      if (g + 1 < J) fetch_chunk(J, g + 1);
+      else if (J + 1 < NJ) fetch_chunk(J + 1, 0);
+#pragma unroll
+      for (int kk = 0; kk < PW; kk += 8) {
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[g * PW + kk], lb[kk], acc, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[g * PW + kk + 4], lb[kk + 4], acc2, 0, 0, 0);
       }
     }
     double dzc[PW / 4];
 #pragma unroll
     for (int q = 0; q < PW / 4; ++q) dzc[q] = dz[q];
-    __syncthreads();
-    if (J + 1 < NJ) fetch(j0 + PW);
-    d4 acc[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
-    const double* xa = X + (wr + (lane & 15)) * XLD + (lane >> 4);
-    const double* lb = Lr + (wc + (lane & 15)) * XLD + (lane >> 4);
-    for (int kk = 0; kk < j0; kk += 16) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[kk + 4 * u], lb[kk + 4 * u], acc[u], 0, 0, 0);
-    }
+    if (J + 1 < NJ) fetch_inv(J + 1);
     // Y = X_J - acc, kept in registers until every wave has read X_<J
     double y[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e)
-      y[e] = X[(wr + (lane >> 4) + 4 * e) * XLD + j0 + wc + (lane & 15)] -
-             ((acc[0][e] + acc[1][e]) + (acc[2][e] + acc[3][e]));
+      y[e] = X[(wr + (lane >> 4) + 4 * e) * XLD + j0 + wc + (lane & 15)] - (acc[e] + acc2[e]);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 4; ++e) X[(wr + (lane >> 4) + 4 * e) * XLD + j0 + wc + (lane & 15)] = y[e];
