@@ -788,7 +788,7 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std
       bool any = false;
       for (int32_t id : lev_tasks[(size_t)L]) {
         const UpdTask& u = p->upd[(size_t)id];
-        any |= u.big && u.partner >= 0 && u.c_end - u.c_begin >= 2;
+        any |= u.partner >= 0 && u.c_end - u.c_begin >= 2;
       }
       if (!any) continue;
       int32_t best_sp = 1;
@@ -798,7 +798,7 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std
         for (int32_t id : lev_tasks[(size_t)L]) {
           const UpdTask& u = p->upd[(size_t)id];
           const int64_t ncon = u.c_end - u.c_begin;
-          const int32_t s_u = (u.big && u.partner >= 0) ? (int32_t)std::max<int64_t>(1, std::min<int64_t>(sp, ncon / 2)) : 1;
+          const int32_t s_u = u.partner >= 0 ? (int32_t)std::max<int64_t>(1, std::min<int64_t>(sp, ncon / 2)) : 1;
           const int64_t nblk = blocks(u);
           for (int32_t part = 0; part < s_u; ++part) {
             const double d = dur(u, ncon * (part + 1) / s_u - ncon * part / s_u);
@@ -822,7 +822,7 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std
       }
       for (int32_t id : lev_tasks[(size_t)L]) {
         UpdTask& u = p->upd[(size_t)id];
-        if (!u.big || u.partner < 0) continue;
+        if (u.partner < 0) continue;
         const int32_t ncon = u.c_end - u.c_begin;
         const int32_t sp = std::min(best_sp, ncon / 2);
         if (sp < 2) continue;

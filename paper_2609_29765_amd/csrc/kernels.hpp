@@ -71,11 +71,15 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
                                            const UpdTaskD* __restrict__ tasks,
                                            const ContribD* __restrict__ contribs,
                                            const int32_t* __restrict__ maps,
-                                           double* __restrict__ S, const double* __restrict__ parts,
+                                           double* __restrict__ S, double* __restrict__ parts,
                                            double* smem) {
   const int32_t task = items[4 * it], bx = items[4 * it + 1], by = items[4 * it + 2];
+  const int32_t part = items[4 * it + 3];
   const UpdTaskD u = tasks[task];
   const int32_t r0 = bx * UB, c0 = by * UB;
+  const int32_t ncon = u.c_end - u.c_begin;
+  const int32_t cb = u.c_begin + (int32_t)((int64_t)ncon * part / u.nsplit);
+  const int32_t ce = u.c_begin + (int32_t)((int64_t)ncon * (part + 1) / u.nsplit);
   const int32_t ncols = u.diag ? u.c_rows : NB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
@@ -89,7 +93,7 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
   // operand rows (and at a contribution boundary its row maps) fetched into
   // registers while the current one runs; absent rows load as zeros
   constexpr int KSTEPS = NB / UKT;
-  const int32_t nsteps = (u.c_end - u.c_begin) * KSTEPS;
+  const int32_t nsteps = (ce - cb) * KSTEPS;
   int32_t sa = -1, sb = -1;
   const double* pa = S;
   const double* pb = S;
@@ -112,7 +116,7 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
     b1 = sb >= 0 ? reinterpret_cast<const double2*>(pb + k0)[1] : z;
   };
   if (nsteps > 0) {
-    open_contrib(u.c_begin);
+    open_contrib(cb);
     fetch(0);
   }
   double* As = smem;
@@ -127,7 +131,7 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
     __syncthreads();
     if (st + 1 < nsteps) {
       const int32_t kn = (st + 1) % KSTEPS;
-      if (kn == 0) open_contrib(u.c_begin + (st + 1) / KSTEPS);
+      if (kn == 0) open_contrib(cb + (st + 1) / KSTEPS);
       fetch(kn * UKT);
     }
 #pragma unroll
@@ -143,9 +147,25 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
     }
     __syncthreads();
   }
-  // epilogue: lane holds D[i][j] with j = lane % 16, i = lane / 16 + 4 e
+  // epilogue: lane holds D[i][j] with j = lane % 16, i = lane / 16 + 4 e;
+  // parts > 0 of a split range write their partial slot, which the tile's
+  // next update task folds in
   double* C = S + u.c_off;
   const int64_t slot = (int64_t)u.c_rows * NB;
+  if (part > 0) {
+    double* pp = parts + u.part_off + (part - 1) * slot;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int32_t i = r0 + wr + a * 16 + (lane >> 4) + 4 * e;
+          const int32_t j = c0 + wc + b * 16 + (lane & 15);
+          if (i < u.c_rows && j < ncols && (!u.diag || j <= i)) pp[(int64_t)i * NB + j] = acc[a][b][e];
+        }
+    return;
+  }
   for (int q = 0; q < u.in_npart; ++q) {
     const double* pq = parts + u.in_part_off + q * slot;
 #pragma unroll
