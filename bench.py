@@ -272,7 +272,8 @@ def extra_backward():
     from paper_2609_29765_amd.autotune import autotune
     w = workloads.differentiable_arrowhead(20, 25, 8, 0)
     v = torch.from_numpy(w.values).cuda()
-    a, table = autotune(w.n, w.colptr, w.rowind, v, nbs=(32, 64, 128), ordering="nd", trials=3)
+    a, table = autotune(w.n, w.colptr, w.rowind, v, nbs=(32, 64, 128), ordering="nd", trials=3,
+                        objective="logdet_grad")
     one = torch.ones(1, dtype=torch.float64, device="cuda")
     dv = torch.from_numpy(w.dvalues).cuda()
 

@@ -13,11 +13,14 @@ from . import stc
 
 
 def autotune(n, colptr, rowind, values, nbs=(64, 128, 256), modes=("auto",), ordering="auto",
-             batched=False, trials=3, warmup=1):
+             batched=False, trials=3, warmup=1, objective="factorize"):
     """Return (best Analysis, bound; table of every candidate).
 
     values: device float64 [nnz] (batched=False) or [B, nnz] (batched=True).
-    Each table row: nb, mode, ms per factorization call, levels, tile flops.
+    objective: "factorize" times one factorization call; "logdet_grad" times
+    a factorization followed by the logdet reverse mode (the unit of work of
+    a gradient-based fit).
+    Each table row: nb, mode, ms per call, levels, tile flops.
     Candidates that lose release their workspace.
     """
     import torch
@@ -34,11 +37,15 @@ def autotune(n, colptr, rowind, values, nbs=(64, 128, 256), modes=("auto",), ord
                 a = stc.Analysis(n, colptr, rowind, nb=nb, mode=mode, ordering="given", perm=perm)
             a.bind(batch=values.shape[0] if batched else 1)
 
+            one = torch.ones(1, dtype=torch.float64, device=values.device)
+
             def run():
                 if batched:
                     a.factorize_batched(values)
                 else:
                     a.factorize(values)
+                    if objective == "logdet_grad":
+                        a.logdet_backward(one)
 
             for _ in range(warmup):
                 run()
