@@ -1033,7 +1033,7 @@ __global__ __launch_bounds__(256) void k_trtri(const int32_t* __restrict__ items
 // with its lower triangle stored); B_t(p, j) is row p of a tile (through an
 // optional map), j the output column.  K is staged in LDS in chunks of 16.
 constexpr int CB = 64;
-constexpr int CKT = 16;
+constexpr int CKT = 32;
 constexpr int CLD = CKT + 1;
 template <int NB>
 constexpr int con_lds() { return 2 * CB * CLD + (CB + 2 * NB + 1) / 2; }  // As, Bs, row map, two K maps
@@ -1066,14 +1066,14 @@ __global__ __launch_bounds__(256) void k_backcon(BackArgs g) {
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
   // Per term, its row map and both contraction maps go to LDS once; then the
-  // 16-wide chunks of K run with the next chunk's values read into registers
-  // while the current one is on MFMA.  Each thread stages four A elements --
-  // (row tid/4, p = 4 (tid%4) .. +3) for a stored or symmetric A, (rows
-  // 4 (tid%16) .. +3, p = tid/16) for a transposed one -- and four B elements
-  // (p = tid/16, columns c0 + 4 (tid%16) .. +3).
-  const int arow_n = tid >> 2, apq_n = (tid & 3) * 4;
-  const int arow_t = (tid & 15) * 4, apq_t = tid >> 4;
-  const int bp = tid >> 4, bj = (tid & 15) * 4;
+  // 32-wide chunks of K run with the next chunk's values read into registers
+  // while the current one is on MFMA.  Each thread stages eight A elements --
+  // (row tid/4, p = 8 (tid%4) .. +7) for a stored or symmetric A, (rows
+  // 8 (tid%8) .. +7, p = tid/8) for a transposed one -- and eight B elements
+  // (p = tid/8, columns c0 + 8 (tid%8) .. +7).
+  const int arow_n = tid >> 2, apq_n = (tid & 3) * 8;
+  const int arow_t = (tid & 7) * 8, apq_t = tid >> 3;
+  const int bp = tid >> 3, bj = (tid & 7) * 8;
   for (int32_t t = u.t_begin; t < u.t_end; ++t) {
     const ConTermD c = g.terms[t];
     const double* A = (c.a_buf == 0 ? g.L : (c.a_buf == 1 ? g.Z : g.M)) + c.a_off;
@@ -1089,10 +1089,10 @@ __global__ __launch_bounds__(256) void k_backcon(BackArgs g) {
       bq[p] = c.b_qmap < 0 ? p : g.maps[c.b_qmap + p];
     }
     __syncthreads();
-    double av[4], bv[4];
+    double av[8], bv[8];
     auto fetch = [&](int32_t k0) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < 8; ++e) {
         const int32_t rl = tr ? arow_t + e : arow_n;
         const int32_t pl = k0 + (tr ? apq_t : apq_n + e);
         const int32_t rr = arow[rl], qq = pl < c.K ? aq[pl] : -1;
@@ -1107,7 +1107,7 @@ __global__ __launch_bounds__(256) void k_backcon(BackArgs g) {
       const int32_t pb = k0 + bp;
       const int32_t qb = pb < c.K ? bq[pb] : -1;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < 8; ++e) {
         const int32_t j = c0 + bj + e;
         const double v = B[(int64_t)max(qb, 0) * NB + min(j, NB - 1)];
         bv[e] = (qb >= 0 && j < NB) ? v : 0.0;
@@ -1116,7 +1116,7 @@ __global__ __launch_bounds__(256) void k_backcon(BackArgs g) {
     fetch(0);
     for (int32_t k0 = 0; k0 < c.K; k0 += CKT) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < 8; ++e) {
         As[(tr ? arow_t + e : arow_n) * CLD + (tr ? apq_t : apq_n + e)] = av[e];
         Bs[(bj + e) * CLD + bp] = bv[e];
       }
