@@ -769,70 +769,110 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std
       if (u.big) bigblocks[(size_t)u.level] += blocks(u);
     for (UpdTask& u : p->upd)
       if (u.big && bigblocks[(size_t)u.level] < 64 && u.c_end - u.c_begin <= 2) u.big = 0;
-    // Split of the early groups' contribution ranges, chosen per level: every
-    // split s in 1..16 is tried by simulating longest-first list scheduling of
-    // the level's update items on wg_slots concurrent work-groups, and the
-    // split with the shortest estimated makespan is kept (ties: fewer parts).
+    // Split of the early groups' K streams.  The update kernels run a task
+    // as one stream of (contribution, 16-wide K chunk) steps, nb / 16 per
+    // contribution, so a task can be cut at any step; a part is at least
+    // kMinPart steps, and parts s > 0 leave partial slots that the task's
+    // partner (its tile's next update, at a later level) folds in.  A
+    // level's split is chosen among two families -- every splittable task
+    // in s parts (s = 1..16), or every splittable task cut into parts of at
+    // most 8 t steps (t = 1..16) -- by the estimated makespan of the level
+    // plus those of the levels holding the partners it affects.  Makespans
+    // come from simulating longest-first list scheduling of a level's items
+    // on wg_slots concurrent work-groups.  Two passes over the levels in
+    // order; the second sees the first pass's splits of later levels.
     // Item durations are in units of one 128-block contribution; a 64-block
-    // contribution is a quarter; the epilogue costs a quarter plus a tenth per
-    // folded partial slot.
+    // contribution is a quarter; the epilogue costs a quarter, and each
+    // folded partial slot 0.45 (128-block) or 0.12 (64-block) -- measured
+    // on MI355X, where folding a 128-block slot takes about half the time of
+    // one contribution.
     (void)items;
-    auto dur = [&](const UpdTask& u, int64_t ncon_part) {
-      return (u.big ? 1.0 : 0.25) * (double)ncon_part + 0.25 + 0.1 * u.in_npart;
+    const int64_t ksteps = std::max<int64_t>(1, nb / 16);
+    constexpr int64_t kMinPart = 8;
+    auto steps_of = [&](const UpdTask& u) { return (int64_t)(u.c_end - u.c_begin) * ksteps; };
+    auto max_parts = [&](const UpdTask& u) -> int32_t {
+      return u.partner >= 0 ? (int32_t)std::max<int64_t>(1, std::min<int64_t>(16, steps_of(u) / kMinPart)) : 1;
+    };
+    auto dur = [&](const UpdTask& u, int64_t steps_part) {
+      return (u.big ? 1.0 : 0.25) * (double)steps_part / (double)ksteps + 0.25 + (u.big ? 0.45 : 0.12) * u.in_npart;
     };
     std::vector<std::vector<int32_t>> lev_tasks((size_t)nlev);
     for (int32_t id = 0; id < (int32_t)p->upd.size(); ++id) lev_tasks[(size_t)p->upd[(size_t)id].level].push_back(id);
     const int64_t slots = p->wg_slots;
     std::vector<double> durs;
-    for (int32_t L = 0; L < nlev; ++L) {
-      bool any = false;
+    // estimated makespan of level L with the tasks' current nsplit / in_npart
+    auto makespan = [&](int32_t L) {
+      durs.clear();
       for (int32_t id : lev_tasks[(size_t)L]) {
         const UpdTask& u = p->upd[(size_t)id];
-        any |= u.partner >= 0 && u.c_end - u.c_begin >= 2;
+        const int64_t tot = steps_of(u), nblk = blocks(u);
+        for (int32_t part = 0; part < u.nsplit; ++part) {
+          const double d = dur(u, tot * (part + 1) / u.nsplit - tot * part / u.nsplit);
+          for (int64_t b = 0; b < nblk; ++b) durs.push_back(d);
+        }
       }
-      if (!any) continue;
-      int32_t best_sp = 1;
-      double best = 1e300;
-      for (int32_t sp = 1; sp <= 16; ++sp) {
-        durs.clear();
-        for (int32_t id : lev_tasks[(size_t)L]) {
+      if (durs.empty()) return 0.0;
+      std::sort(durs.begin(), durs.end(), std::greater<double>());
+      std::priority_queue<double, std::vector<double>, std::greater<double>> q;
+      for (int64_t x = 0; x < std::min<int64_t>(slots, (int64_t)durs.size()); ++x) q.push(0.0);
+      double mk = 0;
+      for (double d : durs) {
+        const double t = q.top() + d;
+        q.pop();
+        q.push(t);
+        mk = std::max(mk, t);
+      }
+      return mk;
+    };
+    auto apply = [&](const std::vector<int32_t>& ids, const std::vector<int32_t>& sp) {
+      for (size_t x = 0; x < ids.size(); ++x) {
+        UpdTask& u = p->upd[(size_t)ids[x]];
+        u.nsplit = sp[x];
+        if (u.partner >= 0) p->upd[(size_t)u.partner].in_npart = sp[x] - 1;
+      }
+    };
+    std::vector<int32_t> cand, best_s, plev;
+    for (int32_t pass = 0; pass < 2; ++pass)
+      for (int32_t L = 0; L < nlev; ++L) {
+        const std::vector<int32_t>& ids = lev_tasks[(size_t)L];
+        bool any = false;
+        plev.clear();
+        for (int32_t id : ids) {
           const UpdTask& u = p->upd[(size_t)id];
-          const int64_t ncon = u.c_end - u.c_begin;
-          const int32_t s_u = u.partner >= 0 ? (int32_t)std::max<int64_t>(1, std::min<int64_t>(sp, ncon / 2)) : 1;
-          const int64_t nblk = blocks(u);
-          for (int32_t part = 0; part < s_u; ++part) {
-            const double d = dur(u, ncon * (part + 1) / s_u - ncon * part / s_u);
-            for (int64_t x = 0; x < nblk; ++x) durs.push_back(d);
+          if (max_parts(u) > 1) {
+            any = true;
+            plev.push_back(p->upd[(size_t)u.partner].level);
           }
         }
-        std::sort(durs.begin(), durs.end(), std::greater<double>());
-        std::priority_queue<double, std::vector<double>, std::greater<double>> q;
-        for (int64_t x = 0; x < slots; ++x) q.push(0.0);
-        double mk = 0;
-        for (double d : durs) {
-          const double t = q.top() + d;
-          q.pop();
-          q.push(t);
-          mk = std::max(mk, t);
-        }
-        if (mk < best - 1e-9) {
-          best = mk;
-          best_sp = sp;
-        }
+        if (!any) continue;
+        std::sort(plev.begin(), plev.end());
+        plev.erase(std::unique(plev.begin(), plev.end()), plev.end());
+        double best = 1e300;
+        for (int32_t fam = 0; fam < 2; ++fam)
+          for (int32_t c = 1; c <= 16; ++c) {
+            cand.assign(ids.size(), 1);
+            for (size_t x = 0; x < ids.size(); ++x) {
+              const UpdTask& u = p->upd[(size_t)ids[x]];
+              const int64_t want = fam == 0 ? c : (steps_of(u) + c * kMinPart - 1) / (c * kMinPart);
+              cand[x] = (int32_t)std::max<int64_t>(1, std::min<int64_t>(want, max_parts(u)));
+            }
+            apply(ids, cand);
+            double cost = makespan(L);
+            for (int32_t l2 : plev) cost += makespan(l2);
+            if (cost < best - 1e-9) {
+              best = cost;
+              best_s = cand;
+            }
+          }
+        apply(ids, best_s);
       }
-      for (int32_t id : lev_tasks[(size_t)L]) {
-        UpdTask& u = p->upd[(size_t)id];
-        if (u.partner < 0) continue;
-        const int32_t ncon = u.c_end - u.c_begin;
-        const int32_t sp = std::min(best_sp, ncon / 2);
-        if (sp < 2) continue;
-        u.nsplit = sp;
-        u.part_off = p->parts;
-        p->parts += (int64_t)(sp - 1) * u.c_rows * nb;
-        UpdTask& l = p->upd[(size_t)u.partner];
-        l.in_part_off = u.part_off;
-        l.in_npart = sp - 1;
-      }
+    for (UpdTask& u : p->upd) {
+      if (u.nsplit < 2) continue;
+      u.part_off = p->parts;
+      p->parts += (int64_t)(u.nsplit - 1) * u.c_rows * nb;
+      UpdTask& l = p->upd[(size_t)u.partner];
+      l.in_part_off = u.part_off;
+      l.in_npart = u.nsplit - 1;
     }
     for (int32_t id = 0; id < (int32_t)p->upd.size(); ++id) {
       const UpdTask& u = p->upd[(size_t)id];
@@ -853,8 +893,8 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std
     // level runs as a longest-processing-time-first list schedule
     auto item_dur = [&](const int32_t* q) {
       const UpdTask& u = p->upd[(size_t)q[0]];
-      const int64_t ncon = u.c_end - u.c_begin;
-      return dur(u, ncon * (q[3] + 1) / u.nsplit - ncon * q[3] / u.nsplit);
+      const int64_t tot = steps_of(u);
+      return dur(u, tot * (q[3] + 1) / u.nsplit - tot * q[3] / u.nsplit);
     };
     for (Level& L : p->levels)
       for (std::vector<int32_t>* v : {&L.big_items, &L.upd_items}) {

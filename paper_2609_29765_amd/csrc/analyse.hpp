@@ -84,7 +84,7 @@ struct UpdTask {
   int32_t level = 0;
   int32_t big = 0;        // 128 x 128 blocks (else 64 x 64)
   int32_t partner = -1;   // for an early group: the tile's last group
-  int32_t nsplit = 1;     // contribution range split over this many work-groups
+  int32_t nsplit = 1;     // K-step stream split over this many work-groups
   int64_t part_off = 0;   // partial slots written when nsplit > 1
   int64_t in_part_off = 0;
   int32_t in_npart = 0;   // partial slots folded in by this task

@@ -11,7 +11,7 @@ struct UpdTaskD {     // one output tile and its run of contributions
   int64_t in_part_off;  // partial slots of an earlier split task to fold in
   int32_t c_rows, diag;
   int32_t c_begin, c_end;
-  int32_t nsplit;       // contribution range split across nsplit work-groups
+  int32_t nsplit;       // K-step stream split across nsplit work-groups
   int32_t in_npart;     // number of partial slots to fold in
 };
 

@@ -77,9 +77,6 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
   const int32_t part = items[4 * it + 3];
   const UpdTaskD u = tasks[task];
   const int32_t r0 = bx * UB, c0 = by * UB;
-  const int32_t ncon = u.c_end - u.c_begin;
-  const int32_t cb = u.c_begin + (int32_t)((int64_t)ncon * part / u.nsplit);
-  const int32_t ce = u.c_begin + (int32_t)((int64_t)ncon * (part + 1) / u.nsplit);
   const int32_t ncols = u.diag ? u.c_rows : NB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
@@ -91,9 +88,13 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
 
   // one stream of (contribution, 16-wide K chunk) steps, the next step's
   // operand rows (and at a contribution boundary its row maps) fetched into
-  // registers while the current one runs; absent rows load as zeros
+  // registers while the current one runs; absent rows load as zeros.  Part
+  // p of a task split nsplit ways runs steps [S p / nsplit, S (p+1) / nsplit)
+  // of the task's S steps.
   constexpr int KSTEPS = NB / UKT;
-  const int32_t nsteps = (ce - cb) * KSTEPS;
+  const int32_t tot = (u.c_end - u.c_begin) * KSTEPS;
+  const int32_t g0 = (int32_t)((int64_t)tot * part / u.nsplit);
+  const int32_t nsteps = (int32_t)((int64_t)tot * (part + 1) / u.nsplit) - g0;
   int32_t sa = -1, sb = -1;
   const double* pa = S;
   const double* pb = S;
@@ -116,8 +117,8 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
     b1 = sb >= 0 ? reinterpret_cast<const double2*>(pb + k0)[1] : z;
   };
   if (nsteps > 0) {
-    open_contrib(cb);
-    fetch(0);
+    open_contrib(u.c_begin + g0 / KSTEPS);
+    fetch((g0 % KSTEPS) * UKT);
   }
   double* As = smem;
   double* Bs = smem + UB * ULD;
@@ -130,8 +131,8 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
     }
     __syncthreads();
     if (st + 1 < nsteps) {
-      const int32_t kn = (st + 1) % KSTEPS;
-      if (kn == 0) open_contrib(cb + (st + 1) / KSTEPS);
+      const int32_t g = g0 + st + 1, kn = g % KSTEPS;
+      if (kn == 0) open_contrib(u.c_begin + g / KSTEPS);
       fetch(kn * UKT);
     }
 #pragma unroll
@@ -231,9 +232,6 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
   const int lr = tid >> 1, lk = (tid & 1) * 8;  // row and k offset this thread stages
-  const int32_t ncon = u.c_end - u.c_begin;
-  const int32_t cb = u.c_begin + (int32_t)((int64_t)ncon * part / u.nsplit);
-  const int32_t ce = u.c_begin + (int32_t)((int64_t)ncon * (part + 1) / u.nsplit);
 
   d4 acc[4][4];
 #pragma unroll
@@ -245,8 +243,12 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
   // operand rows (and, at a contribution boundary, its row maps) are fetched
   // into registers while the current step runs on MFMA, so contribution
   // boundaries cost no extra latency.  Rows a map leaves out load as zeros.
+  // Part p of a task split nsplit ways runs steps [S p / nsplit,
+  // S (p+1) / nsplit) of the task's S steps.
   constexpr int KSTEPS = NB / UKT2;
-  const int32_t nsteps = (ce - cb) * KSTEPS;
+  const int32_t tot = (u.c_end - u.c_begin) * KSTEPS;
+  const int32_t g0 = (int32_t)((int64_t)tot * part / u.nsplit);
+  const int32_t nsteps = (int32_t)((int64_t)tot * (part + 1) / u.nsplit) - g0;
   int32_t sa = -1, sb = -1;
   const double* pa = S;
   const double* pb = S;
@@ -270,8 +272,8 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
     }
   };
   if (nsteps > 0) {
-    open_contrib(cb);
-    fetch(0);
+    open_contrib(u.c_begin + g0 / KSTEPS);
+    fetch((g0 % KSTEPS) * UKT2);
   }
   for (int32_t st = 0; st < nsteps; ++st) {
     double* As = smem + (st & 1) * 2 * UB2 * ULD2;
@@ -285,8 +287,8 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
     }
     __syncthreads();
     if (st + 1 < nsteps) {
-      const int32_t kn = (st + 1) % KSTEPS;
-      if (kn == 0) open_contrib(cb + (st + 1) / KSTEPS);
+      const int32_t g = g0 + st + 1, kn = g % KSTEPS;
+      if (kn == 0) open_contrib(u.c_begin + g / KSTEPS);
       fetch(kn * UKT2);
     }
 #pragma unroll
