@@ -24,6 +24,7 @@
 #include "analyse.hpp"
 
 #include <algorithm>
+#include <map>
 #include <queue>
 #include <cmath>
 #include <functional>
@@ -967,6 +968,107 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std
 // ---------------------------------------------------------------------------
 // backward plan
 // ---------------------------------------------------------------------------
+
+void kernel_dag(const Plan& p, std::vector<KernelNode>* out) {
+  out->clear();
+  // data objects: tiles by store offset, and partial slots by split task
+  // (keys -1 - task)
+  std::map<int64_t, int32_t> last_writer;
+  std::map<int64_t, std::vector<int32_t>> readers;
+  std::vector<std::vector<uint64_t>> reach;  // ancestors of each node, bitset
+  std::vector<int64_t> rd, wr;
+  std::vector<std::pair<std::vector<int64_t>, std::vector<int64_t>>> acc;  // per node of the level
+  std::vector<int32_t> split_src(p.upd.size(), -1);  // task -> split task whose slots it folds
+  for (int32_t e = 0; e < (int32_t)p.upd.size(); ++e)
+    if (p.upd[(size_t)e].nsplit > 1 && p.upd[(size_t)e].partner >= 0) split_src[(size_t)p.upd[(size_t)e].partner] = e;
+  for (int32_t L = 0; L < (int32_t)p.levels.size(); ++L) {
+    const Level& lv = p.levels[(size_t)L];
+    const int32_t first = (int32_t)out->size();
+    acc.clear();
+    for (int32_t kind = 0; kind < 3; ++kind) {
+      rd.clear();
+      wr.clear();
+      if (kind == 0) {
+        for (int32_t k : lv.potrf) wr.push_back((int64_t)k * p.nb * p.nb);
+      } else if (kind == 1) {
+        for (const std::vector<int32_t>* v : {&lv.big_items, &lv.upd_items})
+          for (size_t x = 0; x < v->size(); x += 4) {
+            const int32_t id = (*v)[x];
+            const UpdTask& u = p.upd[(size_t)id];
+            wr.push_back(u.c_off);
+            for (int32_t c = u.c_begin; c < u.c_end; ++c) {
+              rd.push_back(p.contribs[(size_t)c].a_off);
+              rd.push_back(p.contribs[(size_t)c].b_off);
+            }
+            if (u.nsplit > 1) wr.push_back(-1 - (int64_t)id);
+          }
+        // partial slots folded in by a partner: the split task that names it
+        for (const std::vector<int32_t>* v : {&lv.big_items, &lv.upd_items})
+          for (size_t x = 0; x < v->size(); x += 4) {
+            const int32_t e = split_src[(size_t)(*v)[x]];
+            if (e >= 0) rd.push_back(-1 - (int64_t)e);
+          }
+      } else {
+        for (size_t x = 0; x < lv.trsm_items.size(); x += 2) {
+          const TrsmTask& t = p.trsm[(size_t)lv.trsm_items[x]];
+          rd.push_back(t.l_off);
+          wr.push_back(t.x_off);
+        }
+      }
+      if (rd.empty() && wr.empty()) continue;
+      std::sort(rd.begin(), rd.end());
+      rd.erase(std::unique(rd.begin(), rd.end()), rd.end());
+      std::sort(wr.begin(), wr.end());
+      wr.erase(std::unique(wr.begin(), wr.end()), wr.end());
+      KernelNode nd;
+      nd.level = L;
+      nd.kind = kind;
+      std::vector<int32_t> cand;
+      for (int64_t o : rd) {
+        auto it = last_writer.find(o);
+        if (it != last_writer.end()) cand.push_back(it->second);
+      }
+      for (int64_t o : wr) {
+        auto it = last_writer.find(o);
+        if (it != last_writer.end()) cand.push_back(it->second);
+        auto jt = readers.find(o);
+        if (jt != readers.end()) cand.insert(cand.end(), jt->second.begin(), jt->second.end());
+      }
+      std::sort(cand.begin(), cand.end());
+      cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+      const int32_t id = (int32_t)out->size();
+      const size_t words = (size_t)id / 64 + 1;
+      std::vector<uint64_t> anc(words, 0);
+      auto has = [&](const std::vector<uint64_t>& b, int32_t i) {
+        return (size_t)i / 64 < b.size() && ((b[(size_t)i / 64] >> (i % 64)) & 1);
+      };
+      // transitive reduction: drop a candidate that another candidate reaches
+      for (int32_t d : cand) {
+        bool redundant = false;
+        for (int32_t d2 : cand)
+          if (d2 != d && has(reach[(size_t)d2], d)) {
+            redundant = true;
+            break;
+          }
+        if (!redundant) nd.deps.push_back(d);
+        for (size_t w = 0; w < reach[(size_t)d].size(); ++w) anc[w] |= reach[(size_t)d][w];
+        anc[(size_t)d / 64] |= uint64_t(1) << (d % 64);
+      }
+      reach.push_back(std::move(anc));
+      out->push_back(std::move(nd));
+      acc.emplace_back(rd, wr);
+    }
+    // the level's kernels touch disjoint data: update the state after all
+    for (size_t x = 0; x < acc.size(); ++x) {
+      const int32_t id = first + (int32_t)x;
+      for (int64_t o : acc[x].first) readers[o].push_back(id);
+      for (int64_t o : acc[x].second) {
+        last_writer[o] = id;
+        readers[o].clear();
+      }
+    }
+  }
+}
 
 int build_backward(const Symbolic& s, Plan* p, BackPlan* b, std::string* why) {
   (void)why;

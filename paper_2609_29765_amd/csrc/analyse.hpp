@@ -139,6 +139,19 @@ struct Plan {
 // contribution ranges is balanced for (0 = 384, measured best on MI355X)
 int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std::string* why);
 
+// The kernels of the level schedule as a dependency graph, in place of a
+// barrier between consecutive levels: node (level, kind) with kind 0 POTRF,
+// 1 updates, 2 TRSM, for every non-empty kernel, in level order.  A node
+// depends on the earlier nodes that last wrote what it reads (a tile, a
+// diagonal tile with its 32 x 32 inverses, a split task's partial slots) and
+// on those that last wrote or since read what it writes -- the edges
+// Algorithm 2 waits for through its progress matrix -- transitively reduced.
+struct KernelNode {
+  int32_t level, kind;
+  std::vector<int32_t> deps;
+};
+void kernel_dag(const Plan& p, std::vector<KernelNode>* out);
+
 // Reverse mode of log det through the factorization.  For the logdet
 // cotangent the adjoint of the blocked Cholesky restricted to pattern(L) is
 // the selected inverse Z = (P A P^T)^-1 on pattern(L); it is computed by the

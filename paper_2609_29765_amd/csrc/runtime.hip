@@ -1,12 +1,14 @@
 // runtime.hip -- C ABI of libstc.so (declared in include/stc.h): workspace
-// layout, metadata upload, level launches of the static tile schedule, HIP
-// graph capture/replay, and the consumers of the resident factor.
+// layout, metadata upload, the static tile schedule as a HIP graph, and the
+// consumers of the resident factor.
 //
 // The schedule is Algorithm 1's task set with the dependencies Algorithm 2
 // enforces through its progress matrix (a SYRK/GEMM reads finished TRSM
-// tiles, a TRSM reads its finished diagonal tile), grouped into levels: every
-// kernel of a level depends only on earlier levels, so one stream and the
-// kernel boundaries replace the spin-waits on the progress matrix.
+// tiles, a TRSM reads its finished diagonal tile), grouped into levels whose
+// kernels (POTRF, updates, TRSM) touch disjoint data.  The graph holds one
+// node per kernel with edges only to the kernels whose data it uses, so graph
+// edges and kernel boundaries replace the spin-waits on the progress matrix
+// and kernels of consecutive levels overlap where the data allows.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -186,33 +188,8 @@ struct Prof {
 // measurement kinds: the value load and the level kernels
 enum { kKindLoad = 0, kKindPotrf = 1, kKindUpdBig = 2, kKindUpd = 3, kKindTrsm = 4, kKinds = 5 };
 
-// side streams and events for forking the kernels of a level onto concurrent
-// graph branches during capture (default priority, non-blocking)
-struct Fork {
-  hipStream_t side[2] = {nullptr, nullptr};
-  hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
-  int make() {
-    for (int i = 0; i < 2; ++i) HIPCHK(hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-    for (int i = 0; i < 2; ++i) HIPCHK(hipEventCreateWithFlags(&join[i], hipEventDisableTiming));
-    return 0;
-  }
-  ~Fork() {
-    for (int i = 0; i < 2; ++i) {
-      if (side[i]) (void)hipStreamDestroy(side[i]);
-      if (join[i]) (void)hipEventDestroy(join[i]);
-    }
-    if (fork) (void)hipEventDestroy(fork);
-  }
-};
-
-// launch every level of the schedule for `members` value sets.  A level runs
-// up to three kernels (POTRF, updates, TRSM), which touch disjoint tiles:
-// with `fork` they go on concurrent branches joined before the next level,
-// otherwise one after the other on `st`; with prof, each launch is timed and
-// charged to its kernel with the tile-algorithmic flops of its tasks
-template <int NB>
-int launch_levels_nb(stc_handle* h, int32_t members, hipStream_t st, Prof* prof, Fork* fork) {
+// arguments of the kernels of level li
+LevelArgs level_args(const stc_handle* h, size_t li) {
   LevelArgs a;
   a.utasks = h->d_upd;
   a.contribs = h->d_contrib;
@@ -226,73 +203,128 @@ int launch_levels_nb(stc_handle* h, int32_t members, hipStream_t st, Prof* prof,
   a.nreal = (int32_t)h->sym.n;
   a.parts = h->d_parts;
   a.pstride = h->plan.parts;
-  hipEvent_t ev = nullptr;
+  const LevelOffsets& L = h->lv[li];
+  a.potrf = h->d_potrf + L.p_off;
+  a.big = h->d_big_items + 4 * (int64_t)L.g_off;
+  a.upd = h->d_upd_items + 4 * (int64_t)L.u_off;
+  a.trsm = h->d_trsm_items + 2 * (int64_t)L.t_off;
+  a.np = L.p_cnt;
+  a.nbig = L.g_cnt;
+  a.nu = L.u_cnt;
+  a.nt = L.t_cnt;
+  return a;
+}
+
+// kernel, grid and dynamic LDS of kind (0 POTRF, 1 updates, 2 TRSM) of a level
+template <int NB>
+void level_kernel(const LevelOffsets& L, int kind, int32_t members, const void** fn, dim3* grid,
+                  size_t* lds) {
+  if (kind == 0) {
+    *fn = reinterpret_cast<const void*>(&k_potrf<NB>);
+    *grid = dim3(L.p_cnt, members);
+    *lds = sizeof(double) * k_potrf_lds<NB>();
+  } else if (kind == 1) {
+    *fn = L.g_cnt ? reinterpret_cast<const void*>(&k_upd<NB, true>) : reinterpret_cast<const void*>(&k_upd<NB, false>);
+    *grid = dim3(L.g_cnt + L.u_cnt, members);
+    *lds = sizeof(double) * std::max(L.g_cnt ? UPD2_LDS : 0, L.u_cnt ? UPD_LDS : 0);
+  } else {
+    *fn = reinterpret_cast<const void*>(&k_trsm<NB>);
+    *grid = dim3(L.t_cnt, members);
+    *lds = sizeof(double) * trsm_lds<NB>();
+  }
+}
+
+// launch every level of the schedule for `members` value sets one kernel
+// after another on `st`, each timed and charged to its kernel with the
+// tile-algorithmic flops of its tasks (measurement path; the factorization
+// itself replays the dependency graph built by get_graph)
+template <int NB>
+int launch_levels_nb(stc_handle* h, int32_t members, hipStream_t st, Prof* prof) {
+  static const int kind_of[3] = {kKindPotrf, -1, kKindTrsm};
   for (size_t li = 0; li < h->lv.size(); ++li) {
     const LevelOffsets& L = h->lv[li];
     const Level& PL = h->plan.levels[li];
-    a.potrf = h->d_potrf + L.p_off;
-    a.big = h->d_big_items + 4 * (int64_t)L.g_off;
-    a.upd = h->d_upd_items + 4 * (int64_t)L.u_off;
-    a.trsm = h->d_trsm_items + 2 * (int64_t)L.t_off;
-    a.np = L.p_cnt;
-    a.nbig = L.g_cnt;
-    a.nu = L.u_cnt;
-    a.nt = L.t_cnt;
-    const bool has_u = L.u_cnt + L.g_cnt > 0;
-    const int nk = (L.p_cnt > 0) + has_u + (L.t_cnt > 0);
-    if (nk == 0) continue;
-    // the update kernel (the largest) stays on st; the others may fork
-    const bool forking = fork && !prof && nk > 1;
-    int nside = 0;
-    if (forking) HIPCHK(hipEventRecord(fork->fork, st));
-    if (L.p_cnt) {
-      hipStream_t s = st;
-      if (forking && (has_u || L.t_cnt)) {
-        s = fork->side[nside];
-        HIPCHK(hipStreamWaitEvent(s, fork->fork, 0));
-      }
-      if (prof && prof->begin(s, &ev)) return STC_ERR_HIP;
-      hipLaunchKernelGGL((k_potrf<NB>), dim3(L.p_cnt, members), dim3(256), sizeof(double) * k_potrf_lds<NB>(),
-                         s, a);
-      if (prof && prof->end(kKindPotrf, PL.flops_potrf * members, s, ev)) return STC_ERR_HIP;
-      if (s != st) HIPCHK(hipEventRecord(fork->join[nside++], s));
-    }
-    if (L.t_cnt) {
-      hipStream_t s = st;
-      if (forking && has_u) {
-        s = fork->side[nside];
-        HIPCHK(hipStreamWaitEvent(s, fork->fork, 0));
-      }
-      if (prof && prof->begin(s, &ev)) return STC_ERR_HIP;
-      hipLaunchKernelGGL((k_trsm<NB>), dim3(L.t_cnt, members), dim3(256), sizeof(double) * trsm_lds<NB>(), s,
-                         a);
-      if (prof && prof->end(kKindTrsm, PL.flops_trsm * members, s, ev)) return STC_ERR_HIP;
-      if (s != st) HIPCHK(hipEventRecord(fork->join[nside++], s));
-    }
-    if (has_u) {
-      const int lds = std::max(L.g_cnt ? UPD2_LDS : 0, L.u_cnt ? UPD_LDS : 0);
-      const dim3 grid(L.g_cnt + L.u_cnt, members);
+    LevelArgs a = level_args(h, li);
+    for (int kind = 0; kind < 3; ++kind) {
+      const int cnt = kind == 0 ? L.p_cnt : kind == 1 ? L.g_cnt + L.u_cnt : L.t_cnt;
+      if (cnt == 0) continue;
+      const void* fn;
+      dim3 grid;
+      size_t lds;
+      level_kernel<NB>(L, kind, members, &fn, &grid, &lds);
+      hipEvent_t ev = nullptr;
       if (prof && prof->begin(st, &ev)) return STC_ERR_HIP;
-      if (L.g_cnt)
-        hipLaunchKernelGGL((k_upd<NB, true>), grid, dim3(256), sizeof(double) * lds, st, a);
-      else
-        hipLaunchKernelGGL((k_upd<NB, false>), grid, dim3(256), sizeof(double) * lds, st, a);
-      if (prof && prof->end(L.g_cnt ? kKindUpdBig : kKindUpd, PL.flops_upd * members, st, ev))
-        return STC_ERR_HIP;
+      void* args[] = {&a};
+      HIPCHK(hipLaunchKernel(fn, grid, dim3(256), args, lds, st));
+      const int pk = kind == 1 ? (L.g_cnt ? kKindUpdBig : kKindUpd) : kind_of[kind];
+      const double fl = kind == 0 ? PL.flops_potrf : kind == 1 ? PL.flops_upd : PL.flops_trsm;
+      if (prof && prof->end(pk, fl * members, st, ev)) return STC_ERR_HIP;
     }
-    for (int i = 0; i < nside; ++i) HIPCHK(hipStreamWaitEvent(st, fork->join[i], 0));
   }
   HIPCHK(hipGetLastError());
   return 0;
 }
 
-int launch_levels(stc_handle* h, int32_t members, hipStream_t st, Prof* prof = nullptr,
-                  Fork* fork = nullptr) {
+// the schedule as a HIP graph of its kernel dependency graph: every
+// non-empty kernel of a level is a node that waits only for the kernels whose
+// data it uses (kernel_dag), so the kernels of consecutive levels overlap
+// wherever the data allows
+template <int NB>
+int build_graph_nb(stc_handle* h, int32_t members, hipGraphExec_t* ex) {
+  std::vector<KernelNode> dag;
+  kernel_dag(h->plan, &dag);
+  // the argument blocks stay alive until the graph is instantiated
+  std::vector<LevelArgs> args(dag.size());
+  std::vector<void*> kargs(dag.size());
+  std::vector<hipGraphNode_t> nodes(dag.size());
+  std::vector<hipGraphNode_t> deps;
+  hipGraph_t g;
+  HIPCHK(hipGraphCreate(&g, 0));
+  for (size_t x = 0; x < dag.size(); ++x) {
+    const LevelOffsets& L = h->lv[(size_t)dag[x].level];
+    args[x] = level_args(h, (size_t)dag[x].level);
+    const void* fn;
+    dim3 grid;
+    size_t lds;
+    level_kernel<NB>(L, dag[x].kind, members, &fn, &grid, &lds);
+    kargs[x] = &args[x];
+    hipKernelNodeParams kp{};
+    kp.blockDim = dim3(256);
+    kp.gridDim = grid;
+    kp.func = const_cast<void*>(fn);
+    kp.kernelParams = &kargs[x];
+    kp.extra = nullptr;
+    kp.sharedMemBytes = (unsigned)lds;
+    deps.clear();
+    for (int32_t d : dag[x].deps) deps.push_back(nodes[(size_t)d]);
+    const hipError_t e = hipGraphAddKernelNode(&nodes[x], g, deps.data(), deps.size(), &kp);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return fail(STC_ERR_HIP, std::string("hipGraphAddKernelNode: ") + hipGetErrorString(e));
+    }
+  }
+  const hipError_t e = hipGraphInstantiate(ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(STC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  return 0;
+}
+
+int launch_levels(stc_handle* h, int32_t members, hipStream_t st, Prof* prof) {
   switch (h->plan.nb) {
-    case 32: return launch_levels_nb<32>(h, members, st, prof, fork);
-    case 64: return launch_levels_nb<64>(h, members, st, prof, fork);
-    case 128: return launch_levels_nb<128>(h, members, st, prof, fork);
-    case 256: return launch_levels_nb<256>(h, members, st, prof, fork);
+    case 32: return launch_levels_nb<32>(h, members, st, prof);
+    case 64: return launch_levels_nb<64>(h, members, st, prof);
+    case 128: return launch_levels_nb<128>(h, members, st, prof);
+    case 256: return launch_levels_nb<256>(h, members, st, prof);
+  }
+  return fail(STC_ERR_ARG, "unsupported tile size");
+}
+
+int build_graph(stc_handle* h, int32_t members, hipGraphExec_t* ex) {
+  switch (h->plan.nb) {
+    case 32: return build_graph_nb<32>(h, members, ex);
+    case 64: return build_graph_nb<64>(h, members, ex);
+    case 128: return build_graph_nb<128>(h, members, ex);
+    case 256: return build_graph_nb<256>(h, members, ex);
   }
   return fail(STC_ERR_ARG, "unsupported tile size");
 }
@@ -303,30 +335,9 @@ int get_graph(stc_handle* h, int32_t members, hipGraphExec_t* out) {
     *out = it->second;
     return 0;
   }
-  hipStream_t cs;
-  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-  Fork fork;
-  if (fork.make()) {
-    (void)hipStreamDestroy(cs);
-    return STC_ERR_HIP;
-  }
-  HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
-  int rc = launch_levels(h, members, cs, nullptr, &fork);
-  hipGraph_t g;
-  hipError_t e = hipStreamEndCapture(cs, &g);
-  if (rc) {
-    (void)hipStreamDestroy(cs);
-    return rc;
-  }
-  if (e != hipSuccess) {
-    (void)hipStreamDestroy(cs);
-    return fail(STC_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-  }
   hipGraphExec_t ex;
-  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  (void)hipStreamDestroy(cs);
-  if (e != hipSuccess) return fail(STC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  const int rc = build_graph(h, members, &ex);
+  if (rc) return rc;
   h->graphs[members] = ex;
   *out = ex;
   return 0;
