@@ -897,19 +897,37 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std
       const int64_t tot = steps_of(u);
       return dur(u, tot * (q[3] + 1) / u.nsplit - tot * q[3] / u.nsplit);
     };
-    for (Level& L : p->levels)
+    for (Level& L : p->levels) {
+      double w_big_early = 0, w_upd_early = 0;
       for (std::vector<int32_t>* v : {&L.big_items, &L.upd_items}) {
         const size_t cnt = v->size() / 4;
         std::vector<size_t> order(cnt);
         for (size_t x = 0; x < cnt; ++x) order[x] = x;
+        // last groups first (their consumers are in the next level), each
+        // part longest first
+        auto early = [&](size_t x) { return p->upd[(size_t)(*v)[4 * x]].partner >= 0; };
         std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+          if (early(a) != early(b)) return early(b);
           return item_dur(&(*v)[4 * a]) > item_dur(&(*v)[4 * b]);
         });
+        int32_t nlast = 0;
+        double w_early = 0;
+        for (size_t x = 0; x < cnt; ++x) {
+          nlast += early(x) ? 0 : 1;
+          if (early(x)) w_early += item_dur(&(*v)[4 * x]);
+        }
+        (v == &L.big_items ? L.big_last : L.upd_last) = nlast;
+        (v == &L.big_items ? w_big_early : w_upd_early) = w_early;
         std::vector<int32_t> out(v->size());
         for (size_t x = 0; x < cnt; ++x)
           std::copy(v->begin() + 4 * order[x], v->begin() + 4 * order[x] + 4, out.begin() + 4 * x);
         v->swap(out);
       }
+      // the last groups get a launch of their own (so that the next level's
+      // TRSM / POTRF need not wait for the early groups) only when the early
+      // groups fill at least one round of the device; otherwise one launch
+      if (w_big_early + w_upd_early < (double)p->wg_slots) L.big_last = L.upd_last = 0;
+    }
   }
   p->flops_tile = flops;
   for (int64_t j = 0; j < n; ++j) {
@@ -985,14 +1003,21 @@ void kernel_dag(const Plan& p, std::vector<KernelNode>* out) {
     const Level& lv = p.levels[(size_t)L];
     const int32_t first = (int32_t)out->size();
     acc.clear();
-    for (int32_t kind = 0; kind < 3; ++kind) {
+    for (int32_t kind = 0; kind < 4; ++kind) {
       rd.clear();
       wr.clear();
+      // item ranges of the update kinds: last groups lead each list
+      auto lo = [&](const std::vector<int32_t>* v) {
+        return kind == 3 ? (size_t)0 : 4 * (size_t)(v == &lv.big_items ? lv.big_last : lv.upd_last);
+      };
+      auto hi = [&](const std::vector<int32_t>* v) {
+        return kind == 1 ? v->size() : 4 * (size_t)(v == &lv.big_items ? lv.big_last : lv.upd_last);
+      };
       if (kind == 0) {
         for (int32_t k : lv.potrf) wr.push_back((int64_t)k * p.nb * p.nb);
-      } else if (kind == 1) {
+      } else if (kind == 1 || kind == 3) {
         for (const std::vector<int32_t>* v : {&lv.big_items, &lv.upd_items})
-          for (size_t x = 0; x < v->size(); x += 4) {
+          for (size_t x = lo(v); x < hi(v); x += 4) {
             const int32_t id = (*v)[x];
             const UpdTask& u = p.upd[(size_t)id];
             wr.push_back(u.c_off);
@@ -1004,7 +1029,7 @@ void kernel_dag(const Plan& p, std::vector<KernelNode>* out) {
           }
         // partial slots folded in by a partner: the split task that names it
         for (const std::vector<int32_t>* v : {&lv.big_items, &lv.upd_items})
-          for (size_t x = 0; x < v->size(); x += 4) {
+          for (size_t x = lo(v); x < hi(v); x += 4) {
             const int32_t e = split_src[(size_t)(*v)[x]];
             if (e >= 0) rd.push_back(-1 - (int64_t)e);
           }

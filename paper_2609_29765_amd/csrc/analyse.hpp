@@ -100,6 +100,7 @@ struct TrsmTask {
 struct Level {
   std::vector<int32_t> big_items;   // quads: task, block row, block col, part (128 blocks)
   std::vector<int32_t> upd_items;   // quads: task, block row, block col, part (64 blocks)
+  int32_t big_last = 0, upd_last = 0;  // leading items of each list that belong to last groups
   std::vector<int32_t> potrf;       // block columns
   std::vector<int32_t> trsm_items;  // pairs: trsm task, row block
   double flops = 0;                 // tile-algorithmic flops of the level's tasks
@@ -141,7 +142,8 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std
 
 // The kernels of the level schedule as a dependency graph, in place of a
 // barrier between consecutive levels: node (level, kind) with kind 0 POTRF,
-// 1 updates, 2 TRSM, for every non-empty kernel, in level order.  A node
+// 1 the early groups' updates, 2 TRSM, 3 the last groups' updates, for every
+// non-empty kernel, in level order.  A node
 // depends on the earlier nodes that last wrote what it reads (a tile, a
 // diagonal tile with its 32 x 32 inverses, a split task's partial slots) and
 // on those that last wrote or since read what it writes -- the edges

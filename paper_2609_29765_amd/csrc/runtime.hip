@@ -47,7 +47,7 @@ constexpr int32_t kMaxRhs = 64;
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct LevelOffsets {
-  int32_t u_off, u_cnt, g_off, g_cnt, p_off, p_cnt, t_off, t_cnt;
+  int32_t u_off, u_cnt, g_off, g_cnt, p_off, p_cnt, t_off, t_cnt, u_last, g_last;
 };
 
 }  // namespace
@@ -188,8 +188,10 @@ struct Prof {
 // measurement kinds: the value load and the level kernels
 enum { kKindLoad = 0, kKindPotrf = 1, kKindUpdBig = 2, kKindUpd = 3, kKindTrsm = 4, kKinds = 5 };
 
-// arguments of the kernels of level li
-LevelArgs level_args(const stc_handle* h, size_t li) {
+// arguments of kernel `kind` (0 POTRF, 1 early-group updates, 2 TRSM, 3
+// last-group updates) of level li; the last groups' items lead the level's
+// item lists
+LevelArgs level_args(const stc_handle* h, size_t li, int kind) {
   LevelArgs a;
   a.utasks = h->d_upd;
   a.contribs = h->d_contrib;
@@ -212,26 +214,39 @@ LevelArgs level_args(const stc_handle* h, size_t li) {
   a.nbig = L.g_cnt;
   a.nu = L.u_cnt;
   a.nt = L.t_cnt;
+  if (kind == 3) {
+    a.nbig = L.g_last;
+    a.nu = L.u_last;
+  } else if (kind == 1) {
+    a.big += 4 * (int64_t)L.g_last;
+    a.upd += 4 * (int64_t)L.u_last;
+    a.nbig = L.g_cnt - L.g_last;
+    a.nu = L.u_cnt - L.u_last;
+  }
   return a;
 }
 
-// kernel, grid and dynamic LDS of kind (0 POTRF, 1 updates, 2 TRSM) of a level
+// kernel, grid and dynamic LDS of a level's kernel with arguments a
 template <int NB>
-void level_kernel(const LevelOffsets& L, int kind, int32_t members, const void** fn, dim3* grid,
+void level_kernel(const LevelArgs& a, int kind, int32_t members, const void** fn, dim3* grid,
                   size_t* lds) {
   if (kind == 0) {
     *fn = reinterpret_cast<const void*>(&k_potrf<NB>);
-    *grid = dim3(L.p_cnt, members);
+    *grid = dim3(a.np, members);
     *lds = sizeof(double) * k_potrf_lds<NB>();
-  } else if (kind == 1) {
-    *fn = L.g_cnt ? reinterpret_cast<const void*>(&k_upd<NB, true>) : reinterpret_cast<const void*>(&k_upd<NB, false>);
-    *grid = dim3(L.g_cnt + L.u_cnt, members);
-    *lds = sizeof(double) * std::max(L.g_cnt ? UPD2_LDS : 0, L.u_cnt ? UPD_LDS : 0);
+  } else if (kind == 1 || kind == 3) {
+    *fn = a.nbig ? reinterpret_cast<const void*>(&k_upd<NB, true>) : reinterpret_cast<const void*>(&k_upd<NB, false>);
+    *grid = dim3(a.nbig + a.nu, members);
+    *lds = sizeof(double) * std::max(a.nbig ? UPD2_LDS : 0, a.nu ? UPD_LDS : 0);
   } else {
     *fn = reinterpret_cast<const void*>(&k_trsm<NB>);
-    *grid = dim3(L.t_cnt, members);
+    *grid = dim3(a.nt, members);
     *lds = sizeof(double) * trsm_lds<NB>();
   }
+}
+
+int kernel_count(const LevelArgs& a, int kind) {
+  return kind == 0 ? a.np : kind == 2 ? a.nt : a.nbig + a.nu;
 }
 
 // launch every level of the schedule for `members` value sets one kernel
@@ -240,23 +255,23 @@ void level_kernel(const LevelOffsets& L, int kind, int32_t members, const void**
 // itself replays the dependency graph built by get_graph)
 template <int NB>
 int launch_levels_nb(stc_handle* h, int32_t members, hipStream_t st, Prof* prof) {
-  static const int kind_of[3] = {kKindPotrf, -1, kKindTrsm};
   for (size_t li = 0; li < h->lv.size(); ++li) {
     const LevelOffsets& L = h->lv[li];
     const Level& PL = h->plan.levels[li];
-    LevelArgs a = level_args(h, li);
+    // the level's updates as one launch (kind 1 with every item), so each
+    // kernel is charged the level's flops of its kind
     for (int kind = 0; kind < 3; ++kind) {
-      const int cnt = kind == 0 ? L.p_cnt : kind == 1 ? L.g_cnt + L.u_cnt : L.t_cnt;
-      if (cnt == 0) continue;
+      LevelArgs a = level_args(h, li, 2);
+      if (kernel_count(a, kind) == 0) continue;
       const void* fn;
       dim3 grid;
       size_t lds;
-      level_kernel<NB>(L, kind, members, &fn, &grid, &lds);
+      level_kernel<NB>(a, kind, members, &fn, &grid, &lds);
       hipEvent_t ev = nullptr;
       if (prof && prof->begin(st, &ev)) return STC_ERR_HIP;
       void* args[] = {&a};
       HIPCHK(hipLaunchKernel(fn, grid, dim3(256), args, lds, st));
-      const int pk = kind == 1 ? (L.g_cnt ? kKindUpdBig : kKindUpd) : kind_of[kind];
+      const int pk = kind == 0 ? kKindPotrf : kind == 2 ? kKindTrsm : (L.g_cnt ? kKindUpdBig : kKindUpd);
       const double fl = kind == 0 ? PL.flops_potrf : kind == 1 ? PL.flops_upd : PL.flops_trsm;
       if (prof && prof->end(pk, fl * members, st, ev)) return STC_ERR_HIP;
     }
@@ -281,12 +296,11 @@ int build_graph_nb(stc_handle* h, int32_t members, hipGraphExec_t* ex) {
   hipGraph_t g;
   HIPCHK(hipGraphCreate(&g, 0));
   for (size_t x = 0; x < dag.size(); ++x) {
-    const LevelOffsets& L = h->lv[(size_t)dag[x].level];
-    args[x] = level_args(h, (size_t)dag[x].level);
+    args[x] = level_args(h, (size_t)dag[x].level, dag[x].kind);
     const void* fn;
     dim3 grid;
     size_t lds;
-    level_kernel<NB>(L, dag[x].kind, members, &fn, &grid, &lds);
+    level_kernel<NB>(args[x], dag[x].kind, members, &fn, &grid, &lds);
     kargs[x] = &args[x];
     hipKernelNodeParams kp{};
     kp.blockDim = dim3(256);
@@ -486,6 +500,8 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
       LevelOffsets x;
       x.u_off = (int32_t)(h->upd_items.size() / 4);
       x.u_cnt = (int32_t)(L.upd_items.size() / 4);
+      x.u_last = L.upd_last;
+      x.g_last = L.big_last;
       h->upd_items.insert(h->upd_items.end(), L.upd_items.begin(), L.upd_items.end());
       x.g_off = (int32_t)(h->big_items.size() / 4);
       x.g_cnt = (int32_t)(L.big_items.size() / 4);
