@@ -154,6 +154,10 @@ def headline(args):
         "avg_launch_ms": round(avg_ms, 5),
         "flops_per_launch": flops_per_launch,
     }
+    if dom in ("k_upd<G>", "k_upd") and work["flops_update"] > 0:
+        # operand rows read + output tiles read and written, the plan's
+        # update bytes shared out in proportion to the launch's flops
+        roofline["algorithmic_bytes_per_launch"] = work["bytes_update"] * flops_per_launch / work["flops_update"]
     fam_ms = sum(agg[k][0] for k in level_kinds)
     fam_fl = sum(agg[k][2] for k in level_kinds)
     kinds = {k: {"ms_per_factorization": round(v[0] / args.prof_reps, 4), "launches": v[1] // args.prof_reps,
