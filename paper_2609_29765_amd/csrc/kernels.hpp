@@ -206,16 +206,26 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
 
 // ---------------------------------------------------------------------------
 // fused update on a 128 x 128 block (dense or nearly full tiles): four waves
-// of 64 x 64, K staged in LDS in chunks of 16 with two buffers and register
-// prefetch of the next chunk.  A task may split its contribution range over
-// nsplit work-groups: part 0 updates the tile, parts s > 0 write partial
-// sums that the tile's next update task folds in (in_part_off, in_npart).
+// of 64 x 64, K staged in LDS in chunks of 16 through two stages filled by
+// direct global-to-LDS loads.  A task may split its K stream over nsplit
+// work-groups: part 0 updates the tile, parts s > 0 write partial sums that
+// the tile's next update task folds in (in_part_off, in_npart).
 // ---------------------------------------------------------------------------
 
 constexpr int UB2 = 128;
 constexpr int UKT2 = 16;
-constexpr int ULD2 = UKT2 + 1;
-constexpr int UPD2_LDS = 4 * UB2 * ULD2;  // two buffers x {A, B}
+constexpr int DLD = UKT2;                  // doubles per staged row (no padding)
+constexpr int DSTAGE = 2 * UB2 * DLD;      // A and B rows of one K chunk
+constexpr int UPD2_LDS = 2 * DSTAGE;       // two stages
+
+typedef __attribute__((address_space(1))) void gvoid_t;
+typedef __attribute__((address_space(3))) void lvoid_t;
+
+// position of the 16-byte pair p of staged row r within the row: p ^ key(r).
+// Rows are 128 bytes, so without the swizzle every row would start on the
+// same LDS bank; with it, the 8 (or 16) rows one 128-bit fragment read
+// serves per cycle fall on distinct banks for 32 (or 64) banks of 4 bytes.
+__device__ __forceinline__ int dkey(int r) { return (r & 7) ^ ((r >> 3) & 1); }
 
 template <int NB>
 __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __restrict__ items,
@@ -223,7 +233,7 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
                                                const ContribD* __restrict__ contribs,
                                                const int32_t* __restrict__ maps,
                                                double* __restrict__ S, double* __restrict__ parts,
-                                               double* smem) {
+                                               const double* __restrict__ zrow, double* smem) {
   const int32_t task = items[4 * it], bx = items[4 * it + 1], by = items[4 * it + 2];
   const int32_t part = items[4 * it + 3];
   const UpdTaskD u = tasks[task];
@@ -231,7 +241,6 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
   const int32_t ncols = u.diag ? u.c_rows : NB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
-  const int lr = tid >> 1, lk = (tid & 1) * 8;  // row and k offset this thread stages
 
   d4 acc[4][4];
 #pragma unroll
@@ -239,70 +248,84 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-  // One stream of (contribution, 16-wide K chunk) steps: the next step's
-  // operand rows (and, at a contribution boundary, its row maps) are fetched
-  // into registers while the current step runs on MFMA, so contribution
-  // boundaries cost no extra latency.  Rows a map leaves out load as zeros.
-  // Part p of a task split nsplit ways runs steps [S p / nsplit,
-  // S (p+1) / nsplit) of the task's S steps.
+  // One stream of (contribution, 16-wide K chunk) steps.  The operand rows
+  // of a step go from global memory straight into one of two LDS stages,
+  // 16 bytes per lane: wave w fills rows 32 w + 8 j + lane / 8 (j = 0..3) of
+  // A and of B, lane l bringing the pair (l % 8) ^ key(row) of its row, so
+  // that the rows are stored swizzled.  A step's loads are issued right after
+  // the barrier that opens the previous step (every wave has then finished
+  // reading that stage) and waited for before the next barrier.  Rows a map
+  // leaves out load from zrow (zeros).  Part p of a task split nsplit ways
+  // runs steps [S p / nsplit, S (p+1) / nsplit) of the task's S steps.
   constexpr int KSTEPS = NB / UKT2;
   const int32_t tot = (u.c_end - u.c_begin) * KSTEPS;
   const int32_t g0 = (int32_t)((int64_t)tot * part / u.nsplit);
   const int32_t nsteps = (int32_t)((int64_t)tot * (part + 1) / u.nsplit) - g0;
-  int32_t sa = -1, sb = -1;
-  const double* pa = S;
-  const double* pb = S;
+  const int srow = 32 * wave + (lane >> 3);
+  const double* pa[4];
+  const double* pb[4];
   auto open_contrib = [&](int32_t ci) {
     const ContribD c = contribs[ci];
-    const int32_t r = r0 + lr;
-    sa = -1;
-    sb = -1;
-    if (r < u.c_rows) sa = c.rowmap < 0 ? (r < c.a_rows ? r : -1) : maps[c.rowmap + r];
-    const int32_t cc = c0 + lr;
-    if (cc < ncols) sb = c.colmap < 0 ? (cc < c.b_rows ? cc : -1) : maps[c.colmap + cc];
-    pa = S + c.a_off + (int64_t)max(sa, 0) * NB + lk;
-    pb = S + c.b_off + (int64_t)max(sb, 0) * NB + lk;
-  };
-  double2 ra[4], rb[4];
-  auto fetch = [&](int32_t k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      ra[q] = sa >= 0 ? reinterpret_cast<const double2*>(pa + k0)[q] : make_double2(0.0, 0.0);
-      rb[q] = sb >= 0 ? reinterpret_cast<const double2*>(pb + k0)[q] : make_double2(0.0, 0.0);
+    for (int j = 0; j < 4; ++j) {
+      const int lr = srow + 8 * j;
+      const int p2 = 2 * ((lane & 7) ^ dkey(lr));
+      const int32_t r = r0 + lr, cc = c0 + lr;
+      int32_t sa = -1, sb = -1;
+      if (r < u.c_rows) sa = c.rowmap < 0 ? (r < c.a_rows ? r : -1) : maps[c.rowmap + r];
+      if (cc < ncols) sb = c.colmap < 0 ? (cc < c.b_rows ? cc : -1) : maps[c.colmap + cc];
+      pa[j] = (sa >= 0 ? S + c.a_off + (int64_t)sa * NB : zrow) + p2;
+      pb[j] = (sb >= 0 ? S + c.b_off + (int64_t)sb * NB : zrow) + p2;
     }
   };
+  auto issue = [&](int32_t st, int32_t kn) {
+    double* As = smem + (st & 1) * DSTAGE;
+    double* Bs = As + UB2 * DLD;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      __builtin_amdgcn_global_load_lds((gvoid_t*)(pa[j] + kn * UKT2), (lvoid_t*)(As + (4 * wave + j) * 8 * DLD), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((gvoid_t*)(pb[j] + kn * UKT2), (lvoid_t*)(Bs + (4 * wave + j) * 8 * DLD), 16, 0, 0);
+    }
+  };
+  // A fragment: lane holds A[i = lane % 16][k] for the pair lane / 16 of a
+  // group of four pairs, both k of the pair in one 128-bit read (x feeds the
+  // first MFMA of the pair, y the second); B likewise -- the same order of
+  // the K sum for both operands
+  const int fkey = dkey(lane & 15);
   if (nsteps > 0) {
     open_contrib(u.c_begin + g0 / KSTEPS);
-    fetch((g0 % KSTEPS) * UKT2);
+    issue(0, g0 % KSTEPS);
   }
   for (int32_t st = 0; st < nsteps; ++st) {
-    double* As = smem + (st & 1) * 2 * UB2 * ULD2;
-    double* Bs = As + UB2 * ULD2;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      As[lr * ULD2 + lk + 2 * q] = ra[q].x;
-      As[lr * ULD2 + lk + 2 * q + 1] = ra[q].y;
-      Bs[lr * ULD2 + lk + 2 * q] = rb[q].x;
-      Bs[lr * ULD2 + lk + 2 * q + 1] = rb[q].y;
-    }
+    __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0): this wave's loads of step st are in LDS
     __syncthreads();
     if (st + 1 < nsteps) {
       const int32_t g = g0 + st + 1, kn = g % KSTEPS;
       if (kn == 0) open_contrib(u.c_begin + g / KSTEPS);
-      fetch(kn * UKT2);
+      issue(st + 1, kn);
     }
+    const double* As = smem + (st & 1) * DSTAGE;
+    const double* Bs = As + UB2 * DLD;
 #pragma unroll
-    for (int kk = 0; kk < UKT2; kk += 4) {
-      double af[4], bf[4];
+    for (int gq = 0; gq < 2; ++gq) {
+      const int slot = (4 * gq + (lane >> 4)) ^ fkey;
+      double2 af[4], bf[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) af[a] = As[(wr + a * 16 + (lane & 15)) * ULD2 + kk + (lane >> 4)];
+      for (int a = 0; a < 4; ++a)
+        af[a] = *reinterpret_cast<const double2*>(As + (wr + a * 16 + (lane & 15)) * DLD + 2 * slot);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) bf[b] = Bs[(wc + b * 16 + (lane & 15)) * ULD2 + kk + (lane >> 4)];
+      for (int b = 0; b < 4; ++b)
+        bf[b] = *reinterpret_cast<const double2*>(Bs + (wc + b * 16 + (lane & 15)) * DLD + 2 * slot);
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].x, bf[b].x, acc[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].y, bf[b].y, acc[a][b], 0, 0, 0);
     }
   }
   // epilogue: lane holds D[i][j] with j = lane % 16, i = lane / 16 + 4 e.
@@ -911,6 +934,7 @@ struct LevelArgs {
   const int32_t* trsm;    // pairs
   int32_t np, nbig, nu, nt;
   double* parts;          // partial-sum slots
+  const double* zrow;     // n_b zeros: the source of rows a gather map leaves out
   int64_t pstride;
   const UpdTaskD* utasks;
   const ContribD* contribs;
@@ -953,7 +977,7 @@ __global__ __launch_bounds__(256, 2) void k_upd(LevelArgs a) {
   double* parts = a.parts + (int64_t)member * a.pstride;
   int32_t b = blockIdx.x;
   if (HAS_G && b < a.nbig) {
-    if constexpr (NB >= UB2 && HAS_G) dev_update_big<NB>(b, a.big, a.utasks, a.contribs, a.maps, S, parts, smem);
+    if constexpr (NB >= UB2 && HAS_G) dev_update_big<NB>(b, a.big, a.utasks, a.contribs, a.maps, S, parts, a.zrow, smem);
     return;
   }
   b -= a.nbig;

@@ -74,6 +74,7 @@ struct stc_handle {
   int32_t* d_upd_items = nullptr;
   int32_t* d_big_items = nullptr;
   double* d_parts = nullptr;  // partial-sum slots, per member
+  double* d_zrow = nullptr;   // n_b zeros (rows a gather map leaves out)
   int32_t* d_potrf = nullptr;
   int32_t* d_trsm_items = nullptr;
   int32_t* d_perm = nullptr;
@@ -145,6 +146,7 @@ size_t layout(const stc_handle* hc, int32_t batch, char* base) {
   take(&h->d_y, sizeof(double) * (size_t)padded_n(h) * kMaxRhs);
   take(&h->d_dinv, sizeof(double) * (size_t)dinv_stride(h) * (size_t)batch);
   take(&h->d_parts, sizeof(double) * (size_t)p.parts * (size_t)batch);
+  take(&h->d_zrow, sizeof(double) * (size_t)p.nb);
   take(&h->d_bterms, sizeof(ConTermD) * h->back.terms.size());
   take(&h->d_btasks, sizeof(ConTaskD) * h->back.tasks.size());
   take(&h->d_bitems, sizeof(int32_t) * h->back_items.size());
@@ -204,6 +206,7 @@ LevelArgs level_args(const stc_handle* h, size_t li, int kind) {
   a.info = h->d_info;
   a.nreal = (int32_t)h->sym.n;
   a.parts = h->d_parts;
+  a.zrow = h->d_zrow;
   a.pstride = h->plan.parts;
   const LevelOffsets& L = h->lv[li];
   a.potrf = h->d_potrf + L.p_off;
@@ -578,6 +581,7 @@ int stc_bind(stc_handle* h, void* d_ws, size_t bytes, int32_t batch, void* strea
       (rc = upload(h->d_col_tiles, p.col_tiles)) || (rc = upload(h->d_fwd_blk, p.fwd_level_blk)) ||
       (rc = upload(h->d_bwd_blk, p.bwd_level_blk)))
     return rc;
+  HIPCHK(hipMemset(h->d_zrow, 0, sizeof(double) * (size_t)p.nb));
   const BackPlan& bp = h->back;
   std::vector<ConTermD> bt(bp.terms.size());
   for (size_t i = 0; i < bt.size(); ++i) {
