@@ -57,14 +57,30 @@ __global__ void k_value_load(const double* __restrict__ vals, const int64_t* __r
 }
 
 // ---------------------------------------------------------------------------
+// operand staging shared by the update kernels: K chunks of 16 doubles per
+// row go from global memory straight into LDS, 16 bytes per lane (the lane's
+// bytes land at the instruction's LDS base + 16 lane), rows unpadded
+// ---------------------------------------------------------------------------
+
+constexpr int DLD = 16;  // doubles per staged row
+
+typedef __attribute__((address_space(1))) void gvoid_t;
+typedef __attribute__((address_space(3))) void lvoid_t;
+
+// position of the 16-byte pair p of staged row r within the row: p ^ key(r).
+// Rows are 128 bytes, so without the swizzle every row would start on the
+// same LDS bank; with it, the 8 (or 16) rows one 128-bit fragment read
+// serves per cycle fall on distinct banks for 32 (or 64) banks of 4 bytes.
+__device__ __forceinline__ int dkey(int r) { return (r & 7) ^ ((r >> 3) & 1); }
+
+// ---------------------------------------------------------------------------
 // fused update: C -= sum_c A_c B_c^T on one 64 x 64 block of an output tile
 // ---------------------------------------------------------------------------
 
 constexpr int UB = 64;   // output block
 constexpr int UKT = 16;  // K chunk staged in LDS
-constexpr int ULD = UKT + 1;
-
-constexpr int UPD_LDS = 2 * UB * ULD;  // doubles: As, Bs
+constexpr int USTAGE = 2 * UB * DLD;  // A and B rows of one K chunk
+constexpr int UPD_LDS = 2 * USTAGE;   // two stages
 
 template <int NB>
 __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict__ items,
@@ -72,7 +88,7 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
                                            const ContribD* __restrict__ contribs,
                                            const int32_t* __restrict__ maps,
                                            double* __restrict__ S, double* __restrict__ parts,
-                                           double* smem) {
+                                           const double* __restrict__ zrow, double* smem) {
   const int32_t task = items[4 * it], bx = items[4 * it + 1], by = items[4 * it + 2];
   const int32_t part = items[4 * it + 3];
   const UpdTaskD u = tasks[task];
@@ -80,73 +96,86 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
   const int32_t ncols = u.diag ? u.c_rows : NB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  const int srow = tid >> 2, skq = (tid & 3) * 4;  // row and 4 columns this thread stages
 
   d4 acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-  // one stream of (contribution, 16-wide K chunk) steps, the next step's
-  // operand rows (and at a contribution boundary its row maps) fetched into
-  // registers while the current one runs; absent rows load as zeros.  Part
-  // p of a task split nsplit ways runs steps [S p / nsplit, S (p+1) / nsplit)
-  // of the task's S steps.
+  // one stream of (contribution, 16-wide K chunk) steps through two LDS
+  // stages: wave w fills rows 16 w + 8 j + lane / 8 (j = 0, 1) of A and of
+  // B, lane l bringing the pair (l % 8) ^ key(row); a step's loads are issued
+  // right after the barrier that opens the previous step and waited for
+  // before the next barrier; rows a map leaves out load from zrow (zeros).
+  // Part p of a task split nsplit ways runs steps [S p / nsplit,
+  // S (p+1) / nsplit) of the task's S steps.
   constexpr int KSTEPS = NB / UKT;
   const int32_t tot = (u.c_end - u.c_begin) * KSTEPS;
   const int32_t g0 = (int32_t)((int64_t)tot * part / u.nsplit);
   const int32_t nsteps = (int32_t)((int64_t)tot * (part + 1) / u.nsplit) - g0;
-  int32_t sa = -1, sb = -1;
-  const double* pa = S;
-  const double* pb = S;
+  const int srow = 16 * wave + (lane >> 3);
+  const double* pa[2];
+  const double* pb[2];
   auto open_contrib = [&](int32_t ci) {
     const ContribD c = contribs[ci];
-    const int32_t r = r0 + srow, cc = c0 + srow;
-    sa = -1;
-    sb = -1;
-    if (r < u.c_rows) sa = c.rowmap < 0 ? (r < c.a_rows ? r : -1) : maps[c.rowmap + r];
-    if (cc < ncols) sb = c.colmap < 0 ? (cc < c.b_rows ? cc : -1) : maps[c.colmap + cc];
-    pa = S + c.a_off + (int64_t)max(sa, 0) * NB + skq;
-    pb = S + c.b_off + (int64_t)max(sb, 0) * NB + skq;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int lr = srow + 8 * j;
+      const int p2 = 2 * ((lane & 7) ^ dkey(lr));
+      const int32_t r = r0 + lr, cc = c0 + lr;
+      int32_t sa = -1, sb = -1;
+      if (r < u.c_rows) sa = c.rowmap < 0 ? (r < c.a_rows ? r : -1) : maps[c.rowmap + r];
+      if (cc < ncols) sb = c.colmap < 0 ? (cc < c.b_rows ? cc : -1) : maps[c.colmap + cc];
+      pa[j] = (sa >= 0 ? S + c.a_off + (int64_t)sa * NB : zrow) + p2;
+      pb[j] = (sb >= 0 ? S + c.b_off + (int64_t)sb * NB : zrow) + p2;
+    }
   };
-  double2 a0, a1, b0, b1;
-  auto fetch = [&](int32_t k0) {
-    const double2 z = make_double2(0.0, 0.0);
-    a0 = sa >= 0 ? reinterpret_cast<const double2*>(pa + k0)[0] : z;
-    a1 = sa >= 0 ? reinterpret_cast<const double2*>(pa + k0)[1] : z;
-    b0 = sb >= 0 ? reinterpret_cast<const double2*>(pb + k0)[0] : z;
-    b1 = sb >= 0 ? reinterpret_cast<const double2*>(pb + k0)[1] : z;
+  auto issue = [&](int32_t st, int32_t kn) {
+    double* As = smem + (st & 1) * USTAGE;
+    double* Bs = As + UB * DLD;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      __builtin_amdgcn_global_load_lds((gvoid_t*)(pa[j] + kn * UKT), (lvoid_t*)(As + (2 * wave + j) * 8 * DLD), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((gvoid_t*)(pb[j] + kn * UKT), (lvoid_t*)(Bs + (2 * wave + j) * 8 * DLD), 16, 0, 0);
+    }
   };
+  // fragments: lane holds the pair lane / 16 of a group of four pairs of
+  // row lane % 16 (x feeds the first MFMA of the pair, y the second)
+  const int fkey = dkey(lane & 15);
   if (nsteps > 0) {
     open_contrib(u.c_begin + g0 / KSTEPS);
-    fetch((g0 % KSTEPS) * UKT);
+    issue(0, g0 % KSTEPS);
   }
-  double* As = smem;
-  double* Bs = smem + UB * ULD;
   for (int32_t st = 0; st < nsteps; ++st) {
-    {
-      double* da = As + srow * ULD + skq;
-      double* db = Bs + srow * ULD + skq;
-      da[0] = a0.x; da[1] = a0.y; da[2] = a1.x; da[3] = a1.y;
-      db[0] = b0.x; db[1] = b0.y; db[2] = b1.x; db[3] = b1.y;
-    }
+    __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0): this wave's loads of step st are in LDS
     __syncthreads();
     if (st + 1 < nsteps) {
       const int32_t g = g0 + st + 1, kn = g % KSTEPS;
       if (kn == 0) open_contrib(u.c_begin + g / KSTEPS);
-      fetch(kn * UKT);
+      issue(st + 1, kn);
     }
+    const double* As = smem + (st & 1) * USTAGE;
+    const double* Bs = As + UB * DLD;
 #pragma unroll
-    for (int kk = 0; kk < UKT; kk += 4) {
-      // A fragment: lane holds A[i = lane % 16][k = lane / 16]
-      // B fragment: lane holds B[k = lane / 16][j = lane % 16] = Bop[j][k]
-      double af[2], bf[2];
-      for (int a = 0; a < 2; ++a) af[a] = As[(wr + a * 16 + (lane & 15)) * ULD + kk + (lane >> 4)];
-      for (int b = 0; b < 2; ++b) bf[b] = Bs[(wc + b * 16 + (lane & 15)) * ULD + kk + (lane >> 4)];
+    for (int gq = 0; gq < 2; ++gq) {
+      const int slot = (4 * gq + (lane >> 4)) ^ fkey;
+      double2 af[2], bf[2];
+#pragma unroll
       for (int a = 0; a < 2; ++a)
+        af[a] = *reinterpret_cast<const double2*>(As + (wr + a * 16 + (lane & 15)) * DLD + 2 * slot);
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        bf[b] = *reinterpret_cast<const double2*>(Bs + (wc + b * 16 + (lane & 15)) * DLD + 2 * slot);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
         for (int b = 0; b < 2; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].x, bf[b].x, acc[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].y, bf[b].y, acc[a][b], 0, 0, 0);
     }
-    __syncthreads();
   }
   // epilogue: lane holds D[i][j] with j = lane % 16, i = lane / 16 + 4 e;
   // parts > 0 of a split range write their partial slot, which the tile's
@@ -214,18 +243,8 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
 
 constexpr int UB2 = 128;
 constexpr int UKT2 = 16;
-constexpr int DLD = UKT2;                  // doubles per staged row (no padding)
 constexpr int DSTAGE = 2 * UB2 * DLD;      // A and B rows of one K chunk
 constexpr int UPD2_LDS = 2 * DSTAGE;       // two stages
-
-typedef __attribute__((address_space(1))) void gvoid_t;
-typedef __attribute__((address_space(3))) void lvoid_t;
-
-// position of the 16-byte pair p of staged row r within the row: p ^ key(r).
-// Rows are 128 bytes, so without the swizzle every row would start on the
-// same LDS bank; with it, the 8 (or 16) rows one 128-bit fragment read
-// serves per cycle fall on distinct banks for 32 (or 64) banks of 4 bytes.
-__device__ __forceinline__ int dkey(int r) { return (r & 7) ^ ((r >> 3) & 1); }
 
 template <int NB>
 __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __restrict__ items,
@@ -970,7 +989,7 @@ __global__ __launch_bounds__(256) void k_potrf(LevelArgs a) {
 // HAS_G compiles the 128-block path in or out, so a level without it keeps
 // the smaller register footprint of the 64-block path
 template <int NB, bool HAS_G>
-__global__ __launch_bounds__(256, 2) void k_upd(LevelArgs a) {
+__global__ __launch_bounds__(256, HAS_G ? 2 : 3) void k_upd(LevelArgs a) {
   extern __shared__ double smem[];
   const int32_t member = blockIdx.y;
   double* S = a.store + (int64_t)member * a.mstride;
@@ -981,7 +1000,7 @@ __global__ __launch_bounds__(256, 2) void k_upd(LevelArgs a) {
     return;
   }
   b -= a.nbig;
-  dev_update<NB>(b, a.upd, a.utasks, a.contribs, a.maps, S, parts, smem);
+  dev_update<NB>(b, a.upd, a.utasks, a.contribs, a.maps, S, parts, a.zrow, smem);
 }
 
 template <int NB>
