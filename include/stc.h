@@ -43,6 +43,7 @@ extern "C" {
 #define STC_ERR_STATE (-3)   /* wrong call order (e.g. logdet before factorize)    */
 #define STC_ERR_ALLOC (-4)   /* host allocation failed or workspace too small      */
 #define STC_ERR_HIP (-5)     /* a HIP runtime call failed                          */
+#define STC_ERR_SCHEDULE (-6) /* stc_check_schedule found a conflicting pair of kernels */
 #define STC_NOT_SPD 1        /* numerical: a pivot was not positive and finite     */
 
 /* orderings (Sec. 3): the paper runs several fill-reducing heuristics and scores
@@ -183,6 +184,20 @@ int stc_get_factor(stc_handle* h, double* h_Lx, void* stream);
    recurrence, 2 per multiply-add); [9] its levels (kernel launches after the
    diagonal-tile inverses). */
 int stc_get_work(const stc_handle* h, double* work);
+
+/* Host check of the factorization schedule, no device work.  The
+   factorization replays a graph with one node per non-empty POTRF, update
+   and TRSM kernel of a level, whose edges stand for the waits Algorithm 2
+   performs on its progress matrix (Sec. 5.3).  This re-derives from the plan
+   the data each kernel reads and writes (tiles, diagonal tiles with their
+   32 x 32 inverses, split-K partial slots) and verifies that the kernels of
+   one level touch disjoint data, that every edge points to an earlier node,
+   and that every two kernels that both touch one object, at least one of
+   them writing it, are ordered by a path of edges.  stats (host) int64[4]
+   receives: nodes, edges, pairs of kernels the graph leaves unordered (and
+   that may therefore overlap), data objects.  Returns 0, STC_ERR_ARG for a
+   null argument, or STC_ERR_SCHEDULE with stc_last_error naming the pair. */
+int stc_check_schedule(const stc_handle* h, int64_t* stats);
 
 /* Measurement helper: one factorization of d_values (device) double[nnz]
    with the same kernels as stc_factorize, launched one by one instead of from

@@ -786,6 +786,94 @@ int stc_get_tasks(const stc_handle* h, int32_t* tasks) {
   return 0;
 }
 
+int stc_check_schedule(const stc_handle* h, int64_t* stats) {
+  if (!h || !stats) return fail(STC_ERR_ARG, "null argument");
+  const Plan& p = h->plan;
+  std::vector<KernelNode> dag;
+  kernel_dag(p, &dag);
+  const size_t N = dag.size();
+  // objects: tiles by store offset; partial slots by their offset, negated
+  // minus one; per object the nodes that read and that write it
+  std::map<int64_t, std::vector<std::pair<int32_t, bool>>> touch;
+  std::vector<std::vector<std::pair<int64_t, bool>>> acc(N);
+  for (size_t x = 0; x < N; ++x) {
+    const Level& lv = p.levels[(size_t)dag[x].level];
+    auto& a = acc[x];
+    if (dag[x].kind == 0) {
+      for (int32_t k : lv.potrf) a.emplace_back((int64_t)k * p.nb * p.nb, true);
+    } else if (dag[x].kind == 2) {
+      for (size_t q = 0; q < lv.trsm_items.size(); q += 2) {
+        const TrsmTask& t = p.trsm[(size_t)lv.trsm_items[q]];
+        a.emplace_back(t.l_off, false);
+        a.emplace_back(t.x_off, true);
+      }
+    } else {
+      for (const std::vector<int32_t>* v : {&lv.big_items, &lv.upd_items}) {
+        const size_t nl = 4 * (size_t)(v == &lv.big_items ? lv.big_last : lv.upd_last);
+        for (size_t q = 0; q < v->size(); q += 4) {
+          if ((q < nl) != (dag[x].kind == 3)) continue;
+          const UpdTask& u = p.upd[(size_t)(*v)[q]];
+          a.emplace_back(u.c_off, true);
+          for (int32_t c = u.c_begin; c < u.c_end; ++c) {
+            a.emplace_back(p.contribs[(size_t)c].a_off, false);
+            a.emplace_back(p.contribs[(size_t)c].b_off, false);
+          }
+          if (u.nsplit > 1) a.emplace_back(-1 - u.part_off, true);
+          if (u.in_npart > 0) a.emplace_back(-1 - u.in_part_off, false);
+        }
+      }
+    }
+    std::sort(a.begin(), a.end());
+    // an object both read and written by one node counts as written
+    std::vector<std::pair<int64_t, bool>> m;
+    for (const auto& e : a) {
+      if (!m.empty() && m.back().first == e.first) m.back().second = m.back().second || e.second;
+      else m.push_back(e);
+    }
+    a.swap(m);
+    for (const auto& e : a) touch[e.first].emplace_back((int32_t)x, e.second);
+  }
+  // ancestors of every node
+  const size_t W = N / 64 + 1;
+  std::vector<uint64_t> anc(N * W, 0);
+  int64_t edges = 0;
+  for (size_t x = 0; x < N; ++x)
+    for (int32_t d : dag[x].deps) {
+      if (d < 0 || (size_t)d >= x) return fail(STC_ERR_SCHEDULE, "kernel graph edge to a later node");
+      ++edges;
+      for (size_t w = 0; w < W; ++w) anc[x * W + w] |= anc[(size_t)d * W + w];
+      anc[x * W + (size_t)d / 64] |= uint64_t(1) << (d % 64);
+    }
+  auto ordered = [&](int32_t a, int32_t b) {  // a < b
+    return (anc[(size_t)b * W + (size_t)a / 64] >> (a % 64)) & 1;
+  };
+  for (const auto& kv : touch) {
+    const auto& v = kv.second;
+    for (size_t i = 0; i < v.size(); ++i)
+      for (size_t j = i + 1; j < v.size(); ++j) {
+        if (!v[i].second && !v[j].second) continue;
+        const int32_t a = std::min(v[i].first, v[j].first), b = std::max(v[i].first, v[j].first);
+        if (a == b) continue;
+        if (dag[(size_t)a].level == dag[(size_t)b].level)
+          return fail(STC_ERR_SCHEDULE, "kernels of level " + std::to_string(dag[(size_t)a].level) +
+                                            " touch one object, one of them writing it");
+        if (!ordered(a, b))
+          return fail(STC_ERR_SCHEDULE, "unordered kernels (level " + std::to_string(dag[(size_t)a].level) +
+                                            ", kind " + std::to_string(dag[(size_t)a].kind) + ") and (level " +
+                                            std::to_string(dag[(size_t)b].level) + ", kind " +
+                                            std::to_string(dag[(size_t)b].kind) + ") share an object");
+      }
+  }
+  int64_t unordered = 0;
+  for (size_t b = 0; b < N; ++b)
+    for (size_t a = 0; a < b; ++a) unordered += ordered((int32_t)a, (int32_t)b) ? 0 : 1;
+  stats[0] = (int64_t)N;
+  stats[1] = edges;
+  stats[2] = unordered;
+  stats[3] = (int64_t)touch.size();
+  return 0;
+}
+
 int stc_get_work(const stc_handle* h, double* w) {
   if (!h || !w) return fail(STC_ERR_ARG, "null argument");
   const Plan& p = h->plan;

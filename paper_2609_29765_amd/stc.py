@@ -31,7 +31,8 @@ EXPORTS = [
     "stc_analyse", "stc_workspace_bytes", "stc_bind", "stc_factorize", "stc_factorize_batched",
     "stc_logdet", "stc_solve", "stc_logdet_backward", "stc_info", "stc_get_sizes",
     "stc_get_features", "stc_get_perm", "stc_get_etree", "stc_get_L_pattern", "stc_get_tiles",
-    "stc_get_tasks", "stc_get_factor", "stc_get_work", "stc_profile_factorize", "stc_fp64_mfma_peak", "stc_destroy",
+    "stc_get_tasks", "stc_get_factor", "stc_get_work", "stc_check_schedule", "stc_profile_factorize",
+    "stc_fp64_mfma_peak", "stc_destroy",
     "stc_last_error",
 ]
 
@@ -76,6 +77,7 @@ def lib():
     L.stc_get_tasks.argtypes = [vp, _i32p]
     L.stc_get_factor.argtypes = [vp, _f64p, vp]
     L.stc_get_work.argtypes = [vp, _f64p]
+    L.stc_check_schedule.argtypes = [vp, _i64p]
     L.stc_profile_factorize.argtypes = [vp, vp, vp, _f64p, _i64p, _f64p]
     L.stc_fp64_mfma_peak.argtypes = [vp, _f64p]
     L.stc_destroy.argtypes = [vp]
@@ -272,6 +274,14 @@ class Analysis:
         keys = ["flops_update", "flops_potrf", "flops_trsm", "flops_tile", "flops_exact",
                 "bytes_update", "bytes_load", "levels", "flops_backward", "levels_backward"]
         return dict(zip(keys, (float(x) for x in w)))
+
+    def check_schedule(self):
+        """Host check of the kernel dependency graph the factorization replays
+        (see stc_check_schedule); raises on a conflicting pair of kernels.
+        Returns {nodes, edges, unordered_pairs, objects}."""
+        st = np.zeros(4, dtype=np.int64)
+        _check(lib().stc_check_schedule(self._h, st))
+        return dict(zip(["nodes", "edges", "unordered_pairs", "objects"], (int(x) for x in st)))
 
     KERNEL_KINDS = ["load", "k_potrf", "k_upd<G>", "k_upd", "k_trsm"]
 

@@ -1,0 +1,55 @@
+"""Host checks of the factorization schedule (no device work).
+
+The factorization replays a graph with one node per POTRF, update and TRSM
+kernel of a level, whose edges stand for the waits Algorithm 2 performs on
+its progress matrix (Sec. 5.3).  stc_check_schedule re-derives from the plan
+what every kernel reads and writes and verifies that each two kernels that
+touch one object, one of them writing it, are ordered by the graph.  Small
+work-group slot counts force split K streams (partial slots folded by a later
+task) and separate last-group update nodes, so every kind of edge occurs.
+"""
+import numpy as np
+import pytest
+
+from tests._build_once import ensure_built
+
+ensure_built()
+
+from paper_2609_29765_amd import stc as S  # noqa: E402
+from paper_2609_29765_amd import workloads as W  # noqa: E402
+
+
+def _check(w, nb, ordering, mode="auto", wg_slots=0):
+    a = S.Analysis(w.n, w.colptr, w.rowind, nb=nb, mode=mode, ordering=ordering, wg_slots=wg_slots)
+    st = a.check_schedule()
+    assert st["nodes"] >= 1 and st["objects"] >= 1
+    assert st["edges"] >= st["nodes"] - 1 - st["unordered_pairs"] or st["nodes"] == 1
+    return st
+
+
+@pytest.mark.parametrize("nb", [32, 64, 128, 256])
+@pytest.mark.parametrize("slots", [0, 4, 32])
+def test_dense(nb, slots):
+    _check(W.dense_spd(3 * nb + 37, 0.3, 1), nb, "natural", mode="dense", wg_slots=slots)
+
+
+@pytest.mark.parametrize("nb", [32, 64, 128])
+@pytest.mark.parametrize("slots", [0, 8])
+def test_gmrf_nd(nb, slots):
+    _check(W.gmrf_grid2d(40, 40), nb, "nd", wg_slots=slots)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random(seed):
+    rng = np.random.default_rng(77 + seed)
+    n = int(rng.integers(100, 700))
+    w = W.random_spd(n, float(rng.choice([0.005, 0.02, 0.1])), seed, dense_rows=int(rng.integers(0, 3)))
+    nb = int(rng.choice([32, 64, 128]))
+    ordering = ["natural", "rcm", "nd", "auto"][seed % 4]
+    _check(w, nb, ordering, wg_slots=int(rng.choice([0, 2, 16])))
+
+
+def test_bordered_and_batched_patterns():
+    _check(W.spatiotemporal_arrowhead(T=10, m=20, nborder=8), 64, "nd", wg_slots=8)
+    _check(W.differentiable_arrowhead(6, 10, 8, 0), 32, "nd")
+    _check(W.batched_laplacian3d(m=10, B=2), 64, "nd", wg_slots=4)
