@@ -82,8 +82,10 @@ typedef struct {
   const int32_t* perm;   /* (host) perm[new] = old, read when ordering == GIVEN  */
   int32_t wg_slots;      /* schedule: concurrent update work-groups the per-
                             level split of long update chains (deterministic
-                            split-K) is balanced for; 0 = 384 (the best of a
-                            sweep on MI355X).  Changes timing only.            */
+                            split-K) is balanced for, and the early-group
+                            work above which a level's last groups get a
+                            launch of their own; 0 = 448 (the best of a sweep
+                            on MI355X).  Changes timing only.                  */
 } stc_opts;
 
 /* Analyse a sparsity pattern once (Sec. 3, Sec. 5.1-5.2).

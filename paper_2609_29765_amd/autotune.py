@@ -13,14 +13,15 @@ from . import stc
 
 
 def autotune(n, colptr, rowind, values, nbs=(64, 128, 256), modes=("auto",), ordering="auto",
-             batched=False, trials=3, warmup=1, objective="factorize"):
+             batched=False, trials=3, warmup=1, objective="factorize", slots=(0,)):
     """Return (best Analysis, bound; table of every candidate).
 
     values: device float64 [nnz] (batched=False) or [B, nnz] (batched=True).
     objective: "factorize" times one factorization call; "logdet_grad" times
     a factorization followed by the logdet reverse mode (the unit of work of
     a gradient-based fit).
-    Each table row: nb, mode, ms per call, levels, tile flops.
+    slots: candidate wg_slots of the schedule (0 = the library default).
+    Each table row: nb, mode, wg_slots, ms per call, levels, tile flops.
     Candidates that lose release their workspace.
     """
     import torch
@@ -28,42 +29,41 @@ def autotune(n, colptr, rowind, values, nbs=(64, 128, 256), modes=("auto",), ord
     perm = None
     best = None
     table = []
-    for nb in nbs:
-        for mode in modes:
-            if perm is None:
-                a = stc.Analysis(n, colptr, rowind, nb=nb, mode=mode, ordering=ordering)
-                perm = a.perm()
+    for nb, mode, ws in ((nb, mode, ws) for nb in nbs for mode in modes for ws in slots):
+        if perm is None:
+            a = stc.Analysis(n, colptr, rowind, nb=nb, mode=mode, ordering=ordering, wg_slots=ws)
+            perm = a.perm()
+        else:
+            a = stc.Analysis(n, colptr, rowind, nb=nb, mode=mode, ordering="given", perm=perm, wg_slots=ws)
+        a.bind(batch=values.shape[0] if batched else 1)
+
+        one = torch.ones(1, dtype=torch.float64, device=values.device)
+
+        def run():
+            if batched:
+                a.factorize_batched(values)
             else:
-                a = stc.Analysis(n, colptr, rowind, nb=nb, mode=mode, ordering="given", perm=perm)
-            a.bind(batch=values.shape[0] if batched else 1)
+                a.factorize(values)
+                if objective == "logdet_grad":
+                    a.logdet_backward(one)
 
-            one = torch.ones(1, dtype=torch.float64, device=values.device)
-
-            def run():
-                if batched:
-                    a.factorize_batched(values)
-                else:
-                    a.factorize(values)
-                    if objective == "logdet_grad":
-                        a.logdet_backward(one)
-
-            for _ in range(warmup):
-                run()
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(trials):
-                run()
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / trials
-            table.append(dict(nb=a.nb, mode=a.mode, ms=round(ms, 4), levels=a.nlevels,
-                              tile_gflop=round(a.work()["flops_tile"] / 1e9, 3)))
-            if best is None or ms < best[0]:
-                if best is not None:
-                    best[1].release()
-                best = (ms, a)
-            else:
-                a.release()
+        for _ in range(warmup):
+            run()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(trials):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / trials
+        table.append(dict(nb=a.nb, mode=a.mode, wg_slots=ws, ms=round(ms, 4), levels=a.nlevels,
+                          tile_gflop=round(a.work()["flops_tile"] / 1e9, 3)))
+        if best is None or ms < best[0]:
+            if best is not None:
+                best[1].release()
+            best = (ms, a)
+        else:
+            a.release()
     return best[1], table

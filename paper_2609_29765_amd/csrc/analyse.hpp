@@ -109,7 +109,7 @@ struct Level {
 
 struct Plan {
   int32_t nb = 64, NT = 0;
-  int64_t wg_slots = 384;  // concurrent update work-groups the split balances for
+  int64_t wg_slots = 448;  // concurrent update work-groups the split balances for
   int32_t bm = 64;          // small update block (rows and columns)
   int64_t parts = 0;        // doubles of partial-sum slots per value set
   int32_t br = 32;          // rows per TRSM work item
@@ -137,7 +137,7 @@ struct Plan {
 };
 
 // wg_slots: concurrent update work-groups the per-level split of long
-// contribution ranges is balanced for (0 = 384, measured best on MI355X)
+// contribution ranges is balanced for (0 = 448, measured best on MI355X)
 int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std::string* why);
 
 // The kernels of the level schedule as a dependency graph, in place of a
