@@ -421,8 +421,11 @@ constexpr int PLD = PW + 1;
 // (rows c0..c0+3 of L read by LDS broadcast), the 4 x 4 pivot block (t of
 // lanes c0..c0+3, by readlane) is factored with uniform scalar arithmetic,
 // and each lane finishes its four entries by a 4-term forward substitution.
-// The reads of a step precede its writes in program order, and a wave's LDS
-// operations execute in that order.  Writes L (lower, diagonal included,
+// The part of the next block's sums over earlier columns is formed before
+// this block's pivots, the part over this block's columns after them.  The
+// reads of earlier columns never meet this block's writes, the reads of this
+// block's columns follow them in program order, and a wave's LDS operations
+// execute in that order.  Writes L (lower, diagonal included,
 // zeros above) to P, the inverse (row-major, stride PLD) to Z and 1 / L_cc to
 // rdiag.  Returns the first failing pivot (0-based) or -1; uniform across the
 // wave.
@@ -454,18 +457,25 @@ __device__ __forceinline__ int chol32_wave(double* P, double* Z, double* rdiag, 
     x[j] = lo ? a : (j == r ? 1.0 : 0.0);
   }
   double myd = 1.0, myrs = 1.0;  // lane r < 32 keeps pivot r and its 1 / L_rr
+  double t[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) t[q] = x[q];
 #pragma unroll
   for (int c0 = 0; c0 < PW; c0 += 4) {
-    double t[4];
+    // the next block's partial sums over the columns before this block do
+    // not wait for this block's pivots: they are formed first
+    double tn[4] = {0.0, 0.0, 0.0, 0.0};
+    if (c0 + 4 < PW) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      double s0 = 0.0, s1 = 0.0;
+      for (int q = 0; q < 4; ++q) {
+        double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-      for (int p = 0; p < c0; ++p) {
-        if (p & 1) s1 = fma(x[p], P[(c0 + q) * PLD + p], s1);
-        else s0 = fma(x[p], P[(c0 + q) * PLD + p], s0);
+        for (int p = 0; p < c0; ++p) {
+          if (p & 1) s1 = fma(x[p], P[(c0 + 4 + q) * PLD + p], s1);
+          else s0 = fma(x[p], P[(c0 + 4 + q) * PLD + p], s0);
+        }
+        tn[q] = x[c0 + 4 + q] - (s0 + s1);
       }
-      t[q] = x[c0 + q] - (s0 + s1);
     }
     // pivot block T_iq = t_q of lane c0 + i (i >= q), factored uniformly
     double T[4][4];
@@ -507,6 +517,16 @@ __device__ __forceinline__ int chol32_wave(double* P, double* Z, double* rdiag, 
       for (int q = 0; q < 4; ++q) P[r * PLD + c0 + q] = v[q];
     }
     __builtin_amdgcn_wave_barrier();
+    // the next block's partial sums over this block's columns
+    if (c0 + 4 < PW) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double u = tn[q];
+#pragma unroll
+        for (int p = c0; p < c0 + 4; ++p) u = fma(-x[p], P[(c0 + 4 + q) * PLD + p], u);
+        t[q] = u;
+      }
+    }
   }
   if (lo) rdiag[r] = myrs;
   if (!lo) {
