@@ -178,8 +178,19 @@ def headline(args):
     del xa, xb
     log(f"measured FP64 MFMA issue {mfma_peak:.1f} TFLOP/s, library DGEMM n={nd} {dgemm_tf:.1f} TFLOP/s")
 
+    # the consumers of the resident factor on the same workload (Sec. 6.7):
+    # logdet, and the solve for 1 and 8 right-hand sides
+    a.factorize(vals)
+    b1 = torch.randn(w.n, dtype=torch.float64, device="cuda")
+    b8 = torch.randn(w.n, 8, dtype=torch.float64, device="cuda")
+    a.logdet(), a.solve(b1.clone()), a.solve(b8.clone())  # graphs captured on first use
+    uses = {"logdet_ms": round(timed(lambda: a.logdet(), 10), 4),
+            "solve_1rhs_ms": round(timed(lambda: a.solve(b1), 5), 4),
+            "solve_8rhs_ms": round(timed(lambda: a.solve(b8), 5), 4)}
+    log(f"resident factor: {uses}")
+
     return dict(
-        ms_step=ms_step, logdet=ld, analyse_s=t_analyse, a=a, w=w, work=work, roofline=roofline,
+        ms_step=ms_step, logdet=ld, analyse_s=t_analyse, a=a, w=w, work=work, roofline=roofline, uses=uses,
         kinds=kinds, level_family_tflops=round(fam_fl / (fam_ms * 1e-3) / 1e12, 3),
         peaks={"mfma_issue": round(mfma_peak, 2), "dgemm_library_8192": round(dgemm_tf, 2)})
 
@@ -454,6 +465,7 @@ def main():
         "cpu_baseline": cpu,
         "extras": extras,
         "logdet": hl["logdet"],
+        "factor_uses": hl["uses"],
         "analyse_s": round(hl["analyse_s"], 3),
     }
     print(json.dumps(line), flush=True)

@@ -130,8 +130,15 @@ int stc_factorize_batched(stc_handle* h, const double* d_values, int32_t B, doub
    d_out (device) double[1]; NaN if that factorization failed. */
 int stc_logdet(stc_handle* h, double* d_out, void* stream);
 
-/* Solve A X = B in place with the last single factorization: d_b (device)
-   double[n * nrhs], column-major, original numbering, 1 <= nrhs <= 64. */
+/* Solve A X = B in place with the last single factorization (Sec. 6.7: the
+   factor stays on the device and is reused): d_b (device) double[n * nrhs],
+   column-major, original numbering, 1 <= nrhs <= 64.  Forward and backward
+   block sweeps over the factor's tiles, level by level, for up to 8 columns
+   at a time (the factor is read once per group): a level's diagonal blocks
+   are solved, then the products of the tiles they unlock are subtracted from
+   the blocks those tiles feed, each fed block by one work item in a fixed
+   tile order, so results are reproducible bit for bit.  The sweeps for each
+   group are captured in a graph on first use. */
 int stc_solve(stc_handle* h, double* d_b, int32_t nrhs, void* stream);
 
 /* Reverse mode of logdet through the last single factorization: given the

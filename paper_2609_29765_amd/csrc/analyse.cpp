@@ -597,6 +597,7 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std
     colmap_of[t] = (int32_t)p->maps.size();
     p->maps.insert(p->maps.end(), inv.begin() + t * nb, inv.begin() + (t + 1) * nb);
   }
+  p->tile_imap = colmap_of;
 
   // fused update tasks from Algorithm 1's list, and the level schedule
   std::vector<int32_t> lvT((size_t)ntiles, -1), lvP((size_t)NT, -1);

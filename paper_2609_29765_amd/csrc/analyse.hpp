@@ -119,6 +119,8 @@ struct Plan {
   std::vector<int64_t> lmap;        // L entry (CSC order) -> store offset
   std::vector<int32_t> maps;        // gather maps
   std::vector<int32_t> diag_h;      // real rows of each diagonal tile
+  std::vector<int32_t> tile_imap;   // per off-diagonal tile: offset in maps of its inverse row map
+                                    // (block row -> stored row, -1 if absent), or -1 when full
   std::vector<Contrib> contribs;
   std::vector<UpdTask> upd;
   std::vector<TrsmTask> trsm;

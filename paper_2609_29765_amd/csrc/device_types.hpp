@@ -50,7 +50,8 @@ struct ConTaskD {
 struct TileD {        // off-diagonal tile as the solve sees it
   int64_t off;        // store offset
   int64_t roff;       // offset of its active rows in the row pool
-  int32_t m, k, cnt, pad;
+  int32_t m, k, cnt;
+  int32_t imap;       // offset in the map pool of block row -> stored row (-1 absent), -1 if full
 };
 
 }  // namespace stc

@@ -1320,81 +1320,222 @@ __global__ void k_perm_out(const double* __restrict__ y, const int32_t* __restri
   b[r * n + perm[a]] = y[r * np + a];
 }
 
-// forward: block row m owns y_m: y_m -= sum_k L_mk y_k, then y_m <- L_mm^-1 y_m
+// Both sweeps run level by level over the blocks of the tile grid and read L
+// once per group of up to SR right-hand sides (rhs-major in y, stride np).
+// After a level's diagonal blocks are solved, a panel kernel subtracts the
+// products of the tiles they unlock straight from the right-hand sides of
+// the blocks those tiles feed (forward: b_m -= L_mk y_k; backward:
+// y_k -= L_mk^T x_m).  One work item owns one fed block (a 64-row chunk of it,
+// forward) and runs through its tiles of the level in a fixed order, so there
+// are no races and no atomics and results are reproducible bit for bit.  The
+// diagonal blocks are solved 32 rows at a time with the inverses of the
+// 32 x 32 diagonal blocks of L that the factorization keeps (dinv).
+constexpr int SR = 8;      // right-hand sides per sweep
+constexpr int SCH = 64;    // block rows of a forward panel work item
+
+// y_k <- L_kk^-1 y_k: per 32-row block J, the block row of L_kk left of the
+// diagonal block and the block's inverse staged in LDS,
+// s = r_J - L_(J,<J) y_(<J), y_J = D_J s
 template <int NB>
-__global__ __launch_bounds__(256) void k_fwd(const int32_t* __restrict__ blks,
-                                             const int32_t* __restrict__ row_ptr,
-                                             const int32_t* __restrict__ row_tiles,
-                                             const TileD* __restrict__ tiles,
-                                             const int32_t* __restrict__ rows,
-                                             const double* __restrict__ S, double* __restrict__ y,
-                                             int64_t np, int32_t nrhs) {
-  __shared__ double ys[NB];
-  const int32_t m = blks[blockIdx.x];
+__global__ __launch_bounds__(256) void k_sfwd_diag(const int32_t* __restrict__ blks,
+                                                   const double* __restrict__ S,
+                                                   const double* __restrict__ dinv,
+                                                   double* __restrict__ y, int64_t np, int32_t nrhs) {
+  constexpr int LW = NB - PW + 1;
+  __shared__ double r[NB * SR];   // r[i * SR + c]
+  __shared__ double s[PW * SR];
+  __shared__ double Ls[PW * LW];
+  __shared__ double Ds[PW * PLD];
+  const int32_t k = blks[blockIdx.x];
   const int tid = threadIdx.x;
-  const double* Lmm = S + (int64_t)m * NB * NB;
-  for (int32_t r = 0; r < nrhs; ++r) {
-    double* yr = y + (int64_t)r * np;
-    for (int i = tid; i < NB; i += 256) ys[i] = yr[(int64_t)m * NB + i];
+  for (int x = tid; x < NB * SR; x += 256) {
+    const int i = x / SR, c = x % SR;
+    r[x] = c < nrhs ? y[(int64_t)c * np + (int64_t)k * NB + i] : 0.0;
+  }
+  const double* L = S + (int64_t)k * NB * NB;
+  const double* D = dinv + (int64_t)k * NB * PW;
+  const int i = tid / SR, c = tid % SR;  // 32 rows x SR right-hand sides
+  for (int J = 0; J < NB / PW; ++J) {
+    const int w = J * PW;
+    for (int x = tid; x < PW * w; x += 256) Ls[(x / w) * LW + x % w] = L[(int64_t)(w + x / w) * NB + x % w];
+    for (int x = tid; x < PW * PW; x += 256) Ds[(x / PW) * PLD + x % PW] = D[J * PW * PW + x];
     __syncthreads();
-    for (int32_t x = row_ptr[m]; x < row_ptr[m + 1]; ++x) {
-      const TileD t = tiles[row_tiles[x]];
-      const double* yk = yr + (int64_t)t.k * NB;
-      for (int q = tid; q < t.cnt; q += 256) {
-        const double* pr = S + t.off + (int64_t)q * NB;
-        double v = 0.0;
-        for (int c = 0; c < NB; ++c) v += pr[c] * yk[c];
-        ys[rows[t.roff + q]] -= v;
-      }
-      __syncthreads();
+    double v0 = r[(w + i) * SR + c], v1 = 0.0;
+    for (int p = 0; p < w; p += 2) {
+      v0 = fma(-Ls[i * LW + p], r[p * SR + c], v0);
+      v1 = fma(-Ls[i * LW + p + 1], r[(p + 1) * SR + c], v1);
     }
-    for (int c = 0; c < NB; ++c) {
-      if (tid == 0) ys[c] /= Lmm[(int64_t)c * NB + c];
-      __syncthreads();
-      for (int i = c + 1 + tid; i < NB; i += 256) ys[i] -= Lmm[(int64_t)i * NB + c] * ys[c];
-      __syncthreads();
-    }
-    for (int i = tid; i < NB; i += 256) yr[(int64_t)m * NB + i] = ys[i];
+    s[i * SR + c] = v0 + v1;
     __syncthreads();
+    double u = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < PW; ++q) u = fma(Ds[i * PLD + q], s[q * SR + c], u);
+    r[(w + i) * SR + c] = u;
+    __syncthreads();
+  }
+  for (int x = tid; x < NB * SR; x += 256) {
+    const int ii = x / SR, cc = x % SR;
+    if (cc < nrhs) y[(int64_t)cc * np + (int64_t)k * NB + ii] = r[x];
   }
 }
 
-// backward: block column k owns x_k: x_k -= sum_m L_mk^T x_m, then x_k <- L_kk^-T x_k
+// forward panel item (m, i0, tiles [t0, t1)): for block rows i0 .. i0 + 63 of
+// block m, b_m(i) -= sum over the tiles (m, k) of L_mk(q(i)) y_k, q(i) the
+// tile's stored row of block row i (its inverse row map; identity when the
+// tile is full).  8 lanes per row over interleaved column pairs, reduced by
+// shuffles.
 template <int NB>
-__global__ __launch_bounds__(256) void k_bwd(const int32_t* __restrict__ blks,
-                                             const int32_t* __restrict__ col_ptr,
-                                             const int32_t* __restrict__ col_tiles,
-                                             const TileD* __restrict__ tiles,
-                                             const int32_t* __restrict__ rows,
-                                             const double* __restrict__ S, double* __restrict__ y,
-                                             int64_t np, int32_t nrhs) {
-  __shared__ double ys[NB];
+__global__ __launch_bounds__(256) void k_sfwd_panel(const int32_t* __restrict__ items,
+                                                    const int32_t* __restrict__ tlist,
+                                                    const TileD* __restrict__ tiles,
+                                                    const int32_t* __restrict__ maps,
+                                                    const double* __restrict__ S,
+                                                    double* __restrict__ y, int64_t np, int32_t nrhs) {
+  __shared__ double ys[NB * SR];  // ys[col * SR + c]
+  const int32_t m = items[4 * blockIdx.x], i0 = items[4 * blockIdx.x + 1];
+  const int32_t t0 = items[4 * blockIdx.x + 2], t1 = items[4 * blockIdx.x + 3];
+  const int tid = threadIdx.x;
+  const int j = tid & 7, rl = tid >> 3;  // lane of the row group, row of the pass
+  double acc[2][SR];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int c = 0; c < SR; ++c) acc[h][c] = 0.0;
+  for (int32_t z = t0; z < t1; ++z) {
+    const TileD tl = tiles[tlist[z]];
+    __syncthreads();  // ys is free
+    for (int x = tid; x < NB * SR; x += 256) {
+      const int col = x / SR, c = x % SR;
+      ys[x] = c < nrhs ? y[(int64_t)c * np + (int64_t)tl.k * NB + col] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = i0 + rl + 32 * h;
+      const int32_t q = i >= NB ? -1 : (tl.imap < 0 ? i : maps[tl.imap + i]);
+      if (q >= 0) {
+        const double* Lr = S + tl.off + (int64_t)q * NB;
+#pragma unroll 4
+        for (int col = 2 * j; col < NB; col += 16) {
+          const double2 l = *reinterpret_cast<const double2*>(Lr + col);
+#pragma unroll
+          for (int c = 0; c < SR; ++c)
+            acc[h][c] = fma(l.x, ys[col * SR + c], fma(l.y, ys[(col + 1) * SR + c], acc[h][c]));
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int c = 0; c < SR; ++c) {
+      acc[h][c] += __shfl_xor(acc[h][c], 1);
+      acc[h][c] += __shfl_xor(acc[h][c], 2);
+      acc[h][c] += __shfl_xor(acc[h][c], 4);
+    }
+    double mine = acc[h][0];  // lane j of the row group keeps right-hand side j
+#pragma unroll
+    for (int c = 1; c < SR; ++c) mine = j == c ? acc[h][c] : mine;
+    const int i = i0 + rl + 32 * h;
+    if (i < NB && j < nrhs) y[(int64_t)j * np + (int64_t)m * NB + i] -= mine;
+  }
+}
+
+// x_k <- L_kk^-T y_k: per 32-row block J from the last, the block column of
+// L_kk below the diagonal block and the block's inverse staged in LDS,
+// s = r_J - L_(>J,J)^T x_(>J), x_J = D_J^T s
+template <int NB>
+__global__ __launch_bounds__(256) void k_sbwd_diag(const int32_t* __restrict__ blks,
+                                                   const double* __restrict__ S,
+                                                   const double* __restrict__ dinv,
+                                                   double* __restrict__ y, int64_t np, int32_t nrhs) {
+  __shared__ double r[NB * SR];
+  __shared__ double s[PW * SR];
+  __shared__ double Lc[(NB - PW) * PLD + 1];
+  __shared__ double Ds[PW * PLD];
   const int32_t k = blks[blockIdx.x];
   const int tid = threadIdx.x;
-  const double* Lkk = S + (int64_t)k * NB * NB;
-  for (int32_t r = 0; r < nrhs; ++r) {
-    double* yr = y + (int64_t)r * np;
-    for (int i = tid; i < NB; i += 256) ys[i] = yr[(int64_t)k * NB + i];
+  for (int x = tid; x < NB * SR; x += 256) {
+    const int i = x / SR, c = x % SR;
+    r[x] = c < nrhs ? y[(int64_t)c * np + (int64_t)k * NB + i] : 0.0;
+  }
+  const double* L = S + (int64_t)k * NB * NB;
+  const double* D = dinv + (int64_t)k * NB * PW;
+  const int i = tid / SR, c = tid % SR;
+  for (int J = NB / PW - 1; J >= 0; --J) {
+    const int p0 = (J + 1) * PW, h = NB - p0;  // rows below the diagonal block
+    for (int x = tid; x < h * PW; x += 256) Lc[(x / PW) * PLD + x % PW] = L[(int64_t)(p0 + x / PW) * NB + J * PW + x % PW];
+    for (int x = tid; x < PW * PW; x += 256) Ds[(x / PW) * PLD + x % PW] = D[J * PW * PW + x];
     __syncthreads();
-    for (int32_t x = col_ptr[k]; x < col_ptr[k + 1]; ++x) {
-      const TileD t = tiles[col_tiles[x]];
-      const double* ym = yr + (int64_t)t.m * NB;
-      const double* P = S + t.off;
-      for (int c = tid; c < NB; c += 256) {
-        double v = 0.0;
-        for (int q = 0; q < t.cnt; ++q) v += P[(int64_t)q * NB + c] * ym[rows[t.roff + q]];
-        ys[c] -= v;
-      }
-      __syncthreads();
+    double v0 = r[(J * PW + i) * SR + c], v1 = 0.0;
+    for (int p = 0; p < h; p += 2) {
+      v0 = fma(-Lc[p * PLD + i], r[(p0 + p) * SR + c], v0);
+      v1 = fma(-Lc[(p + 1) * PLD + i], r[(p0 + p + 1) * SR + c], v1);
     }
-    for (int c = NB - 1; c >= 0; --c) {
-      if (tid == 0) ys[c] /= Lkk[(int64_t)c * NB + c];
-      __syncthreads();
-      for (int i = tid; i < c; i += 256) ys[i] -= Lkk[(int64_t)c * NB + i] * ys[c];
-      __syncthreads();
-    }
-    for (int i = tid; i < NB; i += 256) yr[(int64_t)k * NB + i] = ys[i];
+    s[i * SR + c] = v0 + v1;
     __syncthreads();
+    double u = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < PW; ++q) u = fma(Ds[q * PLD + i], s[q * SR + c], u);
+    r[(J * PW + i) * SR + c] = u;
+    __syncthreads();
+  }
+  for (int x = tid; x < NB * SR; x += 256) {
+    const int ii = x / SR, cc = x % SR;
+    if (cc < nrhs) y[(int64_t)cc * np + (int64_t)k * NB + ii] = r[x];
+  }
+}
+
+// backward panel item (k, tiles [t0, t1)): y_k -= sum over the tiles (m, k)
+// of L_mk^T x_m.  Per tile the entries of x_m at its active rows are gathered
+// into LDS; a thread owns a column and a share of the rows; the shares are
+// summed in LDS in a fixed order.
+template <int NB>
+__global__ __launch_bounds__(256) void k_sbwd_panel(const int32_t* __restrict__ items,
+                                                    const int32_t* __restrict__ tlist,
+                                                    const TileD* __restrict__ tiles,
+                                                    const int32_t* __restrict__ rows,
+                                                    const double* __restrict__ S,
+                                                    double* __restrict__ y, int64_t np, int32_t nrhs) {
+  constexpr int SH = 256 / NB;  // row shares per column
+  __shared__ double xg[NB * SR];  // xg[q * SR + c]: x_m at the tile's stored row q
+  __shared__ double red[(SH > 1 ? SH : 1) * NB * SR];
+  const int32_t k = items[3 * blockIdx.x], t0 = items[3 * blockIdx.x + 1], t1 = items[3 * blockIdx.x + 2];
+  const int tid = threadIdx.x;
+  const int col = tid % NB, sh = tid / NB;
+  double acc[SR];
+#pragma unroll
+  for (int c = 0; c < SR; ++c) acc[c] = 0.0;
+  for (int32_t z = t0; z < t1; ++z) {
+    const TileD tl = tiles[tlist[z]];
+    __syncthreads();  // xg is free
+    for (int x = tid; x < tl.cnt * SR; x += 256) {
+      const int q = x / SR, c = x % SR;
+      xg[x] = c < nrhs ? y[(int64_t)c * np + (int64_t)tl.m * NB + rows[tl.roff + q]] : 0.0;
+    }
+    __syncthreads();
+    const double* P = S + tl.off + col;
+#pragma unroll 4
+    for (int q = sh; q < tl.cnt; q += SH) {
+      const double l = P[(int64_t)q * NB];
+#pragma unroll
+      for (int c = 0; c < SR; ++c) acc[c] = fma(l, xg[q * SR + c], acc[c]);
+    }
+  }
+  double* yk = y + (int64_t)k * NB;
+  if constexpr (SH == 1) {
+#pragma unroll
+    for (int c = 0; c < SR; ++c)
+      if (c < nrhs) yk[(int64_t)c * np + col] -= acc[c];
+  } else {
+#pragma unroll
+    for (int c = 0; c < SR; ++c) red[(sh * NB + col) * SR + c] = acc[c];
+    __syncthreads();
+    for (int x = tid; x < NB * SR; x += 256) {
+      double v = 0.0;
+      for (int z = 0; z < SH; ++z) v += red[z * NB * SR + x];
+      if (x % SR < nrhs) yk[(int64_t)(x % SR) * np + x / SR] -= v;
+    }
   }
 }
 

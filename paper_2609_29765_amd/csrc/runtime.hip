@@ -58,6 +58,15 @@ struct stc_handle {
   std::vector<LevelOffsets> lv;
   // flattened level work lists (host)
   std::vector<int32_t> upd_items, big_items, potrf_list, trsm_items;
+  // solve sweeps: per level, the panel work items (forward: fed block, first
+  // block row, range in the tile list; backward: fed block, range) and their
+  // offsets, and the tile lists the ranges point into
+  std::vector<int32_t> sfwd_items, sfwd_ptr, sbwd_items, sbwd_ptr, sfwd_tl, sbwd_tl;
+  int32_t* d_sfwd_items = nullptr;
+  int32_t* d_sbwd_items = nullptr;
+  int32_t* d_sfwd_tl = nullptr;
+  int32_t* d_sbwd_tl = nullptr;
+  std::map<int32_t, hipGraphExec_t> solve_graphs;  // by right-hand sides per sweep
   // binding
   int device = -1;
   char* ws = nullptr;
@@ -102,6 +111,7 @@ struct stc_handle {
   hipGraphExec_t back_graph = nullptr;
   ~stc_handle() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto& g : solve_graphs) (void)hipGraphExecDestroy(g.second);
     if (back_graph) (void)hipGraphExecDestroy(back_graph);
   }
 };
@@ -144,6 +154,10 @@ size_t layout(const stc_handle* hc, int32_t batch, char* base) {
   take(&h->d_info, sizeof(int32_t) * (size_t)batch);
   take(&h->d_ld, sizeof(double) * (size_t)batch);
   take(&h->d_y, sizeof(double) * (size_t)padded_n(h) * kMaxRhs);
+  take(&h->d_sfwd_items, sizeof(int32_t) * h->sfwd_items.size());
+  take(&h->d_sbwd_items, sizeof(int32_t) * h->sbwd_items.size());
+  take(&h->d_sfwd_tl, sizeof(int32_t) * h->sfwd_tl.size());
+  take(&h->d_sbwd_tl, sizeof(int32_t) * h->sbwd_tl.size());
   take(&h->d_dinv, sizeof(double) * (size_t)dinv_stride(h) * (size_t)batch);
   take(&h->d_parts, sizeof(double) * (size_t)p.parts * (size_t)batch);
   take(&h->d_zrow, sizeof(double) * (size_t)p.nb);
@@ -346,6 +360,64 @@ int build_graph(stc_handle* h, int32_t members, hipGraphExec_t* ex) {
   return fail(STC_ERR_ARG, "unsupported tile size");
 }
 
+// the forward and backward sweeps over right-hand sides [g0, g0 + nr) of
+// d_y, level by level: diagonal blocks, then the panel tiles they unlock
+template <int NB>
+void launch_sweeps_nb(stc_handle* h, int32_t nr, int32_t g0, hipStream_t st) {
+  const Plan& p = h->plan;
+  const int64_t np = padded_n(h);
+  double* y = h->d_y + (int64_t)g0 * np;
+  for (size_t L = 0; L + 1 < p.fwd_level_ptr.size(); ++L) {
+    const int32_t a = p.fwd_level_ptr[L], b = p.fwd_level_ptr[L + 1];
+    if (b > a)
+      hipLaunchKernelGGL((k_sfwd_diag<NB>), dim3(b - a), dim3(256), 0, st, h->d_fwd_blk + a, h->d_store,
+                         h->d_dinv, y, np, nr);
+    const int32_t c = h->sfwd_ptr[L], d = h->sfwd_ptr[L + 1];
+    if (d > c)
+      hipLaunchKernelGGL((k_sfwd_panel<NB>), dim3(d - c), dim3(256), 0, st, h->d_sfwd_items + 4 * (int64_t)c,
+                         h->d_sfwd_tl, h->d_tiles, h->d_maps, h->d_store, y, np, nr);
+  }
+  for (size_t L = 0; L + 1 < p.bwd_level_ptr.size(); ++L) {
+    const int32_t a = p.bwd_level_ptr[L], b = p.bwd_level_ptr[L + 1];
+    if (b > a)
+      hipLaunchKernelGGL((k_sbwd_diag<NB>), dim3(b - a), dim3(256), 0, st, h->d_bwd_blk + a, h->d_store,
+                         h->d_dinv, y, np, nr);
+    const int32_t c = h->sbwd_ptr[L], d = h->sbwd_ptr[L + 1];
+    if (d > c)
+      hipLaunchKernelGGL((k_sbwd_panel<NB>), dim3(d - c), dim3(256), 0, st, h->d_sbwd_items + 3 * (int64_t)c,
+                         h->d_sbwd_tl, h->d_tiles, h->d_rows, h->d_store, y, np, nr);
+  }
+}
+
+int get_solve_graph(stc_handle* h, int32_t nr, int32_t g0, hipGraphExec_t* out) {
+  const int32_t key = nr * 1024 + g0;
+  auto it = h->solve_graphs.find(key);
+  if (it != h->solve_graphs.end()) {
+    *out = it->second;
+    return 0;
+  }
+  hipStream_t cs;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+  switch (h->plan.nb) {
+    case 32: launch_sweeps_nb<32>(h, nr, g0, cs); break;
+    case 64: launch_sweeps_nb<64>(h, nr, g0, cs); break;
+    case 128: launch_sweeps_nb<128>(h, nr, g0, cs); break;
+    case 256: launch_sweeps_nb<256>(h, nr, g0, cs); break;
+  }
+  hipGraph_t g;
+  hipError_t e = hipStreamEndCapture(cs, &g);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) return fail(STC_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  hipGraphExec_t ex;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(STC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  h->solve_graphs[key] = ex;
+  *out = ex;
+  return 0;
+}
+
 int get_graph(stc_handle* h, int32_t members, hipGraphExec_t* out) {
   auto it = h->graphs.find(members);
   if (it != h->graphs.end()) {
@@ -517,6 +589,52 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
       h->trsm_items.insert(h->trsm_items.end(), L.trsm_items.begin(), L.trsm_items.end());
       h->lv.push_back(x);
     }
+    // solve work items, level by level: the tiles a level's blocks unlock,
+    // grouped by the block they feed (tiles of one group in a fixed order)
+    const Plan& pl = h->plan;
+    std::map<int32_t, std::vector<int32_t>> feed;
+    h->sfwd_ptr.push_back(0);
+    for (size_t L = 0; L + 1 < pl.fwd_level_ptr.size(); ++L) {
+      feed.clear();
+      for (int32_t b = pl.fwd_level_ptr[L]; b < pl.fwd_level_ptr[L + 1]; ++b) {
+        const int32_t k = pl.fwd_level_blk[(size_t)b];
+        for (int32_t z = pl.col_tiles_ptr[(size_t)k]; z < pl.col_tiles_ptr[(size_t)k + 1]; ++z) {
+          const int32_t t = pl.col_tiles[(size_t)z];
+          feed[h->sym.tiles[(size_t)t].m].push_back(t);
+        }
+      }
+      for (const auto& kv : feed) {
+        const int32_t t0 = (int32_t)h->sfwd_tl.size();
+        h->sfwd_tl.insert(h->sfwd_tl.end(), kv.second.begin(), kv.second.end());
+        const int32_t t1 = (int32_t)h->sfwd_tl.size();
+        for (int32_t i0 = 0; i0 < pl.nb; i0 += SCH) {
+          h->sfwd_items.push_back(kv.first);
+          h->sfwd_items.push_back(i0);
+          h->sfwd_items.push_back(t0);
+          h->sfwd_items.push_back(t1);
+        }
+      }
+      h->sfwd_ptr.push_back((int32_t)(h->sfwd_items.size() / 4));
+    }
+    h->sbwd_ptr.push_back(0);
+    for (size_t L = 0; L + 1 < pl.bwd_level_ptr.size(); ++L) {
+      feed.clear();
+      for (int32_t b = pl.bwd_level_ptr[L]; b < pl.bwd_level_ptr[L + 1]; ++b) {
+        const int32_t m = pl.bwd_level_blk[(size_t)b];
+        for (int32_t z = pl.row_tiles_ptr[(size_t)m]; z < pl.row_tiles_ptr[(size_t)m + 1]; ++z) {
+          const int32_t t = pl.row_tiles[(size_t)z];
+          feed[h->sym.tiles[(size_t)t].k].push_back(t);
+        }
+      }
+      for (const auto& kv : feed) {
+        const int32_t t0 = (int32_t)h->sbwd_tl.size();
+        h->sbwd_tl.insert(h->sbwd_tl.end(), kv.second.begin(), kv.second.end());
+        h->sbwd_items.push_back(kv.first);
+        h->sbwd_items.push_back(t0);
+        h->sbwd_items.push_back((int32_t)h->sbwd_tl.size());
+      }
+      h->sbwd_ptr.push_back((int32_t)(h->sbwd_items.size() / 3));
+    }
     *out = h;
     return 0;
   } catch (const std::bad_alloc&) {
@@ -542,6 +660,8 @@ int stc_bind(stc_handle* h, void* d_ws, size_t bytes, int32_t batch, void* strea
     return fail(STC_ERR_ALLOC, "workspace too small: need " + std::to_string(need) + " bytes");
   for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.second);
   h->graphs.clear();
+  for (auto& g : h->solve_graphs) (void)hipGraphExecDestroy(g.second);
+  h->solve_graphs.clear();
   if (h->back_graph) (void)hipGraphExecDestroy(h->back_graph);
   h->back_graph = nullptr;
   h->factored = false;
@@ -568,7 +688,7 @@ int stc_bind(stc_handle* h, void* d_ws, size_t bytes, int32_t batch, void* strea
     tr[i] = TrsmTaskD{p.trsm[i].x_off, p.trsm[i].l_off, p.trsm[i].rows, p.trsm[i].k};
   std::vector<TileD> tl(s.tiles.size());
   for (size_t i = 0; i < tl.size(); ++i)
-    tl[i] = TileD{p.tile_off[i], s.tiles[i].roff, s.tiles[i].m, s.tiles[i].k, s.tiles[i].cnt, 0};
+    tl[i] = TileD{p.tile_off[i], s.tiles[i].roff, s.tiles[i].m, s.tiles[i].k, s.tiles[i].cnt, p.tile_imap[i]};
   int rc = 0;
   if ((rc = upload(h->d_vmap, p.vmap)) || (rc = upload(h->d_maps, p.maps)) ||
       (rc = upload(h->d_upd, upd)) || (rc = upload(h->d_contrib, con)) ||
@@ -579,7 +699,9 @@ int stc_bind(stc_handle* h, void* d_ws, size_t bytes, int32_t batch, void* strea
       (rc = upload(h->d_rows, s.rows)) || (rc = upload(h->d_row_ptr, p.row_tiles_ptr)) ||
       (rc = upload(h->d_row_tiles, p.row_tiles)) || (rc = upload(h->d_col_ptr, p.col_tiles_ptr)) ||
       (rc = upload(h->d_col_tiles, p.col_tiles)) || (rc = upload(h->d_fwd_blk, p.fwd_level_blk)) ||
-      (rc = upload(h->d_bwd_blk, p.bwd_level_blk)))
+      (rc = upload(h->d_bwd_blk, p.bwd_level_blk)) || (rc = upload(h->d_sfwd_items, h->sfwd_items)) ||
+      (rc = upload(h->d_sbwd_items, h->sbwd_items)) || (rc = upload(h->d_sfwd_tl, h->sfwd_tl)) ||
+      (rc = upload(h->d_sbwd_tl, h->sbwd_tl)))
     return rc;
   HIPCHK(hipMemset(h->d_zrow, 0, sizeof(double) * (size_t)p.nb));
   const BackPlan& bp = h->back;
@@ -650,29 +772,16 @@ int stc_solve(stc_handle* h, double* d_b, int32_t nrhs, void* stream) {
   if (nrhs < 1 || nrhs > kMaxRhs) return fail(STC_ERR_ARG, "nrhs must be in [1, 64]");
   if (!h->factored) return fail(STC_ERR_STATE, "solve before factorize");
   hipStream_t st = (hipStream_t)stream;
-  const Plan& p = h->plan;
   const int64_t n = h->sym.n, np = padded_n(h);
   hipLaunchKernelGGL(k_perm_in, dim3((unsigned)((np * nrhs + 255) / 256)), dim3(256), 0, st, d_b,
                      h->d_perm, n, np, nrhs, h->d_y);
-  auto sweep = [&](auto fwd_kernel, auto bwd_kernel) {
-    for (size_t L = 0; L + 1 < p.fwd_level_ptr.size(); ++L) {
-      int32_t a = p.fwd_level_ptr[L], b = p.fwd_level_ptr[L + 1];
-      if (b > a)
-        hipLaunchKernelGGL(fwd_kernel, dim3(b - a), dim3(256), 0, st, h->d_fwd_blk + a, h->d_row_ptr,
-                           h->d_row_tiles, h->d_tiles, h->d_rows, h->d_store, h->d_y, np, nrhs);
-    }
-    for (size_t L = 0; L + 1 < p.bwd_level_ptr.size(); ++L) {
-      int32_t a = p.bwd_level_ptr[L], b = p.bwd_level_ptr[L + 1];
-      if (b > a)
-        hipLaunchKernelGGL(bwd_kernel, dim3(b - a), dim3(256), 0, st, h->d_bwd_blk + a, h->d_col_ptr,
-                           h->d_col_tiles, h->d_tiles, h->d_rows, h->d_store, h->d_y, np, nrhs);
-    }
-  };
-  switch (p.nb) {
-    case 32: sweep(k_fwd<32>, k_bwd<32>); break;
-    case 64: sweep(k_fwd<64>, k_bwd<64>); break;
-    case 128: sweep(k_fwd<128>, k_bwd<128>); break;
-    case 256: sweep(k_fwd<256>, k_bwd<256>); break;
+  // groups of up to SR right-hand sides, each one replay of the captured sweeps
+  for (int32_t g0 = 0; g0 < nrhs; g0 += SR) {
+    const int32_t nr = std::min<int32_t>(SR, nrhs - g0);
+    hipGraphExec_t ex;
+    rc = get_solve_graph(h, nr, g0, &ex);
+    if (rc) return rc;
+    HIPCHK(hipGraphLaunch(ex, st));
   }
   hipLaunchKernelGGL(k_perm_out, dim3((unsigned)((n * nrhs + 255) / 256)), dim3(256), 0, st, h->d_y,
                      h->d_perm, n, np, nrhs, d_b);
