@@ -1334,15 +1334,18 @@ constexpr int SR = 8;      // right-hand sides per sweep
 constexpr int SCH = 64;    // block rows of a forward panel work item
 
 // y_k <- L_kk^-1 y_k: per 32-row block J, the block row of L_kk left of the
-// diagonal block and the block's inverse staged in LDS,
-// s = r_J - L_(J,<J) y_(<J), y_J = D_J s
+// diagonal block and the block's inverse are staged in LDS (coalesced), then
+// s = r_J - L_(J,<J) y_(<J) with the K range split over 8 threads per row
+// (each keeping all right-hand sides) and the parts summed in a fixed order,
+// then y_J = D_J s
 template <int NB>
 __global__ __launch_bounds__(256) void k_sfwd_diag(const int32_t* __restrict__ blks,
                                                    const double* __restrict__ S,
                                                    const double* __restrict__ dinv,
                                                    double* __restrict__ y, int64_t np, int32_t nrhs) {
   constexpr int LW = NB - PW + 1;
-  __shared__ double r[NB * SR];   // r[i * SR + c]
+  __shared__ double r[NB * SR];      // r[i * SR + c]
+  __shared__ double part[PW * 8 * SR];
   __shared__ double s[PW * SR];
   __shared__ double Ls[PW * LW];
   __shared__ double Ds[PW * PLD];
@@ -1354,23 +1357,50 @@ __global__ __launch_bounds__(256) void k_sfwd_diag(const int32_t* __restrict__ b
   }
   const double* L = S + (int64_t)k * NB * NB;
   const double* D = dinv + (int64_t)k * NB * PW;
-  const int i = tid / SR, c = tid % SR;  // 32 rows x SR right-hand sides
+  const int row = tid >> 3, sub = tid & 7;  // staging and K-split layout: 32 rows x 8
   for (int J = 0; J < NB / PW; ++J) {
     const int w = J * PW;
-    for (int x = tid; x < PW * w; x += 256) Ls[(x / w) * LW + x % w] = L[(int64_t)(w + x / w) * NB + x % w];
-    for (int x = tid; x < PW * PW; x += 256) Ds[(x / PW) * PLD + x % PW] = D[J * PW * PW + x];
-    __syncthreads();
-    double v0 = r[(w + i) * SR + c], v1 = 0.0;
-    for (int p = 0; p < w; p += 2) {
-      v0 = fma(-Ls[i * LW + p], r[p * SR + c], v0);
-      v1 = fma(-Ls[i * LW + p + 1], r[(p + 1) * SR + c], v1);
+    {
+      const double* src = L + (int64_t)(w + row) * NB;
+      for (int col = 2 * sub; col < w; col += 16) {
+        const double2 v = *reinterpret_cast<const double2*>(src + col);
+        Ls[row * LW + col] = v.x;
+        Ls[row * LW + col + 1] = v.y;
+      }
+      const double4 d = *reinterpret_cast<const double4*>(D + J * PW * PW + row * PW + 4 * sub);
+      Ds[row * PLD + 4 * sub] = d.x;
+      Ds[row * PLD + 4 * sub + 1] = d.y;
+      Ds[row * PLD + 4 * sub + 2] = d.z;
+      Ds[row * PLD + 4 * sub + 3] = d.w;
     }
-    s[i * SR + c] = v0 + v1;
     __syncthreads();
-    double u = 0.0;
+    double acc[SR];
+#pragma unroll
+    for (int c = 0; c < SR; ++c) acc[c] = 0.0;
+#pragma unroll 4
+    for (int p = sub; p < w; p += 8) {
+      const double l = Ls[row * LW + p];
+#pragma unroll
+      for (int c = 0; c < SR; ++c) acc[c] = fma(l, r[p * SR + c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < SR; ++c) part[(row * 8 + sub) * SR + c] = acc[c];
+    __syncthreads();
+    {
+      const int i = tid / SR, c = tid % SR;
+      double v = r[(w + i) * SR + c];
+#pragma unroll
+      for (int z = 0; z < 8; ++z) v -= part[(i * 8 + z) * SR + c];
+      s[i * SR + c] = v;
+    }
+    __syncthreads();
+    {
+      const int i = tid / SR, c = tid % SR;
+      double u = 0.0;
 #pragma unroll 8
-    for (int q = 0; q < PW; ++q) u = fma(Ds[i * PLD + q], s[q * SR + c], u);
-    r[(w + i) * SR + c] = u;
+      for (int q = 0; q < PW; ++q) u = fma(Ds[i * PLD + q], s[q * SR + c], u);
+      r[(w + i) * SR + c] = u;
+    }
     __syncthreads();
   }
   for (int x = tid; x < NB * SR; x += 256) {
@@ -1442,14 +1472,16 @@ __global__ __launch_bounds__(256) void k_sfwd_panel(const int32_t* __restrict__ 
 }
 
 // x_k <- L_kk^-T y_k: per 32-row block J from the last, the block column of
-// L_kk below the diagonal block and the block's inverse staged in LDS,
-// s = r_J - L_(>J,J)^T x_(>J), x_J = D_J^T s
+// L_kk below the diagonal block and the block's inverse are staged in LDS
+// (coalesced), then s = r_J - L_(>J,J)^T x_(>J) with the row range split over
+// 8 threads per column (parts summed in a fixed order), then x_J = D_J^T s
 template <int NB>
 __global__ __launch_bounds__(256) void k_sbwd_diag(const int32_t* __restrict__ blks,
                                                    const double* __restrict__ S,
                                                    const double* __restrict__ dinv,
                                                    double* __restrict__ y, int64_t np, int32_t nrhs) {
   __shared__ double r[NB * SR];
+  __shared__ double part[PW * 8 * SR];
   __shared__ double s[PW * SR];
   __shared__ double Lc[(NB - PW) * PLD + 1];
   __shared__ double Ds[PW * PLD];
@@ -1461,23 +1493,51 @@ __global__ __launch_bounds__(256) void k_sbwd_diag(const int32_t* __restrict__ b
   }
   const double* L = S + (int64_t)k * NB * NB;
   const double* D = dinv + (int64_t)k * NB * PW;
-  const int i = tid / SR, c = tid % SR;
+  const int row = tid >> 3, sub = tid & 7;
   for (int J = NB / PW - 1; J >= 0; --J) {
     const int p0 = (J + 1) * PW, h = NB - p0;  // rows below the diagonal block
-    for (int x = tid; x < h * PW; x += 256) Lc[(x / PW) * PLD + x % PW] = L[(int64_t)(p0 + x / PW) * NB + J * PW + x % PW];
-    for (int x = tid; x < PW * PW; x += 256) Ds[(x / PW) * PLD + x % PW] = D[J * PW * PW + x];
-    __syncthreads();
-    double v0 = r[(J * PW + i) * SR + c], v1 = 0.0;
-    for (int p = 0; p < h; p += 2) {
-      v0 = fma(-Lc[p * PLD + i], r[(p0 + p) * SR + c], v0);
-      v1 = fma(-Lc[(p + 1) * PLD + i], r[(p0 + p + 1) * SR + c], v1);
+    for (int p = row; p < h; p += 32) {
+      const double4 v = *reinterpret_cast<const double4*>(L + (int64_t)(p0 + p) * NB + J * PW + 4 * sub);
+      Lc[p * PLD + 4 * sub] = v.x;
+      Lc[p * PLD + 4 * sub + 1] = v.y;
+      Lc[p * PLD + 4 * sub + 2] = v.z;
+      Lc[p * PLD + 4 * sub + 3] = v.w;
     }
-    s[i * SR + c] = v0 + v1;
+    {
+      const double4 d = *reinterpret_cast<const double4*>(D + J * PW * PW + row * PW + 4 * sub);
+      Ds[row * PLD + 4 * sub] = d.x;
+      Ds[row * PLD + 4 * sub + 1] = d.y;
+      Ds[row * PLD + 4 * sub + 2] = d.z;
+      Ds[row * PLD + 4 * sub + 3] = d.w;
+    }
     __syncthreads();
-    double u = 0.0;
+    double acc[SR];
+#pragma unroll
+    for (int c = 0; c < SR; ++c) acc[c] = 0.0;
+#pragma unroll 4
+    for (int p = sub; p < h; p += 8) {
+      const double l = Lc[p * PLD + row];
+#pragma unroll
+      for (int c = 0; c < SR; ++c) acc[c] = fma(l, r[(p0 + p) * SR + c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < SR; ++c) part[(row * 8 + sub) * SR + c] = acc[c];
+    __syncthreads();
+    {
+      const int i = tid / SR, c = tid % SR;
+      double v = r[(J * PW + i) * SR + c];
+#pragma unroll
+      for (int z = 0; z < 8; ++z) v -= part[(i * 8 + z) * SR + c];
+      s[i * SR + c] = v;
+    }
+    __syncthreads();
+    {
+      const int i = tid / SR, c = tid % SR;
+      double u = 0.0;
 #pragma unroll 8
-    for (int q = 0; q < PW; ++q) u = fma(Ds[q * PLD + i], s[q * SR + c], u);
-    r[(J * PW + i) * SR + c] = u;
+      for (int q = 0; q < PW; ++q) u = fma(Ds[q * PLD + i], s[q * SR + c], u);
+      r[(J * PW + i) * SR + c] = u;
+    }
     __syncthreads();
   }
   for (int x = tid; x < NB * SR; x += 256) {
@@ -1486,10 +1546,12 @@ __global__ __launch_bounds__(256) void k_sbwd_diag(const int32_t* __restrict__ b
   }
 }
 
-// backward panel item (k, tiles [t0, t1)): y_k -= sum over the tiles (m, k)
-// of L_mk^T x_m.  Per tile the entries of x_m at its active rows are gathered
-// into LDS; a thread owns a column and a share of the rows; the shares are
-// summed in LDS in a fixed order.
+// backward panel item (k, j0, tiles [t0, t1)): columns j0 .. j0 + 63 of
+// y_k -= sum over the tiles (m, k) of L_mk^T x_m.  Per tile the entries of
+// x_m at its active rows are gathered into LDS; a thread owns a column and a
+// quarter of the rows; the quarters are summed in LDS in a fixed order.
+constexpr int SBC = 64;  // columns of a backward panel work item
+
 template <int NB>
 __global__ __launch_bounds__(256) void k_sbwd_panel(const int32_t* __restrict__ items,
                                                     const int32_t* __restrict__ tlist,
@@ -1497,12 +1559,14 @@ __global__ __launch_bounds__(256) void k_sbwd_panel(const int32_t* __restrict__ 
                                                     const int32_t* __restrict__ rows,
                                                     const double* __restrict__ S,
                                                     double* __restrict__ y, int64_t np, int32_t nrhs) {
-  constexpr int SH = 256 / NB;  // row shares per column
+  constexpr int CW = NB < SBC ? NB : SBC;  // columns per item
+  constexpr int SH = 256 / CW;             // row shares per column
   __shared__ double xg[NB * SR];  // xg[q * SR + c]: x_m at the tile's stored row q
-  __shared__ double red[(SH > 1 ? SH : 1) * NB * SR];
-  const int32_t k = items[3 * blockIdx.x], t0 = items[3 * blockIdx.x + 1], t1 = items[3 * blockIdx.x + 2];
+  __shared__ double red[SH * CW * SR];
+  const int32_t k = items[4 * blockIdx.x], j0 = items[4 * blockIdx.x + 1];
+  const int32_t t0 = items[4 * blockIdx.x + 2], t1 = items[4 * blockIdx.x + 3];
   const int tid = threadIdx.x;
-  const int col = tid % NB, sh = tid / NB;
+  const int col = tid % CW, sh = tid / CW;
   double acc[SR];
 #pragma unroll
   for (int c = 0; c < SR; ++c) acc[c] = 0.0;
@@ -1514,28 +1578,22 @@ __global__ __launch_bounds__(256) void k_sbwd_panel(const int32_t* __restrict__ 
       xg[x] = c < nrhs ? y[(int64_t)c * np + (int64_t)tl.m * NB + rows[tl.roff + q]] : 0.0;
     }
     __syncthreads();
-    const double* P = S + tl.off + col;
-#pragma unroll 4
+    const double* P = S + tl.off + j0 + col;
+#pragma unroll 8
     for (int q = sh; q < tl.cnt; q += SH) {
       const double l = P[(int64_t)q * NB];
 #pragma unroll
       for (int c = 0; c < SR; ++c) acc[c] = fma(l, xg[q * SR + c], acc[c]);
     }
   }
-  double* yk = y + (int64_t)k * NB;
-  if constexpr (SH == 1) {
 #pragma unroll
-    for (int c = 0; c < SR; ++c)
-      if (c < nrhs) yk[(int64_t)c * np + col] -= acc[c];
-  } else {
-#pragma unroll
-    for (int c = 0; c < SR; ++c) red[(sh * NB + col) * SR + c] = acc[c];
-    __syncthreads();
-    for (int x = tid; x < NB * SR; x += 256) {
-      double v = 0.0;
-      for (int z = 0; z < SH; ++z) v += red[z * NB * SR + x];
-      if (x % SR < nrhs) yk[(int64_t)(x % SR) * np + x / SR] -= v;
-    }
+  for (int c = 0; c < SR; ++c) red[(sh * CW + col) * SR + c] = acc[c];
+  __syncthreads();
+  double* yk = y + (int64_t)k * NB + j0;
+  for (int x = tid; x < CW * SR; x += 256) {
+    double v = 0.0;
+    for (int z = 0; z < SH; ++z) v += red[z * CW * SR + x];
+    if (x % SR < nrhs) yk[(int64_t)(x % SR) * np + x / SR] -= v;
   }
 }
 

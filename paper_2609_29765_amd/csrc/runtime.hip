@@ -384,7 +384,7 @@ void launch_sweeps_nb(stc_handle* h, int32_t nr, int32_t g0, hipStream_t st) {
                          h->d_dinv, y, np, nr);
     const int32_t c = h->sbwd_ptr[L], d = h->sbwd_ptr[L + 1];
     if (d > c)
-      hipLaunchKernelGGL((k_sbwd_panel<NB>), dim3(d - c), dim3(256), 0, st, h->d_sbwd_items + 3 * (int64_t)c,
+      hipLaunchKernelGGL((k_sbwd_panel<NB>), dim3(d - c), dim3(256), 0, st, h->d_sbwd_items + 4 * (int64_t)c,
                          h->d_sbwd_tl, h->d_tiles, h->d_rows, h->d_store, y, np, nr);
   }
 }
@@ -629,11 +629,15 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
       for (const auto& kv : feed) {
         const int32_t t0 = (int32_t)h->sbwd_tl.size();
         h->sbwd_tl.insert(h->sbwd_tl.end(), kv.second.begin(), kv.second.end());
-        h->sbwd_items.push_back(kv.first);
-        h->sbwd_items.push_back(t0);
-        h->sbwd_items.push_back((int32_t)h->sbwd_tl.size());
+        const int32_t t1 = (int32_t)h->sbwd_tl.size();
+        for (int32_t j0 = 0; j0 < pl.nb; j0 += SBC) {
+          h->sbwd_items.push_back(kv.first);
+          h->sbwd_items.push_back(j0);
+          h->sbwd_items.push_back(t0);
+          h->sbwd_items.push_back(t1);
+        }
       }
-      h->sbwd_ptr.push_back((int32_t)(h->sbwd_items.size() / 3));
+      h->sbwd_ptr.push_back((int32_t)(h->sbwd_items.size() / 4));
     }
     *out = h;
     return 0;
