@@ -1358,22 +1358,36 @@ __global__ __launch_bounds__(256) void k_sfwd_diag(const int32_t* __restrict__ b
   const double* L = S + (int64_t)k * NB * NB;
   const double* D = dinv + (int64_t)k * NB * PW;
   const int row = tid >> 3, sub = tid & 7;  // staging and K-split layout: 32 rows x 8
+  // step J's block row of L and inverse are read into registers during step
+  // J - 1 and written to LDS when step J begins
+  constexpr int NPF = NB > PW ? (NB - PW) / 16 : 1;
+  double2 pf[NPF];
+  double4 pd;
+  auto fetch = [&](int J) {
+    const int w = J * PW;
+    const double* src = L + (int64_t)(w + row) * NB;
+#pragma unroll
+    for (int q = 0; q < NPF; ++q)
+      if (2 * sub + 16 * q < w) pf[q] = *reinterpret_cast<const double2*>(src + 2 * sub + 16 * q);
+    pd = *reinterpret_cast<const double4*>(D + J * PW * PW + row * PW + 4 * sub);
+  };
+  fetch(0);
   for (int J = 0; J < NB / PW; ++J) {
     const int w = J * PW;
-    {
-      const double* src = L + (int64_t)(w + row) * NB;
-      for (int col = 2 * sub; col < w; col += 16) {
-        const double2 v = *reinterpret_cast<const double2*>(src + col);
-        Ls[row * LW + col] = v.x;
-        Ls[row * LW + col + 1] = v.y;
+#pragma unroll
+    for (int q = 0; q < NPF; ++q) {
+      const int col = 2 * sub + 16 * q;
+      if (col < w) {
+        Ls[row * LW + col] = pf[q].x;
+        Ls[row * LW + col + 1] = pf[q].y;
       }
-      const double4 d = *reinterpret_cast<const double4*>(D + J * PW * PW + row * PW + 4 * sub);
-      Ds[row * PLD + 4 * sub] = d.x;
-      Ds[row * PLD + 4 * sub + 1] = d.y;
-      Ds[row * PLD + 4 * sub + 2] = d.z;
-      Ds[row * PLD + 4 * sub + 3] = d.w;
     }
+    Ds[row * PLD + 4 * sub] = pd.x;
+    Ds[row * PLD + 4 * sub + 1] = pd.y;
+    Ds[row * PLD + 4 * sub + 2] = pd.z;
+    Ds[row * PLD + 4 * sub + 3] = pd.w;
     __syncthreads();
+    if (J + 1 < NB / PW) fetch(J + 1);
     double acc[SR];
 #pragma unroll
     for (int c = 0; c < SR; ++c) acc[c] = 0.0;
@@ -1494,23 +1508,38 @@ __global__ __launch_bounds__(256) void k_sbwd_diag(const int32_t* __restrict__ b
   const double* L = S + (int64_t)k * NB * NB;
   const double* D = dinv + (int64_t)k * NB * PW;
   const int row = tid >> 3, sub = tid & 7;
+  // step J's block column of L and inverse are read into registers during
+  // step J + 1 and written to LDS when step J begins
+  constexpr int NPF = NB > PW ? (NB - PW) / 32 : 1;
+  double4 pf[NPF];
+  double4 pd;
+  auto fetch = [&](int J) {
+    const int p0 = (J + 1) * PW, h = NB - p0;
+#pragma unroll
+    for (int q = 0; q < NPF; ++q)
+      if (row + 32 * q < h)
+        pf[q] = *reinterpret_cast<const double4*>(L + (int64_t)(p0 + row + 32 * q) * NB + J * PW + 4 * sub);
+    pd = *reinterpret_cast<const double4*>(D + J * PW * PW + row * PW + 4 * sub);
+  };
+  fetch(NB / PW - 1);
   for (int J = NB / PW - 1; J >= 0; --J) {
     const int p0 = (J + 1) * PW, h = NB - p0;  // rows below the diagonal block
-    for (int p = row; p < h; p += 32) {
-      const double4 v = *reinterpret_cast<const double4*>(L + (int64_t)(p0 + p) * NB + J * PW + 4 * sub);
-      Lc[p * PLD + 4 * sub] = v.x;
-      Lc[p * PLD + 4 * sub + 1] = v.y;
-      Lc[p * PLD + 4 * sub + 2] = v.z;
-      Lc[p * PLD + 4 * sub + 3] = v.w;
+#pragma unroll
+    for (int q = 0; q < NPF; ++q) {
+      const int p = row + 32 * q;
+      if (p < h) {
+        Lc[p * PLD + 4 * sub] = pf[q].x;
+        Lc[p * PLD + 4 * sub + 1] = pf[q].y;
+        Lc[p * PLD + 4 * sub + 2] = pf[q].z;
+        Lc[p * PLD + 4 * sub + 3] = pf[q].w;
+      }
     }
-    {
-      const double4 d = *reinterpret_cast<const double4*>(D + J * PW * PW + row * PW + 4 * sub);
-      Ds[row * PLD + 4 * sub] = d.x;
-      Ds[row * PLD + 4 * sub + 1] = d.y;
-      Ds[row * PLD + 4 * sub + 2] = d.z;
-      Ds[row * PLD + 4 * sub + 3] = d.w;
-    }
+    Ds[row * PLD + 4 * sub] = pd.x;
+    Ds[row * PLD + 4 * sub + 1] = pd.y;
+    Ds[row * PLD + 4 * sub + 2] = pd.z;
+    Ds[row * PLD + 4 * sub + 3] = pd.w;
     __syncthreads();
+    if (J > 0) fetch(J - 1);
     double acc[SR];
 #pragma unroll
     for (int c = 0; c < SR; ++c) acc[c] = 0.0;
