@@ -87,6 +87,21 @@ def log(msg):
 # headline: dense route, n = 12288, tile 256
 # ---------------------------------------------------------------------------
 
+def kind_table(prof, work):
+    """Per kernel kind of one eager factorization: time, launches, FP64
+    TFLOP/s of the tile-algorithmic flops (update, POTRF, TRSM kinds) and, for
+    the value load (zero fill plus scatter), GB/s of its algorithmic bytes."""
+    out = {}
+    for k, (ms, cnt, fl) in prof.items():
+        e = {"ms_per_factorization": round(ms, 4), "launches": cnt,
+             "avg_launch_ms": round(ms / max(cnt, 1), 5),
+             "tflops": round(fl / (ms * 1e-3) / 1e12, 3) if ms > 0 and fl > 0 else None}
+        if k == "load" and ms > 0:
+            e["hbm_gbs"] = round(work["bytes_load"] / (ms * 1e-3) / 1e9, 1)
+        out[k] = e
+    return out
+
+
 def headline(args):
     import torch
     stc = load_lib()
@@ -160,10 +175,8 @@ def headline(args):
         roofline["algorithmic_bytes_per_launch"] = work["bytes_update"] * flops_per_launch / work["flops_update"]
     fam_ms = sum(agg[k][0] for k in level_kinds)
     fam_fl = sum(agg[k][2] for k in level_kinds)
-    kinds = {k: {"ms_per_factorization": round(v[0] / args.prof_reps, 4), "launches": v[1] // args.prof_reps,
-                 "avg_launch_ms": round(v[0] / max(v[1], 1), 5),
-                 "tflops": round(v[2] / (v[0] * 1e-3) / 1e12, 3) if v[0] > 0 and v[2] > 0 else None}
-             for k, v in agg.items()}
+    kinds = kind_table({k: (v[0] / args.prof_reps, v[1] // args.prof_reps, v[2] / args.prof_reps)
+                        for k, v in agg.items()}, work)
     log(f"roofline {symbol}: {achieved:.2f} TFLOP/s over {cnt_d // args.prof_reps} launches; "
         f"all level kernels {fam_fl / (fam_ms * 1e-3) / 1e12:.2f} TFLOP/s")
 
@@ -245,7 +258,7 @@ def extra_semisparse():
             "gflops_exact": round(wk["flops_exact"] / (ms * 1e-3) / 1e9, 1),
             "tile_gflop": round(wk["flops_tile"] / 1e9, 2), "exact_gflop": round(wk["flops_exact"] / 1e9, 2),
             "autotune": table, "autotune_s": round(t_tune, 1),
-            "kernels": {k: {"ms": round(x[0], 3), "launches": x[1]} for k, x in prof.items()},
+            "kernels": kind_table(prof, wk),
             "logdet": float(a.logdet().item())}
 
 

@@ -1326,10 +1326,14 @@ __global__ void k_perm_out(const double* __restrict__ y, const int32_t* __restri
 // products of the tiles they unlock straight from the right-hand sides of
 // the blocks those tiles feed (forward: b_m -= L_mk y_k; backward:
 // y_k -= L_mk^T x_m).  One work item owns one fed block (a 64-row chunk of it,
-// forward) and runs through its tiles of the level in a fixed order, so there
+// forward; a 64-column chunk, backward) and runs through its tiles of the level in a fixed order, so there
 // are no races and no atomics and results are reproducible bit for bit.  The
 // diagonal blocks are solved 32 rows at a time with the inverses of the
-// 32 x 32 diagonal blocks of L that the factorization keeps (dinv).
+// 32 x 32 diagonal blocks of L that the factorization keeps (dinv).  The
+// kernels are compiled for R = 1 (a single right-hand side) and R = SR (a
+// group of 2 .. 8, the unused columns zero); every column is computed by the
+// same operations in the same order whatever R, so its result does not
+// depend on how many columns share the pass.
 constexpr int SR = 8;      // right-hand sides per sweep
 constexpr int SCH = 64;    // block rows of a forward panel work item
 
@@ -1338,21 +1342,21 @@ constexpr int SCH = 64;    // block rows of a forward panel work item
 // s = r_J - L_(J,<J) y_(<J) with the K range split over 8 threads per row
 // (each keeping all right-hand sides) and the parts summed in a fixed order,
 // then y_J = D_J s
-template <int NB>
+template <int NB, int R>
 __global__ __launch_bounds__(256) void k_sfwd_diag(const int32_t* __restrict__ blks,
                                                    const double* __restrict__ S,
                                                    const double* __restrict__ dinv,
                                                    double* __restrict__ y, int64_t np, int32_t nrhs) {
   constexpr int LW = NB - PW + 1;
-  __shared__ double r[NB * SR];      // r[i * SR + c]
-  __shared__ double part[PW * 8 * SR];
-  __shared__ double s[PW * SR];
+  __shared__ double r[NB * R];      // r[i * R + c]
+  __shared__ double part[PW * 8 * R];
+  __shared__ double s[PW * R];
   __shared__ double Ls[PW * LW];
   __shared__ double Ds[PW * PLD];
   const int32_t k = blks[blockIdx.x];
   const int tid = threadIdx.x;
-  for (int x = tid; x < NB * SR; x += 256) {
-    const int i = x / SR, c = x % SR;
+  for (int x = tid; x < NB * R; x += 256) {
+    const int i = x / R, c = x % R;
     r[x] = c < nrhs ? y[(int64_t)c * np + (int64_t)k * NB + i] : 0.0;
   }
   const double* L = S + (int64_t)k * NB * NB;
@@ -1388,37 +1392,37 @@ __global__ __launch_bounds__(256) void k_sfwd_diag(const int32_t* __restrict__ b
     Ds[row * PLD + 4 * sub + 3] = pd.w;
     __syncthreads();
     if (J + 1 < NB / PW) fetch(J + 1);
-    double acc[SR];
+    double acc[R];
 #pragma unroll
-    for (int c = 0; c < SR; ++c) acc[c] = 0.0;
+    for (int c = 0; c < R; ++c) acc[c] = 0.0;
 #pragma unroll 4
     for (int p = sub; p < w; p += 8) {
       const double l = Ls[row * LW + p];
 #pragma unroll
-      for (int c = 0; c < SR; ++c) acc[c] = fma(l, r[p * SR + c], acc[c]);
+      for (int c = 0; c < R; ++c) acc[c] = fma(l, r[p * R + c], acc[c]);
     }
 #pragma unroll
-    for (int c = 0; c < SR; ++c) part[(row * 8 + sub) * SR + c] = acc[c];
+    for (int c = 0; c < R; ++c) part[(row * 8 + sub) * R + c] = acc[c];
     __syncthreads();
-    {
-      const int i = tid / SR, c = tid % SR;
-      double v = r[(w + i) * SR + c];
+    if (tid < PW * R) {
+      const int i = tid / R, c = tid % R;
+      double v = r[(w + i) * R + c];
 #pragma unroll
-      for (int z = 0; z < 8; ++z) v -= part[(i * 8 + z) * SR + c];
-      s[i * SR + c] = v;
+      for (int z = 0; z < 8; ++z) v -= part[(i * 8 + z) * R + c];
+      s[i * R + c] = v;
     }
     __syncthreads();
-    {
-      const int i = tid / SR, c = tid % SR;
+    if (tid < PW * R) {
+      const int i = tid / R, c = tid % R;
       double u = 0.0;
 #pragma unroll 8
-      for (int q = 0; q < PW; ++q) u = fma(Ds[i * PLD + q], s[q * SR + c], u);
-      r[(w + i) * SR + c] = u;
+      for (int q = 0; q < PW; ++q) u = fma(Ds[i * PLD + q], s[q * R + c], u);
+      r[(w + i) * R + c] = u;
     }
     __syncthreads();
   }
-  for (int x = tid; x < NB * SR; x += 256) {
-    const int ii = x / SR, cc = x % SR;
+  for (int x = tid; x < NB * R; x += 256) {
+    const int ii = x / R, cc = x % R;
     if (cc < nrhs) y[(int64_t)cc * np + (int64_t)k * NB + ii] = r[x];
   }
 }
@@ -1426,60 +1430,67 @@ __global__ __launch_bounds__(256) void k_sfwd_diag(const int32_t* __restrict__ b
 // forward panel item (m, i0, tiles [t0, t1)): for block rows i0 .. i0 + 63 of
 // block m, b_m(i) -= sum over the tiles (m, k) of L_mk(q(i)) y_k, q(i) the
 // tile's stored row of block row i (its inverse row map; identity when the
-// tile is full).  8 lanes per row over interleaved column pairs, reduced by
-// shuffles.
-template <int NB>
+// tile is full).  8 lanes per row over interleaved column pairs, two rows per
+// thread, reduced by shuffles.  A tile's rows are read into registers before
+// y_k is gathered, so the loads of both overlap.
+template <int NB, int R>
 __global__ __launch_bounds__(256) void k_sfwd_panel(const int32_t* __restrict__ items,
                                                     const int32_t* __restrict__ tlist,
                                                     const TileD* __restrict__ tiles,
                                                     const int32_t* __restrict__ maps,
                                                     const double* __restrict__ S,
                                                     double* __restrict__ y, int64_t np, int32_t nrhs) {
-  __shared__ double ys[NB * SR];  // ys[col * SR + c]
+  constexpr int NC = NB / 16;  // column pairs per lane
+  __shared__ double ys[NB * R];  // ys[col * R + c]
   const int32_t m = items[4 * blockIdx.x], i0 = items[4 * blockIdx.x + 1];
   const int32_t t0 = items[4 * blockIdx.x + 2], t1 = items[4 * blockIdx.x + 3];
   const int tid = threadIdx.x;
   const int j = tid & 7, rl = tid >> 3;  // lane of the row group, row of the pass
-  double acc[2][SR];
+  double acc[2][R];
 #pragma unroll
   for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int c = 0; c < SR; ++c) acc[h][c] = 0.0;
+    for (int c = 0; c < R; ++c) acc[h][c] = 0.0;
   for (int32_t z = t0; z < t1; ++z) {
     const TileD tl = tiles[tlist[z]];
-    __syncthreads();  // ys is free
-    for (int x = tid; x < NB * SR; x += 256) {
-      const int col = x / SR, c = x % SR;
-      ys[x] = c < nrhs ? y[(int64_t)c * np + (int64_t)tl.k * NB + col] : 0.0;
-    }
-    __syncthreads();
+    double2 lv[2][NC];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int i = i0 + rl + 32 * h;
       const int32_t q = i >= NB ? -1 : (tl.imap < 0 ? i : maps[tl.imap + i]);
-      if (q >= 0) {
-        const double* Lr = S + tl.off + (int64_t)q * NB;
-#pragma unroll 4
-        for (int col = 2 * j; col < NB; col += 16) {
-          const double2 l = *reinterpret_cast<const double2*>(Lr + col);
+      const double* Lr = S + tl.off + (int64_t)(q < 0 ? 0 : q) * NB + 2 * j;
 #pragma unroll
-          for (int c = 0; c < SR; ++c)
-            acc[h][c] = fma(l.x, ys[col * SR + c], fma(l.y, ys[(col + 1) * SR + c], acc[h][c]));
-        }
+      for (int u = 0; u < NC; ++u)
+        lv[h][u] = q >= 0 ? *reinterpret_cast<const double2*>(Lr + 16 * u) : make_double2(0.0, 0.0);
+    }
+    __syncthreads();  // ys is free
+    for (int x = tid; x < NB * R; x += 256) {
+      const int col = x / R, c = x % R;
+      ys[x] = c < nrhs ? y[(int64_t)c * np + (int64_t)tl.k * NB + col] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NC; ++u) {
+      const int col = 2 * j + 16 * u;
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        const double y0 = ys[col * R + c], y1 = ys[(col + 1) * R + c];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) acc[h][c] = fma(lv[h][u].x, y0, fma(lv[h][u].y, y1, acc[h][c]));
       }
     }
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
 #pragma unroll
-    for (int c = 0; c < SR; ++c) {
+    for (int c = 0; c < R; ++c) {
       acc[h][c] += __shfl_xor(acc[h][c], 1);
       acc[h][c] += __shfl_xor(acc[h][c], 2);
       acc[h][c] += __shfl_xor(acc[h][c], 4);
     }
     double mine = acc[h][0];  // lane j of the row group keeps right-hand side j
 #pragma unroll
-    for (int c = 1; c < SR; ++c) mine = j == c ? acc[h][c] : mine;
+    for (int c = 1; c < R; ++c) mine = j == c ? acc[h][c] : mine;
     const int i = i0 + rl + 32 * h;
     if (i < NB && j < nrhs) y[(int64_t)j * np + (int64_t)m * NB + i] -= mine;
   }
@@ -1489,20 +1500,20 @@ __global__ __launch_bounds__(256) void k_sfwd_panel(const int32_t* __restrict__ 
 // L_kk below the diagonal block and the block's inverse are staged in LDS
 // (coalesced), then s = r_J - L_(>J,J)^T x_(>J) with the row range split over
 // 8 threads per column (parts summed in a fixed order), then x_J = D_J^T s
-template <int NB>
+template <int NB, int R>
 __global__ __launch_bounds__(256) void k_sbwd_diag(const int32_t* __restrict__ blks,
                                                    const double* __restrict__ S,
                                                    const double* __restrict__ dinv,
                                                    double* __restrict__ y, int64_t np, int32_t nrhs) {
-  __shared__ double r[NB * SR];
-  __shared__ double part[PW * 8 * SR];
-  __shared__ double s[PW * SR];
+  __shared__ double r[NB * R];
+  __shared__ double part[PW * 8 * R];
+  __shared__ double s[PW * R];
   __shared__ double Lc[(NB - PW) * PLD + 1];
   __shared__ double Ds[PW * PLD];
   const int32_t k = blks[blockIdx.x];
   const int tid = threadIdx.x;
-  for (int x = tid; x < NB * SR; x += 256) {
-    const int i = x / SR, c = x % SR;
+  for (int x = tid; x < NB * R; x += 256) {
+    const int i = x / R, c = x % R;
     r[x] = c < nrhs ? y[(int64_t)c * np + (int64_t)k * NB + i] : 0.0;
   }
   const double* L = S + (int64_t)k * NB * NB;
@@ -1540,48 +1551,49 @@ __global__ __launch_bounds__(256) void k_sbwd_diag(const int32_t* __restrict__ b
     Ds[row * PLD + 4 * sub + 3] = pd.w;
     __syncthreads();
     if (J > 0) fetch(J - 1);
-    double acc[SR];
+    double acc[R];
 #pragma unroll
-    for (int c = 0; c < SR; ++c) acc[c] = 0.0;
+    for (int c = 0; c < R; ++c) acc[c] = 0.0;
 #pragma unroll 4
     for (int p = sub; p < h; p += 8) {
       const double l = Lc[p * PLD + row];
 #pragma unroll
-      for (int c = 0; c < SR; ++c) acc[c] = fma(l, r[(p0 + p) * SR + c], acc[c]);
+      for (int c = 0; c < R; ++c) acc[c] = fma(l, r[(p0 + p) * R + c], acc[c]);
     }
 #pragma unroll
-    for (int c = 0; c < SR; ++c) part[(row * 8 + sub) * SR + c] = acc[c];
+    for (int c = 0; c < R; ++c) part[(row * 8 + sub) * R + c] = acc[c];
     __syncthreads();
-    {
-      const int i = tid / SR, c = tid % SR;
-      double v = r[(J * PW + i) * SR + c];
+    if (tid < PW * R) {
+      const int i = tid / R, c = tid % R;
+      double v = r[(J * PW + i) * R + c];
 #pragma unroll
-      for (int z = 0; z < 8; ++z) v -= part[(i * 8 + z) * SR + c];
-      s[i * SR + c] = v;
+      for (int z = 0; z < 8; ++z) v -= part[(i * 8 + z) * R + c];
+      s[i * R + c] = v;
     }
     __syncthreads();
-    {
-      const int i = tid / SR, c = tid % SR;
+    if (tid < PW * R) {
+      const int i = tid / R, c = tid % R;
       double u = 0.0;
 #pragma unroll 8
-      for (int q = 0; q < PW; ++q) u = fma(Ds[q * PLD + i], s[q * SR + c], u);
-      r[(J * PW + i) * SR + c] = u;
+      for (int q = 0; q < PW; ++q) u = fma(Ds[q * PLD + i], s[q * R + c], u);
+      r[(J * PW + i) * R + c] = u;
     }
     __syncthreads();
   }
-  for (int x = tid; x < NB * SR; x += 256) {
-    const int ii = x / SR, cc = x % SR;
+  for (int x = tid; x < NB * R; x += 256) {
+    const int ii = x / R, cc = x % R;
     if (cc < nrhs) y[(int64_t)cc * np + (int64_t)k * NB + ii] = r[x];
   }
 }
 
 // backward panel item (k, j0, tiles [t0, t1)): columns j0 .. j0 + 63 of
-// y_k -= sum over the tiles (m, k) of L_mk^T x_m.  Per tile the entries of
-// x_m at its active rows are gathered into LDS; a thread owns a column and a
-// quarter of the rows; the quarters are summed in LDS in a fixed order.
+// y_k -= sum over the tiles (m, k) of L_mk^T x_m.  A thread owns two adjacent
+// columns and every eighth stored row; its rows of a tile are read into
+// registers before the entries of x_m at the tile's active rows are gathered
+// into LDS.  The eight row shares are summed in LDS in a fixed order.
 constexpr int SBC = 64;  // columns of a backward panel work item
 
-template <int NB>
+template <int NB, int R>
 __global__ __launch_bounds__(256) void k_sbwd_panel(const int32_t* __restrict__ items,
                                                     const int32_t* __restrict__ tlist,
                                                     const TileD* __restrict__ tiles,
@@ -1589,40 +1601,58 @@ __global__ __launch_bounds__(256) void k_sbwd_panel(const int32_t* __restrict__ 
                                                     const double* __restrict__ S,
                                                     double* __restrict__ y, int64_t np, int32_t nrhs) {
   constexpr int CW = NB < SBC ? NB : SBC;  // columns per item
-  constexpr int SH = 256 / CW;             // row shares per column
-  __shared__ double xg[NB * SR];  // xg[q * SR + c]: x_m at the tile's stored row q
-  __shared__ double red[SH * CW * SR];
+  constexpr int CP = CW / 2;               // column pairs
+  constexpr int SH = 256 / CP;             // row shares
+  constexpr int NQ = NB / SH;              // stored rows per thread at most
+  __shared__ double xg[NB * R];  // xg[q * R + c]: x_m at the tile's stored row q
+  __shared__ double red[SH * CW * R];
   const int32_t k = items[4 * blockIdx.x], j0 = items[4 * blockIdx.x + 1];
   const int32_t t0 = items[4 * blockIdx.x + 2], t1 = items[4 * blockIdx.x + 3];
   const int tid = threadIdx.x;
-  const int col = tid % CW, sh = tid / CW;
-  double acc[SR];
+  const int cp = tid % CP, sh = tid / CP;
+  double acc[2][R];
 #pragma unroll
-  for (int c = 0; c < SR; ++c) acc[c] = 0.0;
+  for (int e = 0; e < 2; ++e)
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc[e][c] = 0.0;
   for (int32_t z = t0; z < t1; ++z) {
     const TileD tl = tiles[tlist[z]];
+    const double* P = S + tl.off + j0 + 2 * cp;
+    double2 lv[NQ];
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+      const int q = sh + SH * u;
+      lv[u] = q < tl.cnt ? *reinterpret_cast<const double2*>(P + (int64_t)q * NB) : make_double2(0.0, 0.0);
+    }
     __syncthreads();  // xg is free
-    for (int x = tid; x < tl.cnt * SR; x += 256) {
-      const int q = x / SR, c = x % SR;
+    for (int x = tid; x < tl.cnt * R; x += 256) {
+      const int q = x / R, c = x % R;
       xg[x] = c < nrhs ? y[(int64_t)c * np + (int64_t)tl.m * NB + rows[tl.roff + q]] : 0.0;
     }
     __syncthreads();
-    const double* P = S + tl.off + j0 + col;
-#pragma unroll 8
-    for (int q = sh; q < tl.cnt; q += SH) {
-      const double l = P[(int64_t)q * NB];
 #pragma unroll
-      for (int c = 0; c < SR; ++c) acc[c] = fma(l, xg[q * SR + c], acc[c]);
+    for (int u = 0; u < NQ; ++u) {
+      const int q = sh + SH * u;
+      if (q < tl.cnt) {
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+          const double xv = xg[q * R + c];
+          acc[0][c] = fma(lv[u].x, xv, acc[0][c]);
+          acc[1][c] = fma(lv[u].y, xv, acc[1][c]);
+        }
+      }
     }
   }
 #pragma unroll
-  for (int c = 0; c < SR; ++c) red[(sh * CW + col) * SR + c] = acc[c];
+  for (int e = 0; e < 2; ++e)
+#pragma unroll
+    for (int c = 0; c < R; ++c) red[(sh * CW + 2 * cp + e) * R + c] = acc[e][c];
   __syncthreads();
   double* yk = y + (int64_t)k * NB + j0;
-  for (int x = tid; x < CW * SR; x += 256) {
+  for (int x = tid; x < CW * R; x += 256) {
     double v = 0.0;
-    for (int z = 0; z < SH; ++z) v += red[z * CW * SR + x];
-    if (x % SR < nrhs) yk[(int64_t)(x % SR) * np + x / SR] -= v;
+    for (int z = 0; z < SH; ++z) v += red[z * CW * R + x];
+    if (x % R < nrhs) yk[(int64_t)(x % R) * np + x / R] -= v;
   }
 }
 

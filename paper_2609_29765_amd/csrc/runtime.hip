@@ -362,31 +362,37 @@ int build_graph(stc_handle* h, int32_t members, hipGraphExec_t* ex) {
 
 // the forward and backward sweeps over right-hand sides [g0, g0 + nr) of
 // d_y, level by level: diagonal blocks, then the panel tiles they unlock
-template <int NB>
-void launch_sweeps_nb(stc_handle* h, int32_t nr, int32_t g0, hipStream_t st) {
+template <int NB, int R>
+void launch_sweeps_r(stc_handle* h, int32_t nr, int32_t g0, hipStream_t st) {
   const Plan& p = h->plan;
   const int64_t np = padded_n(h);
   double* y = h->d_y + (int64_t)g0 * np;
   for (size_t L = 0; L + 1 < p.fwd_level_ptr.size(); ++L) {
     const int32_t a = p.fwd_level_ptr[L], b = p.fwd_level_ptr[L + 1];
     if (b > a)
-      hipLaunchKernelGGL((k_sfwd_diag<NB>), dim3(b - a), dim3(256), 0, st, h->d_fwd_blk + a, h->d_store,
+      hipLaunchKernelGGL((k_sfwd_diag<NB, R>), dim3(b - a), dim3(256), 0, st, h->d_fwd_blk + a, h->d_store,
                          h->d_dinv, y, np, nr);
     const int32_t c = h->sfwd_ptr[L], d = h->sfwd_ptr[L + 1];
     if (d > c)
-      hipLaunchKernelGGL((k_sfwd_panel<NB>), dim3(d - c), dim3(256), 0, st, h->d_sfwd_items + 4 * (int64_t)c,
+      hipLaunchKernelGGL((k_sfwd_panel<NB, R>), dim3(d - c), dim3(256), 0, st, h->d_sfwd_items + 4 * (int64_t)c,
                          h->d_sfwd_tl, h->d_tiles, h->d_maps, h->d_store, y, np, nr);
   }
   for (size_t L = 0; L + 1 < p.bwd_level_ptr.size(); ++L) {
     const int32_t a = p.bwd_level_ptr[L], b = p.bwd_level_ptr[L + 1];
     if (b > a)
-      hipLaunchKernelGGL((k_sbwd_diag<NB>), dim3(b - a), dim3(256), 0, st, h->d_bwd_blk + a, h->d_store,
+      hipLaunchKernelGGL((k_sbwd_diag<NB, R>), dim3(b - a), dim3(256), 0, st, h->d_bwd_blk + a, h->d_store,
                          h->d_dinv, y, np, nr);
     const int32_t c = h->sbwd_ptr[L], d = h->sbwd_ptr[L + 1];
     if (d > c)
-      hipLaunchKernelGGL((k_sbwd_panel<NB>), dim3(d - c), dim3(256), 0, st, h->d_sbwd_items + 4 * (int64_t)c,
+      hipLaunchKernelGGL((k_sbwd_panel<NB, R>), dim3(d - c), dim3(256), 0, st, h->d_sbwd_items + 4 * (int64_t)c,
                          h->d_sbwd_tl, h->d_tiles, h->d_rows, h->d_store, y, np, nr);
   }
+}
+
+template <int NB>
+void launch_sweeps_nb(stc_handle* h, int32_t nr, int32_t g0, hipStream_t st) {
+  if (nr == 1) launch_sweeps_r<NB, 1>(h, nr, g0, st);
+  else launch_sweeps_r<NB, SR>(h, nr, g0, st);
 }
 
 int get_solve_graph(stc_handle* h, int32_t nr, int32_t g0, hipGraphExec_t* out) {

@@ -253,7 +253,9 @@ class Analysis:
         _need_cuda(b)
         self._ws_device()
         one = b.dim() == 1
-        B = b.reshape(self.n, -1)
+        if not (b.shape[0] == self.n and b.dim() in (1, 2)):
+            raise ValueError(f"b must have shape [{self.n}] or [{self.n}, nrhs], got {tuple(b.shape)}")
+        B = b.reshape(self.n, 1) if one else b
         nrhs = B.shape[1]
         X = B.t().contiguous()  # column-major n x nrhs
         _check(lib().stc_solve(self._h, _dptr(X), int(nrhs), _stream_ptr()))

@@ -172,3 +172,36 @@ def test_graph_replays_agree():
 def test_differentiable_arrowhead_full_size():
     w = W.differentiable_arrowhead(20, 25, 8, 0)
     run_case(w, "nd", 64, "auto")
+
+
+@pytest.mark.parametrize("nb,mode,nrhs", [(32, "semisparse", 2), (64, "semisparse", 8), (64, "dense", 11),
+                                          (128, "semisparse", 17), (256, "dense", 64)])
+def test_solve_many_right_hand_sides(nb, mode, nrhs):
+    # groups of 8 columns with a ragged last group, the 64-column maximum,
+    # ragged last tile; every column against the oracle's solve
+    rng = np.random.default_rng(700 + nrhs)
+    w = W.random_spd(nb * 3 + 19, 0.05, nrhs, dense_rows=2)
+    o = O.Analysis(w.n, w.colptr, w.rowind, "nd", nb=nb, mode=mode)
+    Lo, info_o = o.factor(w.values)
+    assert info_o == 0
+    a = S.Analysis(w.n, w.colptr, w.rowind, nb=nb, mode=mode, ordering="nd").bind()
+    print(f"[gpu] solve n={w.n} nb={nb} mode={a.mode} nrhs={nrhs}", flush=True)
+    a.factorize(dev(w.values))
+    assert a.info() == 0
+    B = rng.standard_normal((w.n, nrhs))
+    X = a.solve(dev(B)).cpu().numpy()
+    Xo = o.solve(Lo, B)
+    for c in range(nrhs):
+        assert np.max(np.abs(X[:, c] - Xo[:, c])) <= 1e-10 * np.max(np.abs(Xo[:, c])), c
+    # a second call with fewer columns reuses the handle's graphs and scratch
+    x1 = a.solve(dev(B[:, 0].copy())).cpu().numpy()
+    assert np.array_equal(x1, X[:, 0])
+
+
+def test_solve_rejects_bad_column_counts():
+    w = W.random_spd(100, 0.05, 3)
+    a = S.Analysis(w.n, w.colptr, w.rowind, nb=32, ordering="nd").bind()
+    a.factorize(dev(w.values))
+    for nrhs in (65, 0):
+        with pytest.raises(S.STCError):
+            a.solve(torch.zeros(w.n, nrhs, dtype=torch.float64, device="cuda"))
