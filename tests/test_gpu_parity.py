@@ -205,3 +205,27 @@ def test_solve_rejects_bad_column_counts():
     for nrhs in (65, 0):
         with pytest.raises(S.STCError):
             a.solve(torch.zeros(w.n, nrhs, dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.parametrize("n,nb,mode", [(1, 32, "auto"), (2, 32, "dense"), (20, 64, "semisparse"),
+                                       (128, 128, "dense"), (129, 128, "semisparse"), (256, 256, "dense")])
+def test_degenerate_sizes(n, nb, mode):
+    # one scalar, fewer rows than a tile, exactly one tile, one row past a tile
+    w = W.random_spd(n, 0.3, n)
+    run_case(w, "natural" if n < 3 else "nd", nb, mode)
+
+
+def test_diagonal_solve_and_batch_of_one():
+    # no off-diagonal tile: the sweeps hold diagonal kernels only
+    n = 300
+    d = np.random.default_rng(4).uniform(0.5, 2.0, n)
+    colptr = np.arange(n + 1, dtype=np.int64)
+    rowind = np.arange(n, dtype=np.int32)
+    a = S.Analysis(n, colptr, rowind, nb=64, ordering="natural").bind(batch=2)
+    a.factorize(dev(d))
+    b = np.random.default_rng(5).standard_normal((n, 3))
+    x = a.solve(dev(b)).cpu().numpy()
+    assert np.max(np.abs(x - b / d[:, None])) <= 1e-14 * np.max(np.abs(b / d[:, None]))
+    ld, info = a.factorize_batched(dev(d[None, :].copy()))
+    assert int(info.cpu()[0]) == 0
+    assert abs(float(ld.cpu()[0]) - np.log(d).sum()) <= 1e-12 * abs(np.log(d).sum())
