@@ -1,7 +1,8 @@
 """GPU parity: the HIP path (libstc.so through its C ABI) against the oracle on
 the same seeded inputs.
 
-Tolerances (written here, derived in the design doc): factor entries per column
+Tolerances (both sides in FP64, summing in different orders, so they agree to
+rounding amplified by each column's conditioning): factor entries per column
 ||dL_:j||_inf <= 1e-10 ||L_:j||_inf on the identical pattern; logdet
 |d| <= 1e-12 * max(|ld|, sum |2 log L_ii|); solve relative 1e-10 of the
 oracle's solution; pivot failures bit-exact (same first failing column).
