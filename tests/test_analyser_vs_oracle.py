@@ -98,3 +98,13 @@ def test_abi_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(lib, name), name
     assert declared == set(S.EXPORTS)
+
+
+def test_empty_and_malformed_inputs_rejected():
+    # n = 0 and n < 0 are argument errors; a column with no entry (no
+    # diagonal) and an upper-triangle entry are pattern errors
+    for n, cp, ri, code in [(0, [0], [], -1), (-1, [0], [], -1), (1, [0, 0], [], -2),
+                            (2, [0, 1, 3], [0, 1, 0], -2)]:
+        with pytest.raises(S.STCError) as e:
+            S.Analysis(n, np.array(cp, np.int64), np.array(ri, np.int32))
+        assert e.value.code == code
