@@ -82,7 +82,7 @@ constexpr int UKT = 16;  // K chunk staged in LDS
 constexpr int USTAGE = 2 * UB * DLD;  // A and B rows of one K chunk
 constexpr int UPD_LDS = 2 * USTAGE;   // two stages
 
-template <int NB>
+template <int NB, bool CULL>
 __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict__ items,
                                            const UpdTaskD* __restrict__ tasks,
                                            const ContribD* __restrict__ contribs,
@@ -115,6 +115,7 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
   const int srow = 16 * wave + (lane >> 3);
   const double* pa[2];
   const double* pb[2];
+  uint32_t cmask = 0xF, mk0 = 0xF, mk1 = 0xF;  // group masks: contribution being issued, stages 0 and 1
   auto open_contrib = [&](int32_t ci) {
     const ContribD c = contribs[ci];
 #pragma unroll
@@ -128,8 +129,21 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
       pa[j] = (sa >= 0 ? S + c.a_off + (int64_t)sa * NB : zrow) + p2;
       pb[j] = (sb >= 0 ? S + c.b_off + (int64_t)sb * NB : zrow) + p2;
     }
+    // which 16-row groups of this wave's A rows and B rows the contribution
+    // fills (lanes 0..31, one row each); products with an empty group are skipped
+    if constexpr (CULL) {
+      const int32_t r = r0 + wr + lane, cc = c0 + wc + lane;
+      bool ha = false, hb = false;
+      if (lane < 32 && r < u.c_rows) ha = c.rowmap < 0 ? r < c.a_rows : maps[c.rowmap + r] >= 0;
+      if (lane < 32 && cc < ncols) hb = c.colmap < 0 ? cc < c.b_rows : maps[c.colmap + cc] >= 0;
+      const uint64_t ba = __ballot(ha), bb = __ballot(hb);
+      cmask = ((ba & 0xFFFFull) ? 1u : 0u) | ((ba & 0xFFFF0000ull) ? 2u : 0u) | ((bb & 0xFFFFull) ? 4u : 0u) |
+              ((bb & 0xFFFF0000ull) ? 8u : 0u);
+    }
   };
   auto issue = [&](int32_t st, int32_t kn) {
+    if (st & 1) mk1 = cmask;
+    else mk0 = cmask;
     double* As = smem + (st & 1) * USTAGE;
     double* Bs = As + UB * DLD;
 #pragma unroll
@@ -155,6 +169,7 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
     }
     const double* As = smem + (st & 1) * USTAGE;
     const double* Bs = As + UB * DLD;
+    const uint32_t m = CULL ? ((st & 1) ? mk1 : mk0) : 0xFu;
 #pragma unroll
     for (int gq = 0; gq < 2; ++gq) {
       const int slot = (4 * gq + (lane >> 4)) ^ fkey;
@@ -169,12 +184,14 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].x, bf[b].x, acc[a][b], 0, 0, 0);
+          if ((m >> a) & (m >> (2 + b)) & 1u)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].x, bf[b].x, acc[a][b], 0, 0, 0);
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].y, bf[b].y, acc[a][b], 0, 0, 0);
+          if ((m >> a) & (m >> (2 + b)) & 1u)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].y, bf[b].y, acc[a][b], 0, 0, 0);
     }
   }
   // epilogue: lane holds D[i][j] with j = lane % 16, i = lane / 16 + 4 e;
@@ -246,7 +263,7 @@ constexpr int UKT2 = 16;
 constexpr int DSTAGE = 2 * UB2 * DLD;      // A and B rows of one K chunk
 constexpr int UPD2_LDS = 2 * DSTAGE;       // two stages
 
-template <int NB>
+template <int NB, bool CULL>
 __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __restrict__ items,
                                                const UpdTaskD* __restrict__ tasks,
                                                const ContribD* __restrict__ contribs,
@@ -283,6 +300,7 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
   const int srow = 32 * wave + (lane >> 3);
   const double* pa[4];
   const double* pb[4];
+  uint32_t cmask = 0xFF, mk0 = 0xFF, mk1 = 0xFF;  // group masks: contribution being issued, stages 0 and 1
   auto open_contrib = [&](int32_t ci) {
     const ContribD c = contribs[ci];
 #pragma unroll
@@ -296,8 +314,25 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
       pa[j] = (sa >= 0 ? S + c.a_off + (int64_t)sa * NB : zrow) + p2;
       pb[j] = (sb >= 0 ? S + c.b_off + (int64_t)sb * NB : zrow) + p2;
     }
+    // which of this wave's 16-row groups of A (its output rows) and of B
+    // (its output columns) the contribution fills: products of two groups
+    // of which one is all absent rows are zero and are skipped
+    if constexpr (CULL) {
+      const int32_t r = r0 + wr + lane, cc = c0 + wc + lane;
+      bool ha = false, hb = false;
+      if (r < u.c_rows) ha = c.rowmap < 0 ? r < c.a_rows : maps[c.rowmap + r] >= 0;
+      if (cc < ncols) hb = c.colmap < 0 ? cc < c.b_rows : maps[c.colmap + cc] >= 0;
+      const uint64_t ba = __ballot(ha), bb = __ballot(hb);
+      uint32_t m = 0;
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        m |= (((ba >> (16 * g)) & 0xFFFFull) ? 1u << g : 0u) | (((bb >> (16 * g)) & 0xFFFFull) ? 16u << g : 0u);
+      cmask = m;
+    }
   };
   auto issue = [&](int32_t st, int32_t kn) {
+    if (st & 1) mk1 = cmask;
+    else mk0 = cmask;
     double* As = smem + (st & 1) * DSTAGE;
     double* Bs = As + UB2 * DLD;
 #pragma unroll
@@ -325,6 +360,7 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
     }
     const double* As = smem + (st & 1) * DSTAGE;
     const double* Bs = As + UB2 * DLD;
+    const uint32_t m = CULL ? ((st & 1) ? mk1 : mk0) : 0xFFu;
 #pragma unroll
     for (int gq = 0; gq < 2; ++gq) {
       const int slot = (4 * gq + (lane >> 4)) ^ fkey;
@@ -339,12 +375,14 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].x, bf[b].x, acc[a][b], 0, 0, 0);
+          if ((m >> a) & (m >> (4 + b)) & 1u)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].x, bf[b].x, acc[a][b], 0, 0, 0);
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].y, bf[b].y, acc[a][b], 0, 0, 0);
+          if ((m >> a) & (m >> (4 + b)) & 1u)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].y, bf[b].y, acc[a][b], 0, 0, 0);
     }
   }
   // epilogue: lane holds D[i][j] with j = lane % 16, i = lane / 16 + 4 e.
@@ -1008,7 +1046,9 @@ __global__ __launch_bounds__(256) void k_potrf(LevelArgs a) {
 
 // HAS_G compiles the 128-block path in or out, so a level without it keeps
 // the smaller register footprint of the 64-block path
-template <int NB, bool HAS_G>
+// CULL: skip the products of 16-row operand groups that a contribution
+// leaves empty (active-column plans; dense plans never have one)
+template <int NB, bool HAS_G, bool CULL>
 __global__ __launch_bounds__(256, HAS_G ? 2 : 3) void k_upd(LevelArgs a) {
   extern __shared__ double smem[];
   const int32_t member = blockIdx.y;
@@ -1016,11 +1056,11 @@ __global__ __launch_bounds__(256, HAS_G ? 2 : 3) void k_upd(LevelArgs a) {
   double* parts = a.parts + (int64_t)member * a.pstride;
   int32_t b = blockIdx.x;
   if (HAS_G && b < a.nbig) {
-    if constexpr (NB >= UB2 && HAS_G) dev_update_big<NB>(b, a.big, a.utasks, a.contribs, a.maps, S, parts, a.zrow, smem);
+    if constexpr (NB >= UB2 && HAS_G) dev_update_big<NB, CULL>(b, a.big, a.utasks, a.contribs, a.maps, S, parts, a.zrow, smem);
     return;
   }
   b -= a.nbig;
-  dev_update<NB>(b, a.upd, a.utasks, a.contribs, a.maps, S, parts, a.zrow, smem);
+  dev_update<NB, CULL>(b, a.upd, a.utasks, a.contribs, a.maps, S, parts, a.zrow, smem);
 }
 
 template <int NB>

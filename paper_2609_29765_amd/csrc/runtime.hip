@@ -201,6 +201,10 @@ struct Prof {
   }
 };
 
+// active-column plans skip the MFMA products of empty 16-row groups; dense
+// plans have none and keep the unconditional loop
+bool uses_cull(const stc_handle* h) { return h->sym.mode != kModeDense; }
+
 // measurement kinds: the value load and the level kernels
 enum { kKindLoad = 0, kKindPotrf = 1, kKindUpdBig = 2, kKindUpd = 3, kKindTrsm = 4, kKinds = 5 };
 
@@ -245,14 +249,19 @@ LevelArgs level_args(const stc_handle* h, size_t li, int kind) {
 
 // kernel, grid and dynamic LDS of a level's kernel with arguments a
 template <int NB>
-void level_kernel(const LevelArgs& a, int kind, int32_t members, const void** fn, dim3* grid,
+void level_kernel(const LevelArgs& a, int kind, int32_t members, bool cull, const void** fn, dim3* grid,
                   size_t* lds) {
   if (kind == 0) {
     *fn = reinterpret_cast<const void*>(&k_potrf<NB>);
     *grid = dim3(a.np, members);
     *lds = sizeof(double) * k_potrf_lds<NB>();
   } else if (kind == 1 || kind == 3) {
-    *fn = a.nbig ? reinterpret_cast<const void*>(&k_upd<NB, true>) : reinterpret_cast<const void*>(&k_upd<NB, false>);
+    if (cull)
+      *fn = a.nbig ? reinterpret_cast<const void*>(&k_upd<NB, true, true>)
+                   : reinterpret_cast<const void*>(&k_upd<NB, false, true>);
+    else
+      *fn = a.nbig ? reinterpret_cast<const void*>(&k_upd<NB, true, false>)
+                   : reinterpret_cast<const void*>(&k_upd<NB, false, false>);
     *grid = dim3(a.nbig + a.nu, members);
     *lds = sizeof(double) * std::max(a.nbig ? UPD2_LDS : 0, a.nu ? UPD_LDS : 0);
   } else {
@@ -283,7 +292,7 @@ int launch_levels_nb(stc_handle* h, int32_t members, hipStream_t st, Prof* prof)
       const void* fn;
       dim3 grid;
       size_t lds;
-      level_kernel<NB>(a, kind, members, &fn, &grid, &lds);
+      level_kernel<NB>(a, kind, members, uses_cull(h), &fn, &grid, &lds);
       hipEvent_t ev = nullptr;
       if (prof && prof->begin(st, &ev)) return STC_ERR_HIP;
       void* args[] = {&a};
@@ -317,7 +326,7 @@ int build_graph_nb(stc_handle* h, int32_t members, hipGraphExec_t* ex) {
     const void* fn;
     dim3 grid;
     size_t lds;
-    level_kernel<NB>(args[x], dag[x].kind, members, &fn, &grid, &lds);
+    level_kernel<NB>(args[x], dag[x].kind, members, uses_cull(h), &fn, &grid, &lds);
     kargs[x] = &args[x];
     hipKernelNodeParams kp{};
     kp.blockDim = dim3(256);
