@@ -186,8 +186,9 @@ def headline(args):
     avg_ms = ms_d / cnt_d
     flops_per_launch = fl_d / cnt_d
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
-    symbol = {"k_potrf": f"k_potrf<{a.nb}>", "k_upd<G>": f"k_upd<{a.nb}, true>",
-              "k_upd": f"k_upd<{a.nb}, false>", "k_trsm": f"k_trsm<{a.nb}>"}[dom]
+    cull = "false" if a.mode == "dense" else "true"  # active-column plans run the group-skipping update kernels
+    symbol = {"k_potrf": f"k_potrf<{a.nb}>", "k_upd<G>": f"k_upd<{a.nb}, true, {cull}>",
+              "k_upd": f"k_upd<{a.nb}, false, {cull}>", "k_trsm": f"k_trsm<{a.nb}>"}[dom]
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "traffic_dense12288_nb256.json")
     if os.path.exists(tfile):
