@@ -108,3 +108,17 @@ def test_empty_and_malformed_inputs_rejected():
         with pytest.raises(S.STCError) as e:
             S.Analysis(n, np.array(cp, np.int64), np.array(ri, np.int32))
         assert e.value.code == code
+
+
+def test_no_device_fails_loudly():
+    # the product path has no CPU fallback: without a HIP device binding and
+    # factorizing raise instead of computing anything on the host
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a HIP device is visible")
+    w = W.random_spd(50, 0.1, 0)
+    a = S.Analysis(w.n, w.colptr, w.rowind, nb=32)
+    with pytest.raises(RuntimeError, match="HIP device"):
+        a.bind()
+    with pytest.raises(RuntimeError, match="HIP device"):
+        a.factorize(torch.from_numpy(w.values))
