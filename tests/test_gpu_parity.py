@@ -230,3 +230,15 @@ def test_diagonal_solve_and_batch_of_one():
     ld, info = a.factorize_batched(dev(d[None, :].copy()))
     assert int(info.cpu()[0]) == 0
     assert abs(float(ld.cpu()[0]) - np.log(d).sum()) <= 1e-12 * abs(np.log(d).sum())
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_large_tiles_semisparse(seed):
+    # tiles of 128 and 256 on random sparse patterns: the update kernels skip
+    # 16-row groups a contribution leaves empty, so partly filled groups in
+    # many shapes must still give the oracle's factor
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(300, 900))
+    w = W.random_spd(n, float(rng.choice([0.005, 0.02, 0.06])), 40 + seed, dense_rows=int(rng.integers(0, 5)))
+    nb = [128, 256][seed % 2]
+    run_case(w, ["nd", "rcm"][seed // 2 % 2], nb, "semisparse")
