@@ -134,11 +134,12 @@ int stc_logdet(stc_handle* h, double* d_out, void* stream);
    factor stays on the device and is reused): d_b (device) double[n * nrhs],
    column-major, original numbering, 1 <= nrhs <= 64.  Forward and backward
    block sweeps over the factor's tiles, level by level, for up to 8 columns
-   at a time (the factor is read once per group): a level's diagonal blocks
-   are solved, then the products of the tiles they unlock are subtracted from
-   the blocks those tiles feed, each fed block by one work item in a fixed
-   tile order, so results are reproducible bit for bit.  The sweeps for each
-   group are captured in a graph on first use. */
+   at a time (the factor is read once per group): the products of the tiles
+   a level's solved blocks unlock are subtracted from the blocks those tiles
+   feed, each fed block (or chunk of it) by one work item in a fixed tile
+   order, so results are reproducible bit for bit; the work item of a block
+   of the next level then solves its diagonal block in the same launch.  The
+   sweeps for each group are captured in a graph on first use. */
 int stc_solve(stc_handle* h, double* d_b, int32_t nrhs, void* stream);
 
 /* Reverse mode of logdet through the last single factorization: given the
@@ -164,7 +165,8 @@ int stc_info(stc_handle* h, int32_t* info);
    sizes (host) int64[16]: n, nnz(tril A), nnz(L), nb, N_T, non-empty
    off-diagonal tiles, total stored active rows, tasks, mode (1 dense,
    2 semisparse), route, dense rows set aside, ordering used, active tiles
-   (off-diagonal + N_T), tile-store doubles per value set, levels, reserved. */
+   (off-diagonal + N_T), tile-store doubles per value set, levels, kernel
+   launches of the forward and backward sweeps of one solve group. */
 int stc_get_sizes(const stc_handle* h, int64_t* sizes);
 /* features (host) double[3]: fill ratio phi, mean occupancy rho, skew sigma */
 int stc_get_features(const stc_handle* h, double* features);

@@ -1362,128 +1362,39 @@ __global__ void k_perm_out(const double* __restrict__ y, const int32_t* __restri
 
 // Both sweeps run level by level over the blocks of the tile grid and read L
 // once per group of up to SR right-hand sides (rhs-major in y, stride np).
-// After a level's diagonal blocks are solved, a panel kernel subtracts the
-// products of the tiles they unlock straight from the right-hand sides of
-// the blocks those tiles feed (forward: b_m -= L_mk y_k; backward:
-// y_k -= L_mk^T x_m).  One work item owns one fed block (a 64-row chunk of it,
-// forward; a 64-column chunk, backward) and runs through its tiles of the level in a fixed order, so there
-// are no races and no atomics and results are reproducible bit for bit.  The
-// diagonal blocks are solved 32 rows at a time with the inverses of the
-// 32 x 32 diagonal blocks of L that the factorization keeps (dinv).  The
-// kernels are compiled for R = 1 (a single right-hand side) and R = SR (a
-// group of 2 .. 8, the unused columns zero); every column is computed by the
-// same operations in the same order whatever R, so its result does not
-// depend on how many columns share the pass.
+// Launch q of a sweep holds two kinds of work items.  A step item owns a
+// block of level q: it subtracts the products of the tiles that feed the
+// block from blocks of level q - 1 (forward: b_m -= L_mk y_k; backward:
+// y_k -= L_mk^T x_m), then solves the block's diagonal block with its
+// right-hand sides held in LDS throughout.  A panel item subtracts the
+// level q - 1 products for a 64-row (forward) or 64-column (backward) chunk
+// of a block of a later level, in place in y.  A block of level q depends on
+// at least one block of level q - 1 and all its other contributions come
+// from earlier launches, so one launch per level suffices.  Every item runs
+// through its tiles in a fixed order: no races, no atomics, and results are
+// reproducible bit for bit.  Diagonal blocks are solved 32 rows at a time
+// with the inverses of the 32 x 32 diagonal blocks of L that the
+// factorization keeps (dinv).  The kernels are compiled for R = 1 (a single
+// right-hand side) and R = SR (a group of 2 .. 8, the unused columns zero);
+// every column is computed by the same operations in the same order whatever
+// R, so its result does not depend on how many columns share the pass.
 constexpr int SR = 8;      // right-hand sides per sweep
-constexpr int SCH = 64;    // block rows of a forward panel work item
+constexpr int SCH = 64;    // block rows of a forward panel chunk
+constexpr int SBC = 64;    // columns of a backward panel chunk
 
-// y_k <- L_kk^-1 y_k: per 32-row block J, the block row of L_kk left of the
-// diagonal block and the block's inverse are staged in LDS (coalesced), then
-// s = r_J - L_(J,<J) y_(<J) with the K range split over 8 threads per row
-// (each keeping all right-hand sides) and the parts summed in a fixed order,
-// then y_J = D_J s
-template <int NB, int R>
-__global__ __launch_bounds__(256) void k_sfwd_diag(const int32_t* __restrict__ blks,
-                                                   const double* __restrict__ S,
-                                                   const double* __restrict__ dinv,
-                                                   double* __restrict__ y, int64_t np, int32_t nrhs) {
-  constexpr int LW = NB - PW + 1;
-  __shared__ double r[NB * R];      // r[i * R + c]
-  __shared__ double part[PW * 8 * R];
-  __shared__ double s[PW * R];
-  __shared__ double Ls[PW * LW];
-  __shared__ double Ds[PW * PLD];
-  const int32_t k = blks[blockIdx.x];
-  const int tid = threadIdx.x;
-  for (int x = tid; x < NB * R; x += 256) {
-    const int i = x / R, c = x % R;
-    r[x] = c < nrhs ? y[(int64_t)c * np + (int64_t)k * NB + i] : 0.0;
-  }
-  const double* L = S + (int64_t)k * NB * NB;
-  const double* D = dinv + (int64_t)k * NB * PW;
-  const int row = tid >> 3, sub = tid & 7;  // staging and K-split layout: 32 rows x 8
-  // step J's block row of L and inverse are read into registers during step
-  // J - 1 and written to LDS when step J begins
-  constexpr int NPF = NB > PW ? (NB - PW) / 16 : 1;
-  double2 pf[NPF];
-  double4 pd;
-  auto fetch = [&](int J) {
-    const int w = J * PW;
-    const double* src = L + (int64_t)(w + row) * NB;
-#pragma unroll
-    for (int q = 0; q < NPF; ++q)
-      if (2 * sub + 16 * q < w) pf[q] = *reinterpret_cast<const double2*>(src + 2 * sub + 16 * q);
-    pd = *reinterpret_cast<const double4*>(D + J * PW * PW + row * PW + 4 * sub);
-  };
-  fetch(0);
-  for (int J = 0; J < NB / PW; ++J) {
-    const int w = J * PW;
-#pragma unroll
-    for (int q = 0; q < NPF; ++q) {
-      const int col = 2 * sub + 16 * q;
-      if (col < w) {
-        Ls[row * LW + col] = pf[q].x;
-        Ls[row * LW + col + 1] = pf[q].y;
-      }
-    }
-    Ds[row * PLD + 4 * sub] = pd.x;
-    Ds[row * PLD + 4 * sub + 1] = pd.y;
-    Ds[row * PLD + 4 * sub + 2] = pd.z;
-    Ds[row * PLD + 4 * sub + 3] = pd.w;
-    __syncthreads();
-    if (J + 1 < NB / PW) fetch(J + 1);
-    double acc[R];
-#pragma unroll
-    for (int c = 0; c < R; ++c) acc[c] = 0.0;
-#pragma unroll 4
-    for (int p = sub; p < w; p += 8) {
-      const double l = Ls[row * LW + p];
-#pragma unroll
-      for (int c = 0; c < R; ++c) acc[c] = fma(l, r[p * R + c], acc[c]);
-    }
-#pragma unroll
-    for (int c = 0; c < R; ++c) part[(row * 8 + sub) * R + c] = acc[c];
-    __syncthreads();
-    if (tid < PW * R) {
-      const int i = tid / R, c = tid % R;
-      double v = r[(w + i) * R + c];
-#pragma unroll
-      for (int z = 0; z < 8; ++z) v -= part[(i * 8 + z) * R + c];
-      s[i * R + c] = v;
-    }
-    __syncthreads();
-    if (tid < PW * R) {
-      const int i = tid / R, c = tid % R;
-      double u = 0.0;
-#pragma unroll 8
-      for (int q = 0; q < PW; ++q) u = fma(Ds[i * PLD + q], s[q * R + c], u);
-      r[(w + i) * R + c] = u;
-    }
-    __syncthreads();
-  }
-  for (int x = tid; x < NB * R; x += 256) {
-    const int ii = x / R, cc = x % R;
-    if (cc < nrhs) y[(int64_t)cc * np + (int64_t)k * NB + ii] = r[x];
-  }
-}
-
-// forward panel item (m, i0, tiles [t0, t1)): for block rows i0 .. i0 + 63 of
-// block m, b_m(i) -= sum over the tiles (m, k) of L_mk(q(i)) y_k, q(i) the
-// tile's stored row of block row i (its inverse row map; identity when the
-// tile is full).  8 lanes per row over interleaved column pairs, two rows per
-// thread, reduced by shuffles.  A tile's rows are read into registers before
-// y_k is gathered, so the loads of both overlap.
-template <int NB, int R>
-__global__ __launch_bounds__(256) void k_sfwd_panel(const int32_t* __restrict__ items,
-                                                    const int32_t* __restrict__ tlist,
-                                                    const TileD* __restrict__ tiles,
-                                                    const int32_t* __restrict__ maps,
-                                                    const double* __restrict__ S,
-                                                    double* __restrict__ y, int64_t np, int32_t nrhs) {
+// forward panel chunk (rows i0 .. i0 + 63, tiles [t0, t1)): for each row i,
+// sum over the tiles (m, k) of L_mk(q(i)) y_k, q(i) the tile's stored row of
+// block row i (its inverse row map; identity when the tile is full), handed
+// to put(i, c, value) for right-hand side c.  8 lanes per row over
+// interleaved column pairs, two rows per thread, reduced by shuffles.  A
+// tile's rows are read into registers before y_k is gathered into ys, so the
+// loads of both overlap.
+template <int NB, int R, class Put>
+__device__ __forceinline__ void sfwd_panel(int32_t i0, int32_t t0, int32_t t1, const int32_t* __restrict__ tlist,
+                                           const TileD* __restrict__ tiles, const int32_t* __restrict__ maps,
+                                           const double* __restrict__ S, const double* __restrict__ y,
+                                           int64_t np, int32_t nrhs, double* ys, Put put) {
   constexpr int NC = NB / 16;  // column pairs per lane
-  __shared__ double ys[NB * R];  // ys[col * R + c]
-  const int32_t m = items[4 * blockIdx.x], i0 = items[4 * blockIdx.x + 1];
-  const int32_t t0 = items[4 * blockIdx.x + 2], t1 = items[4 * blockIdx.x + 3];
   const int tid = threadIdx.x;
   const int j = tid & 7, rl = tid >> 3;  // lane of the row group, row of the pass
   double acc[2][R];
@@ -1532,57 +1443,60 @@ __global__ __launch_bounds__(256) void k_sfwd_panel(const int32_t* __restrict__ 
 #pragma unroll
     for (int c = 1; c < R; ++c) mine = j == c ? acc[h][c] : mine;
     const int i = i0 + rl + 32 * h;
-    if (i < NB && j < nrhs) y[(int64_t)j * np + (int64_t)m * NB + i] -= mine;
+    if (i < NB && j < nrhs) put(i, j, mine);
   }
 }
 
-// x_k <- L_kk^-T y_k: per 32-row block J from the last, the block column of
-// L_kk below the diagonal block and the block's inverse are staged in LDS
-// (coalesced), then s = r_J - L_(>J,J)^T x_(>J) with the row range split over
-// 8 threads per column (parts summed in a fixed order), then x_J = D_J^T s
-template <int NB, int R>
-__global__ __launch_bounds__(256) void k_sbwd_diag(const int32_t* __restrict__ blks,
-                                                   const double* __restrict__ S,
-                                                   const double* __restrict__ dinv,
-                                                   double* __restrict__ y, int64_t np, int32_t nrhs) {
-  __shared__ double r[NB * R];
-  __shared__ double part[PW * 8 * R];
-  __shared__ double s[PW * R];
-  __shared__ double Lc[(NB - PW) * PLD + 1];
-  __shared__ double Ds[PW * PLD];
-  const int32_t k = blks[blockIdx.x];
-  const int tid = threadIdx.x;
-  for (int x = tid; x < NB * R; x += 256) {
-    const int i = x / R, c = x % R;
-    r[x] = c < nrhs ? y[(int64_t)c * np + (int64_t)k * NB + i] : 0.0;
-  }
-  const double* L = S + (int64_t)k * NB * NB;
-  const double* D = dinv + (int64_t)k * NB * PW;
-  const int row = tid >> 3, sub = tid & 7;
-  // step J's block column of L and inverse are read into registers during
-  // step J + 1 and written to LDS when step J begins
-  constexpr int NPF = NB > PW ? (NB - PW) / 32 : 1;
-  double4 pf[NPF];
+// registers that carry a diagonal step's block row (forward) or block
+// column (backward) of L_kk and its 32 x 32 inverse from global memory to LDS
+template <int NB, class V>
+struct DiagFetch {
+  static constexpr int N = NB > PW ? (NB - PW) / (sizeof(V) / 8 * 8) : 1;
+  V pf[N];
   double4 pd;
-  auto fetch = [&](int J) {
-    const int p0 = (J + 1) * PW, h = NB - p0;
+};
+
+// forward step J's block row of L_kk (left of the diagonal block) and inverse
+// into registers: 32 rows x 8 threads, interleaved column pairs
+template <int NB>
+__device__ __forceinline__ void sfwd_fetch(int32_t k, int J, const double* __restrict__ S,
+                                           const double* __restrict__ dinv, DiagFetch<NB, double2>& f) {
+  const int tid = threadIdx.x, row = tid >> 3, sub = tid & 7;
+  const int w = J * PW;
+  const double* src = S + (int64_t)k * NB * NB + (int64_t)(w + row) * NB;
 #pragma unroll
-    for (int q = 0; q < NPF; ++q)
-      if (row + 32 * q < h)
-        pf[q] = *reinterpret_cast<const double4*>(L + (int64_t)(p0 + row + 32 * q) * NB + J * PW + 4 * sub);
-    pd = *reinterpret_cast<const double4*>(D + J * PW * PW + row * PW + 4 * sub);
-  };
-  fetch(NB / PW - 1);
-  for (int J = NB / PW - 1; J >= 0; --J) {
-    const int p0 = (J + 1) * PW, h = NB - p0;  // rows below the diagonal block
+  for (int q = 0; q < DiagFetch<NB, double2>::N; ++q)
+    if (2 * sub + 16 * q < w) f.pf[q] = *reinterpret_cast<const double2*>(src + 2 * sub + 16 * q);
+  f.pd = *reinterpret_cast<const double4*>(dinv + (int64_t)k * NB * PW + J * PW * PW + row * PW + 4 * sub);
+}
+
+// r <- L_kk^-1 r (r[i * R + c] in LDS): per 32-row block J, the block row of
+// L_kk left of the diagonal block and the block's inverse are staged in LDS
+// (coalesced), then s = r_J - L_(J,<J) r_(<J) with the K range split over 8
+// threads per row (each keeping all right-hand sides) and the parts summed
+// in a fixed order, then r_J = D_J s.  Steps alternate between two register
+// sets, step J + 2's rows being read during step J; steps 0 and 1 must be in
+// f0 and f1 on entry (sfwd_fetch).  Ends with a barrier.
+template <int NB, int R>
+__device__ __forceinline__ void sfwd_diag(int32_t k, const double* __restrict__ S, const double* __restrict__ dinv,
+                                          DiagFetch<NB, double2>& f0, DiagFetch<NB, double2>& f1, double* r,
+                                          double* part, double* s, double* Ls, double* Ds) {
+  constexpr int LW = NB - PW + 1;
+  constexpr int NPF = DiagFetch<NB, double2>::N;
+  const int tid = threadIdx.x;
+  const int row = tid >> 3, sub = tid & 7;  // staging and K-split layout: 32 rows x 8
+#pragma unroll
+  for (int J = 0; J < NB / PW; ++J) {
+    DiagFetch<NB, double2>& f = (J & 1) ? f1 : f0;
+    const double2* pf = f.pf;
+    const double4 pd = f.pd;
+    const int w = J * PW;
 #pragma unroll
     for (int q = 0; q < NPF; ++q) {
-      const int p = row + 32 * q;
-      if (p < h) {
-        Lc[p * PLD + 4 * sub] = pf[q].x;
-        Lc[p * PLD + 4 * sub + 1] = pf[q].y;
-        Lc[p * PLD + 4 * sub + 2] = pf[q].z;
-        Lc[p * PLD + 4 * sub + 3] = pf[q].w;
+      const int col = 2 * sub + 16 * q;
+      if (col < w) {
+        Ls[row * LW + col] = pf[q].x;
+        Ls[row * LW + col + 1] = pf[q].y;
       }
     }
     Ds[row * PLD + 4 * sub] = pd.x;
@@ -1590,22 +1504,22 @@ __global__ __launch_bounds__(256) void k_sbwd_diag(const int32_t* __restrict__ b
     Ds[row * PLD + 4 * sub + 2] = pd.z;
     Ds[row * PLD + 4 * sub + 3] = pd.w;
     __syncthreads();
-    if (J > 0) fetch(J - 1);
+    if (J + 2 < NB / PW) sfwd_fetch<NB>(k, J + 2, S, dinv, f);
     double acc[R];
 #pragma unroll
     for (int c = 0; c < R; ++c) acc[c] = 0.0;
 #pragma unroll 4
-    for (int p = sub; p < h; p += 8) {
-      const double l = Lc[p * PLD + row];
+    for (int p = sub; p < w; p += 8) {
+      const double l = Ls[row * LW + p];
 #pragma unroll
-      for (int c = 0; c < R; ++c) acc[c] = fma(l, r[(p0 + p) * R + c], acc[c]);
+      for (int c = 0; c < R; ++c) acc[c] = fma(l, r[p * R + c], acc[c]);
     }
 #pragma unroll
     for (int c = 0; c < R; ++c) part[(row * 8 + sub) * R + c] = acc[c];
     __syncthreads();
     if (tid < PW * R) {
       const int i = tid / R, c = tid % R;
-      double v = r[(J * PW + i) * R + c];
+      double v = r[(w + i) * R + c];
 #pragma unroll
       for (int z = 0; z < 8; ++z) v -= part[(i * 8 + z) * R + c];
       s[i * R + c] = v;
@@ -1615,39 +1529,80 @@ __global__ __launch_bounds__(256) void k_sbwd_diag(const int32_t* __restrict__ b
       const int i = tid / R, c = tid % R;
       double u = 0.0;
 #pragma unroll 8
-      for (int q = 0; q < PW; ++q) u = fma(Ds[q * PLD + i], s[q * R + c], u);
-      r[(J * PW + i) * R + c] = u;
+      for (int q = 0; q < PW; ++q) u = fma(Ds[i * PLD + q], s[q * R + c], u);
+      r[(w + i) * R + c] = u;
     }
     __syncthreads();
   }
+}
+
+// one forward launch: items [4 * b] = (block, first row, t0, t1); the first
+// nstep items are step items (first row unused), the rest panel chunks
+template <int NB, int R>
+__global__ __launch_bounds__(256) void k_sfwd_step(const int32_t* __restrict__ items, int32_t nstep,
+                                                   const int32_t* __restrict__ tlist,
+                                                   const TileD* __restrict__ tiles,
+                                                   const int32_t* __restrict__ maps,
+                                                   const double* __restrict__ S,
+                                                   const double* __restrict__ dinv,
+                                                   double* __restrict__ y, int64_t np, int32_t nrhs) {
+  static_assert(NB <= 256, "the gathered y_k shares the partial sums' LDS");
+  constexpr int LW = NB - PW + 1;
+  __shared__ double r[NB * R];
+  __shared__ double part[PW * 8 * R];  // also the gathered y_k of the products
+  __shared__ double s[PW * R];
+  __shared__ double Ls[PW * LW];
+  __shared__ double Ds[PW * PLD];
+  const int32_t m = items[4 * blockIdx.x], i0 = items[4 * blockIdx.x + 1];
+  const int32_t t0 = items[4 * blockIdx.x + 2], t1 = items[4 * blockIdx.x + 3];
+  double* ym = y + (int64_t)m * NB;
+  if ((int32_t)blockIdx.x >= nstep) {
+    sfwd_panel<NB, R>(i0, t0, t1, tlist, tiles, maps, S, y, np, nrhs, part,
+                      [&](int i, int c, double v) { ym[(int64_t)c * np + i] -= v; });
+    return;
+  }
+  DiagFetch<NB, double2> f0, f1;  // the diagonal phase's first loads overlap the products
+  sfwd_fetch<NB>(m, 0, S, dinv, f0);
+  if (NB / PW > 1) sfwd_fetch<NB>(m, 1, S, dinv, f1);
+  const int tid = threadIdx.x;
   for (int x = tid; x < NB * R; x += 256) {
-    const int ii = x / R, cc = x % R;
-    if (cc < nrhs) y[(int64_t)cc * np + (int64_t)k * NB + ii] = r[x];
+    const int i = x / R, c = x % R;
+    r[x] = c < nrhs ? ym[(int64_t)c * np + i] : 0.0;
+  }
+  if (t1 > t0)
+    for (int c0 = 0; c0 < NB; c0 += SCH)
+      sfwd_panel<NB, R>(c0, t0, t1, tlist, tiles, maps, S, y, np, nrhs, part,
+                        [&](int i, int c, double v) { r[i * R + c] -= v; });
+  __syncthreads();
+  sfwd_diag<NB, R>(m, S, dinv, f0, f1, r, part, s, Ls, Ds);
+  for (int x = tid; x < NB * R; x += 256) {
+    const int i = x / R, c = x % R;
+    if (c < nrhs) ym[(int64_t)c * np + i] = r[x];
   }
 }
 
-// backward panel item (k, j0, tiles [t0, t1)): columns j0 .. j0 + 63 of
-// y_k -= sum over the tiles (m, k) of L_mk^T x_m.  A thread owns two adjacent
-// columns and every eighth stored row; its rows of a tile are read into
+// backward panel chunk (columns j0 .. j0 + CW - 1 of block k, tiles [t0, t1)):
+// for each column j, sum over the tiles (m, k) of (L_mk^T x_m)(j), handed to
+// put(x, value) with x = (j - j0) * R + c.  A thread owns two adjacent
+// columns and every SH-th stored row; its rows of a tile are read into
 // registers before the entries of x_m at the tile's active rows are gathered
-// into LDS.  The eight row shares are summed in LDS in a fixed order.
-constexpr int SBC = 64;  // columns of a backward panel work item
+// into xg.  The SH row shares are summed in red in a fixed order.  Ends with
+// a barrier.
+template <int NB>
+struct SbwdShape {
+  static constexpr int CW = NB < SBC ? NB : SBC;  // columns per chunk
+  static constexpr int CP = CW / 2;               // column pairs
+  static constexpr int SH = 256 / CP;             // row shares
+  static constexpr int NQ = NB / SH;              // stored rows per thread at most
+};
 
-template <int NB, int R>
-__global__ __launch_bounds__(256) void k_sbwd_panel(const int32_t* __restrict__ items,
-                                                    const int32_t* __restrict__ tlist,
-                                                    const TileD* __restrict__ tiles,
-                                                    const int32_t* __restrict__ rows,
-                                                    const double* __restrict__ S,
-                                                    double* __restrict__ y, int64_t np, int32_t nrhs) {
-  constexpr int CW = NB < SBC ? NB : SBC;  // columns per item
-  constexpr int CP = CW / 2;               // column pairs
-  constexpr int SH = 256 / CP;             // row shares
-  constexpr int NQ = NB / SH;              // stored rows per thread at most
-  __shared__ double xg[NB * R];  // xg[q * R + c]: x_m at the tile's stored row q
-  __shared__ double red[SH * CW * R];
-  const int32_t k = items[4 * blockIdx.x], j0 = items[4 * blockIdx.x + 1];
-  const int32_t t0 = items[4 * blockIdx.x + 2], t1 = items[4 * blockIdx.x + 3];
+template <int NB, int R, class Put>
+__device__ __forceinline__ void sbwd_panel(int32_t j0, int32_t t0, int32_t t1, const int32_t* __restrict__ tlist,
+                                           const TileD* __restrict__ tiles, const int32_t* __restrict__ rows,
+                                           const double* __restrict__ S, const double* __restrict__ y,
+                                           int64_t np, int32_t nrhs, double* xg, double* red, Put put) {
+  constexpr int CW = SbwdShape<NB>::CW, CP = SbwdShape<NB>::CP;
+  constexpr int SH = SbwdShape<NB>::SH, NQ = SbwdShape<NB>::NQ;
   const int tid = threadIdx.x;
   const int cp = tid % CP, sh = tid / CP;
   double acc[2][R];
@@ -1688,11 +1643,149 @@ __global__ __launch_bounds__(256) void k_sbwd_panel(const int32_t* __restrict__ 
 #pragma unroll
     for (int c = 0; c < R; ++c) red[(sh * CW + 2 * cp + e) * R + c] = acc[e][c];
   __syncthreads();
-  double* yk = y + (int64_t)k * NB + j0;
   for (int x = tid; x < CW * R; x += 256) {
     double v = 0.0;
     for (int z = 0; z < SH; ++z) v += red[z * CW * R + x];
-    if (x % R < nrhs) yk[(int64_t)(x % R) * np + x / R] -= v;
+    if (x % R < nrhs) put(x, v);
+  }
+  __syncthreads();
+}
+
+// backward step J's block column of L_kk (below the diagonal block) and
+// inverse into registers: 32 rows x 8 threads, four columns each
+template <int NB>
+__device__ __forceinline__ void sbwd_fetch(int32_t k, int J, const double* __restrict__ S,
+                                           const double* __restrict__ dinv, DiagFetch<NB, double4>& f) {
+  const int tid = threadIdx.x, row = tid >> 3, sub = tid & 7;
+  const int p0 = (J + 1) * PW, h = NB - p0;
+  const double* L = S + (int64_t)k * NB * NB;
+#pragma unroll
+  for (int q = 0; q < DiagFetch<NB, double4>::N; ++q)
+    if (row + 32 * q < h)
+      f.pf[q] = *reinterpret_cast<const double4*>(L + (int64_t)(p0 + row + 32 * q) * NB + J * PW + 4 * sub);
+  f.pd = *reinterpret_cast<const double4*>(dinv + (int64_t)k * NB * PW + J * PW * PW + row * PW + 4 * sub);
+}
+
+// r <- L_kk^-T r (r[i * R + c] in LDS): per 32-row block J from the last, the
+// block column of L_kk below the diagonal block and the block's inverse are
+// staged in LDS (coalesced), then s = r_J - L_(>J,J)^T r_(>J) with the row
+// range split over 8 threads per column (parts summed in a fixed order), then
+// r_J = D_J^T s.  Steps alternate between two register sets, step J - 2's
+// rows being read during step J; the last two steps' must be in f0 (the last)
+// and f1 on entry (sbwd_fetch).  Ends with a barrier.
+template <int NB, int R>
+__device__ __forceinline__ void sbwd_diag(int32_t k, const double* __restrict__ S, const double* __restrict__ dinv,
+                                          DiagFetch<NB, double4>& f0, DiagFetch<NB, double4>& f1, double* r,
+                                          double* part, double* s, double* Lc, double* Ds) {
+  constexpr int NPF = DiagFetch<NB, double4>::N;
+  constexpr int NJ = NB / PW;
+  const int tid = threadIdx.x;
+  const int row = tid >> 3, sub = tid & 7;
+#pragma unroll
+  for (int J = NJ - 1; J >= 0; --J) {
+    DiagFetch<NB, double4>& f = ((NJ - 1 - J) & 1) ? f1 : f0;
+    const double4* pf = f.pf;
+    const double4 pd = f.pd;
+    const int p0 = (J + 1) * PW, h = NB - p0;  // rows below the diagonal block
+#pragma unroll
+    for (int q = 0; q < NPF; ++q) {
+      const int p = row + 32 * q;
+      if (p < h) {
+        Lc[p * PLD + 4 * sub] = pf[q].x;
+        Lc[p * PLD + 4 * sub + 1] = pf[q].y;
+        Lc[p * PLD + 4 * sub + 2] = pf[q].z;
+        Lc[p * PLD + 4 * sub + 3] = pf[q].w;
+      }
+    }
+    Ds[row * PLD + 4 * sub] = pd.x;
+    Ds[row * PLD + 4 * sub + 1] = pd.y;
+    Ds[row * PLD + 4 * sub + 2] = pd.z;
+    Ds[row * PLD + 4 * sub + 3] = pd.w;
+    __syncthreads();
+    if (J > 1) sbwd_fetch<NB>(k, J - 2, S, dinv, f);
+    double acc[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc[c] = 0.0;
+#pragma unroll 4
+    for (int p = sub; p < h; p += 8) {
+      const double l = Lc[p * PLD + row];
+#pragma unroll
+      for (int c = 0; c < R; ++c) acc[c] = fma(l, r[(p0 + p) * R + c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < R; ++c) part[(row * 8 + sub) * R + c] = acc[c];
+    __syncthreads();
+    if (tid < PW * R) {
+      const int i = tid / R, c = tid % R;
+      double v = r[(J * PW + i) * R + c];
+#pragma unroll
+      for (int z = 0; z < 8; ++z) v -= part[(i * 8 + z) * R + c];
+      s[i * R + c] = v;
+    }
+    __syncthreads();
+    if (tid < PW * R) {
+      const int i = tid / R, c = tid % R;
+      double u = 0.0;
+#pragma unroll 8
+      for (int q = 0; q < PW; ++q) u = fma(Ds[q * PLD + i], s[q * R + c], u);
+      r[(J * PW + i) * R + c] = u;
+    }
+    __syncthreads();
+  }
+}
+
+// one backward launch: items [4 * b] = (block, first column, t0, t1); the
+// first nstep items are step items (first column unused), the rest panel
+// chunks.  The diagonal phase's LDS (part | s | Lc | Ds) and the products'
+// LDS (xg | red) share one buffer.
+template <int NB, int R>
+struct SbwdLds {
+  static constexpr int DIAG = PW * 8 * R + PW * R + (NB - PW) * PLD + 1 + PW * PLD;
+  static constexpr int PROD = NB * R + SbwdShape<NB>::SH * SbwdShape<NB>::CW * R;
+  static constexpr int SIZE = DIAG > PROD ? DIAG : PROD;
+};
+
+template <int NB, int R>
+__global__ __launch_bounds__(256) void k_sbwd_step(const int32_t* __restrict__ items, int32_t nstep,
+                                                   const int32_t* __restrict__ tlist,
+                                                   const TileD* __restrict__ tiles,
+                                                   const int32_t* __restrict__ rows,
+                                                   const double* __restrict__ S,
+                                                   const double* __restrict__ dinv,
+                                                   double* __restrict__ y, int64_t np, int32_t nrhs) {
+  __shared__ double r[NB * R];
+  __shared__ double sm[SbwdLds<NB, R>::SIZE];
+  double* xg = sm;
+  double* red = sm + NB * R;
+  const int32_t k = items[4 * blockIdx.x], j0 = items[4 * blockIdx.x + 1];
+  const int32_t t0 = items[4 * blockIdx.x + 2], t1 = items[4 * blockIdx.x + 3];
+  double* yk = y + (int64_t)k * NB;
+  if ((int32_t)blockIdx.x >= nstep) {
+    sbwd_panel<NB, R>(j0, t0, t1, tlist, tiles, rows, S, y, np, nrhs, xg, red,
+                      [&](int x, double v) { yk[(int64_t)(x % R) * np + j0 + x / R] -= v; });
+    return;
+  }
+  DiagFetch<NB, double4> f0, f1;  // the diagonal phase's first loads overlap the products
+  sbwd_fetch<NB>(k, NB / PW - 1, S, dinv, f0);
+  if (NB / PW > 1) sbwd_fetch<NB>(k, NB / PW - 2, S, dinv, f1);
+  const int tid = threadIdx.x;
+  for (int x = tid; x < NB * R; x += 256) {
+    const int i = x / R, c = x % R;
+    r[x] = c < nrhs ? yk[(int64_t)c * np + i] : 0.0;
+  }
+  if (t1 > t0)
+    for (int c0 = 0; c0 < NB; c0 += SbwdShape<NB>::CW)
+      sbwd_panel<NB, R>(c0, t0, t1, tlist, tiles, rows, S, y, np, nrhs, xg, red,
+                        [&](int x, double v) { r[c0 * R + x] -= v; });
+  __syncthreads();
+  double* part = sm;
+  double* s = part + PW * 8 * R;
+  double* Lc = s + PW * R;
+  double* Ds = Lc + (NB - PW) * PLD + 1;
+  sbwd_diag<NB, R>(k, S, dinv, f0, f1, r, part, s, Lc, Ds);
+  for (int x = tid; x < NB * R; x += 256) {
+    const int i = x / R, c = x % R;
+    if (c < nrhs) yk[(int64_t)c * np + i] = r[x];
   }
 }
 

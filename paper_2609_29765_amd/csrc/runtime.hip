@@ -62,6 +62,7 @@ struct stc_handle {
   // block row, range in the tile list; backward: fed block, range) and their
   // offsets, and the tile lists the ranges point into
   std::vector<int32_t> sfwd_items, sfwd_ptr, sbwd_items, sbwd_ptr, sfwd_tl, sbwd_tl;
+  std::vector<int32_t> sfwd_nstep, sbwd_nstep;  // step items leading each launch
   int32_t* d_sfwd_items = nullptr;
   int32_t* d_sbwd_items = nullptr;
   int32_t* d_sfwd_tl = nullptr;
@@ -370,31 +371,23 @@ int build_graph(stc_handle* h, int32_t members, hipGraphExec_t* ex) {
 }
 
 // the forward and backward sweeps over right-hand sides [g0, g0 + nr) of
-// d_y, level by level: diagonal blocks, then the panel tiles they unlock
+// d_y: one launch per level, each solving that level's blocks after the
+// products of the level before
 template <int NB, int R>
 void launch_sweeps_r(stc_handle* h, int32_t nr, int32_t g0, hipStream_t st) {
-  const Plan& p = h->plan;
   const int64_t np = padded_n(h);
   double* y = h->d_y + (int64_t)g0 * np;
-  for (size_t L = 0; L + 1 < p.fwd_level_ptr.size(); ++L) {
-    const int32_t a = p.fwd_level_ptr[L], b = p.fwd_level_ptr[L + 1];
-    if (b > a)
-      hipLaunchKernelGGL((k_sfwd_diag<NB, R>), dim3(b - a), dim3(256), 0, st, h->d_fwd_blk + a, h->d_store,
-                         h->d_dinv, y, np, nr);
-    const int32_t c = h->sfwd_ptr[L], d = h->sfwd_ptr[L + 1];
+  for (size_t q = 0; q < h->sfwd_nstep.size(); ++q) {
+    const int32_t c = h->sfwd_ptr[q], d = h->sfwd_ptr[q + 1];
     if (d > c)
-      hipLaunchKernelGGL((k_sfwd_panel<NB, R>), dim3(d - c), dim3(256), 0, st, h->d_sfwd_items + 4 * (int64_t)c,
-                         h->d_sfwd_tl, h->d_tiles, h->d_maps, h->d_store, y, np, nr);
+      hipLaunchKernelGGL((k_sfwd_step<NB, R>), dim3(d - c), dim3(256), 0, st, h->d_sfwd_items + 4 * (int64_t)c,
+                       h->sfwd_nstep[q], h->d_sfwd_tl, h->d_tiles, h->d_maps, h->d_store, h->d_dinv, y, np, nr);
   }
-  for (size_t L = 0; L + 1 < p.bwd_level_ptr.size(); ++L) {
-    const int32_t a = p.bwd_level_ptr[L], b = p.bwd_level_ptr[L + 1];
-    if (b > a)
-      hipLaunchKernelGGL((k_sbwd_diag<NB, R>), dim3(b - a), dim3(256), 0, st, h->d_bwd_blk + a, h->d_store,
-                         h->d_dinv, y, np, nr);
-    const int32_t c = h->sbwd_ptr[L], d = h->sbwd_ptr[L + 1];
+  for (size_t q = 0; q < h->sbwd_nstep.size(); ++q) {
+    const int32_t c = h->sbwd_ptr[q], d = h->sbwd_ptr[q + 1];
     if (d > c)
-      hipLaunchKernelGGL((k_sbwd_panel<NB, R>), dim3(d - c), dim3(256), 0, st, h->d_sbwd_items + 4 * (int64_t)c,
-                         h->d_sbwd_tl, h->d_tiles, h->d_rows, h->d_store, y, np, nr);
+      hipLaunchKernelGGL((k_sbwd_step<NB, R>), dim3(d - c), dim3(256), 0, st, h->d_sbwd_items + 4 * (int64_t)c,
+                       h->sbwd_nstep[q], h->d_sbwd_tl, h->d_tiles, h->d_rows, h->d_store, h->d_dinv, y, np, nr);
   }
 }
 
@@ -604,56 +597,80 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
       h->trsm_items.insert(h->trsm_items.end(), L.trsm_items.begin(), L.trsm_items.end());
       h->lv.push_back(x);
     }
-    // solve work items, level by level: the tiles a level's blocks unlock,
-    // grouped by the block they feed (tiles of one group in a fixed order)
+    // solve work items.  Level q's blocks are solved by step items that
+    // first apply the tiles feeding them from level q - 1, in one launch with
+    // the panel chunks for later blocks that level q - 1 feeds.  A step item
+    // reads its tiles whole where a panel chunk reads a 1 / (n_b / chunk)
+    // share of them, so where that serial excess passes kStepFuseBytes at
+    // some block of the level (a saved launch is worth well under a
+    // microsecond) the level gets two launches instead: every chunk of level
+    // q - 1's products, then step items with no tiles.  Tiles of one item are
+    // taken in a fixed order.
     const Plan& pl = h->plan;
-    std::map<int32_t, std::vector<int32_t>> feed;
-    h->sfwd_ptr.push_back(0);
-    for (size_t L = 0; L + 1 < pl.fwd_level_ptr.size(); ++L) {
-      feed.clear();
-      for (int32_t b = pl.fwd_level_ptr[L]; b < pl.fwd_level_ptr[L + 1]; ++b) {
-        const int32_t k = pl.fwd_level_blk[(size_t)b];
-        for (int32_t z = pl.col_tiles_ptr[(size_t)k]; z < pl.col_tiles_ptr[(size_t)k + 1]; ++z) {
-          const int32_t t = pl.col_tiles[(size_t)z];
-          feed[h->sym.tiles[(size_t)t].m].push_back(t);
+    constexpr double kStepFuseBytes = 65536.0;
+    auto sweep_items = [&](const std::vector<int32_t>& lptr, const std::vector<int32_t>& lblk,
+                           const std::vector<int32_t>& tptr, const std::vector<int32_t>& tix, bool fwd,
+                           int32_t chunk, std::vector<int32_t>* items, std::vector<int32_t>* ptr,
+                           std::vector<int32_t>* nstep, std::vector<int32_t>* tl) {
+      const int32_t nlev = (int32_t)lptr.size() - 1;
+      std::vector<int32_t> lev((size_t)h->sym.NT, -1);
+      for (int32_t L = 0; L < nlev; ++L)
+        for (int32_t b = lptr[(size_t)L]; b < lptr[(size_t)L + 1]; ++b) lev[(size_t)lblk[(size_t)b]] = L;
+      std::map<int32_t, std::vector<int32_t>> feed;
+      auto close_launch = [&](int32_t ns) {
+        nstep->push_back(ns);
+        ptr->push_back((int32_t)(items->size() / 4));
+      };
+      auto panel_chunks = [&](int32_t fed, const std::vector<int32_t>& ts) {
+        const int32_t t0 = (int32_t)tl->size();
+        tl->insert(tl->end(), ts.begin(), ts.end());
+        const int32_t t1 = (int32_t)tl->size();
+        for (int32_t i0 = 0; i0 < pl.nb; i0 += chunk) items->insert(items->end(), {fed, i0, t0, t1});
+      };
+      ptr->push_back(0);
+      for (int32_t q = 0; q < nlev; ++q) {
+        feed.clear();
+        if (q > 0)
+          for (int32_t b = lptr[(size_t)q - 1]; b < lptr[(size_t)q]; ++b) {
+            const int32_t k = lblk[(size_t)b];
+            for (int32_t z = tptr[(size_t)k]; z < tptr[(size_t)k + 1]; ++z) {
+              const int32_t t = tix[(size_t)z];
+              const TileInfo& ti = h->sym.tiles[(size_t)t];
+              feed[fwd ? ti.m : ti.k].push_back(t);
+            }
+          }
+        double excess = 0.0;  // largest serial excess of a step item, bytes
+        for (int32_t b = lptr[(size_t)q]; b < lptr[(size_t)q + 1]; ++b) {
+          auto it = feed.find(lblk[(size_t)b]);
+          if (it == feed.end()) continue;
+          double rows = 0.0;
+          for (int32_t t : it->second) rows += h->sym.tiles[(size_t)t].cnt;
+          excess = std::max(excess, rows * (double)std::max(0, pl.nb - chunk) * sizeof(double));
         }
-      }
-      for (const auto& kv : feed) {
-        const int32_t t0 = (int32_t)h->sfwd_tl.size();
-        h->sfwd_tl.insert(h->sfwd_tl.end(), kv.second.begin(), kv.second.end());
-        const int32_t t1 = (int32_t)h->sfwd_tl.size();
-        for (int32_t i0 = 0; i0 < pl.nb; i0 += SCH) {
-          h->sfwd_items.push_back(kv.first);
-          h->sfwd_items.push_back(i0);
-          h->sfwd_items.push_back(t0);
-          h->sfwd_items.push_back(t1);
+        const bool fuse = excess <= kStepFuseBytes;
+        if (!fuse) {
+          for (const auto& kv : feed) panel_chunks(kv.first, kv.second);
+          close_launch(0);
         }
-      }
-      h->sfwd_ptr.push_back((int32_t)(h->sfwd_items.size() / 4));
-    }
-    h->sbwd_ptr.push_back(0);
-    for (size_t L = 0; L + 1 < pl.bwd_level_ptr.size(); ++L) {
-      feed.clear();
-      for (int32_t b = pl.bwd_level_ptr[L]; b < pl.bwd_level_ptr[L + 1]; ++b) {
-        const int32_t m = pl.bwd_level_blk[(size_t)b];
-        for (int32_t z = pl.row_tiles_ptr[(size_t)m]; z < pl.row_tiles_ptr[(size_t)m + 1]; ++z) {
-          const int32_t t = pl.row_tiles[(size_t)z];
-          feed[h->sym.tiles[(size_t)t].k].push_back(t);
+        int32_t ns = 0;
+        for (int32_t b = lptr[(size_t)q]; b < lptr[(size_t)q + 1]; ++b) {
+          const int32_t m = lblk[(size_t)b];
+          const int32_t t0 = (int32_t)tl->size();
+          auto it = feed.find(m);
+          if (fuse && it != feed.end()) tl->insert(tl->end(), it->second.begin(), it->second.end());
+          items->insert(items->end(), {m, 0, t0, (int32_t)tl->size()});
+          ++ns;
         }
+        if (fuse)
+          for (const auto& kv : feed)
+            if (lev[(size_t)kv.first] != q) panel_chunks(kv.first, kv.second);
+        close_launch(ns);
       }
-      for (const auto& kv : feed) {
-        const int32_t t0 = (int32_t)h->sbwd_tl.size();
-        h->sbwd_tl.insert(h->sbwd_tl.end(), kv.second.begin(), kv.second.end());
-        const int32_t t1 = (int32_t)h->sbwd_tl.size();
-        for (int32_t j0 = 0; j0 < pl.nb; j0 += SBC) {
-          h->sbwd_items.push_back(kv.first);
-          h->sbwd_items.push_back(j0);
-          h->sbwd_items.push_back(t0);
-          h->sbwd_items.push_back(t1);
-        }
-      }
-      h->sbwd_ptr.push_back((int32_t)(h->sbwd_items.size() / 4));
-    }
+    };
+    sweep_items(pl.fwd_level_ptr, pl.fwd_level_blk, pl.col_tiles_ptr, pl.col_tiles, true, SCH, &h->sfwd_items,
+                &h->sfwd_ptr, &h->sfwd_nstep, &h->sfwd_tl);
+    sweep_items(pl.bwd_level_ptr, pl.bwd_level_blk, pl.row_tiles_ptr, pl.row_tiles, false, SBC, &h->sbwd_items,
+                &h->sbwd_ptr, &h->sbwd_nstep, &h->sbwd_tl);
     *out = h;
     return 0;
   } catch (const std::bad_alloc&) {
@@ -857,7 +874,8 @@ int stc_get_sizes(const stc_handle* h, int64_t* z) {
   for (const TileInfo& t : s.tiles) rows += t.cnt;
   int64_t v[16] = {s.n, s.qnz, s.lnz, s.nb, s.NT, (int64_t)s.tiles.size(), rows,
                    (int64_t)(s.tasks.size() / 4), s.mode, s.route, s.ndense, s.method, s.tact,
-                   h->plan.store, (int64_t)h->plan.levels.size(), 0};
+                   h->plan.store, (int64_t)h->plan.levels.size(),
+                   (int64_t)(h->sfwd_nstep.size() + h->sbwd_nstep.size())};
   std::memcpy(z, v, sizeof(v));
   return 0;
 }

@@ -133,8 +133,8 @@ class Analysis:
         sz = np.zeros(16, np.int64)
         _check(L.stc_get_sizes(h, sz))
         (self.n, self.qnz, self.lnz, self.nb, self.NT, self.ntiles, self.nrows, self.ntasks,
-         mode_i, route_i, self.ndense, self.method, self.tact, self.store, self.nlevels) = (
-            int(x) for x in sz[:15])
+         mode_i, route_i, self.ndense, self.method, self.tact, self.store, self.nlevels,
+         self.solve_launches) = (int(x) for x in sz)
         self.mode = {1: "dense", 2: "semisparse"}[mode_i]
         self.route = ROUTES[route_i]
         f = np.zeros(3)
