@@ -1382,31 +1382,31 @@ constexpr int SR = 8;      // right-hand sides per sweep
 constexpr int SCH = 64;    // block rows of a forward panel chunk
 constexpr int SBC = 64;    // columns of a backward panel chunk
 
-// forward panel chunk (rows i0 .. i0 + 63, tiles [t0, t1)): for each row i,
+// forward products for rows i0 .. i0 + 32 H - 1 (tiles [t0, t1)): for each row i,
 // sum over the tiles (m, k) of L_mk(q(i)) y_k, q(i) the tile's stored row of
 // block row i (its inverse row map; identity when the tile is full), handed
 // to put(i, c, value) for right-hand side c.  8 lanes per row over
-// interleaved column pairs, two rows per thread, reduced by shuffles.  A
+// interleaved column pairs, H rows per thread, reduced by shuffles.  A
 // tile's rows are read into registers before y_k is gathered into ys, so the
 // loads of both overlap.
-template <int NB, int R, class Put>
-__device__ __forceinline__ void sfwd_panel(int32_t i0, int32_t t0, int32_t t1, const int32_t* __restrict__ tlist,
-                                           const TileD* __restrict__ tiles, const int32_t* __restrict__ maps,
+template <int NB, int R, int H, class Put>
+__device__ __forceinline__ void sfwd_panel(int32_t i0, int32_t t0, int32_t t1, const TileD* __restrict__ tlist,
+                                           const int32_t* __restrict__ maps,
                                            const double* __restrict__ S, const double* __restrict__ y,
                                            int64_t np, int32_t nrhs, double* ys, Put put) {
   constexpr int NC = NB / 16;  // column pairs per lane
   const int tid = threadIdx.x;
   const int j = tid & 7, rl = tid >> 3;  // lane of the row group, row of the pass
-  double acc[2][R];
+  double acc[H][R];
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < H; ++h)
 #pragma unroll
     for (int c = 0; c < R; ++c) acc[h][c] = 0.0;
   for (int32_t z = t0; z < t1; ++z) {
-    const TileD tl = tiles[tlist[z]];
-    double2 lv[2][NC];
+    const TileD tl = tlist[z];
+    double2 lv[H][NC];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < H; ++h) {
       const int i = i0 + rl + 32 * h;
       const int32_t q = i >= NB ? -1 : (tl.imap < 0 ? i : maps[tl.imap + i]);
       const double* Lr = S + tl.off + (int64_t)(q < 0 ? 0 : q) * NB + 2 * j;
@@ -1427,12 +1427,12 @@ __device__ __forceinline__ void sfwd_panel(int32_t i0, int32_t t0, int32_t t1, c
       for (int c = 0; c < R; ++c) {
         const double y0 = ys[col * R + c], y1 = ys[(col + 1) * R + c];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) acc[h][c] = fma(lv[h][u].x, y0, fma(lv[h][u].y, y1, acc[h][c]));
+        for (int h = 0; h < H; ++h) acc[h][c] = fma(lv[h][u].x, y0, fma(lv[h][u].y, y1, acc[h][c]));
       }
     }
   }
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < H; ++h) {
 #pragma unroll
     for (int c = 0; c < R; ++c) {
       acc[h][c] += __shfl_xor(acc[h][c], 1);
@@ -1536,12 +1536,12 @@ __device__ __forceinline__ void sfwd_diag(int32_t k, const double* __restrict__ 
   }
 }
 
-// one forward launch: items [4 * b] = (block, first row, t0, t1); the first
-// nstep items are step items (first row unused), the rest panel chunks
+// one forward launch: items [4 * b] = (block, first row, t0, t1), tiles
+// [t0, t1) of tlist; the first nstep items are step items (first row unused),
+// the rest panel chunks
 template <int NB, int R>
 __global__ __launch_bounds__(256) void k_sfwd_step(const int32_t* __restrict__ items, int32_t nstep,
-                                                   const int32_t* __restrict__ tlist,
-                                                   const TileD* __restrict__ tiles,
+                                                   const TileD* __restrict__ tlist,
                                                    const int32_t* __restrict__ maps,
                                                    const double* __restrict__ S,
                                                    const double* __restrict__ dinv,
@@ -1557,8 +1557,8 @@ __global__ __launch_bounds__(256) void k_sfwd_step(const int32_t* __restrict__ i
   const int32_t t0 = items[4 * blockIdx.x + 2], t1 = items[4 * blockIdx.x + 3];
   double* ym = y + (int64_t)m * NB;
   if ((int32_t)blockIdx.x >= nstep) {
-    sfwd_panel<NB, R>(i0, t0, t1, tlist, tiles, maps, S, y, np, nrhs, part,
-                      [&](int i, int c, double v) { ym[(int64_t)c * np + i] -= v; });
+    sfwd_panel<NB, R, SCH / 32>(i0, t0, t1, tlist, maps, S, y, np, nrhs, part,
+                                [&](int i, int c, double v) { ym[(int64_t)c * np + i] -= v; });
     return;
   }
   DiagFetch<NB, double2> f0, f1;  // the diagonal phase's first loads overlap the products
@@ -1569,10 +1569,16 @@ __global__ __launch_bounds__(256) void k_sfwd_step(const int32_t* __restrict__ i
     const int i = x / R, c = x % R;
     r[x] = c < nrhs ? ym[(int64_t)c * np + i] : 0.0;
   }
-  if (t1 > t0)
-    for (int c0 = 0; c0 < NB; c0 += SCH)
-      sfwd_panel<NB, R>(c0, t0, t1, tlist, tiles, maps, S, y, np, nrhs, part,
-                        [&](int i, int c, double v) { r[i * R + c] -= v; });
+  // up to n_b 128 one pass over the tiles covers every row, else 64-row chunks
+  auto put_r = [&](int i, int c, double v) { r[i * R + c] -= v; };
+  if (t1 > t0) {
+    if constexpr (NB <= 128) {
+      sfwd_panel<NB, R, NB / 32>(0, t0, t1, tlist, maps, S, y, np, nrhs, part, put_r);
+    } else {
+      for (int c0 = 0; c0 < NB; c0 += SCH)
+        sfwd_panel<NB, R, SCH / 32>(c0, t0, t1, tlist, maps, S, y, np, nrhs, part, put_r);
+    }
+  }
   __syncthreads();
   sfwd_diag<NB, R>(m, S, dinv, f0, f1, r, part, s, Ls, Ds);
   for (int x = tid; x < NB * R; x += 256) {
@@ -1588,21 +1594,22 @@ __global__ __launch_bounds__(256) void k_sfwd_step(const int32_t* __restrict__ i
 // registers before the entries of x_m at the tile's active rows are gathered
 // into xg.  The SH row shares are summed in red in a fixed order.  Ends with
 // a barrier.
-template <int NB>
+template <int NB, int CW_>
 struct SbwdShape {
-  static constexpr int CW = NB < SBC ? NB : SBC;  // columns per chunk
-  static constexpr int CP = CW / 2;               // column pairs
-  static constexpr int SH = 256 / CP;             // row shares
-  static constexpr int NQ = NB / SH;              // stored rows per thread at most
+  static constexpr int CW = CW_;       // columns per pass
+  static constexpr int CP = CW / 2;    // column pairs
+  static constexpr int SH = 256 / CP;  // row shares
+  static constexpr int NQ = NB / SH;   // stored rows per thread at most
 };
+constexpr int sbwd_chunk(int nb) { return nb < SBC ? nb : SBC; }
 
-template <int NB, int R, class Put>
-__device__ __forceinline__ void sbwd_panel(int32_t j0, int32_t t0, int32_t t1, const int32_t* __restrict__ tlist,
-                                           const TileD* __restrict__ tiles, const int32_t* __restrict__ rows,
+template <int NB, int R, int CW_, class Put>
+__device__ __forceinline__ void sbwd_panel(int32_t j0, int32_t t0, int32_t t1, const TileD* __restrict__ tlist,
+                                           const int32_t* __restrict__ rows,
                                            const double* __restrict__ S, const double* __restrict__ y,
                                            int64_t np, int32_t nrhs, double* xg, double* red, Put put) {
-  constexpr int CW = SbwdShape<NB>::CW, CP = SbwdShape<NB>::CP;
-  constexpr int SH = SbwdShape<NB>::SH, NQ = SbwdShape<NB>::NQ;
+  constexpr int CW = SbwdShape<NB, CW_>::CW, CP = SbwdShape<NB, CW_>::CP;
+  constexpr int SH = SbwdShape<NB, CW_>::SH, NQ = SbwdShape<NB, CW_>::NQ;
   const int tid = threadIdx.x;
   const int cp = tid % CP, sh = tid / CP;
   double acc[2][R];
@@ -1611,7 +1618,7 @@ __device__ __forceinline__ void sbwd_panel(int32_t j0, int32_t t0, int32_t t1, c
 #pragma unroll
     for (int c = 0; c < R; ++c) acc[e][c] = 0.0;
   for (int32_t z = t0; z < t1; ++z) {
-    const TileD tl = tiles[tlist[z]];
+    const TileD tl = tlist[z];
     const double* P = S + tl.off + j0 + 2 * cp;
     double2 lv[NQ];
 #pragma unroll
@@ -1734,21 +1741,20 @@ __device__ __forceinline__ void sbwd_diag(int32_t k, const double* __restrict__ 
   }
 }
 
-// one backward launch: items [4 * b] = (block, first column, t0, t1); the
-// first nstep items are step items (first column unused), the rest panel
-// chunks.  The diagonal phase's LDS (part | s | Lc | Ds) and the products'
+// one backward launch: items [4 * b] = (block, first column, t0, t1), tiles
+// [t0, t1) of tlist; the first nstep items are step items (first column
+// unused), the rest panel chunks.  The diagonal phase's LDS (part | s | Lc | Ds) and the products'
 // LDS (xg | red) share one buffer.
 template <int NB, int R>
 struct SbwdLds {
   static constexpr int DIAG = PW * 8 * R + PW * R + (NB - PW) * PLD + 1 + PW * PLD;
-  static constexpr int PROD = NB * R + SbwdShape<NB>::SH * SbwdShape<NB>::CW * R;
+  static constexpr int PROD = NB * R + 512 * R;  // xg, then SH x CW x R partial sums
   static constexpr int SIZE = DIAG > PROD ? DIAG : PROD;
 };
 
 template <int NB, int R>
 __global__ __launch_bounds__(256) void k_sbwd_step(const int32_t* __restrict__ items, int32_t nstep,
-                                                   const int32_t* __restrict__ tlist,
-                                                   const TileD* __restrict__ tiles,
+                                                   const TileD* __restrict__ tlist,
                                                    const int32_t* __restrict__ rows,
                                                    const double* __restrict__ S,
                                                    const double* __restrict__ dinv,
@@ -1761,8 +1767,8 @@ __global__ __launch_bounds__(256) void k_sbwd_step(const int32_t* __restrict__ i
   const int32_t t0 = items[4 * blockIdx.x + 2], t1 = items[4 * blockIdx.x + 3];
   double* yk = y + (int64_t)k * NB;
   if ((int32_t)blockIdx.x >= nstep) {
-    sbwd_panel<NB, R>(j0, t0, t1, tlist, tiles, rows, S, y, np, nrhs, xg, red,
-                      [&](int x, double v) { yk[(int64_t)(x % R) * np + j0 + x / R] -= v; });
+    sbwd_panel<NB, R, sbwd_chunk(NB)>(j0, t0, t1, tlist, rows, S, y, np, nrhs, xg, red,
+                                      [&](int x, double v) { yk[(int64_t)(x % R) * np + j0 + x / R] -= v; });
     return;
   }
   DiagFetch<NB, double4> f0, f1;  // the diagonal phase's first loads overlap the products
@@ -1773,10 +1779,17 @@ __global__ __launch_bounds__(256) void k_sbwd_step(const int32_t* __restrict__ i
     const int i = x / R, c = x % R;
     r[x] = c < nrhs ? yk[(int64_t)c * np + i] : 0.0;
   }
-  if (t1 > t0)
-    for (int c0 = 0; c0 < NB; c0 += SbwdShape<NB>::CW)
-      sbwd_panel<NB, R>(c0, t0, t1, tlist, tiles, rows, S, y, np, nrhs, xg, red,
-                        [&](int x, double v) { r[c0 * R + x] -= v; });
+  // up to n_b 128 one pass over the tiles covers every column, else chunks
+  if (t1 > t0) {
+    if constexpr (NB <= 128) {
+      sbwd_panel<NB, R, NB>(0, t0, t1, tlist, rows, S, y, np, nrhs, xg, red,
+                            [&](int x, double v) { r[x] -= v; });
+    } else {
+      for (int c0 = 0; c0 < NB; c0 += SBC)
+        sbwd_panel<NB, R, SBC>(c0, t0, t1, tlist, rows, S, y, np, nrhs, xg, red,
+                               [&](int x, double v) { r[c0 * R + x] -= v; });
+    }
+  }
   __syncthreads();
   double* part = sm;
   double* s = part + PW * 8 * R;

@@ -65,8 +65,8 @@ struct stc_handle {
   std::vector<int32_t> sfwd_nstep, sbwd_nstep;  // step items leading each launch
   int32_t* d_sfwd_items = nullptr;
   int32_t* d_sbwd_items = nullptr;
-  int32_t* d_sfwd_tl = nullptr;
-  int32_t* d_sbwd_tl = nullptr;
+  TileD* d_sfwd_tl = nullptr;  // descriptors of each item's tiles, in item order
+  TileD* d_sbwd_tl = nullptr;
   std::map<int32_t, hipGraphExec_t> solve_graphs;  // by right-hand sides per sweep
   // binding
   int device = -1;
@@ -88,7 +88,6 @@ struct stc_handle {
   int32_t* d_potrf = nullptr;
   int32_t* d_trsm_items = nullptr;
   int32_t* d_perm = nullptr;
-  TileD* d_tiles = nullptr;
   int32_t* d_rows = nullptr;
   int32_t *d_row_ptr = nullptr, *d_row_tiles = nullptr, *d_col_ptr = nullptr,
           *d_col_tiles = nullptr, *d_fwd_blk = nullptr, *d_bwd_blk = nullptr;
@@ -144,7 +143,6 @@ size_t layout(const stc_handle* hc, int32_t batch, char* base) {
   take(&h->d_potrf, sizeof(int32_t) * h->potrf_list.size());
   take(&h->d_trsm_items, sizeof(int32_t) * h->trsm_items.size());
   take(&h->d_perm, sizeof(int32_t) * (size_t)s.n);
-  take(&h->d_tiles, sizeof(TileD) * s.tiles.size());
   take(&h->d_rows, sizeof(int32_t) * s.rows.size());
   take(&h->d_row_ptr, sizeof(int32_t) * p.row_tiles_ptr.size());
   take(&h->d_row_tiles, sizeof(int32_t) * p.row_tiles.size());
@@ -157,8 +155,8 @@ size_t layout(const stc_handle* hc, int32_t batch, char* base) {
   take(&h->d_y, sizeof(double) * (size_t)padded_n(h) * kMaxRhs);
   take(&h->d_sfwd_items, sizeof(int32_t) * h->sfwd_items.size());
   take(&h->d_sbwd_items, sizeof(int32_t) * h->sbwd_items.size());
-  take(&h->d_sfwd_tl, sizeof(int32_t) * h->sfwd_tl.size());
-  take(&h->d_sbwd_tl, sizeof(int32_t) * h->sbwd_tl.size());
+  take(&h->d_sfwd_tl, sizeof(TileD) * h->sfwd_tl.size());
+  take(&h->d_sbwd_tl, sizeof(TileD) * h->sbwd_tl.size());
   take(&h->d_dinv, sizeof(double) * (size_t)dinv_stride(h) * (size_t)batch);
   take(&h->d_parts, sizeof(double) * (size_t)p.parts * (size_t)batch);
   take(&h->d_zrow, sizeof(double) * (size_t)p.nb);
@@ -381,13 +379,13 @@ void launch_sweeps_r(stc_handle* h, int32_t nr, int32_t g0, hipStream_t st) {
     const int32_t c = h->sfwd_ptr[q], d = h->sfwd_ptr[q + 1];
     if (d > c)
       hipLaunchKernelGGL((k_sfwd_step<NB, R>), dim3(d - c), dim3(256), 0, st, h->d_sfwd_items + 4 * (int64_t)c,
-                       h->sfwd_nstep[q], h->d_sfwd_tl, h->d_tiles, h->d_maps, h->d_store, h->d_dinv, y, np, nr);
+                       h->sfwd_nstep[q], h->d_sfwd_tl, h->d_maps, h->d_store, h->d_dinv, y, np, nr);
   }
   for (size_t q = 0; q < h->sbwd_nstep.size(); ++q) {
     const int32_t c = h->sbwd_ptr[q], d = h->sbwd_ptr[q + 1];
     if (d > c)
       hipLaunchKernelGGL((k_sbwd_step<NB, R>), dim3(d - c), dim3(256), 0, st, h->d_sbwd_items + 4 * (int64_t)c,
-                       h->sbwd_nstep[q], h->d_sbwd_tl, h->d_tiles, h->d_rows, h->d_store, h->d_dinv, y, np, nr);
+                       h->sbwd_nstep[q], h->d_sbwd_tl, h->d_rows, h->d_store, h->d_dinv, y, np, nr);
   }
 }
 
@@ -725,19 +723,22 @@ int stc_bind(stc_handle* h, void* d_ws, size_t bytes, int32_t batch, void* strea
   std::vector<TileD> tl(s.tiles.size());
   for (size_t i = 0; i < tl.size(); ++i)
     tl[i] = TileD{p.tile_off[i], s.tiles[i].roff, s.tiles[i].m, s.tiles[i].k, s.tiles[i].cnt, p.tile_imap[i]};
+  std::vector<TileD> ftl(h->sfwd_tl.size()), btl(h->sbwd_tl.size());
+  for (size_t i = 0; i < ftl.size(); ++i) ftl[i] = tl[(size_t)h->sfwd_tl[i]];
+  for (size_t i = 0; i < btl.size(); ++i) btl[i] = tl[(size_t)h->sbwd_tl[i]];
   int rc = 0;
   if ((rc = upload(h->d_vmap, p.vmap)) || (rc = upload(h->d_maps, p.maps)) ||
       (rc = upload(h->d_upd, upd)) || (rc = upload(h->d_contrib, con)) ||
       (rc = upload(h->d_trsm, tr)) || (rc = upload(h->d_upd_items, h->upd_items)) ||
       (rc = upload(h->d_big_items, h->big_items)) ||
       (rc = upload(h->d_potrf, h->potrf_list)) || (rc = upload(h->d_trsm_items, h->trsm_items)) ||
-      (rc = upload(h->d_perm, s.perm)) || (rc = upload(h->d_tiles, tl)) ||
+      (rc = upload(h->d_perm, s.perm)) ||
       (rc = upload(h->d_rows, s.rows)) || (rc = upload(h->d_row_ptr, p.row_tiles_ptr)) ||
       (rc = upload(h->d_row_tiles, p.row_tiles)) || (rc = upload(h->d_col_ptr, p.col_tiles_ptr)) ||
       (rc = upload(h->d_col_tiles, p.col_tiles)) || (rc = upload(h->d_fwd_blk, p.fwd_level_blk)) ||
       (rc = upload(h->d_bwd_blk, p.bwd_level_blk)) || (rc = upload(h->d_sfwd_items, h->sfwd_items)) ||
-      (rc = upload(h->d_sbwd_items, h->sbwd_items)) || (rc = upload(h->d_sfwd_tl, h->sfwd_tl)) ||
-      (rc = upload(h->d_sbwd_tl, h->sbwd_tl)))
+      (rc = upload(h->d_sbwd_items, h->sbwd_items)) || (rc = upload(h->d_sfwd_tl, ftl)) ||
+      (rc = upload(h->d_sbwd_tl, btl)))
     return rc;
   HIPCHK(hipMemset(h->d_zrow, 0, sizeof(double) * (size_t)p.nb));
   const BackPlan& bp = h->back;
