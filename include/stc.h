@@ -210,6 +210,19 @@ int stc_get_work(const stc_handle* h, double* work);
    null argument, or STC_ERR_SCHEDULE with stc_last_error naming the pair. */
 int stc_check_schedule(const stc_handle* h, int64_t* stats);
 
+/* Host check of the solve's work items (Sec. 6.7: the sweeps over the
+   resident factor), no device work.  Per sweep it replays the launches in
+   order, the items of one launch taken as concurrent, and verifies that every
+   block is solved by exactly one step item, only after every tile that feeds
+   it has been applied; that every tile is applied exactly once (whole, or as
+   one of each of its row / column chunks) and only after a launch that
+   solved its source block; and that no two items of a launch write the same
+   rows.  stats (host) int64[4] receives, over both sweeps: launches, step
+   items, panel items, launches holding both kinds.  Returns 0,
+   STC_ERR_ARG for a null argument, or STC_ERR_SCHEDULE with stc_last_error
+   naming the violation. */
+int stc_check_solve_schedule(const stc_handle* h, int64_t* stats);
+
 /* Measurement helper: one factorization of d_values (device) double[nnz]
    with the same kernels as stc_factorize, launched one by one instead of from
    the graph, with a HIP event pair around each launch on `stream`;

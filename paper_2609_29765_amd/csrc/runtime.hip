@@ -543,6 +543,69 @@ int check_bound(const stc_handle* h) {
 
 }  // namespace
 
+// one sweep's work items against its tile dependencies: launches run in
+// order, the items of one launch concurrently
+static int check_sweep(const stc_handle* h, bool fwd, const std::vector<int32_t>& items,
+                       const std::vector<int32_t>& ptr, const std::vector<int32_t>& nstep,
+                       const std::vector<int32_t>& tl, int32_t chunk, int64_t* st) {
+  const char* sw = fwd ? "forward" : "backward";
+  const int32_t NT = h->sym.NT, nb = h->plan.nb;
+  const int32_t nch = (nb + chunk - 1) / chunk;
+  const size_t ntl = h->sym.tiles.size();
+  auto bad = [&](const std::string& why) { return fail(STC_ERR_SCHEDULE, std::string(sw) + " solve: " + why); };
+  if (ptr.size() != nstep.size() + 1 || ptr.front() != 0 || (size_t)ptr.back() * 4 != items.size())
+    return bad("launch table does not cover the items");
+  std::vector<int32_t> solved((size_t)NT, -1), need((size_t)NT, 0), got((size_t)NT, 0);
+  std::vector<int64_t> done(ntl, 0);  // bit c: chunk c applied; all bits: whole tile
+  const int64_t all = (nch >= 63) ? -1 : ((int64_t(1) << nch) - 1);
+  for (const TileInfo& t : h->sym.tiles) ++need[(size_t)(fwd ? t.m : t.k)];
+  std::map<int64_t, int32_t> owner;  // (block, chunk) -> item, per launch
+  for (size_t q = 0; q < nstep.size(); ++q) {
+    owner.clear();
+    const int32_t a = ptr[q], b = ptr[q + 1];
+    if (b < a || nstep[q] < 0 || nstep[q] > b - a) return bad("bad launch bounds");
+    for (int32_t it = a; it < b; ++it) {
+      const int32_t blk = items[4 * (size_t)it], i0 = items[4 * (size_t)it + 1];
+      const int32_t t0 = items[4 * (size_t)it + 2], t1 = items[4 * (size_t)it + 3];
+      const bool step = it - a < nstep[q];
+      if (blk < 0 || blk >= NT || t0 < 0 || t1 < t0 || (size_t)t1 > tl.size()) return bad("item out of range");
+      if (solved[(size_t)blk] >= 0) return bad("block " + std::to_string(blk) + " written after it was solved");
+      if (!step && (i0 < 0 || i0 >= nb || i0 % chunk)) return bad("chunk offset out of range");
+      for (int32_t c = step ? 0 : i0 / chunk; c < (step ? nch : i0 / chunk + 1); ++c)
+        if (!owner.emplace((int64_t)blk * nch + c, it).second)
+          return bad("two items of one launch write block " + std::to_string(blk));
+      for (int32_t z = t0; z < t1; ++z) {
+        const int32_t t = tl[(size_t)z];
+        if (t < 0 || (size_t)t >= ntl) return bad("tile out of range");
+        const TileInfo& ti = h->sym.tiles[(size_t)t];
+        const int32_t fed = fwd ? ti.m : ti.k, src = fwd ? ti.k : ti.m;
+        if (fed != blk) return bad("tile " + std::to_string(t) + " applied to a block it does not feed");
+        if (solved[(size_t)src] < 0 || solved[(size_t)src] >= (int32_t)q)
+          return bad("tile " + std::to_string(t) + " applied before its source block was solved");
+        const int64_t bits = step ? all : (int64_t(1) << (i0 / chunk));
+        if (done[(size_t)t] & bits) return bad("tile " + std::to_string(t) + " applied twice");
+        done[(size_t)t] |= bits;
+        if (done[(size_t)t] == all) ++got[(size_t)blk];
+      }
+      if (step) {
+        ++st[1];
+        if (got[(size_t)blk] != need[(size_t)blk])
+          return bad("block " + std::to_string(blk) + " solved before all its tiles were applied");
+      } else {
+        ++st[2];
+      }
+    }
+    // blocks are marked solved after the launch: no item of a launch reads
+    // a block that another item of it solves
+    for (int32_t it = a; it < a + nstep[q]; ++it) solved[(size_t)items[4 * (size_t)it]] = (int32_t)q;
+    st[0] += 1;
+    if (nstep[q] > 0 && b - a > nstep[q]) st[3] += 1;
+  }
+  for (int32_t k = 0; k < NT; ++k)
+    if (solved[(size_t)k] < 0) return bad("block " + std::to_string(k) + " never solved");
+  return 0;
+}
+
 extern "C" {
 
 const char* stc_last_error(void) { return g_err.c_str(); }
@@ -930,6 +993,17 @@ int stc_get_tiles(const stc_handle* h, int32_t* m, int32_t* k, int32_t* cnt, int
 int stc_get_tasks(const stc_handle* h, int32_t* tasks) {
   if (!h || !tasks) return fail(STC_ERR_ARG, "null argument");
   std::copy(h->sym.tasks.begin(), h->sym.tasks.end(), tasks);
+  return 0;
+}
+
+int stc_check_solve_schedule(const stc_handle* h, int64_t* stats) {
+  if (!h || !stats) return fail(STC_ERR_ARG, "null argument");
+  int64_t st[4] = {0, 0, 0, 0};
+  int rc = check_sweep(h, true, h->sfwd_items, h->sfwd_ptr, h->sfwd_nstep, h->sfwd_tl, SCH, st);
+  if (rc) return rc;
+  rc = check_sweep(h, false, h->sbwd_items, h->sbwd_ptr, h->sbwd_nstep, h->sbwd_tl, SBC, st);
+  if (rc) return rc;
+  std::memcpy(stats, st, sizeof(st));
   return 0;
 }
 

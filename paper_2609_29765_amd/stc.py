@@ -31,7 +31,7 @@ EXPORTS = [
     "stc_analyse", "stc_workspace_bytes", "stc_bind", "stc_factorize", "stc_factorize_batched",
     "stc_logdet", "stc_solve", "stc_logdet_backward", "stc_info", "stc_get_sizes",
     "stc_get_features", "stc_get_perm", "stc_get_etree", "stc_get_L_pattern", "stc_get_tiles",
-    "stc_get_tasks", "stc_get_factor", "stc_get_work", "stc_check_schedule", "stc_profile_factorize",
+    "stc_get_tasks", "stc_get_factor", "stc_get_work", "stc_check_schedule", "stc_check_solve_schedule", "stc_profile_factorize",
     "stc_fp64_mfma_peak", "stc_destroy",
     "stc_last_error",
 ]
@@ -78,6 +78,7 @@ def lib():
     L.stc_get_factor.argtypes = [vp, _f64p, vp]
     L.stc_get_work.argtypes = [vp, _f64p]
     L.stc_check_schedule.argtypes = [vp, _i64p]
+    L.stc_check_solve_schedule.argtypes = [vp, _i64p]
     L.stc_profile_factorize.argtypes = [vp, vp, vp, _f64p, _i64p, _f64p]
     L.stc_fp64_mfma_peak.argtypes = [vp, _f64p]
     L.stc_destroy.argtypes = [vp]
@@ -284,6 +285,14 @@ class Analysis:
         st = np.zeros(4, dtype=np.int64)
         _check(lib().stc_check_schedule(self._h, st))
         return dict(zip(["nodes", "edges", "unordered_pairs", "objects"], (int(x) for x in st)))
+
+    def check_solve_schedule(self):
+        """Host check of the solve sweeps' work items against the tile
+        dependencies (see stc_check_solve_schedule); raises on a violation.
+        Returns {launches, step_items, panel_items, fused_launches}."""
+        st = np.zeros(4, dtype=np.int64)
+        _check(lib().stc_check_solve_schedule(self._h, st))
+        return dict(zip(["launches", "step_items", "panel_items", "fused_launches"], (int(x) for x in st)))
 
     KERNEL_KINDS = ["load", "k_potrf", "k_upd<G>", "k_upd", "k_trsm"]
 

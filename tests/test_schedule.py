@@ -7,6 +7,13 @@ what every kernel reads and writes and verifies that each two kernels that
 touch one object, one of them writing it, are ordered by the graph.  Small
 work-group slot counts force split K streams (partial slots folded by a later
 task) and separate last-group update nodes, so every kind of edge occurs.
+
+The same patterns go through stc_check_solve_schedule, which replays the
+solve sweeps' launches (Sec. 6.7) and verifies that each block is solved once,
+after all tiles feeding it, and each tile applied once, after its source
+block, with no two items of a launch writing the same rows.  Tile sizes 32
+to 256 cover fused levels (step items that apply their tiles) and split
+ones (n_b 256 dense: a launch of chunks, then one of diagonal solves).
 """
 import numpy as np
 import pytest
@@ -24,6 +31,13 @@ def _check(w, nb, ordering, mode="auto", wg_slots=0):
     st = a.check_schedule()
     assert st["nodes"] >= 1 and st["objects"] >= 1
     assert st["edges"] >= st["nodes"] - 1 - st["unordered_pairs"] or st["nodes"] == 1
+    sv = a.check_solve_schedule()
+    assert sv["step_items"] == 2 * a.NT
+    assert sv["launches"] == a.solve_launches >= 2
+    if a.nb <= 64:  # a step item reads no more than a chunk: every level is one launch
+        assert sv["launches"] <= 2 * a.NT
+    if a.nb == 256 and a.mode == "dense" and a.NT > 2:  # full 256-row tiles: those levels split
+        assert sv["launches"] > 2 * a.NT
     return st
 
 
