@@ -1382,6 +1382,74 @@ constexpr int SR = 8;      // right-hand sides per sweep
 constexpr int SCH = 64;    // block rows of a forward panel chunk
 constexpr int SBC = 64;    // columns of a backward panel chunk
 
+// sum of each value over the 8 adjacent lanes of a row group, left in every
+// lane of the group: ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7)), a_j
+// the value of lane j (every lane forms the same sums, addition commuting)
+template <int R>
+__device__ __forceinline__ void rowsum8(double (&a)[R]) {
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    a[c] += __shfl_xor(a[c], 1);
+    a[c] += __shfl_xor(a[c], 2);
+    a[c] += __shfl_xor(a[c], 4);
+  }
+}
+
+// the same sum of v[0], v[st], .., v[7 st] in one thread
+__device__ __forceinline__ double tree8(const double* v, int st) {
+  return ((v[0] + v[st]) + (v[2 * st] + v[3 * st])) + ((v[4 * st] + v[5 * st]) + (v[6 * st] + v[7 * st]));
+}
+
+// one 32-row diagonal step after the K-split parts: s = r_J - (sum of the 8
+// parts of each entry), then r_J = D s (forward, D_J) or D^T s (backward),
+// each entry's 32 products taken as 8 chains of 4 (q = z, z + 8, z + 16,
+// z + 24) summed as above.  R = 1 keeps the parts in the 8 lanes of a row and
+// sums by shuffles (three barriers per step); wider R, whose entries already
+// fill the work-group, goes through LDS with one thread per (entry, column).
+// Both forms do the same arithmetic, so a column's result does not depend on
+// R.  acc holds this thread's parts (row = tid / 8, lane sub = tid % 8);
+// enters after the step's staging barrier, ends with a barrier.
+template <int R, bool TRANS>
+__device__ __forceinline__ void diag_step(double (&acc)[R], double* rJ, double* s, double* part,
+                                          const double* Ds) {
+  const int tid = threadIdx.x, row = tid >> 3, sub = tid & 7;
+  auto dv = [&](int i, int q) { return TRANS ? Ds[q * PLD + i] : Ds[i * PLD + q]; };
+  if constexpr (R == 1) {
+    rowsum8<1>(acc);
+    if (sub == 0) s[row] = rJ[row] - acc[0];
+    __syncthreads();
+    double a = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) a = fma(dv(row, sub + 8 * t), s[sub + 8 * t], a);
+    double b[1] = {a};
+    rowsum8<1>(b);
+    if (sub == 0) rJ[row] = b[0];
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int c = 0; c < R; ++c) part[(row * 8 + sub) * R + c] = acc[c];
+    __syncthreads();
+    if (tid < PW * R) {
+      const int i = tid / R, c = tid % R;
+      s[tid] = rJ[tid] - tree8(part + i * 8 * R + c, R);
+    }
+    __syncthreads();
+    if (tid < PW * R) {
+      const int i = tid / R, c = tid % R;
+      double ch[8];
+#pragma unroll
+      for (int z = 0; z < 8; ++z) {
+        double a = 0.0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a = fma(dv(i, z + 8 * t), s[(z + 8 * t) * R + c], a);
+        ch[z] = a;
+      }
+      rJ[tid] = tree8(ch, 1);
+    }
+    __syncthreads();
+  }
+}
+
 // forward products for rows i0 .. i0 + 32 H - 1 (tiles [t0, t1)): for each row i,
 // sum over the tiles (m, k) of L_mk(q(i)) y_k, q(i) the tile's stored row of
 // block row i (its inverse row map; identity when the tile is full), handed
@@ -1472,15 +1540,15 @@ __device__ __forceinline__ void sfwd_fetch(int32_t k, int J, const double* __res
 
 // r <- L_kk^-1 r (r[i * R + c] in LDS): per 32-row block J, the block row of
 // L_kk left of the diagonal block and the block's inverse are staged in LDS
-// (coalesced), then s = r_J - L_(J,<J) r_(<J) with the K range split over 8
-// threads per row (each keeping all right-hand sides) and the parts summed
-// in a fixed order, then r_J = D_J s.  Steps alternate between two register
+// (coalesced), then s = r_J - L_(J,<J) r_(<J) with the K range split over
+// the 8 adjacent lanes of a row (each keeping all right-hand sides), and
+// r_J = D_J s (diag_step).  Steps alternate between two register
 // sets, step J + 2's rows being read during step J; steps 0 and 1 must be in
 // f0 and f1 on entry (sfwd_fetch).  Ends with a barrier.
 template <int NB, int R>
 __device__ __forceinline__ void sfwd_diag(int32_t k, const double* __restrict__ S, const double* __restrict__ dinv,
                                           DiagFetch<NB, double2>& f0, DiagFetch<NB, double2>& f1, double* r,
-                                          double* part, double* s, double* Ls, double* Ds) {
+                                          double* s, double* part, double* Ls, double* Ds) {
   constexpr int LW = NB - PW + 1;
   constexpr int NPF = DiagFetch<NB, double2>::N;
   const int tid = threadIdx.x;
@@ -1514,25 +1582,7 @@ __device__ __forceinline__ void sfwd_diag(int32_t k, const double* __restrict__ 
 #pragma unroll
       for (int c = 0; c < R; ++c) acc[c] = fma(l, r[p * R + c], acc[c]);
     }
-#pragma unroll
-    for (int c = 0; c < R; ++c) part[(row * 8 + sub) * R + c] = acc[c];
-    __syncthreads();
-    if (tid < PW * R) {
-      const int i = tid / R, c = tid % R;
-      double v = r[(w + i) * R + c];
-#pragma unroll
-      for (int z = 0; z < 8; ++z) v -= part[(i * 8 + z) * R + c];
-      s[i * R + c] = v;
-    }
-    __syncthreads();
-    if (tid < PW * R) {
-      const int i = tid / R, c = tid % R;
-      double u = 0.0;
-#pragma unroll 8
-      for (int q = 0; q < PW; ++q) u = fma(Ds[i * PLD + q], s[q * R + c], u);
-      r[(w + i) * R + c] = u;
-    }
-    __syncthreads();
+    diag_step<R, false>(acc, r + w * R, s, part, Ds);
   }
 }
 
@@ -1546,10 +1596,10 @@ __global__ __launch_bounds__(256) void k_sfwd_step(const int32_t* __restrict__ i
                                                    const double* __restrict__ S,
                                                    const double* __restrict__ dinv,
                                                    double* __restrict__ y, int64_t np, int32_t nrhs) {
-  static_assert(NB <= 256, "the gathered y_k shares the partial sums' LDS");
   constexpr int LW = NB - PW + 1;
   __shared__ double r[NB * R];
-  __shared__ double part[PW * 8 * R];  // also the gathered y_k of the products
+  __shared__ double ys[(R == 1 ? NB : 256) * R];  // the gathered y_k of the products, then
+                                                  // the diagonal steps' parts (R > 1)
   __shared__ double s[PW * R];
   __shared__ double Ls[PW * LW];
   __shared__ double Ds[PW * PLD];
@@ -1557,7 +1607,7 @@ __global__ __launch_bounds__(256) void k_sfwd_step(const int32_t* __restrict__ i
   const int32_t t0 = items[4 * blockIdx.x + 2], t1 = items[4 * blockIdx.x + 3];
   double* ym = y + (int64_t)m * NB;
   if ((int32_t)blockIdx.x >= nstep) {
-    sfwd_panel<NB, R, SCH / 32>(i0, t0, t1, tlist, maps, S, y, np, nrhs, part,
+    sfwd_panel<NB, R, SCH / 32>(i0, t0, t1, tlist, maps, S, y, np, nrhs, ys,
                                 [&](int i, int c, double v) { ym[(int64_t)c * np + i] -= v; });
     return;
   }
@@ -1573,14 +1623,14 @@ __global__ __launch_bounds__(256) void k_sfwd_step(const int32_t* __restrict__ i
   auto put_r = [&](int i, int c, double v) { r[i * R + c] -= v; };
   if (t1 > t0) {
     if constexpr (NB <= 128) {
-      sfwd_panel<NB, R, NB / 32>(0, t0, t1, tlist, maps, S, y, np, nrhs, part, put_r);
+      sfwd_panel<NB, R, NB / 32>(0, t0, t1, tlist, maps, S, y, np, nrhs, ys, put_r);
     } else {
       for (int c0 = 0; c0 < NB; c0 += SCH)
-        sfwd_panel<NB, R, SCH / 32>(c0, t0, t1, tlist, maps, S, y, np, nrhs, part, put_r);
+        sfwd_panel<NB, R, SCH / 32>(c0, t0, t1, tlist, maps, S, y, np, nrhs, ys, put_r);
     }
   }
   __syncthreads();
-  sfwd_diag<NB, R>(m, S, dinv, f0, f1, r, part, s, Ls, Ds);
+  sfwd_diag<NB, R>(m, S, dinv, f0, f1, r, s, ys, Ls, Ds);
   for (int x = tid; x < NB * R; x += 256) {
     const int i = x / R, c = x % R;
     if (c < nrhs) ym[(int64_t)c * np + i] = r[x];
@@ -1676,14 +1726,14 @@ __device__ __forceinline__ void sbwd_fetch(int32_t k, int J, const double* __res
 // r <- L_kk^-T r (r[i * R + c] in LDS): per 32-row block J from the last, the
 // block column of L_kk below the diagonal block and the block's inverse are
 // staged in LDS (coalesced), then s = r_J - L_(>J,J)^T r_(>J) with the row
-// range split over 8 threads per column (parts summed in a fixed order), then
-// r_J = D_J^T s.  Steps alternate between two register sets, step J - 2's
+// range split over the 8 adjacent lanes of a column, and r_J = D_J^T s
+// (diag_step).  Steps alternate between two register sets, step J - 2's
 // rows being read during step J; the last two steps' must be in f0 (the last)
 // and f1 on entry (sbwd_fetch).  Ends with a barrier.
 template <int NB, int R>
 __device__ __forceinline__ void sbwd_diag(int32_t k, const double* __restrict__ S, const double* __restrict__ dinv,
                                           DiagFetch<NB, double4>& f0, DiagFetch<NB, double4>& f1, double* r,
-                                          double* part, double* s, double* Lc, double* Ds) {
+                                          double* s, double* part, double* Lc, double* Ds) {
   constexpr int NPF = DiagFetch<NB, double4>::N;
   constexpr int NJ = NB / PW;
   const int tid = threadIdx.x;
@@ -1719,35 +1769,17 @@ __device__ __forceinline__ void sbwd_diag(int32_t k, const double* __restrict__ 
 #pragma unroll
       for (int c = 0; c < R; ++c) acc[c] = fma(l, r[(p0 + p) * R + c], acc[c]);
     }
-#pragma unroll
-    for (int c = 0; c < R; ++c) part[(row * 8 + sub) * R + c] = acc[c];
-    __syncthreads();
-    if (tid < PW * R) {
-      const int i = tid / R, c = tid % R;
-      double v = r[(J * PW + i) * R + c];
-#pragma unroll
-      for (int z = 0; z < 8; ++z) v -= part[(i * 8 + z) * R + c];
-      s[i * R + c] = v;
-    }
-    __syncthreads();
-    if (tid < PW * R) {
-      const int i = tid / R, c = tid % R;
-      double u = 0.0;
-#pragma unroll 8
-      for (int q = 0; q < PW; ++q) u = fma(Ds[q * PLD + i], s[q * R + c], u);
-      r[(J * PW + i) * R + c] = u;
-    }
-    __syncthreads();
+    diag_step<R, true>(acc, r + J * PW * R, s, part, Ds);
   }
 }
 
 // one backward launch: items [4 * b] = (block, first column, t0, t1), tiles
 // [t0, t1) of tlist; the first nstep items are step items (first column
-// unused), the rest panel chunks.  The diagonal phase's LDS (part | s | Lc | Ds) and the products'
-// LDS (xg | red) share one buffer.
+// unused), the rest panel chunks.  The diagonal phase's LDS (s | parts |
+// Lc | Ds) and the products' LDS (xg | red) share one buffer.
 template <int NB, int R>
 struct SbwdLds {
-  static constexpr int DIAG = PW * 8 * R + PW * R + (NB - PW) * PLD + 1 + PW * PLD;
+  static constexpr int DIAG = PW * R + (R == 1 ? 0 : PW * 8 * R) + (NB - PW) * PLD + 1 + PW * PLD;
   static constexpr int PROD = NB * R + 512 * R;  // xg, then SH x CW x R partial sums
   static constexpr int SIZE = DIAG > PROD ? DIAG : PROD;
 };
@@ -1791,11 +1823,11 @@ __global__ __launch_bounds__(256) void k_sbwd_step(const int32_t* __restrict__ i
     }
   }
   __syncthreads();
-  double* part = sm;
-  double* s = part + PW * 8 * R;
-  double* Lc = s + PW * R;
+  double* s = sm;
+  double* part = s + PW * R;
+  double* Lc = part + (R == 1 ? 0 : PW * 8 * R);
   double* Ds = Lc + (NB - PW) * PLD + 1;
-  sbwd_diag<NB, R>(k, S, dinv, f0, f1, r, part, s, Lc, Ds);
+  sbwd_diag<NB, R>(k, S, dinv, f0, f1, r, s, part, Lc, Ds);
   for (int x = tid; x < NB * R; x += 256) {
     const int i = x / R, c = x % R;
     if (c < nrhs) yk[(int64_t)c * np + i] = r[x];
