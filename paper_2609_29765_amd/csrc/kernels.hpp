@@ -1515,6 +1515,72 @@ __device__ __forceinline__ void sfwd_panel(int32_t i0, int32_t t0, int32_t t1, c
   }
 }
 
+// forward products of a step item whose block has at most 128 rows: for
+// each tile (m, k) in order, each stored row q takes r(rows(q)) -= L_mk(q)
+// y_k.  A tile's stored rows are distinct block rows, so a tile's updates do
+// not collide, and the tiles follow one another behind barriers.  Reading
+// the stored rows directly (their block rows loaded beside them) keeps the
+// tile's row map off the load chain.  Layout as in sfwd_panel, NB / 32 rows
+// per thread.
+template <int NB, int R>
+__device__ __forceinline__ void sfwd_step_products(int32_t t0, int32_t t1, const TileD* __restrict__ tlist,
+                                                   const int32_t* __restrict__ rows,
+                                                   const double* __restrict__ S, const double* __restrict__ y,
+                                                   int64_t np, int32_t nrhs, double* ys, double* r) {
+  constexpr int NC = NB / 16, H = NB / 32;
+  const int tid = threadIdx.x;
+  const int j = tid & 7, rl = tid >> 3;
+  for (int32_t z = t0; z < t1; ++z) {
+    const TileD tl = tlist[z];
+    double2 lv[H][NC];
+    int32_t dst[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      const int q = rl + 32 * h;
+      const bool ok = q < tl.cnt;
+      dst[h] = ok ? rows[tl.roff + q] : -1;
+      const double* Lr = S + tl.off + (int64_t)(ok ? q : 0) * NB + 2 * j;
+#pragma unroll
+      for (int u = 0; u < NC; ++u)
+        lv[h][u] = ok ? *reinterpret_cast<const double2*>(Lr + 16 * u) : make_double2(0.0, 0.0);
+    }
+    __syncthreads();  // ys is free, the previous tile's updates are done
+    for (int x = tid; x < NB * R; x += 256) {
+      const int col = x / R, c = x % R;
+      ys[x] = c < nrhs ? y[(int64_t)c * np + (int64_t)tl.k * NB + col] : 0.0;
+    }
+    __syncthreads();
+    double acc[H][R];
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+      for (int c = 0; c < R; ++c) acc[h][c] = 0.0;
+#pragma unroll
+    for (int u = 0; u < NC; ++u) {
+      const int col = 2 * j + 16 * u;
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        const double y0 = ys[col * R + c], y1 = ys[(col + 1) * R + c];
+#pragma unroll
+        for (int h = 0; h < H; ++h) acc[h][c] = fma(lv[h][u].x, y0, fma(lv[h][u].y, y1, acc[h][c]));
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        acc[h][c] += __shfl_xor(acc[h][c], 1);
+        acc[h][c] += __shfl_xor(acc[h][c], 2);
+        acc[h][c] += __shfl_xor(acc[h][c], 4);
+      }
+      double mine = acc[h][0];  // lane j of the row group keeps right-hand side j
+#pragma unroll
+      for (int c = 1; c < R; ++c) mine = j == c ? acc[h][c] : mine;
+      if (dst[h] >= 0 && j < nrhs) r[dst[h] * R + j] -= mine;
+    }
+  }
+}
+
 // registers that carry a diagonal step's block row (forward) or block
 // column (backward) of L_kk and its 32 x 32 inverse from global memory to LDS
 template <int NB, class V>
@@ -1593,6 +1659,7 @@ template <int NB, int R>
 __global__ __launch_bounds__(256) void k_sfwd_step(const int32_t* __restrict__ items, int32_t nstep,
                                                    const TileD* __restrict__ tlist,
                                                    const int32_t* __restrict__ maps,
+                                                   const int32_t* __restrict__ rows,
                                                    const double* __restrict__ S,
                                                    const double* __restrict__ dinv,
                                                    double* __restrict__ y, int64_t np, int32_t nrhs) {
@@ -1619,11 +1686,11 @@ __global__ __launch_bounds__(256) void k_sfwd_step(const int32_t* __restrict__ i
     const int i = x / R, c = x % R;
     r[x] = c < nrhs ? ym[(int64_t)c * np + i] : 0.0;
   }
-  // up to n_b 128 one pass over the tiles covers every row, else 64-row chunks
+  // up to n_b 128 one pass over the tiles' stored rows, else 64-row chunks
   auto put_r = [&](int i, int c, double v) { r[i * R + c] -= v; };
   if (t1 > t0) {
     if constexpr (NB <= 128) {
-      sfwd_panel<NB, R, NB / 32>(0, t0, t1, tlist, maps, S, y, np, nrhs, ys, put_r);
+      sfwd_step_products<NB, R>(t0, t1, tlist, rows, S, y, np, nrhs, ys, r);
     } else {
       for (int c0 = 0; c0 < NB; c0 += SCH)
         sfwd_panel<NB, R, SCH / 32>(c0, t0, t1, tlist, maps, S, y, np, nrhs, ys, put_r);

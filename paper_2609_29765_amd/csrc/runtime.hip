@@ -379,7 +379,7 @@ void launch_sweeps_r(stc_handle* h, int32_t nr, int32_t g0, hipStream_t st) {
     const int32_t c = h->sfwd_ptr[q], d = h->sfwd_ptr[q + 1];
     if (d > c)
       hipLaunchKernelGGL((k_sfwd_step<NB, R>), dim3(d - c), dim3(256), 0, st, h->d_sfwd_items + 4 * (int64_t)c,
-                       h->sfwd_nstep[q], h->d_sfwd_tl, h->d_maps, h->d_store, h->d_dinv, y, np, nr);
+                       h->sfwd_nstep[q], h->d_sfwd_tl, h->d_maps, h->d_rows, h->d_store, h->d_dinv, y, np, nr);
   }
   for (size_t q = 0; q < h->sbwd_nstep.size(); ++q) {
     const int32_t c = h->sbwd_ptr[q], d = h->sbwd_ptr[q + 1];
