@@ -199,6 +199,29 @@ def test_solve_many_right_hand_sides(nb, mode, nrhs):
     assert np.array_equal(x1, X[:, 0])
 
 
+def test_solve_mixed_fused_and_split_levels():
+    # n_b 256 on a sparse grid: levels whose step items read few stored rows
+    # apply their tiles inside the step item (in 64-row chunks), the others
+    # get a launch of chunks and then one of diagonal solves
+    w = W.gmrf_grid2d(60, 60)
+    o = O.Analysis(w.n, w.colptr, w.rowind, "nd", nb=256, mode="semisparse")
+    Lo, info_o = o.factor(w.values)
+    assert info_o == 0
+    a = S.Analysis(w.n, w.colptr, w.rowind, nb=256, mode="semisparse", ordering="nd").bind()
+    sv = a.check_solve_schedule()
+    assert sv["fused_launches"] > 0 and sv["launches"] > 2 * a.NT
+    print(f"[gpu] solve n={w.n} nb=256 semisparse, {sv['launches']} launches", flush=True)
+    a.factorize(dev(w.values))
+    assert a.info() == 0
+    B = np.random.default_rng(5).standard_normal((w.n, 8))
+    X = a.solve(dev(B)).cpu().numpy()
+    Xo = o.solve(Lo, B)
+    for c in range(8):
+        assert np.max(np.abs(X[:, c] - Xo[:, c])) <= 1e-10 * np.max(np.abs(Xo[:, c])), c
+    x1 = a.solve(dev(B[:, 3].copy())).cpu().numpy()
+    assert np.array_equal(x1, X[:, 3])
+
+
 def test_solve_rejects_bad_column_counts():
     w = W.random_spd(100, 0.05, 3)
     a = S.Analysis(w.n, w.colptr, w.rowind, nb=32, ordering="nd").bind()
