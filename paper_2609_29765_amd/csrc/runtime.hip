@@ -89,8 +89,6 @@ struct stc_handle {
   int32_t* d_trsm_items = nullptr;
   int32_t* d_perm = nullptr;
   int32_t* d_rows = nullptr;
-  int32_t *d_row_ptr = nullptr, *d_row_tiles = nullptr, *d_col_ptr = nullptr,
-          *d_col_tiles = nullptr, *d_fwd_blk = nullptr, *d_bwd_blk = nullptr;
   double* d_store = nullptr;  // batch stores
   double* d_y = nullptr;      // solve scratch
   double* d_dinv = nullptr;   // inverses of the 32 x 32 diagonal blocks, per member
@@ -144,12 +142,6 @@ size_t layout(const stc_handle* hc, int32_t batch, char* base) {
   take(&h->d_trsm_items, sizeof(int32_t) * h->trsm_items.size());
   take(&h->d_perm, sizeof(int32_t) * (size_t)s.n);
   take(&h->d_rows, sizeof(int32_t) * s.rows.size());
-  take(&h->d_row_ptr, sizeof(int32_t) * p.row_tiles_ptr.size());
-  take(&h->d_row_tiles, sizeof(int32_t) * p.row_tiles.size());
-  take(&h->d_col_ptr, sizeof(int32_t) * p.col_tiles_ptr.size());
-  take(&h->d_col_tiles, sizeof(int32_t) * p.col_tiles.size());
-  take(&h->d_fwd_blk, sizeof(int32_t) * p.fwd_level_blk.size());
-  take(&h->d_bwd_blk, sizeof(int32_t) * p.bwd_level_blk.size());
   take(&h->d_info, sizeof(int32_t) * (size_t)batch);
   take(&h->d_ld, sizeof(double) * (size_t)batch);
   take(&h->d_y, sizeof(double) * (size_t)padded_n(h) * kMaxRhs);
@@ -796,10 +788,7 @@ int stc_bind(stc_handle* h, void* d_ws, size_t bytes, int32_t batch, void* strea
       (rc = upload(h->d_big_items, h->big_items)) ||
       (rc = upload(h->d_potrf, h->potrf_list)) || (rc = upload(h->d_trsm_items, h->trsm_items)) ||
       (rc = upload(h->d_perm, s.perm)) ||
-      (rc = upload(h->d_rows, s.rows)) || (rc = upload(h->d_row_ptr, p.row_tiles_ptr)) ||
-      (rc = upload(h->d_row_tiles, p.row_tiles)) || (rc = upload(h->d_col_ptr, p.col_tiles_ptr)) ||
-      (rc = upload(h->d_col_tiles, p.col_tiles)) || (rc = upload(h->d_fwd_blk, p.fwd_level_blk)) ||
-      (rc = upload(h->d_bwd_blk, p.bwd_level_blk)) || (rc = upload(h->d_sfwd_items, h->sfwd_items)) ||
+      (rc = upload(h->d_rows, s.rows)) || (rc = upload(h->d_sfwd_items, h->sfwd_items)) ||
       (rc = upload(h->d_sbwd_items, h->sbwd_items)) || (rc = upload(h->d_sfwd_tl, ftl)) ||
       (rc = upload(h->d_sbwd_tl, btl)))
     return rc;
