@@ -114,6 +114,39 @@ def semisparse_pass():
           flush=True)
 
 
+def solve_pass():
+    """Kernel-trace runs over the solve: the spatio-temporal arrowhead
+    (n = 101,258, tile 128, ND) factorized once, then three solves with one
+    right-hand side and three with eight, each group's sweeps replayed from
+    its graph (the first call of a group captures it).  Prints one JSON line
+    with the event-timed solves and the sweeps' launch count."""
+    import torch
+    stc = load_lib()
+    from paper_2609_29765_amd import workloads
+    w = workloads.spatiotemporal_arrowhead()
+    v = torch.from_numpy(w.values).cuda()
+    a = stc.Analysis(w.n, w.colptr, w.rowind, nb=128, ordering="nd").bind()
+    a.factorize(v)
+    torch.cuda.synchronize()
+    assert a.info() == 0
+    g = torch.Generator(device="cuda").manual_seed(0)
+    out = {}
+    for nrhs in (1, 8):
+        b = torch.randn((w.n,) if nrhs == 1 else (w.n, nrhs), dtype=torch.float64, device="cuda", generator=g)
+        ms = []
+        for _ in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            a.solve(b)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        out[f"solve_{nrhs}rhs_ms"] = [round(x, 3) for x in ms]
+    print(json.dumps({"workload": "spatio-temporal arrowhead n=101258, tile 128, ND",
+                      "sweep_launches": a.solve_launches, **out}), flush=True)
+
+
 def kind_table(prof, work):
     """Per kernel kind of one eager factorization: time, launches, FP64
     TFLOP/s of the tile-algorithmic flops (update, POTRF, TRSM kinds) and, for
@@ -453,6 +486,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=5120)
     ap.add_argument("--extras-out", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--solve-pass", action="store_true",
+                    help="factorize the semisparse config, then solve it 3 times with 1 and with 8 "
+                         "right-hand sides (for a kernel trace), print one JSON line and exit")
     ap.add_argument("--semisparse-pass", action="store_true",
                     help="only: one eager C3 factorization (kernel by kernel) and a 1 GiB copy, "
                          "for counter runs over the active-column route")
@@ -465,6 +501,9 @@ def main():
         sys.exit(2)
     if args.extras_out:
         run_extras(args.extras_out, args.batch)
+        return
+    if args.solve_pass:
+        solve_pass()
         return
     if args.semisparse_pass:
         semisparse_pass()
