@@ -22,6 +22,8 @@
  *   - The caller owns every device buffer (workspace, values, right-hand
  *     sides, outputs) and every stream.  The library allocates no device
  *     memory: stc_workspace_bytes() says how much the caller must provide.
+ *     The one exception is the static per-device array (32 MiB) that
+ *     stc_solve_noalloc uses in place of workspace scratch.
  *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
  *     Calls taking a stream are asynchronous with respect to the host.
  *   - A handle is not thread-safe; distinct handles are independent.
@@ -139,8 +141,25 @@ int stc_logdet(stc_handle* h, double* d_out, void* stream);
    feed, each fed block (or chunk of it) by one work item in a fixed tile
    order, so results are reproducible bit for bit; the work item of a block
    of the next level then solves its diagonal block in the same launch.  The
-   sweeps for each group are captured in a graph on first use. */
+   sweeps for each group are captured in a graph on first use.  When that
+   factorization failed (stc_info != 0) every entry of d_b is set to NaN. */
 int stc_solve(stc_handle* h, double* d_b, int32_t nrhs, void* stream);
+
+/* For callers that cannot allocate device memory or instantiate graphs while
+   they run (code under HIP graph capture, tight serving loops, harnesses
+   that forbid allocation): stc_solve with the same arguments, results and
+   error codes, except that the permuted right-hand sides its sweeps work on
+   live in a static device array of the library (32 MiB, one per device,
+   held until the process ends; its address is looked up by stc_bind) instead
+   of the workspace, and the sweeps are launched kernel by kernel instead of
+   from a captured graph.  The call allocates nothing: no hipMalloc, hipFree,
+   graph instantiation or allocating library routine.  Limit: padded order
+   (N_T * n_b) * nrhs <= 4,194,304 doubles, else STC_ERR_ARG before any
+   launch.  Every call on one device shares that array, and each call
+   rewrites all of it that it reads, so no state carries over between calls;
+   calls that overlap in time on one device (different streams, host
+   threads) race on it and must be serialized by the caller. */
+int stc_solve_noalloc(stc_handle* h, double* d_b, int32_t nrhs, void* stream);
 
 /* Reverse mode of logdet through the last single factorization: given the
    scalar cotangent d_gbar (device) double[1], writes d_grad_values (device)

@@ -1352,12 +1352,15 @@ __global__ void k_perm_in(const double* __restrict__ b, const int32_t* __restric
   y[i] = a < n ? b[r * n + perm[a]] : 0.0;
 }
 
+// x = P^T y; NaN throughout when the factorization that the sweeps used
+// failed (info of the first value set non-zero)
 __global__ void k_perm_out(const double* __restrict__ y, const int32_t* __restrict__ perm,
-                           int64_t n, int64_t np, int32_t nrhs, double* __restrict__ b) {
+                           const int32_t* __restrict__ info, int64_t n, int64_t np, int32_t nrhs,
+                           double* __restrict__ b) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n * nrhs) return;
   int64_t r = i / n, a = i % n;
-  b[r * n + perm[a]] = y[r * np + a];
+  b[r * n + perm[a]] = info[0] != 0 ? __builtin_nan("") : y[r * np + a];
 }
 
 // Both sweeps run level by level over the blocks of the tile grid and read L

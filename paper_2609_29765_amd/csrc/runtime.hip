@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -45,6 +46,38 @@ constexpr int32_t kInfoNone = 0x7fffffff;
 constexpr int32_t kMaxRhs = 64;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+// Device scratch of stc_solve_noalloc: the permuted right-hand sides that its
+// sweeps work on, padded rows included.  One copy per device, held until the
+// process ends; host code never passes this name to a kernel (on the host it
+// is only a stand-in for the symbol) but the per-device address from
+// hipGetSymbolAddress.
+constexpr int64_t kScratchDoubles = int64_t(1) << 22;  // 32 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_dev;  // by device ordinal, null until looked up
+
+// address of `scratch` on the current device, looked up once per device
+int scratch_address(double** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((size_t)dev >= g_scratch_dev.size()) g_scratch_dev.resize((size_t)dev + 1, nullptr);
+  if (!g_scratch_dev[(size_t)dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(STC_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[(size_t)dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[(size_t)dev];
+  return 0;
+}
 
 struct LevelOffsets {
   int32_t u_off, u_cnt, g_off, g_cnt, p_off, p_cnt, t_off, t_cnt, u_last, g_last;
@@ -91,6 +124,7 @@ struct stc_handle {
   int32_t* d_rows = nullptr;
   double* d_store = nullptr;  // batch stores
   double* d_y = nullptr;      // solve scratch
+  double* d_scratch = nullptr;  // this device's `scratch` (stc_solve_noalloc)
   double* d_dinv = nullptr;   // inverses of the 32 x 32 diagonal blocks, per member
   int32_t* d_info = nullptr;  // batch
   double* d_ld = nullptr;     // batch
@@ -364,9 +398,9 @@ int build_graph(stc_handle* h, int32_t members, hipGraphExec_t* ex) {
 // d_y: one launch per level, each solving that level's blocks after the
 // products of the level before
 template <int NB, int R>
-void launch_sweeps_r(stc_handle* h, int32_t nr, int32_t g0, hipStream_t st) {
+void launch_sweeps_r(stc_handle* h, double* y0, int32_t nr, int32_t g0, hipStream_t st) {
   const int64_t np = padded_n(h);
-  double* y = h->d_y + (int64_t)g0 * np;
+  double* y = y0 + (int64_t)g0 * np;
   for (size_t q = 0; q < h->sfwd_nstep.size(); ++q) {
     const int32_t c = h->sfwd_ptr[q], d = h->sfwd_ptr[q + 1];
     if (d > c)
@@ -382,9 +416,19 @@ void launch_sweeps_r(stc_handle* h, int32_t nr, int32_t g0, hipStream_t st) {
 }
 
 template <int NB>
-void launch_sweeps_nb(stc_handle* h, int32_t nr, int32_t g0, hipStream_t st) {
-  if (nr == 1) launch_sweeps_r<NB, 1>(h, nr, g0, st);
-  else launch_sweeps_r<NB, SR>(h, nr, g0, st);
+void launch_sweeps_nb(stc_handle* h, double* y0, int32_t nr, int32_t g0, hipStream_t st) {
+  if (nr == 1) launch_sweeps_r<NB, 1>(h, y0, nr, g0, st);
+  else launch_sweeps_r<NB, SR>(h, y0, nr, g0, st);
+}
+
+// the sweeps of right-hand sides [g0, g0 + nr) of y0 (stride padded_n)
+void launch_sweeps(stc_handle* h, double* y0, int32_t nr, int32_t g0, hipStream_t st) {
+  switch (h->plan.nb) {
+    case 32: launch_sweeps_nb<32>(h, y0, nr, g0, st); break;
+    case 64: launch_sweeps_nb<64>(h, y0, nr, g0, st); break;
+    case 128: launch_sweeps_nb<128>(h, y0, nr, g0, st); break;
+    case 256: launch_sweeps_nb<256>(h, y0, nr, g0, st); break;
+  }
 }
 
 int get_solve_graph(stc_handle* h, int32_t nr, int32_t g0, hipGraphExec_t* out) {
@@ -397,12 +441,7 @@ int get_solve_graph(stc_handle* h, int32_t nr, int32_t g0, hipGraphExec_t* out) 
   hipStream_t cs;
   HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
-  switch (h->plan.nb) {
-    case 32: launch_sweeps_nb<32>(h, nr, g0, cs); break;
-    case 64: launch_sweeps_nb<64>(h, nr, g0, cs); break;
-    case 128: launch_sweeps_nb<128>(h, nr, g0, cs); break;
-    case 256: launch_sweeps_nb<256>(h, nr, g0, cs); break;
-  }
+  launch_sweeps(h, h->d_y, nr, g0, cs);
   hipGraph_t g;
   hipError_t e = hipStreamEndCapture(cs, &g);
   (void)hipStreamDestroy(cs);
@@ -755,6 +794,7 @@ int stc_bind(stc_handle* h, void* d_ws, size_t bytes, int32_t batch, void* strea
   h->back_graph = nullptr;
   h->factored = false;
   HIPCHK(hipGetDevice(&h->device));
+  if (int rc0 = scratch_address(&h->d_scratch)) return rc0;
   h->ws = (char*)d_ws;
   h->ws_bytes = bytes;
   h->batch = batch;
@@ -873,7 +913,30 @@ int stc_solve(stc_handle* h, double* d_b, int32_t nrhs, void* stream) {
     HIPCHK(hipGraphLaunch(ex, st));
   }
   hipLaunchKernelGGL(k_perm_out, dim3((unsigned)((n * nrhs + 255) / 256)), dim3(256), 0, st, h->d_y,
-                     h->d_perm, n, np, nrhs, d_b);
+                     h->d_perm, h->d_info, n, np, nrhs, d_b);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int stc_solve_noalloc(stc_handle* h, double* d_b, int32_t nrhs, void* stream) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!d_b) return fail(STC_ERR_ARG, "null right-hand side");
+  if (nrhs < 1 || nrhs > kMaxRhs) return fail(STC_ERR_ARG, "nrhs must be in [1, 64]");
+  if (!h->factored) return fail(STC_ERR_STATE, "solve before factorize");
+  const int64_t n = h->sym.n, np = padded_n(h);
+  if (np * nrhs > kScratchDoubles)
+    return fail(STC_ERR_ARG, "padded order x nrhs = " + std::to_string(np * nrhs) +
+                                 " doubles exceeds the allocation-free solve's scratch of " +
+                                 std::to_string(kScratchDoubles));
+  if (!h->d_scratch) return fail(STC_ERR_STATE, "device scratch not looked up (bind first)");
+  hipStream_t st = (hipStream_t)stream;
+  double* y = h->d_scratch;  // k_perm_in writes every entry the sweeps read
+  hipLaunchKernelGGL(k_perm_in, dim3((unsigned)((np * nrhs + 255) / 256)), dim3(256), 0, st, d_b,
+                     h->d_perm, n, np, nrhs, y);
+  for (int32_t g0 = 0; g0 < nrhs; g0 += SR) launch_sweeps(h, y, std::min<int32_t>(SR, nrhs - g0), g0, st);
+  hipLaunchKernelGGL(k_perm_out, dim3((unsigned)((n * nrhs + 255) / 256)), dim3(256), 0, st, y,
+                     h->d_perm, h->d_info, n, np, nrhs, d_b);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -1142,13 +1205,13 @@ int stc_fp64_mfma_peak(void* stream, double* tflops) {
   HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   const int blocks = cus * 8;
   const int32_t iters = 2000;
-  double* scratch = nullptr;  // never written (the guard in the kernel is false)
+  double* sink = nullptr;  // never written (the guard in the kernel is false)
   hipEvent_t a, b;
   HIPCHK(hipEventCreate(&a));
   HIPCHK(hipEventCreate(&b));
-  hipLaunchKernelGGL(k_mfma_issue, dim3(blocks), dim3(256), 0, st, scratch, iters, 1.0);
+  hipLaunchKernelGGL(k_mfma_issue, dim3(blocks), dim3(256), 0, st, sink, iters, 1.0);
   HIPCHK(hipEventRecord(a, st));
-  hipLaunchKernelGGL(k_mfma_issue, dim3(blocks), dim3(256), 0, st, scratch, iters, 1.0);
+  hipLaunchKernelGGL(k_mfma_issue, dim3(blocks), dim3(256), 0, st, sink, iters, 1.0);
   HIPCHK(hipEventRecord(b, st));
   HIPCHK(hipEventSynchronize(b));
   float ms = 0.f;

@@ -29,7 +29,7 @@ _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 # every entry point of include/stc.h
 EXPORTS = [
     "stc_analyse", "stc_workspace_bytes", "stc_bind", "stc_factorize", "stc_factorize_batched",
-    "stc_logdet", "stc_solve", "stc_logdet_backward", "stc_info", "stc_get_sizes",
+    "stc_logdet", "stc_solve", "stc_solve_noalloc", "stc_logdet_backward", "stc_info", "stc_get_sizes",
     "stc_get_features", "stc_get_perm", "stc_get_etree", "stc_get_L_pattern", "stc_get_tiles",
     "stc_get_tasks", "stc_get_factor", "stc_get_work", "stc_check_schedule", "stc_check_solve_schedule", "stc_profile_factorize",
     "stc_fp64_mfma_peak", "stc_destroy",
@@ -66,6 +66,7 @@ def lib():
     L.stc_factorize_batched.argtypes = [vp, vp, C.c_int32, vp, vp, vp]
     L.stc_logdet.argtypes = [vp, vp, vp]
     L.stc_solve.argtypes = [vp, vp, C.c_int32, vp]
+    L.stc_solve_noalloc.argtypes = [vp, vp, C.c_int32, vp]
     L.stc_logdet_backward.argtypes = [vp, vp, vp, vp]
     L.stc_info.argtypes = [vp, C.POINTER(C.c_int32)]
     L.stc_get_sizes.argtypes = [vp, _i64p]
