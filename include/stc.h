@@ -202,6 +202,12 @@ int stc_get_tasks(const stc_handle* h, int32_t* tasks); /* int32[ntasks][4]: op,
    (h_Lx double[nnz(L)]); synchronizes the stream. */
 int stc_get_factor(stc_handle* h, double* h_Lx, void* stream);
 
+/* Copy the factor of value set `member` (0 <= member < the bound batch) of
+   the last batched factorization to the host, in stc_get_L_pattern order
+   (h_Lx double[nnz(L)]); member 0 is also the last single factorization.
+   Synchronizes the stream. */
+int stc_get_batch_factor(stc_handle* h, int32_t member, double* h_Lx, void* stream);
+
 /* Static work of one factorization with this plan (host) double[10]:
    [0] tile-algorithmic flops of the SYRK+GEMM updates: sum |R_kn|^2 n_b over
        SYRK tasks + sum 2 |R_mn| |R_kn| n_b over GEMM tasks (Algorithm 1's
@@ -214,6 +220,15 @@ int stc_get_factor(stc_handle* h, double* h_Lx, void* stream);
    recurrence, 2 per multiply-add); [9] its levels (kernel launches after the
    diagonal-tile inverses). */
 int stc_get_work(const stc_handle* h, double* work);
+
+/* Shape of the replayed schedule (host, no device work), stats (host)
+   int64[4]: [0] update tasks whose K stream is split over several
+   work-groups (deterministic split-K: parts after the first leave partial
+   sums that the tile's next update folds in a fixed order); [1] doubles of
+   partial-sum slots per value set; [2] levels whose last-group updates have
+   a kernel of their own; [3] kernels (graph nodes) of one factorization.
+   All are set by the plan alone (the pattern, n_b, mode and wg_slots). */
+int stc_get_plan_stats(const stc_handle* h, int64_t* stats);
 
 /* Host check of the factorization schedule, no device work.  The
    factorization replays a graph with one node per non-empty POTRF, update

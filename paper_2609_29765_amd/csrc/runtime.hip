@@ -983,6 +983,21 @@ int stc_get_factor(stc_handle* h, double* h_Lx, void* stream) {
   return 0;
 }
 
+int stc_get_batch_factor(stc_handle* h, int32_t member, double* h_Lx, void* stream) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!h_Lx) return fail(STC_ERR_ARG, "null output");
+  if (!h->factored) return fail(STC_ERR_STATE, "factor export before factorize");
+  if (member < 0 || member >= h->batch) return fail(STC_ERR_ARG, "member out of [0, bound batch)");
+  std::vector<double> store((size_t)h->plan.store);
+  HIPCHK(hipMemcpyAsync(store.data(), h->d_store + (int64_t)member * h->plan.store, sizeof(double) * store.size(),
+                        hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  const auto& lm = h->plan.lmap;
+  for (size_t q = 0; q < lm.size(); ++q) h_Lx[q] = store[(size_t)lm[q]];
+  return 0;
+}
+
 int stc_get_sizes(const stc_handle* h, int64_t* z) {
   if (!h || !z) return fail(STC_ERR_ARG, "null argument");
   const Symbolic& s = h->sym;
@@ -1144,6 +1159,24 @@ int stc_check_schedule(const stc_handle* h, int64_t* stats) {
   stats[1] = edges;
   stats[2] = unordered;
   stats[3] = (int64_t)touch.size();
+  return 0;
+}
+
+int stc_get_plan_stats(const stc_handle* h, int64_t* st) {
+  if (!h || !st) return fail(STC_ERR_ARG, "null argument");
+  const Plan& p = h->plan;
+  int64_t split = 0, sep = 0;
+  for (const UpdTask& u : p.upd) split += u.nsplit > 1 ? 1 : 0;
+  for (const LevelOffsets& L : h->lv) {
+    const bool early = L.g_cnt > L.g_last || L.u_cnt > L.u_last;
+    sep += (L.g_last + L.u_last > 0 && early) ? 1 : 0;
+  }
+  std::vector<KernelNode> dag;
+  kernel_dag(p, &dag);
+  st[0] = split;
+  st[1] = p.parts;
+  st[2] = sep;
+  st[3] = (int64_t)dag.size();
   return 0;
 }
 

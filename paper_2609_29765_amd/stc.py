@@ -31,7 +31,7 @@ EXPORTS = [
     "stc_analyse", "stc_workspace_bytes", "stc_bind", "stc_factorize", "stc_factorize_batched",
     "stc_logdet", "stc_solve", "stc_solve_noalloc", "stc_logdet_backward", "stc_info", "stc_get_sizes",
     "stc_get_features", "stc_get_perm", "stc_get_etree", "stc_get_L_pattern", "stc_get_tiles",
-    "stc_get_tasks", "stc_get_factor", "stc_get_work", "stc_check_schedule", "stc_check_solve_schedule", "stc_profile_factorize",
+    "stc_get_tasks", "stc_get_factor", "stc_get_batch_factor", "stc_get_work", "stc_get_plan_stats", "stc_check_schedule", "stc_check_solve_schedule", "stc_profile_factorize",
     "stc_fp64_mfma_peak", "stc_destroy",
     "stc_last_error",
 ]
@@ -77,7 +77,9 @@ def lib():
     L.stc_get_tiles.argtypes = [vp, _i32p, _i32p, _i32p, _i32p, _i8p, _i64p, _i32p, _i32p]
     L.stc_get_tasks.argtypes = [vp, _i32p]
     L.stc_get_factor.argtypes = [vp, _f64p, vp]
+    L.stc_get_batch_factor.argtypes = [vp, C.c_int32, _f64p, vp]
     L.stc_get_work.argtypes = [vp, _f64p]
+    L.stc_get_plan_stats.argtypes = [vp, _i64p]
     L.stc_check_schedule.argtypes = [vp, _i64p]
     L.stc_check_solve_schedule.argtypes = [vp, _i64p]
     L.stc_profile_factorize.argtypes = [vp, vp, vp, _f64p, _i64p, _f64p]
@@ -279,6 +281,14 @@ class Analysis:
                 "bytes_update", "bytes_load", "levels", "flops_backward", "levels_backward"]
         return dict(zip(keys, (float(x) for x in w)))
 
+    def plan_stats(self):
+        """{split_tasks, partial_doubles, separate_last_levels, graph_kernels}
+        of the factorization plan (see stc_get_plan_stats)."""
+        st = np.zeros(4, dtype=np.int64)
+        _check(lib().stc_get_plan_stats(self._h, st))
+        return dict(zip(["split_tasks", "partial_doubles", "separate_last_levels", "graph_kernels"],
+                        (int(x) for x in st)))
+
     def check_schedule(self):
         """Host check of the kernel dependency graph the factorization replays
         (see stc_check_schedule); raises on a conflicting pair of kernels.
@@ -315,11 +325,15 @@ class Analysis:
         _check(lib().stc_info(self._h, C.byref(v)))
         return int(v.value)
 
-    def factor(self):
-        """Host copy of L in L_pattern() order."""
+    def factor(self, member=None):
+        """Host copy of L in L_pattern() order: the last single factorization,
+        or value set `member` of the last batched one."""
         self._ws_device()
         Lx = np.zeros(self.lnz)
-        _check(lib().stc_get_factor(self._h, Lx, _stream_ptr()))
+        if member is None:
+            _check(lib().stc_get_factor(self._h, Lx, _stream_ptr()))
+        else:
+            _check(lib().stc_get_batch_factor(self._h, int(member), Lx, _stream_ptr()))
         return Lx
 
 

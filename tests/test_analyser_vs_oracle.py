@@ -65,6 +65,22 @@ def test_differentiable_arrowhead_full_size():
     assert a.route == "semisparse"
 
 
+@pytest.mark.parametrize("nb", [128, 256])
+def test_spatiotemporal_full_size(nb):
+    """The spatio-temporal arrowhead at its full size (n 101,258) with the
+    ND ordering the bench uses, at both tile sizes the autotuner tries."""
+    a, o = _compare(W.spatiotemporal_arrowhead(), "nd", nb)
+    assert a.route == "semisparse" and a.ndense == 8
+
+
+@pytest.mark.parametrize("nb", [64, 128])
+def test_lap3d_full_size(nb):
+    """The 24^3 Laplacian of the batched workload (one value set: the
+    pattern is shared by every member)."""
+    a, o = _compare(W.batched_laplacian3d(m=24, B=1), "nd", nb)
+    assert a.route == "semisparse"
+
+
 def test_dense_route_small():
     w = W.dense_spd(512, 0.2, 0)
     a, o = _compare(w, "natural", 64)
