@@ -13,9 +13,11 @@ Prints one JSON line.  Besides the headline value it carries:
                 its event-timed average launch duration, against the FP64
                 matrix peak of 78.6 TFLOP/s; HBM traffic per launch from the
                 committed counter summary when it matches the current kernels;
-  cpu_baseline  the oracle (plain serial C, one core) timed on a smaller
-                instance of the same generator, scaled to this order by the
-                flop ratio;
+  cpu_baseline  the oracle (plain serial C, one core) timed on the leading
+                principal blocks of order n/4 and n/2 of this matrix, the
+                larger scaled to the full order by the exact flop ratio
+                (a model, stated as such); cpu_baseline_configs times the
+                oracle on the other workloads beside their GPU figures;
   extras        the other forms of the metric, measured in a child process
                 (so the headline process's kernel statistics cover the
                 headline only): batched factorization of 128 value sets
@@ -442,35 +444,270 @@ def run_extras(path, batch):
 # CPU baseline: the oracle on a bounded sample
 # ---------------------------------------------------------------------------
 
-def cpu_baseline(args):
-    from oracle import oracle
-    from paper_2609_29765_amd import workloads
-    ns = args.cpu_sample_n
-    ws = workloads.dense_spd(ns, 0.2, 0)
-    o = oracle.Analysis(ws.n, ws.colptr, ws.rowind, "natural", nb=args.nb)
-    t0 = time.time()
-    Lx, oinfo = o.factor(ws.values)
-    t_cpu = time.time() - t0
-    assert oinfo == 0
-    scale = (args.n / ns) ** 3
-    model = ""
+def _cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
                 if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
+                    return line.split(":", 1)[1].strip()
     except OSError:
         pass
+    return "the host"
+
+
+def _best_of(fn, reps):
+    """Minimum wall time of reps calls of fn after one warm-up call (the
+    paper's timing convention, Sec. 6.1)."""
+    fn()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return min(ts)
+
+
+def _leading_block(w, m):
+    """Lower CSC of the leading m x m principal block of a workload: an SPD
+    matrix whose Cholesky factor is the leading block of the full factor."""
+    import numpy as np
+    cp, ri, v = w.colptr, w.rowind, w.values
+    keep = ri < m
+    col = np.repeat(np.arange(w.n), np.diff(cp))
+    keep &= col < m
+    cnt = np.bincount(col[keep], minlength=m)[:m]
+    cp2 = np.zeros(m + 1, np.int64)
+    np.cumsum(cnt, out=cp2[1:])
+    return cp2, np.ascontiguousarray(ri[keep], np.int32), np.ascontiguousarray(v[keep])
+
+
+def cpu_baseline(args):
+    """The oracle (plain serial C, one thread) on bounded samples of the
+    headline matrix itself: its leading principal blocks of order n/4 and
+    n/2, whose factors are the leading blocks of the full factor.  Dense
+    Cholesky work grows as the cube of the order, so the full factorization's
+    time is modelled as the larger sample's time times the exact flop ratio;
+    the two samples' rates show how far that rate holds."""
+    from oracle import oracle
+    from paper_2609_29765_amd import workloads
+    w = workloads.dense_spd(args.n, 0.2, 0)
+    flops = lambda m: m * (m + 1) * (2 * m + 1) / 6.0  # sum_j c_j^2 of a dense factor of order m
+    rates = {}
+    t_big, m_big = None, None
+    for m in (args.n // 4, args.n // 2):
+        cp, ri, v = _leading_block(w, m)
+        o = oracle.Analysis(m, cp, ri, "natural", nb=args.nb)
+        t0 = time.perf_counter()
+        _, info = o.factor(v)
+        t = time.perf_counter() - t0
+        assert info == 0
+        rates[m] = (t, flops(m) / t / 1e9)
+        t_big, m_big = t, m
+        log(f"cpu baseline: oracle on the leading {m} x {m} block: {t:.2f} s, {rates[m][1]:.2f} GFLOP/s")
+    scale = flops(args.n) / flops(m_big)
     return {
-        "value": round(1.0 / (t_cpu * scale), 6),
+        "value": round(1.0 / (t_big * scale), 6),
         "unit": "factorizations/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"oracle factorization (serial C, one thread) of the same generator at n={ns} (seed 0) "
-                  f"took {t_cpu:.2f} s on {model or 'the host'} ({os.cpu_count()} logical CPUs visible); "
-                  f"scaled by the flop ratio (n/{ns})^3 = {scale:.2f} to n={args.n}",
+        "sample": f"oracle factorization (serial C, one thread) of the leading principal {m_big} x {m_big} block of "
+                  f"the headline matrix took {t_big:.2f} s on {_cpu_model()} ({os.cpu_count()} logical CPUs visible); "
+                  f"model: times the exact flop ratio {scale:.2f} to n={args.n}.  Rates: "
+                  + ", ".join(f"n={m}: {r[1]:.2f} GFLOP/s ({r[0]:.2f} s)" for m, r in rates.items()),
     }
+
+
+def cpu_baseline_configs(extras):
+    """The oracle on the other workloads, beside the GPU figures of the same
+    run: analysis (symbolic) and factorization (numeric) timed apart; the
+    cheap ones as the minimum of 3 after a warm-up, the spatio-temporal
+    arrowhead once (one factorization is tens of seconds), the batch on four
+    of its 128 members."""
+    from oracle import oracle
+    from paper_2609_29765_amd import workloads
+    ex = extras or {}
+    out = {"cpu": _cpu_model(), "cores": 1, "logical_cpus_visible": os.cpu_count()}
+
+    def gpu(name, key):
+        return ex.get(name, {}).get(key)
+
+    def row(name, w, nb, gpu_ms, reps=3):
+        if reps:
+            t_sym = _best_of(lambda: oracle.Analysis(w.n, w.colptr, w.rowind, "nd", nb=nb), reps)
+            o = oracle.Analysis(w.n, w.colptr, w.rowind, "nd", nb=nb)
+            t_num = _best_of(lambda: o.factor(w.values), reps)
+        else:
+            t0 = time.perf_counter()
+            o = oracle.Analysis(w.n, w.colptr, w.rowind, "nd", nb=nb)
+            t_sym = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            o.factor(w.values)
+            t_num = time.perf_counter() - t0
+        r = {"oracle_symbolic_s": round(t_sym, 4), "oracle_numeric_s": round(t_num, 5),
+             "timing": "min of 3 after a warm-up" if reps else "one run", "gpu_ms": gpu_ms}
+        if gpu_ms:
+            r["gpu_speedup_vs_oracle"] = round(t_num * 1e3 / gpu_ms, 2)
+        log(f"oracle {name}: {r}")
+        return o, r
+
+    w = workloads.gmrf_grid2d(32, 32, 0.1, 0)
+    us = gpu("gmrf_2d", "us_per_factorization")
+    out["gmrf_2d"] = row("gmrf_2d", w, 64, us * 1e-3 if us else None)[1]
+    w = workloads.differentiable_arrowhead(20, 25, 8, 0)
+    o, r = row("backward", w, gpu("backward", "nb") or 128, gpu("backward", "ms_forward"))
+    Lx, _ = o.factor(w.values)
+    r["oracle_selected_inverse_gradient_s"] = round(_best_of(lambda: o.logdet_grad_values(Lx), 3), 4)
+    r["gpu_forward_backward_ms"] = gpu("backward", "ms_forward_backward")
+    out["backward"] = r
+    wb = workloads.batched_laplacian3d(m=24, B=128, seed=0)
+    o = oracle.Analysis(wb.n, wb.colptr, wb.rowind, "nd", nb=gpu("batched", "nb") or 64)
+    o.factor(wb.values[0])
+    ts = []
+    for b in (0, 1, 63, 127):
+        t0 = time.perf_counter()
+        o.factor(wb.values[b])
+        ts.append(time.perf_counter() - t0)
+    per = sum(ts) / len(ts)
+    ms_b = gpu("batched", "ms_batched")
+    out["batched"] = {"oracle_numeric_s_per_member": round(per, 4), "members_timed": [0, 1, 63, 127],
+                      "oracle_numeric_s_batch_model": round(per * 128, 2),
+                      "timing": "one run per member after a warm-up; the batch as 128 x the mean",
+                      "gpu_ms_batched": ms_b,
+                      "gpu_speedup_vs_oracle": round(per * 128 * 1e3 / ms_b, 1) if ms_b else None}
+    log(f"oracle batched: {out['batched']}")
+    w = workloads.spatiotemporal_arrowhead()
+    out["semisparse"] = row("semisparse", w, gpu("semisparse", "nb") or 128,
+                            gpu("semisparse", "ms_per_factorization"), reps=0)[1]
+    return out
+
+
+# ---------------------------------------------------------------------------
+# reduction of rocprofv3 CSV output into the tables under profiles/
+# ---------------------------------------------------------------------------
+
+def _short_kernel(name):
+    """'void stc::k_upd<128, true, true>(stc::LevelArgs)' -> 'k_upd<128, true, true>'."""
+    n = name.strip()
+    if n.startswith("void "):
+        n = n[5:]
+    depth, cut = 0, len(n)
+    for i, ch in enumerate(n):  # drop the argument list: the first '(' outside template brackets
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            cut = i
+            break
+    n = n[:cut]
+    return n[5:] if n.startswith("stc::") else n
+
+
+def _csv_rows(root, suffix):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(root, "**", f"*{suffix}"), recursive=True)):
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def _segments(disp, marker):
+    """Split dispatches (sorted by start) at each dispatch of the marker
+    kernel; a factorization begins with one."""
+    segs, cur = [], []
+    for d in disp:
+        if d["kernel"].startswith(marker) and cur:
+            segs.append(cur)
+            cur = []
+        cur.append(d)
+    if cur:
+        segs.append(cur)
+    return segs
+
+
+def summarize_trace(args):
+    """Markdown summary of a rocprofv3 --kernel-trace CSV directory, and of
+    --pmc counter directories if given: per kernel launches, time, and
+    (with counters) copy-calibrated HBM bytes and MFMA flops."""
+    import statistics
+    disp = []
+    for r in _csv_rows(args.summarize_trace, "kernel_trace.csv"):
+        disp.append({"kernel": _short_kernel(r["Kernel_Name"]), "start": int(r["Start_Timestamp"]),
+                     "end": int(r["End_Timestamp"]), "id": int(r.get("Dispatch_Id", 0) or 0)})
+    disp.sort(key=lambda d: d["start"])
+    if not disp:
+        print("no kernel_trace.csv under " + args.summarize_trace, file=sys.stderr)
+        sys.exit(1)
+    segs = _segments(disp, args.segment_marker)
+    if args.segment is not None:
+        disp = segs[args.segment]
+    if args.kernel_filter:
+        disp = [d for d in disp if any(d["kernel"].startswith(k) for k in args.kernel_filter.split(","))]
+    t0 = min(d["start"] for d in disp)
+    t1 = max(d["end"] for d in disp)
+    busy, last = 0, t0  # union of kernel intervals
+    for d in sorted(disp, key=lambda d: d["start"]):
+        s, e = max(d["start"], last), d["end"]
+        if e > s:
+            busy += e - s
+            last = e
+    print(f"Segments delimited by {args.segment_marker}: {len(segs)}"
+          + (f"; this table: segment {args.segment}" if args.segment is not None else "; this table: all"))
+    print(f"Span {(t1 - t0) / 1e6:.2f} ms, of which {busy / 1e6:.2f} ms has at least one kernel running.\n")
+    per = {}
+    for d in disp:
+        per.setdefault(d["kernel"], []).append((d["end"] - d["start"]) / 1e3)
+    ids = {d["id"] for d in disp}
+    cnt = {}
+    for suffix in ("counter_collection.csv",):
+        for cdir in args.counters or []:
+            for r in _csv_rows(cdir, suffix):
+                k = _short_kernel(r["Kernel_Name"])
+                cnt.setdefault(r["Counter_Name"], []).append((k, int(r.get("Dispatch_Id", 0) or 0),
+                                                             float(r["Counter_Value"])))
+    scale = {}
+    for c, vals in cnt.items():
+        cal = [v for k, _, v in vals if "copy" in k.lower()]
+        if c in ("FETCH_SIZE", "WRITE_SIZE") and cal:
+            scale[c] = 1048576.0 / max(cal)  # KiB the counter reads for the plain 1 GiB copy
+        if args.segment is not None:  # the same run of dispatches as the trace table
+            vals.sort(key=lambda x: x[1])
+            sg = _segments([{"kernel": k, "id": i, "v": v} for k, i, v in vals], args.segment_marker)
+            cnt[c] = [(d["kernel"], d["id"], d["v"]) for d in sg[args.segment]] if args.segment < len(sg) else []
+    cols = ["kernel", "launches", "total ms", "average us", "median us"]
+    extra = [c for c in ("FETCH_SIZE", "WRITE_SIZE") if c in scale]
+    if extra:
+        cols += ["HBM MB", "HBM GB/s"]
+    if "SQ_INSTS_VALU_MFMA_MOPS_F64" in cnt:
+        cols += ["MFMA GFLOP executed"]
+    print("| " + " | ".join(cols) + " |")
+    print("|" + "---|" * len(cols))
+    for k, ts in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        tot = sum(ts)
+        row = [k, str(len(ts)), f"{tot / 1e3:.2f}", f"{tot / len(ts):.1f}", f"{statistics.median(ts):.1f}"]
+        if extra:
+            by = 0.0
+            for c in extra:
+                by += sum(v for kk, _, v in cnt[c] if kk == k) * 1024.0 * scale[c] / args.counter_runs
+            row += [f"{by / 1e6:.1f}", f"{by / (tot * 1e-3) / 1e9:.0f}" if tot > 0 else "-"]
+        if "SQ_INSTS_VALU_MFMA_MOPS_F64" in cnt:
+            mops = sum(v for kk, _, v in cnt["SQ_INSTS_VALU_MFMA_MOPS_F64"] if kk == k) / args.counter_runs
+            row += [f"{mops * 512 / 1e9:.2f}"]
+        print("| " + " | ".join(row) + " |")
+    if scale:
+        print("\nCounter scale from the plain 1 GiB copy: " +
+              ", ".join(f"{c} x {v:.3f}" for c, v in scale.items()))
+    if args.chain:
+        ch = [d for d in disp if d["kernel"].startswith(args.chain)]
+        gaps = [(b["start"] - a["end"]) / 1e3 for a, b in zip(ch[:-1], ch[1:])]
+        tot = sum((d["end"] - d["start"]) for d in ch) / 1e6
+        if gaps:
+            print(f"\nChain of {args.chain}: {len(ch)} launches, {tot:.2f} ms inside them; from the end of one to the "
+                  f"start of the next: median {statistics.median(gaps):.1f} us, mean {statistics.mean(gaps):.1f} us; "
+                  f"launch time plus these intervals: {tot + sum(gaps) / 1e3:.2f} ms of the span.")
+    _ = ids
 
 
 def main():
@@ -484,7 +721,6 @@ def main():
     ap.add_argument("--batch", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--cpu-sample-n", type=int, default=5120)
     ap.add_argument("--extras-out", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--solve-pass", action="store_true",
                     help="factorize the semisparse config, then solve it 3 times with 1 and with 8 "
@@ -494,7 +730,22 @@ def main():
                          "for counter runs over the active-column route")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration runs)")
+    ap.add_argument("--summarize-trace", default=None, metavar="DIR",
+                    help="print a markdown summary of the rocprofv3 kernel-trace CSVs under DIR and exit")
+    ap.add_argument("--counters", action="append", metavar="DIR",
+                    help="with --summarize-trace: rocprofv3 --pmc CSV directories (FETCH_SIZE, WRITE_SIZE, "
+                         "SQ_INSTS_VALU_MFMA_MOPS_F64), calibrated by the plain copy's reading")
+    ap.add_argument("--counter-runs", type=int, default=1,
+                    help="with --counters: factorizations each counter run covers per traced one")
+    ap.add_argument("--segment", type=int, default=None,
+                    help="with --summarize-trace: only the i-th run of dispatches between two marker kernels")
+    ap.add_argument("--segment-marker", default="k_info_reset")
+    ap.add_argument("--kernel-filter", default=None, help="comma-separated kernel name prefixes to keep")
+    ap.add_argument("--chain", default=None, help="kernel name prefix whose successive launches form a chain")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
@@ -536,6 +787,7 @@ def main():
         os.unlink(path)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(args)
+    cpu_cfg = None if (args.no_cpu_baseline or args.no_extras) else cpu_baseline_configs(extras)
 
     ms_step = hl["ms_step"]
     line = {
@@ -561,6 +813,7 @@ def main():
         "kernels": hl["kinds"],
         "measured_peaks_tflops": hl["peaks"],
         "cpu_baseline": cpu,
+        "cpu_baseline_configs": cpu_cfg,
         "extras": extras,
         "logdet": hl["logdet"],
         "factor_uses": hl["uses"],
