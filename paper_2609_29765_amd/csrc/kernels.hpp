@@ -450,23 +450,20 @@ constexpr int PW = 32;
 constexpr int PLD = PW + 1;
 
 // Cholesky of the 32 x 32 block held in P's first 32 rows and the inverse of
-// the factor, by one wave.  Lanes 0..31 hold row r of A in registers and run
-// the left-looking (Crout) recurrence L_rc = (A_rc - sum_{p<c} L_rp L_cp) / L_cc;
-// lanes 32..63 hold the unit vector e_r and run forward substitution for
-// column r of L^-1, z_c = (e_rc - sum_{p<c} L_cp z_p) / L_cc -- the same
-// expression on different registers, so one instruction stream serves both.
-// Columns go four at a time: every lane forms its four partial sums t_q
-// (rows c0..c0+3 of L read by LDS broadcast), the 4 x 4 pivot block (t of
-// lanes c0..c0+3, by readlane) is factored with uniform scalar arithmetic,
-// and each lane finishes its four entries by a 4-term forward substitution.
-// The part of the next block's sums over earlier columns is formed before
-// this block's pivots, the part over this block's columns after them.  The
-// reads of earlier columns never meet this block's writes, the reads of this
-// block's columns follow them in program order, and a wave's LDS operations
-// execute in that order.  Writes L (lower, diagonal included,
-// zeros above) to P, the inverse (row-major, stride PLD) to Z and 1 / L_cc to
-// rdiag.  Returns the first failing pivot (0-based) or -1; uniform across the
-// wave.
+// the factor, by one wave, right-looking.  Lanes 0..31 hold row r of A in
+// registers; lanes 32..63 hold the unit vector e_r and become column r of
+// L^-1 (forward substitution z_c = (e_rc - sum_{p<c} L_cp z_p) / L_cc is the
+// same update on different registers, so one instruction stream serves both).
+// Pivot c: every lane scales its entry c by 1 / L_cc (rows above the pivot
+// keep a zero there), then subtracts x_c L_jc from its entries j > c.  Only
+// the pivot chain is serial: the column's entry in row c + 1 (by readlane)
+// updates x_{c+1}, and x_{c+1} of lane c + 1 (by readlane) is the next pivot.
+// Row c + 2's entry also comes by readlane, so the next chain step finds
+// x_{c+2} ready; the other entries of column c go through LDS (cb, 64
+// doubles, 16-byte aligned: lanes 32..63 write a spare half) and are applied
+// one column later, their loads long done.  Writes L (lower, diagonal
+// included, zeros above) to P and the inverse (row-major, stride PLD) to Z.
+// Returns the first failing pivot (0-based) or -1; uniform across the wave.
 __device__ __forceinline__ double rcp_nr(double d) {
   double r = __builtin_amdgcn_rcp(d);
   r = fma(fma(-d, r, 1.0), r, r);
@@ -485,7 +482,7 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ int chol32_wave(double* P, double* Z, double* rdiag, int lane) {
+__device__ __forceinline__ int chol32_wave(double* P, double* Z, double* cb, int lane) {
   const int r = lane & 31;
   const bool lo = lane < 32;
   double x[PW];
@@ -494,89 +491,58 @@ __device__ __forceinline__ int chol32_wave(double* P, double* Z, double* rdiag, 
     const double a = P[r * PLD + j];
     x[j] = lo ? a : (j == r ? 1.0 : 0.0);
   }
-  double myd = 1.0, myrs = 1.0;  // lane r < 32 keeps pivot r and its 1 / L_rr
-  double t[4];
+  double d = readlane_f64(x[0], 0);
+  double myd = d;  // lane c keeps pivot c
+  double rs = rsqrt_nr(d);
+  double lc[PW];   // entries of column c - 1 of L, from LDS
 #pragma unroll
-  for (int q = 0; q < 4; ++q) t[q] = x[q];
+  for (int c = 0; c < PW; ++c) {
+    x[c] = (lo && r < c) ? 0.0 : x[c] * rs;
+    if (c + 1 < PW) {
+      const double l1 = readlane_f64(x[c], c + 1);
+      x[c + 1] = fma(-x[c], l1, x[c + 1]);
+      d = readlane_f64(x[c + 1], c + 1);
+      myd = (r == c + 1) ? d : myd;
+      const double rs1 = rsqrt_nr(d);
+      if (c + 2 < PW) {
+        const double l2 = readlane_f64(x[c], c + 2);
+        x[c + 2] = fma(-x[c], l2, x[c + 2]);
+      }
+      if (c >= 1) {
 #pragma unroll
-  for (int c0 = 0; c0 < PW; c0 += 4) {
-    // the next block's partial sums over the columns before this block do
-    // not wait for this block's pivots: they are formed first
-    double tn[4] = {0.0, 0.0, 0.0, 0.0};
-    if (c0 + 4 < PW) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-        for (int p = 0; p < c0; ++p) {
-          if (p & 1) s1 = fma(x[p], P[(c0 + 4 + q) * PLD + p], s1);
-          else s0 = fma(x[p], P[(c0 + 4 + q) * PLD + p], s0);
+        for (int j = c + 2; j < PW; ++j) x[j] = fma(-x[c - 1], lc[j], x[j]);
+      }
+      if (c + 3 < PW) {
+        cb[lane] = x[c];
+        int j = c + 3;
+        if (j & 1) {
+          lc[j] = cb[j];
+          ++j;
         }
-        tn[q] = x[c0 + 4 + q] - (s0 + s1);
+#pragma unroll
+        for (; j < PW; j += 2) {
+          const double2 lj = *reinterpret_cast<const double2*>(cb + j);
+          lc[j] = lj.x;
+          lc[j + 1] = lj.y;
+        }
       }
+      rs = rs1;
     }
-    // pivot block T_iq = t_q of lane c0 + i (i >= q), factored uniformly
-    double T[4][4];
+    // keep each column's updates in place: left free, the compiler defers
+    // them to their uses and holds every loaded column in registers
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int q = 0; q <= i; ++q) T[i][q] = readlane_f64(t[q], c0 + i);
-    double Lb[4][4], rs[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      double d = T[q][q];
-#pragma unroll
-      for (int p = 0; p < q; ++p) d = fma(-Lb[q][p], Lb[q][p], d);
-      rs[q] = rsqrt_nr(d);
-      Lb[q][q] = d * rs[q];
-#pragma unroll
-      for (int i = q + 1; i < 4; ++i) {
-        double v = T[i][q];
-#pragma unroll
-        for (int p = 0; p < q; ++p) v = fma(-Lb[i][p], Lb[q][p], v);
-        Lb[i][q] = v * rs[q];
-      }
-      myd = (r == c0 + q) ? d : myd;
-      myrs = (r == c0 + q) ? rs[q] : myrs;
-    }
-    double v[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      double u = t[q];
-#pragma unroll
-      for (int p = 0; p < q; ++p) u = fma(-v[p], Lb[q][p], u);
-      v[q] = (lo && r < c0 + q) ? 0.0 : u * rs[q];
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) x[c0 + q] = v[q];
-    __builtin_amdgcn_wave_barrier();
-    if (lo) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) P[r * PLD + c0 + q] = v[q];
-    }
-    __builtin_amdgcn_wave_barrier();
-    // the next block's partial sums over this block's columns
-    if (c0 + 4 < PW) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        double u = tn[q];
-#pragma unroll
-        for (int p = c0; p < c0 + 4; ++p) u = fma(-x[p], P[(c0 + 4 + q) * PLD + p], u);
-        t[q] = u;
-      }
-    }
+    for (int j = c + 1; j < PW; ++j) asm volatile("" : "+v"(x[j]));
   }
-  if (lo) rdiag[r] = myrs;
-  if (!lo) {
+  double* dst = lo ? P + r * PLD : Z + r;
+  const int step = lo ? 1 : PLD;
 #pragma unroll
-    for (int j = 0; j < PW; ++j) Z[j * PLD + r] = x[j];
-  }
+  for (int j = 0; j < PW; ++j) dst[j * step] = x[j];
   const unsigned long long m = __ballot(lo && (!(myd > 0.0) || !isfinite(myd)));
   return m ? (int)__builtin_ctzll(m) : -1;
 }
 
 template <int NB>
-constexpr int potrf_lds() { return 2 * NB * PLD + PW * PLD + PW; }
+constexpr int potrf_lds() { return 2 * NB * PLD + PW * PLD + 2 * PW; }
 
 // POTRF of one diagonal tile, left-looking over 32-column panels.  A panel
 // (rows j0.., 32 columns) is loaded into LDS in bulk; the columns already
@@ -591,7 +557,7 @@ __device__ __forceinline__ void dev_potrf(int32_t k, double* __restrict__ S,
   double* P = smem;
   double* Sl = smem + NB * PLD;
   double* Z = Sl + NB * PLD;
-  double* rdiag = Z + PW * PLD;
+  double* cb = Z + PW * PLD;  // column broadcast of the 32 x 32 factor
   double* A = S + (int64_t)k * NB * NB;
   double* dinv = dinv_m + (int64_t)k * NB * PW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -667,7 +633,7 @@ __device__ __forceinline__ void dev_potrf(int32_t k, double* __restrict__ S,
     }
     __syncthreads();
     if (wave == 0) {
-      const int bad = chol32_wave(P, Z, rdiag, lane);
+      const int bad = chol32_wave(P, Z, cb, lane);
       if (lane == 0 && bad >= 0 && k * NB + j0 + bad < nreal) atomicMin(inf, k * NB + j0 + bad + 1);
     }
     __syncthreads();
@@ -719,7 +685,7 @@ template <int NB>
 constexpr int la_rbw() { return ((NB - PW) / 16 + 2) / 3; }  // row blocks per waves 1..3
 
 template <int NB>
-constexpr int potrf_la_lds() { return NB * PLD + PW * PLD + PW + 3 * (la_rbw<NB>() * 16 + PW) * LKLD; }
+constexpr int potrf_la_lds() { return NB * PLD + PW * PLD + 2 * PW + 3 * (la_rbw<NB>() * 16 + PW) * LKLD; }
 
 template <int NB>
 __device__ __forceinline__ void dev_potrf_la(int32_t k, double* __restrict__ S,
@@ -729,8 +695,8 @@ __device__ __forceinline__ void dev_potrf_la(int32_t k, double* __restrict__ S,
   constexpr int WROWS = RB3 * 16 + PW;  // staged rows per wave: its A rows, then the B rows
   double* P = smem;
   double* Z = P + NB * PLD;
-  double* rdiag = Z + PW * PLD;
-  double* Wall = rdiag + PW;
+  double* cb = Z + PW * PLD;  // column broadcast of the 32 x 32 factor
+  double* Wall = cb + 2 * PW;
   double* A = S + (int64_t)k * NB * NB;
   double* dinv = dinv_m + (int64_t)k * NB * PW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -758,7 +724,7 @@ __device__ __forceinline__ void dev_potrf_la(int32_t k, double* __restrict__ S,
     for (int b = 0; b < RB3; ++b) acc[b][0] = acc[b][1] = d4{0.0, 0.0, 0.0, 0.0};
     __syncthreads();  // P holds this panel, fully updated
     if (wave == 0) {
-      const int bad = chol32_wave(P, Z, rdiag, lane);
+      const int bad = chol32_wave(P, Z, cb, lane);
       if (lane == 0 && bad >= 0 && k * NB + j0 + bad < nreal) atomicMin(inf, k * NB + j0 + bad + 1);
     } else if (pr1 > 0 && j0 > 0) {
       const int w = wave - 1;
