@@ -145,6 +145,16 @@ int stc_logdet(stc_handle* h, double* d_out, void* stream);
    factorization failed (stc_info != 0) every entry of d_b is set to NaN. */
 int stc_solve(stc_handle* h, double* d_b, int32_t nrhs, void* stream);
 
+/* Solve A_b X_b = B_b in place for value sets b = 0..B-1 of the last batched
+   factorization (1 <= B <= the B of that call; member 0 is also the last
+   single factorization): d_b (device) double[B][n * nrhs], value set b's
+   right-hand sides column-major at d_b + b n nrhs, original numbering,
+   1 <= nrhs <= 8.  The same level sweeps as stc_solve, each launch covering
+   every value set (grid.y = value set), captured in a graph per (B, nrhs
+   group) on first use.  A value set whose factorization failed gets NaN.
+   STC_ERR_STATE before a batched factorization of at least B value sets. */
+int stc_solve_batched(stc_handle* h, double* d_b, int32_t B, int32_t nrhs, void* stream);
+
 /* For callers that cannot allocate device memory or instantiate graphs while
    they run (code under HIP graph capture, tight serving loops, harnesses
    that forbid allocation): stc_solve with the same arguments, results and
@@ -174,6 +184,25 @@ int stc_solve_noalloc(stc_handle* h, double* d_b, int32_t nrhs, void* stream);
    NaN everywhere when that factorization failed (stc_info != 0).  Overwrites
    the workspace's selected-inverse scratch; the factor is left intact. */
 int stc_logdet_backward(stc_handle* h, const double* d_gbar, double* d_grad_values, void* stream);
+
+/* Selected inversion of the last single factorization (Sec. 6.7: the
+   resident factor serves selected inversion, whose diagonal gives the
+   posterior marginal variances of a Gaussian field with precision A).
+   Computes Z = (P A P^T)^-1 on the pattern of L on the device -- the
+   blocked Takahashi recurrence over the tile DAG in reverse, the same sweep
+   as stc_logdet_backward, into the workspace's selected-inverse scratch --
+   and, when d_diag (device) double[n] is not NULL, writes diag(A^-1) to it
+   in original numbering.  NaN throughout when that factorization failed.
+   The factor is left intact; the scratch holds Z until the next
+   factorization (read it with stc_get_selinv). */
+int stc_selinv(stc_handle* h, double* d_diag, void* stream);
+
+/* Copy Z = (P A P^T)^-1 on the pattern of L, as left by the last stc_selinv
+   or stc_logdet_backward of the current factorization, to h_Zx (host)
+   double[nnz(L)] in stc_get_L_pattern order (permuted numbering);
+   synchronizes the stream.  STC_ERR_STATE if no selected inverse of the
+   current factorization is held.  NaN throughout when it failed. */
+int stc_get_selinv(stc_handle* h, double* h_Zx, void* stream);
 
 /* Status of the last single factorization; synchronizes the bound stream.
    info (host) receives 0 or the 1-based permuted column of the first pivot

@@ -1239,6 +1239,19 @@ __global__ void k_logdet_grad(const double* __restrict__ Z, const int64_t* __res
   }
 }
 
+// diag(A^-1) in original numbering from the selected inverse in store
+// layout: out[perm[i]] = Z_ii, NaN when the factorization failed
+__global__ void k_selinv_diag(const double* __restrict__ Z, const int32_t* __restrict__ perm, int64_t n,
+                              int32_t nb, const int32_t* __restrict__ info, double* __restrict__ out) {
+  const bool ok = info[0] == 0;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += step) {
+    const int64_t k = i / nb, r = i % nb;
+    out[perm[i]] = ok ? Z[k * nb * nb + r * nb + r] : __builtin_nan("");
+  }
+}
+
 __global__ __launch_bounds__(256) void k_mfma_issue(double* __restrict__ out, int32_t iters, double seed) {
   const int lane = threadIdx.x & 63;
   double a = seed + lane * 1e-3, b = seed - lane * 1e-3;
@@ -1310,8 +1323,12 @@ __global__ void k_gather(const double* __restrict__ store, const int64_t* __rest
 // solve: permute, forward and backward sweeps over block levels, unpermute
 // ---------------------------------------------------------------------------
 
+// y = P b for nrhs columns of value set blockIdx.y (y stride ystride per
+// value set, padded rows zero)
 __global__ void k_perm_in(const double* __restrict__ b, const int32_t* __restrict__ perm,
-                          int64_t n, int64_t np, int32_t nrhs, double* __restrict__ y) {
+                          int64_t n, int64_t np, int32_t nrhs, double* __restrict__ y, int64_t ystride) {
+  b += (int64_t)blockIdx.y * n * nrhs;
+  y += (int64_t)blockIdx.y * ystride;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= np * nrhs) return;
   int64_t r = i / np, a = i % np;
@@ -1322,11 +1339,13 @@ __global__ void k_perm_in(const double* __restrict__ b, const int32_t* __restric
 // failed (info of the first value set non-zero)
 __global__ void k_perm_out(const double* __restrict__ y, const int32_t* __restrict__ perm,
                            const int32_t* __restrict__ info, int64_t n, int64_t np, int32_t nrhs,
-                           double* __restrict__ b) {
+                           double* __restrict__ b, int64_t ystride) {
+  b += (int64_t)blockIdx.y * n * nrhs;
+  y += (int64_t)blockIdx.y * ystride;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n * nrhs) return;
   int64_t r = i / n, a = i % n;
-  b[r * n + perm[a]] = info[0] != 0 ? __builtin_nan("") : y[r * np + a];
+  b[r * n + perm[a]] = info[blockIdx.y] != 0 ? __builtin_nan("") : y[r * np + a];
 }
 
 // Both sweeps run level by level over the blocks of the tile grid and read L
@@ -1631,7 +1650,11 @@ __global__ __launch_bounds__(256) void k_sfwd_step(const int32_t* __restrict__ i
                                                    const int32_t* __restrict__ rows,
                                                    const double* __restrict__ S,
                                                    const double* __restrict__ dinv,
-                                                   double* __restrict__ y, int64_t np, int32_t nrhs) {
+                                                   double* __restrict__ y, int64_t np, int32_t nrhs,
+                                                   int64_t mstride, int64_t dstride, int64_t ystride) {
+  S += (int64_t)blockIdx.y * mstride;  // value set blockIdx.y: its factor, inverses and right-hand sides
+  dinv += (int64_t)blockIdx.y * dstride;
+  y += (int64_t)blockIdx.y * ystride;
   constexpr int LW = NB - PW + 1;
   __shared__ double r[NB * R];
   __shared__ double ys[(R == 1 ? NB : 256) * R];  // the gathered y_k of the products, then
@@ -1826,7 +1849,11 @@ __global__ __launch_bounds__(256) void k_sbwd_step(const int32_t* __restrict__ i
                                                    const int32_t* __restrict__ rows,
                                                    const double* __restrict__ S,
                                                    const double* __restrict__ dinv,
-                                                   double* __restrict__ y, int64_t np, int32_t nrhs) {
+                                                   double* __restrict__ y, int64_t np, int32_t nrhs,
+                                                   int64_t mstride, int64_t dstride, int64_t ystride) {
+  S += (int64_t)blockIdx.y * mstride;  // value set blockIdx.y: its factor, inverses and right-hand sides
+  dinv += (int64_t)blockIdx.y * dstride;
+  y += (int64_t)blockIdx.y * ystride;
   __shared__ double r[NB * R];
   __shared__ double sm[SbwdLds<NB, R>::SIZE];
   double* xg = sm;

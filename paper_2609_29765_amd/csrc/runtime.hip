@@ -100,7 +100,7 @@ struct stc_handle {
   int32_t* d_sbwd_items = nullptr;
   TileD* d_sfwd_tl = nullptr;  // descriptors of each item's tiles, in item order
   TileD* d_sbwd_tl = nullptr;
-  std::map<int32_t, hipGraphExec_t> solve_graphs;  // by right-hand sides per sweep
+  std::map<int64_t, hipGraphExec_t> solve_graphs;  // by right-hand sides per sweep (batched: negative keys)
   // binding
   int device = -1;
   char* ws = nullptr;
@@ -108,6 +108,8 @@ struct stc_handle {
   int32_t batch = 0;
   hipStream_t last_stream = nullptr;
   bool factored = false;
+  bool zs_ready = false;       // d_zs holds the selected inverse of the last single factorization
+  int32_t fact_members = 0;    // value sets whose stores hold a factor (stc_solve_batched)
   // device views into the workspace (set by bind)
   int64_t* d_vmap = nullptr;
   int32_t* d_maps = nullptr;
@@ -178,7 +180,7 @@ size_t layout(const stc_handle* hc, int32_t batch, char* base) {
   take(&h->d_rows, sizeof(int32_t) * s.rows.size());
   take(&h->d_info, sizeof(int32_t) * (size_t)batch);
   take(&h->d_ld, sizeof(double) * (size_t)batch);
-  take(&h->d_y, sizeof(double) * (size_t)padded_n(h) * kMaxRhs);
+  take(&h->d_y, sizeof(double) * (size_t)padded_n(h) * std::max<size_t>(kMaxRhs, (size_t)SR * (size_t)batch));
   take(&h->d_sfwd_items, sizeof(int32_t) * h->sfwd_items.size());
   take(&h->d_sbwd_items, sizeof(int32_t) * h->sbwd_items.size());
   take(&h->d_sfwd_tl, sizeof(TileD) * h->sfwd_tl.size());
@@ -398,41 +400,47 @@ int build_graph(stc_handle* h, int32_t members, hipGraphExec_t* ex) {
 // d_y: one launch per level, each solving that level's blocks after the
 // products of the level before
 template <int NB, int R>
-void launch_sweeps_r(stc_handle* h, double* y0, int32_t nr, int32_t g0, hipStream_t st) {
-  const int64_t np = padded_n(h);
+void launch_sweeps_r(stc_handle* h, double* y0, int32_t nr, int32_t g0, int32_t members, int64_t ystride,
+                     hipStream_t st) {
+  const int64_t np = padded_n(h), ms = h->plan.store, ds = dinv_stride(h);
   double* y = y0 + (int64_t)g0 * np;
   for (size_t q = 0; q < h->sfwd_nstep.size(); ++q) {
     const int32_t c = h->sfwd_ptr[q], d = h->sfwd_ptr[q + 1];
     if (d > c)
-      hipLaunchKernelGGL((k_sfwd_step<NB, R>), dim3(d - c), dim3(256), 0, st, h->d_sfwd_items + 4 * (int64_t)c,
-                       h->sfwd_nstep[q], h->d_sfwd_tl, h->d_maps, h->d_rows, h->d_store, h->d_dinv, y, np, nr);
+      hipLaunchKernelGGL((k_sfwd_step<NB, R>), dim3(d - c, members), dim3(256), 0, st,
+                         h->d_sfwd_items + 4 * (int64_t)c, h->sfwd_nstep[q], h->d_sfwd_tl, h->d_maps, h->d_rows,
+                         h->d_store, h->d_dinv, y, np, nr, ms, ds, ystride);
   }
   for (size_t q = 0; q < h->sbwd_nstep.size(); ++q) {
     const int32_t c = h->sbwd_ptr[q], d = h->sbwd_ptr[q + 1];
     if (d > c)
-      hipLaunchKernelGGL((k_sbwd_step<NB, R>), dim3(d - c), dim3(256), 0, st, h->d_sbwd_items + 4 * (int64_t)c,
-                       h->sbwd_nstep[q], h->d_sbwd_tl, h->d_rows, h->d_store, h->d_dinv, y, np, nr);
+      hipLaunchKernelGGL((k_sbwd_step<NB, R>), dim3(d - c, members), dim3(256), 0, st,
+                         h->d_sbwd_items + 4 * (int64_t)c, h->sbwd_nstep[q], h->d_sbwd_tl, h->d_rows, h->d_store,
+                         h->d_dinv, y, np, nr, ms, ds, ystride);
   }
 }
 
 template <int NB>
-void launch_sweeps_nb(stc_handle* h, double* y0, int32_t nr, int32_t g0, hipStream_t st) {
-  if (nr == 1) launch_sweeps_r<NB, 1>(h, y0, nr, g0, st);
-  else launch_sweeps_r<NB, SR>(h, y0, nr, g0, st);
+void launch_sweeps_nb(stc_handle* h, double* y0, int32_t nr, int32_t g0, int32_t members, int64_t ystride,
+                      hipStream_t st) {
+  if (nr == 1) launch_sweeps_r<NB, 1>(h, y0, nr, g0, members, ystride, st);
+  else launch_sweeps_r<NB, SR>(h, y0, nr, g0, members, ystride, st);
 }
 
-// the sweeps of right-hand sides [g0, g0 + nr) of y0 (stride padded_n)
-void launch_sweeps(stc_handle* h, double* y0, int32_t nr, int32_t g0, hipStream_t st) {
+// the sweeps of right-hand sides [g0, g0 + nr) of y0 (stride padded_n), for
+// value sets 0..members-1 (value set b's right-hand sides at y0 + b ystride)
+void launch_sweeps(stc_handle* h, double* y0, int32_t nr, int32_t g0, hipStream_t st, int32_t members = 1,
+                   int64_t ystride = 0) {
   switch (h->plan.nb) {
-    case 32: launch_sweeps_nb<32>(h, y0, nr, g0, st); break;
-    case 64: launch_sweeps_nb<64>(h, y0, nr, g0, st); break;
-    case 128: launch_sweeps_nb<128>(h, y0, nr, g0, st); break;
-    case 256: launch_sweeps_nb<256>(h, y0, nr, g0, st); break;
+    case 32: launch_sweeps_nb<32>(h, y0, nr, g0, members, ystride, st); break;
+    case 64: launch_sweeps_nb<64>(h, y0, nr, g0, members, ystride, st); break;
+    case 128: launch_sweeps_nb<128>(h, y0, nr, g0, members, ystride, st); break;
+    case 256: launch_sweeps_nb<256>(h, y0, nr, g0, members, ystride, st); break;
   }
 }
 
-int get_solve_graph(stc_handle* h, int32_t nr, int32_t g0, hipGraphExec_t* out) {
-  const int32_t key = nr * 1024 + g0;
+int get_solve_graph(stc_handle* h, int32_t nr, int32_t g0, hipGraphExec_t* out, int32_t members = 1) {
+  const int64_t key = members > 1 ? -((int64_t)members * 16 + nr) : (int64_t)nr * 1024 + g0;
   auto it = h->solve_graphs.find(key);
   if (it != h->solve_graphs.end()) {
     *out = it->second;
@@ -441,7 +449,7 @@ int get_solve_graph(stc_handle* h, int32_t nr, int32_t g0, hipGraphExec_t* out) 
   hipStream_t cs;
   HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
-  launch_sweeps(h, h->d_y, nr, g0, cs);
+  launch_sweeps(h, h->d_y, nr, g0, cs, members, (int64_t)SR * padded_n(h));
   hipGraph_t g;
   hipError_t e = hipStreamEndCapture(cs, &g);
   (void)hipStreamDestroy(cs);
@@ -793,6 +801,8 @@ int stc_bind(stc_handle* h, void* d_ws, size_t bytes, int32_t batch, void* strea
   if (h->back_graph) (void)hipGraphExecDestroy(h->back_graph);
   h->back_graph = nullptr;
   h->factored = false;
+  h->zs_ready = false;
+  h->fact_members = 0;
   HIPCHK(hipGetDevice(&h->device));
   if (int rc0 = scratch_address(&h->d_scratch)) return rc0;
   h->ws = (char*)d_ws;
@@ -861,6 +871,8 @@ int stc_factorize(stc_handle* h, const double* d_values, void* stream) {
   if (rc) return rc;
   h->last_stream = st;
   h->factored = true;
+  h->zs_ready = false;
+  h->fact_members = std::max<int32_t>(h->fact_members, 1);
   return 0;
 }
 
@@ -879,6 +891,8 @@ int stc_factorize_batched(stc_handle* h, const double* d_values, int32_t B, doub
   HIPCHK(hipGetLastError());
   h->last_stream = st;
   h->factored = B >= 1;  // member 0 is the "last single factorization" too
+  h->zs_ready = false;
+  h->fact_members = B;
   return 0;
 }
 
@@ -903,7 +917,7 @@ int stc_solve(stc_handle* h, double* d_b, int32_t nrhs, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   const int64_t n = h->sym.n, np = padded_n(h);
   hipLaunchKernelGGL(k_perm_in, dim3((unsigned)((np * nrhs + 255) / 256)), dim3(256), 0, st, d_b,
-                     h->d_perm, n, np, nrhs, h->d_y);
+                     h->d_perm, n, np, nrhs, h->d_y, np * nrhs);
   // groups of up to SR right-hand sides, each one replay of the captured sweeps
   for (int32_t g0 = 0; g0 < nrhs; g0 += SR) {
     const int32_t nr = std::min<int32_t>(SR, nrhs - g0);
@@ -913,7 +927,29 @@ int stc_solve(stc_handle* h, double* d_b, int32_t nrhs, void* stream) {
     HIPCHK(hipGraphLaunch(ex, st));
   }
   hipLaunchKernelGGL(k_perm_out, dim3((unsigned)((n * nrhs + 255) / 256)), dim3(256), 0, st, h->d_y,
-                     h->d_perm, h->d_info, n, np, nrhs, d_b);
+                     h->d_perm, h->d_info, n, np, nrhs, d_b, np * nrhs);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int stc_solve_batched(stc_handle* h, double* d_b, int32_t B, int32_t nrhs, void* stream) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!d_b) return fail(STC_ERR_ARG, "null right-hand sides");
+  if (nrhs < 1 || nrhs > SR) return fail(STC_ERR_ARG, "nrhs must be in [1, 8] for a batched solve");
+  if (B < 1 || B > h->batch) return fail(STC_ERR_ARG, "B must be in [1, bound batch]");
+  if (B > h->fact_members)
+    return fail(STC_ERR_STATE, "batched solve needs a batched factorization of at least B value sets");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = h->sym.n, np = padded_n(h), ys = (int64_t)SR * np;
+  hipLaunchKernelGGL(k_perm_in, dim3((unsigned)((np * nrhs + 255) / 256), B), dim3(256), 0, st, d_b, h->d_perm, n,
+                     np, nrhs, h->d_y, ys);
+  hipGraphExec_t ex;
+  rc = get_solve_graph(h, nrhs == 1 ? 1 : SR, 0, &ex, B);
+  if (rc) return rc;
+  HIPCHK(hipGraphLaunch(ex, st));
+  hipLaunchKernelGGL(k_perm_out, dim3((unsigned)((n * nrhs + 255) / 256), B), dim3(256), 0, st, h->d_y, h->d_perm,
+                     h->d_info, n, np, nrhs, d_b, ys);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -933,10 +969,10 @@ int stc_solve_noalloc(stc_handle* h, double* d_b, int32_t nrhs, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   double* y = h->d_scratch;  // k_perm_in writes every entry the sweeps read
   hipLaunchKernelGGL(k_perm_in, dim3((unsigned)((np * nrhs + 255) / 256)), dim3(256), 0, st, d_b,
-                     h->d_perm, n, np, nrhs, y);
+                     h->d_perm, n, np, nrhs, y, np * nrhs);
   for (int32_t g0 = 0; g0 < nrhs; g0 += SR) launch_sweeps(h, y, std::min<int32_t>(SR, nrhs - g0), g0, st);
   hipLaunchKernelGGL(k_perm_out, dim3((unsigned)((n * nrhs + 255) / 256)), dim3(256), 0, st, y,
-                     h->d_perm, h->d_info, n, np, nrhs, d_b);
+                     h->d_perm, h->d_info, n, np, nrhs, d_b, np * nrhs);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -951,11 +987,50 @@ int stc_logdet_backward(stc_handle* h, const double* d_gbar, double* d_grad_valu
   rc = get_back_graph(h, &ex);
   if (rc) return rc;
   HIPCHK(hipGraphLaunch(ex, st));
+  h->zs_ready = true;
+  h->last_stream = st;
   const int64_t qnz = h->sym.qnz;
   const int64_t grid = std::min<int64_t>(4096, (qnz + 255) / 256);
   hipLaunchKernelGGL(k_logdet_grad, dim3((unsigned)grid), dim3(256), 0, st, h->d_zs, h->d_vmap,
                      h->d_bdiag, d_gbar, h->d_info, qnz, d_grad_values);
   HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int stc_selinv(stc_handle* h, double* d_diag, void* stream) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!h->factored) return fail(STC_ERR_STATE, "selected inversion before factorize");
+  hipStream_t st = (hipStream_t)stream;
+  hipGraphExec_t ex;
+  rc = get_back_graph(h, &ex);
+  if (rc) return rc;
+  HIPCHK(hipGraphLaunch(ex, st));
+  h->zs_ready = true;
+  h->last_stream = st;
+  if (d_diag) {
+    const int64_t n = h->sym.n;
+    const int64_t grid = std::min<int64_t>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL(k_selinv_diag, dim3((unsigned)grid), dim3(256), 0, st, h->d_zs, h->d_perm, n, h->plan.nb,
+                       h->d_info, d_diag);
+  }
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int stc_get_selinv(stc_handle* h, double* h_Zx, void* stream) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!h_Zx) return fail(STC_ERR_ARG, "null output");
+  if (!h->zs_ready) return fail(STC_ERR_STATE, "selected inverse export before stc_selinv");
+  std::vector<double> store((size_t)h->plan.store);
+  HIPCHK(hipMemcpyAsync(store.data(), h->d_zs, sizeof(double) * store.size(), hipMemcpyDeviceToHost,
+                        (hipStream_t)stream));
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  int32_t info = 0;
+  HIPCHK(hipMemcpy(&info, h->d_info, sizeof(int32_t), hipMemcpyDeviceToHost));
+  const auto& lm = h->plan.lmap;
+  for (size_t q = 0; q < lm.size(); ++q) h_Zx[q] = info ? std::nan("") : store[(size_t)lm[q]];
   return 0;
 }
 
@@ -1227,6 +1302,8 @@ int stc_profile_factorize(stc_handle* h, const double* d_values, void* stream, d
   if (rc) return rc;
   h->last_stream = st;
   h->factored = true;
+  h->zs_ready = false;
+  h->fact_members = std::max<int32_t>(h->fact_members, 1);
   return 0;
 }
 

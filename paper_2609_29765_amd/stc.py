@@ -29,7 +29,7 @@ _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 # every entry point of include/stc.h
 EXPORTS = [
     "stc_analyse", "stc_workspace_bytes", "stc_bind", "stc_factorize", "stc_factorize_batched",
-    "stc_logdet", "stc_solve", "stc_solve_noalloc", "stc_logdet_backward", "stc_info", "stc_get_sizes",
+    "stc_logdet", "stc_solve", "stc_solve_noalloc", "stc_solve_batched", "stc_logdet_backward", "stc_selinv", "stc_get_selinv", "stc_info", "stc_get_sizes",
     "stc_get_features", "stc_get_perm", "stc_get_etree", "stc_get_L_pattern", "stc_get_tiles",
     "stc_get_tasks", "stc_get_factor", "stc_get_batch_factor", "stc_get_work", "stc_get_plan_stats", "stc_check_schedule", "stc_check_solve_schedule", "stc_profile_factorize",
     "stc_fp64_mfma_peak", "stc_destroy",
@@ -67,7 +67,10 @@ def lib():
     L.stc_logdet.argtypes = [vp, vp, vp]
     L.stc_solve.argtypes = [vp, vp, C.c_int32, vp]
     L.stc_solve_noalloc.argtypes = [vp, vp, C.c_int32, vp]
+    L.stc_solve_batched.argtypes = [vp, vp, C.c_int32, C.c_int32, vp]
     L.stc_logdet_backward.argtypes = [vp, vp, vp, vp]
+    L.stc_selinv.argtypes = [vp, vp, vp]
+    L.stc_get_selinv.argtypes = [vp, _f64p, vp]
     L.stc_info.argtypes = [vp, C.POINTER(C.c_int32)]
     L.stc_get_sizes.argtypes = [vp, _i64p]
     L.stc_get_features.argtypes = [vp, _f64p]
@@ -266,12 +269,42 @@ class Analysis:
         X = X.t()
         return X.reshape(-1) if one else X.contiguous()
 
+    def solve_batched(self, b):
+        """Solve A_b x_b = b_b for every value set b of the last batched
+        factorization: b device float64 [B, n] or [B, n, nrhs] (nrhs <= 8)."""
+        _need_cuda(b)
+        self._ws_device()
+        one = b.dim() == 2
+        if not (b.dim() in (2, 3) and b.shape[1] == self.n):
+            raise ValueError(f"b must have shape [B, {self.n}] or [B, {self.n}, nrhs], got {tuple(b.shape)}")
+        Bv = b.reshape(b.shape[0], self.n, 1) if one else b
+        X = Bv.transpose(1, 2).contiguous()  # per value set column-major n x nrhs
+        _check(lib().stc_solve_batched(self._h, _dptr(X), int(Bv.shape[0]), int(Bv.shape[2]), _stream_ptr()))
+        X = X.transpose(1, 2)
+        return X.reshape(b.shape[0], self.n) if one else X.contiguous()
+
     def logdet_backward(self, gbar):
         import torch
         g = gbar.reshape(1).to(torch.float64).contiguous()
         out = torch.empty(self.qnz, dtype=torch.float64, device=self._ws_device())
         _check(lib().stc_logdet_backward(self._h, _dptr(g), _dptr(out), _stream_ptr()))
         return out
+
+    def selinv(self):
+        """Selected inversion of the last factorization: returns diag(A^-1) in
+        original numbering (device float64 [n]); Z on the pattern of L stays
+        in the workspace (selinv_pattern copies it to the host)."""
+        import torch
+        out = torch.empty(self.n, dtype=torch.float64, device=self._ws_device())
+        _check(lib().stc_selinv(self._h, _dptr(out), _stream_ptr()))
+        return out
+
+    def selinv_pattern(self):
+        """Host copy of Z = (P A P^T)^-1 on the pattern of L (L_pattern order)."""
+        self._ws_device()
+        Zx = np.zeros(self.lnz)
+        _check(lib().stc_get_selinv(self._h, Zx, _stream_ptr()))
+        return Zx
 
     def work(self):
         """Static flop and byte counts of one factorization (see stc_get_work)."""

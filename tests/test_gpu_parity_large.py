@@ -143,3 +143,36 @@ def test_batched_nan_in_one_member():
             continue
         assert info1[b] == 0 and ld1[b] == ld0[b]
         assert np.array_equal(a.factor(member=b), F0[b])
+
+
+def test_solve_batched_members():
+    """stc_solve_batched: each value set of the 24^3 batch (B = 16 of them,
+    1 and 3 right-hand sides) against the oracle's solve with that value
+    set's factor; a failed member gives NaN and leaves the others exact."""
+    B = 16
+    w = W.batched_laplacian3d(m=24, B=B, seed=1)
+    a = S.Analysis(w.n, w.colptr, w.rowind, nb=64, ordering="nd").bind(batch=B)
+    ld, info = a.factorize_batched(dev(w.values))
+    assert np.all(info.cpu().numpy() == 0)
+    o = O.Analysis(w.n, w.colptr, w.rowind, "nd", nb=64)
+    rng = np.random.default_rng(7)
+    for nrhs in (1, 3):
+        b = rng.standard_normal((B, w.n)) if nrhs == 1 else rng.standard_normal((B, w.n, nrhs))
+        x = a.solve_batched(dev(b)).cpu().numpy()
+        for m in (0, 5, 15):
+            Lo, _ = o.factor(w.values[m])
+            xo = o.solve(Lo, b[m])
+            assert np.max(np.abs(x[m] - xo)) <= 1e-10 * np.max(np.abs(xo)), (nrhs, m)
+        # one value set's solve alone equals the batched one bit for bit
+        a1 = S.Analysis(w.n, w.colptr, w.rowind, nb=64, ordering="nd").bind()
+        a1.factorize(dev(w.values[5]))
+        assert np.array_equal(a1.solve(dev(b[5])).cpu().numpy(), x[5])
+    v = w.values.copy()
+    diag = np.nonzero(w.rowind == np.repeat(np.arange(w.n), np.diff(w.colptr)))[0]
+    v[3, diag[100]] = -1.0
+    a.factorize_batched(dev(v))
+    b = rng.standard_normal((B, w.n))
+    x = a.solve_batched(dev(b)).cpu().numpy()
+    assert np.all(np.isnan(x[3])) and np.all(np.isfinite(np.delete(x, 3, axis=0)))
+    with pytest.raises(S.STCError):
+        a.solve_batched(dev(np.zeros((B, w.n, 9))))  # nrhs > 8
