@@ -175,9 +175,19 @@ def headline(args):
     t0 = time.time()
     a = stc.Analysis(w.n, w.colptr, w.rowind, nb=args.nb, mode="auto", ordering="natural")
     t_analyse = time.time() - t0
-    a.bind()
-    work = a.work()
     vals = torch.from_numpy(w.values).cuda()
+    # the schedule axis of the autotuner: concurrent update work-groups the
+    # split-K plan balances for, timed on this matrix at the headline tile
+    tune_table = None
+    if args.tune_slots:
+        from paper_2609_29765_amd.autotune import autotune
+        del a
+        a, tune_table = autotune(w.n, w.colptr, w.rowind, vals, nbs=(args.nb,), ordering="natural", trials=3,
+                                 slots=tuple(int(x) for x in args.tune_slots.split(",")))
+        log(f"schedule tuning: {tune_table}")
+    else:
+        a.bind()
+    work = a.work()
     log(f"n={w.n} nnz={w.nnz} nb={a.nb} mode={a.mode} route={a.route} levels={a.nlevels} "
         f"analyse={t_analyse:.2f}s gen={t_gen:.2f}s")
 
@@ -278,6 +288,7 @@ def headline(args):
 
     return dict(
         ms_step=ms_step, step_stats=step_stats, logdet=ld, analyse_s=t_analyse, a=a, w=w, work=work,
+        tune_table=tune_table, wg_slots=(min(tune_table, key=lambda r: r["ms"])["wg_slots"] if tune_table else 0),
         roofline=roofline, uses=uses,
         kinds=kinds, level_family_tflops=round(fam_fl / (fam_ms * 1e-3) / 1e12, 3),
         peaks={"mfma_issue": round(mfma_peak, 2), "dgemm_library_8192": round(dgemm_tf, 2)})
@@ -719,6 +730,8 @@ def main():
     ap.add_argument("--nb", type=int, default=256)
     ap.add_argument("--prof-reps", type=int, default=3)
     ap.add_argument("--batch", type=int, default=128)
+    ap.add_argument("--tune-slots", default="0,320,640",
+                    help="wg_slots candidates the headline's schedule is tuned over (empty: no tuning)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras-out", default=None, help=argparse.SUPPRESS)
@@ -805,7 +818,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"dense-route random SPD n={args.n}, 20% off-diagonal density, "
                                f"tile {a.nb}, natural order (every tile dense)",
-                   "n": args.n, "nb": a.nb, "nnz_lower": w.nnz, "route": a.route, "levels": a.nlevels},
+                   "n": args.n, "nb": a.nb, "nnz_lower": w.nnz, "route": a.route, "levels": a.nlevels,
+                   "wg_slots": hl["wg_slots"]},
         "gflops_tile": round(work["flops_tile"] / (ms_step * 1e-3) / 1e9, 2),
         "frac_peak_whole_factorization": round(work["flops_tile"] / (ms_step * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4),
         "roofline": hl["roofline"],
@@ -819,6 +833,7 @@ def main():
         "factor_uses": hl["uses"],
         "analyse_s": round(hl["analyse_s"], 3),
         "single_replays": hl["step_stats"],
+        "autotune": hl["tune_table"],
     }
     if cpu:
         # factorizations after which the one-off analysis has paid for itself

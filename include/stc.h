@@ -306,6 +306,20 @@ int stc_profile_factorize(stc_handle* h, const double* d_values, void* stream, d
    (8 work-groups of 4 waves per compute unit).  tflops (host) double[1]. */
 int stc_fp64_mfma_peak(void* stream, double* tflops);
 
+/* Persist the analysis of a handle (Sec. 6.6, Table 6: the analysis is the
+   one-off cost that many factorizations amortize) so that another process
+   can skip it.  stc_save writes the symbolic analysis, the factorization
+   and solve plans and the reverse-mode plan to the file at path (host,
+   NUL-terminated; overwritten); nothing device-side is saved.  stc_load reads
+   such a file into a new unbound handle (*out), which then behaves exactly
+   like the one saved: every export and every result is identical.  The
+   file is for the same library build on the same kind of host: it carries
+   a magic, a format version, the host's type sizes and a checksum, and
+   stc_load returns STC_ERR_ARG for a file that does not match them or is
+   truncated or corrupted, STC_ERR_ALLOC when host memory runs out. */
+int stc_save(const stc_handle* h, const char* path);
+int stc_load(const char* path, stc_handle** out);
+
 void stc_destroy(stc_handle* h);
 const char* stc_last_error(void);
 

@@ -1,5 +1,5 @@
-"""Build libstc.so in-tree: the host analyser (g++) and the HIP runtime and
-kernels (hipcc, gfx950)."""
+"""Build libstc.so in-tree: the host analyser and plan persistence (g++) and
+the HIP runtime and kernels (hipcc, gfx950)."""
 import os
 import subprocess
 import sys
@@ -27,11 +27,14 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     ana_o = os.path.join(BUILD, "analyse.o")
     rt_o = os.path.join(BUILD, "runtime.o")
-    _run(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", os.path.join(CSRC, "analyse.cpp"),
-          "-o", ana_o], verbose)
+    per_o = os.path.join(BUILD, "persist.o")
+    for src, obj in (("analyse.cpp", ana_o), ("persist.cpp", per_o)):
+        _run(["g++", "-O2", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-c", os.path.join(CSRC, src),
+              "-o", obj], verbose)
     _run([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, "runtime.hip"), "-o", rt_o], verbose)
     tmp = OUT + ".tmp"
-    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", rt_o, ana_o, "-o", tmp], verbose)
+    _run([HIPCC, "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", rt_o, ana_o, per_o, "-o", tmp],
+         verbose)
     os.replace(tmp, OUT)
     return OUT
 

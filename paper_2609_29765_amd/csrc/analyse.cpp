@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <map>
 #include <queue>
+#include <thread>
 #include <cmath>
 #include <functional>
 
@@ -455,6 +456,33 @@ int check_pattern(int64_t n, const int64_t* cp, const int32_t* ri, std::string* 
   return 0;
 }
 
+void build_lmap(const Symbolic& s, Plan* p) {
+  const int32_t nb = s.nb, NT = s.NT;
+  const int64_t ntiles = (int64_t)s.tiles.size();
+  std::vector<int64_t> col_first((size_t)NT + 1, 0);
+  for (const TileInfo& t : s.tiles) col_first[t.k + 1]++;
+  for (int32_t k = 0; k < NT; ++k) col_first[k + 1] += col_first[k];
+  std::vector<int32_t> inv((size_t)ntiles * nb, -1);
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const TileInfo& ti = s.tiles[t];
+    for (int32_t r = 0; r < ti.cnt; ++r) inv[(size_t)t * nb + s.rows[ti.roff + r]] = r;
+  }
+  p->lmap.resize((size_t)s.lnz);
+  for (int64_t j = 0; j < s.n; ++j) {
+    const int32_t bj = (int32_t)(j / nb);
+    int64_t t = col_first[bj];  // rows ascend, so the tiles of column j are met in order
+    for (int64_t q = s.lp[j]; q < s.lp[j + 1]; ++q) {
+      const int32_t i = s.li[q], bi = i / nb;
+      if (bi == bj) {
+        p->lmap[q] = (int64_t)bj * nb * nb + (int64_t)(i % nb) * nb + (j % nb);
+        continue;
+      }
+      while (s.tiles[t].m < bi) ++t;
+      p->lmap[q] = p->tile_off[t] + (int64_t)inv[(size_t)t * nb + (i % nb)] * nb + (j % nb);
+    }
+  }
+}
+
 int analyse(int64_t n, const int64_t* cp, const int32_t* ri, int method, int nb, int mode,
             const int32_t* perm, Symbolic* out, std::string* why) {
   int rc = check_pattern(n, cp, ri, why);
@@ -496,13 +524,32 @@ int analyse(int64_t n, const int64_t* cp, const int32_t* ri, int method, int nb,
     out->method = method;
     return analyse_perm(out, nb, mode);
   }
+  // the three candidates are independent: each is ordered and scored on a
+  // thread of its own, as the paper runs its candidate orderings in
+  // parallel (Sec. 3); the choice below reads only their scores
   Symbolic cand[3];
-  for (int m = 0; m < 3; ++m) {
-    cand[m] = fresh();
-    cand[m].perm = fixed_ordering(g, n, m, &cand[m].ndense);
-    cand[m].method = m;
-    analyse_perm(&cand[m], nb, mode);
+  int crc[3] = {0, 0, 0};
+  auto score = [&](int m) {
+    try {
+      cand[m] = fresh();
+      cand[m].perm = fixed_ordering(g, n, m, &cand[m].ndense);
+      cand[m].method = m;
+      crc[m] = analyse_perm(&cand[m], nb, mode);
+    } catch (const std::bad_alloc&) {
+      crc[m] = STC_ERR_ALLOC;
+    }
+  };
+  {
+    std::thread t1(score, 1), t2(score, 2);
+    score(0);
+    t1.join();
+    t2.join();
   }
+  for (int m = 0; m < 3; ++m)
+    if (crc[m]) {
+      *why = "analysis of an ordering candidate failed";
+      return crc[m];
+    }
   int best_fill = 0;
   for (int m = 1; m < 3; ++m)
     if (cand[m].lnz < cand[best_fill].lnz) best_fill = m;
@@ -580,9 +627,7 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std
       int32_t a = s.iperm[s.qi[q]], b = s.iperm[c];
       p->vmap[q] = store_pos(std::max(a, b), std::min(a, b));
     }
-  p->lmap.resize((size_t)s.lnz);
-  for (int64_t j = 0; j < n; ++j)
-    for (int64_t q = s.lp[j]; q < s.lp[j + 1]; ++q) p->lmap[q] = store_pos(s.li[q], (int32_t)j);
+  build_lmap(s, p);
 
   // gather maps: inverse row map of every tile (used as column maps), stored
   // once; identity for full tiles

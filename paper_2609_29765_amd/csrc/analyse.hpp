@@ -189,4 +189,15 @@ struct BackPlan {
 
 int build_backward(const Symbolic& s, Plan* p, BackPlan* b, std::string* why);
 
+// Plan::lmap (the store offset of every entry of L, for the host-side factor
+// and selected-inverse exports) from the tiles and their store offsets.
+void build_lmap(const Symbolic& s, Plan* p);
+
+// The analysed state as a byte stream and back (persist.cpp): magic, format
+// version, type sizes, the three structures (Plan::lmap left out and rebuilt
+// on reading), a checksum.  deserialize_plan returns STC_ERR_ARG with a
+// message for a stream it cannot read.
+int serialize_plan(Symbolic& s, Plan& p, BackPlan& b, std::vector<char>* out);
+int deserialize_plan(const char* data, size_t bytes, Symbolic* s, Plan* p, BackPlan* b, std::string* why);
+
 }  // namespace stc

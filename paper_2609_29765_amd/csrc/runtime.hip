@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -645,6 +646,109 @@ static int check_sweep(const stc_handle* h, bool fwd, const std::vector<int32_t>
   return 0;
 }
 
+// the host-side lists derived from the symbolic analysis and the plans:
+// flattened level work lists and the solve sweeps' work items
+static void finish_handle(stc_handle* h) {
+  h->back_level_ptr.push_back(0);
+  for (const auto& li : h->back.level_items) {
+    h->back_items.insert(h->back_items.end(), li.begin(), li.end());
+    h->back_level_ptr.push_back((int32_t)(h->back_items.size() / 3));
+  }
+  // flatten the level lists
+  for (const Level& L : h->plan.levels) {
+    LevelOffsets x;
+    x.u_off = (int32_t)(h->upd_items.size() / 4);
+    x.u_cnt = (int32_t)(L.upd_items.size() / 4);
+    x.u_last = L.upd_last;
+    x.g_last = L.big_last;
+    h->upd_items.insert(h->upd_items.end(), L.upd_items.begin(), L.upd_items.end());
+    x.g_off = (int32_t)(h->big_items.size() / 4);
+    x.g_cnt = (int32_t)(L.big_items.size() / 4);
+    h->big_items.insert(h->big_items.end(), L.big_items.begin(), L.big_items.end());
+    x.p_off = (int32_t)h->potrf_list.size();
+    x.p_cnt = (int32_t)L.potrf.size();
+    h->potrf_list.insert(h->potrf_list.end(), L.potrf.begin(), L.potrf.end());
+    x.t_off = (int32_t)(h->trsm_items.size() / 2);
+    x.t_cnt = (int32_t)(L.trsm_items.size() / 2);
+    h->trsm_items.insert(h->trsm_items.end(), L.trsm_items.begin(), L.trsm_items.end());
+    h->lv.push_back(x);
+  }
+  // solve work items.  Level q's blocks are solved by step items that
+  // first apply the tiles feeding them from level q - 1, in one launch with
+  // the panel chunks for later blocks that level q - 1 feeds.  A step item
+  // reads its tiles whole where a panel chunk reads a 1 / (n_b / chunk)
+  // share of them, so where that serial excess passes kStepFuseBytes at
+  // some block of the level (a saved launch is worth well under a
+  // microsecond) the level gets two launches instead: every chunk of level
+  // q - 1's products, then step items with no tiles.  Tiles of one item are
+  // taken in a fixed order.
+  const Plan& pl = h->plan;
+  constexpr double kStepFuseBytes = 65536.0;
+  auto sweep_items = [&](const std::vector<int32_t>& lptr, const std::vector<int32_t>& lblk,
+                         const std::vector<int32_t>& tptr, const std::vector<int32_t>& tix, bool fwd,
+                         int32_t chunk, std::vector<int32_t>* items, std::vector<int32_t>* ptr,
+                         std::vector<int32_t>* nstep, std::vector<int32_t>* tl) {
+    const int32_t nlev = (int32_t)lptr.size() - 1;
+    std::vector<int32_t> lev((size_t)h->sym.NT, -1);
+    for (int32_t L = 0; L < nlev; ++L)
+      for (int32_t b = lptr[(size_t)L]; b < lptr[(size_t)L + 1]; ++b) lev[(size_t)lblk[(size_t)b]] = L;
+    std::map<int32_t, std::vector<int32_t>> feed;
+    auto close_launch = [&](int32_t ns) {
+      nstep->push_back(ns);
+      ptr->push_back((int32_t)(items->size() / 4));
+    };
+    auto panel_chunks = [&](int32_t fed, const std::vector<int32_t>& ts) {
+      const int32_t t0 = (int32_t)tl->size();
+      tl->insert(tl->end(), ts.begin(), ts.end());
+      const int32_t t1 = (int32_t)tl->size();
+      for (int32_t i0 = 0; i0 < pl.nb; i0 += chunk) items->insert(items->end(), {fed, i0, t0, t1});
+    };
+    ptr->push_back(0);
+    for (int32_t q = 0; q < nlev; ++q) {
+      feed.clear();
+      if (q > 0)
+        for (int32_t b = lptr[(size_t)q - 1]; b < lptr[(size_t)q]; ++b) {
+          const int32_t k = lblk[(size_t)b];
+          for (int32_t z = tptr[(size_t)k]; z < tptr[(size_t)k + 1]; ++z) {
+            const int32_t t = tix[(size_t)z];
+            const TileInfo& ti = h->sym.tiles[(size_t)t];
+            feed[fwd ? ti.m : ti.k].push_back(t);
+          }
+        }
+      double excess = 0.0;  // largest serial excess of a step item, bytes
+      for (int32_t b = lptr[(size_t)q]; b < lptr[(size_t)q + 1]; ++b) {
+        auto it = feed.find(lblk[(size_t)b]);
+        if (it == feed.end()) continue;
+        double rows = 0.0;
+        for (int32_t t : it->second) rows += h->sym.tiles[(size_t)t].cnt;
+        excess = std::max(excess, rows * (double)std::max(0, pl.nb - chunk) * sizeof(double));
+      }
+      const bool fuse = excess <= kStepFuseBytes;
+      if (!fuse) {
+        for (const auto& kv : feed) panel_chunks(kv.first, kv.second);
+        close_launch(0);
+      }
+      int32_t ns = 0;
+      for (int32_t b = lptr[(size_t)q]; b < lptr[(size_t)q + 1]; ++b) {
+        const int32_t m = lblk[(size_t)b];
+        const int32_t t0 = (int32_t)tl->size();
+        auto it = feed.find(m);
+        if (fuse && it != feed.end()) tl->insert(tl->end(), it->second.begin(), it->second.end());
+        items->insert(items->end(), {m, 0, t0, (int32_t)tl->size()});
+        ++ns;
+      }
+      if (fuse)
+        for (const auto& kv : feed)
+          if (lev[(size_t)kv.first] != q) panel_chunks(kv.first, kv.second);
+      close_launch(ns);
+    }
+  };
+  sweep_items(pl.fwd_level_ptr, pl.fwd_level_blk, pl.col_tiles_ptr, pl.col_tiles, true, SCH, &h->sfwd_items,
+              &h->sfwd_ptr, &h->sfwd_nstep, &h->sfwd_tl);
+  sweep_items(pl.bwd_level_ptr, pl.bwd_level_blk, pl.row_tiles_ptr, pl.row_tiles, false, SBC, &h->sbwd_items,
+              &h->sbwd_ptr, &h->sbwd_nstep, &h->sbwd_tl);
+}
+
 extern "C" {
 
 const char* stc_last_error(void) { return g_err.c_str(); }
@@ -673,104 +777,7 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
       delete h;
       return fail(rc, why);
     }
-    h->back_level_ptr.push_back(0);
-    for (const auto& li : h->back.level_items) {
-      h->back_items.insert(h->back_items.end(), li.begin(), li.end());
-      h->back_level_ptr.push_back((int32_t)(h->back_items.size() / 3));
-    }
-    // flatten the level lists
-    for (const Level& L : h->plan.levels) {
-      LevelOffsets x;
-      x.u_off = (int32_t)(h->upd_items.size() / 4);
-      x.u_cnt = (int32_t)(L.upd_items.size() / 4);
-      x.u_last = L.upd_last;
-      x.g_last = L.big_last;
-      h->upd_items.insert(h->upd_items.end(), L.upd_items.begin(), L.upd_items.end());
-      x.g_off = (int32_t)(h->big_items.size() / 4);
-      x.g_cnt = (int32_t)(L.big_items.size() / 4);
-      h->big_items.insert(h->big_items.end(), L.big_items.begin(), L.big_items.end());
-      x.p_off = (int32_t)h->potrf_list.size();
-      x.p_cnt = (int32_t)L.potrf.size();
-      h->potrf_list.insert(h->potrf_list.end(), L.potrf.begin(), L.potrf.end());
-      x.t_off = (int32_t)(h->trsm_items.size() / 2);
-      x.t_cnt = (int32_t)(L.trsm_items.size() / 2);
-      h->trsm_items.insert(h->trsm_items.end(), L.trsm_items.begin(), L.trsm_items.end());
-      h->lv.push_back(x);
-    }
-    // solve work items.  Level q's blocks are solved by step items that
-    // first apply the tiles feeding them from level q - 1, in one launch with
-    // the panel chunks for later blocks that level q - 1 feeds.  A step item
-    // reads its tiles whole where a panel chunk reads a 1 / (n_b / chunk)
-    // share of them, so where that serial excess passes kStepFuseBytes at
-    // some block of the level (a saved launch is worth well under a
-    // microsecond) the level gets two launches instead: every chunk of level
-    // q - 1's products, then step items with no tiles.  Tiles of one item are
-    // taken in a fixed order.
-    const Plan& pl = h->plan;
-    constexpr double kStepFuseBytes = 65536.0;
-    auto sweep_items = [&](const std::vector<int32_t>& lptr, const std::vector<int32_t>& lblk,
-                           const std::vector<int32_t>& tptr, const std::vector<int32_t>& tix, bool fwd,
-                           int32_t chunk, std::vector<int32_t>* items, std::vector<int32_t>* ptr,
-                           std::vector<int32_t>* nstep, std::vector<int32_t>* tl) {
-      const int32_t nlev = (int32_t)lptr.size() - 1;
-      std::vector<int32_t> lev((size_t)h->sym.NT, -1);
-      for (int32_t L = 0; L < nlev; ++L)
-        for (int32_t b = lptr[(size_t)L]; b < lptr[(size_t)L + 1]; ++b) lev[(size_t)lblk[(size_t)b]] = L;
-      std::map<int32_t, std::vector<int32_t>> feed;
-      auto close_launch = [&](int32_t ns) {
-        nstep->push_back(ns);
-        ptr->push_back((int32_t)(items->size() / 4));
-      };
-      auto panel_chunks = [&](int32_t fed, const std::vector<int32_t>& ts) {
-        const int32_t t0 = (int32_t)tl->size();
-        tl->insert(tl->end(), ts.begin(), ts.end());
-        const int32_t t1 = (int32_t)tl->size();
-        for (int32_t i0 = 0; i0 < pl.nb; i0 += chunk) items->insert(items->end(), {fed, i0, t0, t1});
-      };
-      ptr->push_back(0);
-      for (int32_t q = 0; q < nlev; ++q) {
-        feed.clear();
-        if (q > 0)
-          for (int32_t b = lptr[(size_t)q - 1]; b < lptr[(size_t)q]; ++b) {
-            const int32_t k = lblk[(size_t)b];
-            for (int32_t z = tptr[(size_t)k]; z < tptr[(size_t)k + 1]; ++z) {
-              const int32_t t = tix[(size_t)z];
-              const TileInfo& ti = h->sym.tiles[(size_t)t];
-              feed[fwd ? ti.m : ti.k].push_back(t);
-            }
-          }
-        double excess = 0.0;  // largest serial excess of a step item, bytes
-        for (int32_t b = lptr[(size_t)q]; b < lptr[(size_t)q + 1]; ++b) {
-          auto it = feed.find(lblk[(size_t)b]);
-          if (it == feed.end()) continue;
-          double rows = 0.0;
-          for (int32_t t : it->second) rows += h->sym.tiles[(size_t)t].cnt;
-          excess = std::max(excess, rows * (double)std::max(0, pl.nb - chunk) * sizeof(double));
-        }
-        const bool fuse = excess <= kStepFuseBytes;
-        if (!fuse) {
-          for (const auto& kv : feed) panel_chunks(kv.first, kv.second);
-          close_launch(0);
-        }
-        int32_t ns = 0;
-        for (int32_t b = lptr[(size_t)q]; b < lptr[(size_t)q + 1]; ++b) {
-          const int32_t m = lblk[(size_t)b];
-          const int32_t t0 = (int32_t)tl->size();
-          auto it = feed.find(m);
-          if (fuse && it != feed.end()) tl->insert(tl->end(), it->second.begin(), it->second.end());
-          items->insert(items->end(), {m, 0, t0, (int32_t)tl->size()});
-          ++ns;
-        }
-        if (fuse)
-          for (const auto& kv : feed)
-            if (lev[(size_t)kv.first] != q) panel_chunks(kv.first, kv.second);
-        close_launch(ns);
-      }
-    };
-    sweep_items(pl.fwd_level_ptr, pl.fwd_level_blk, pl.col_tiles_ptr, pl.col_tiles, true, SCH, &h->sfwd_items,
-                &h->sfwd_ptr, &h->sfwd_nstep, &h->sfwd_tl);
-    sweep_items(pl.bwd_level_ptr, pl.bwd_level_blk, pl.row_tiles_ptr, pl.row_tiles, false, SBC, &h->sbwd_items,
-                &h->sbwd_ptr, &h->sbwd_nstep, &h->sbwd_tl);
+    finish_handle(h);
     *out = h;
     return 0;
   } catch (const std::bad_alloc&) {
@@ -1331,6 +1338,55 @@ int stc_fp64_mfma_peak(void* stream, double* tflops) {
   const double flops = (double)blocks * 4 /* waves */ * iters * 16 * (16.0 * 16 * 4 * 2);
   *tflops = flops / (ms * 1e-3) / 1e12;
   return 0;
+}
+
+int stc_save(const stc_handle* h, const char* path) {
+  if (!h || !path) return fail(STC_ERR_ARG, "null argument");
+  try {
+    std::vector<char> buf;
+    stc_handle* m = const_cast<stc_handle*>(h);  // serialization only reads the fields it visits
+    serialize_plan(m->sym, m->plan, m->back, &buf);
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(STC_ERR_ARG, std::string("cannot open ") + path + " for writing");
+    const size_t w = std::fwrite(buf.data(), 1, buf.size(), f);
+    const int cl = std::fclose(f);
+    if (w != buf.size() || cl != 0) return fail(STC_ERR_ARG, std::string("short write to ") + path);
+    return 0;
+  } catch (const std::bad_alloc&) {
+    return fail(STC_ERR_ALLOC, "host allocation failed while saving the analysis");
+  }
+}
+
+int stc_load(const char* path, stc_handle** out) {
+  if (!path || !out) return fail(STC_ERR_ARG, "null argument");
+  *out = nullptr;
+  try {
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(STC_ERR_ARG, std::string("cannot open ") + path);
+    std::vector<char> buf;
+    long sz = -1;
+    if (std::fseek(f, 0, SEEK_END) == 0) sz = std::ftell(f);
+    if (sz < 0 || std::fseek(f, 0, SEEK_SET) != 0) {
+      std::fclose(f);
+      return fail(STC_ERR_ARG, std::string("cannot read ") + path);
+    }
+    buf.resize((size_t)sz);
+    const size_t got = sz ? std::fread(buf.data(), 1, (size_t)sz, f) : 0;
+    std::fclose(f);
+    if (got != (size_t)sz) return fail(STC_ERR_ARG, std::string("short read from ") + path);
+    auto* h = new stc_handle();
+    std::string why;
+    const int rc = deserialize_plan(buf.data(), buf.size(), &h->sym, &h->plan, &h->back, &why);
+    if (rc) {
+      delete h;
+      return fail(rc, why);
+    }
+    finish_handle(h);
+    *out = h;
+    return 0;
+  } catch (const std::bad_alloc&) {
+    return fail(STC_ERR_ALLOC, "host allocation failed while loading the analysis");
+  }
 }
 
 void stc_destroy(stc_handle* h) { delete h; }

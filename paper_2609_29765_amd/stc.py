@@ -32,7 +32,7 @@ EXPORTS = [
     "stc_logdet", "stc_solve", "stc_solve_noalloc", "stc_solve_batched", "stc_logdet_backward", "stc_selinv", "stc_get_selinv", "stc_info", "stc_get_sizes",
     "stc_get_features", "stc_get_perm", "stc_get_etree", "stc_get_L_pattern", "stc_get_tiles",
     "stc_get_tasks", "stc_get_factor", "stc_get_batch_factor", "stc_get_work", "stc_get_plan_stats", "stc_check_schedule", "stc_check_solve_schedule", "stc_profile_factorize",
-    "stc_fp64_mfma_peak", "stc_destroy",
+    "stc_fp64_mfma_peak", "stc_save", "stc_load", "stc_destroy",
     "stc_last_error",
 ]
 
@@ -87,6 +87,8 @@ def lib():
     L.stc_check_solve_schedule.argtypes = [vp, _i64p]
     L.stc_profile_factorize.argtypes = [vp, vp, vp, _f64p, _i64p, _f64p]
     L.stc_fp64_mfma_peak.argtypes = [vp, _f64p]
+    L.stc_save.argtypes = [vp, C.c_char_p]
+    L.stc_load.argtypes = [C.c_char_p, C.POINTER(vp)]
     L.stc_destroy.argtypes = [vp]
     L.stc_destroy.restype = None
     L.stc_last_error.restype = C.c_char_p
@@ -127,15 +129,18 @@ class Analysis:
     """Once-per-pattern analysis; factorize / logdet / solve many times."""
 
     def __init__(self, n, colptr, rowind, nb=64, mode="auto", ordering="auto", perm=None,
-                 wg_slots=0):
+                 wg_slots=0, _handle=None):
         L = lib()
-        self.colptr = np.ascontiguousarray(colptr, np.int64)
-        self.rowind = np.ascontiguousarray(rowind, np.int32)
-        self._perm_in = None if perm is None else np.ascontiguousarray(perm, np.int32)
-        o = _opts(int(nb), MODES[mode], ORDERINGS[ordering],
-                  None if self._perm_in is None else self._perm_in.ctypes.data, int(wg_slots))
-        h = C.c_void_p()
-        _check(L.stc_analyse(int(n), self.colptr, self.rowind, C.byref(o), C.byref(h)))
+        if _handle is None:
+            self.colptr = np.ascontiguousarray(colptr, np.int64)
+            self.rowind = np.ascontiguousarray(rowind, np.int32)
+            self._perm_in = None if perm is None else np.ascontiguousarray(perm, np.int32)
+            o = _opts(int(nb), MODES[mode], ORDERINGS[ordering],
+                      None if self._perm_in is None else self._perm_in.ctypes.data, int(wg_slots))
+            h = C.c_void_p()
+            _check(L.stc_analyse(int(n), self.colptr, self.rowind, C.byref(o), C.byref(h)))
+        else:
+            h = _handle
         self._h = h
         sz = np.zeros(16, np.int64)
         _check(L.stc_get_sizes(h, sz))
@@ -149,6 +154,17 @@ class Analysis:
         self.phi, self.rho, self.sigma = (float(x) for x in f)
         self._ws = None
         self.batch = 0
+
+    def save(self, path):
+        """Write the analysis to a file (see stc_save)."""
+        _check(lib().stc_save(self._h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path):
+        """A new, unbound Analysis read from a file written by save()."""
+        h = C.c_void_p()
+        _check(lib().stc_load(os.fsencode(path), C.byref(h)))
+        return cls(None, None, None, _handle=h)
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -176,3 +176,19 @@ def test_solve_batched_members():
     assert np.all(np.isnan(x[3])) and np.all(np.isfinite(np.delete(x, 3, axis=0)))
     with pytest.raises(S.STCError):
         a.solve_batched(dev(np.zeros((B, w.n, 9))))  # nrhs > 8
+
+
+def test_loaded_analysis_factorizes_identically(tmp_path):
+    """A handle read back by stc_load binds and factorizes to the same bits as
+    the handle that was saved."""
+    w = W.differentiable_arrowhead(20, 25, 8, 0)
+    a = S.Analysis(w.n, w.colptr, w.rowind, nb=128, ordering="auto").bind()
+    a.save(tmp_path / "c5.stc")
+    b = S.Analysis.load(tmp_path / "c5.stc").bind()
+    v = dev(w.values)
+    a.factorize(v)
+    b.factorize(v)
+    assert np.array_equal(a.factor(), b.factor())
+    assert float(a.logdet().item()) == float(b.logdet().item())
+    x = dev(np.random.default_rng(2).standard_normal(w.n))
+    assert np.array_equal(a.solve(x).cpu().numpy(), b.solve(x).cpu().numpy())
