@@ -730,31 +730,49 @@ __device__ __forceinline__ void dev_potrf_la(int32_t k, double* __restrict__ S,
       const int w = wave - 1;
       double* WA = Wall + w * WROWS * LKLD;
       double* WB = WA + RB3 * 16 * LKLD;
-      for (int s0 = 0; s0 < j0; s0 += LKC) {
-        // stage 16 columns of this wave's rows of the next panel, and of the
-        // next panel's first 32 rows, as 4-double segments
-        for (int x = lane; x < WROWS * 4; x += 64) {
+      // 16 columns of this wave's rows of the next panel, and of the next
+      // panel's first 32 rows, as 4-double segments: segment x of a chunk
+      // goes to lane x % 64.  The next chunk's segments are loaded into
+      // registers while the current one is multiplied, so the chunks' load
+      // latencies overlap the MFMA work instead of adding up.
+      constexpr int NIT = (WROWS * 4 + 63) / 64;
+      double2 pv[NIT][2];
+      auto fetch = [&](int s0) {
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+          const int x = lane + 64 * it;
           const int rl = x >> 2, seg = (x & 3) * 4;
-          int grow;  // row of the tile, or -1 for a row block past the panel
+          int grow = -1;  // row of the tile, or -1 for a row block past the panel (or a spare segment)
           if (rl < RB3 * 16) {
             const int t = w + 3 * (rl >> 4);
             grow = t < nrb ? j0 + PW + t * 16 + (rl & 15) : -1;
-          } else {
+          } else if (rl < WROWS) {
             grow = j0 + PW + (rl - RB3 * 16);
           }
-          double2 v0 = make_double2(0.0, 0.0), v1 = v0;
+          pv[it][0] = pv[it][1] = make_double2(0.0, 0.0);
           if (grow >= 0) {
             const double2* src = reinterpret_cast<const double2*>(A + (int64_t)grow * NB + s0 + seg);
-            v0 = src[0];
-            v1 = src[1];
+            pv[it][0] = src[0];
+            pv[it][1] = src[1];
           }
-          double* d = (rl < RB3 * 16 ? WA + rl * LKLD : WB + (rl - RB3 * 16) * LKLD) + seg;
-          d[0] = v0.x;
-          d[1] = v0.y;
-          d[2] = v1.x;
-          d[3] = v1.y;
+        }
+      };
+      fetch(0);
+      for (int s0 = 0; s0 < j0; s0 += LKC) {
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+          const int x = lane + 64 * it;
+          const int rl = x >> 2, seg = (x & 3) * 4;
+          if (rl < WROWS) {
+            double* d = (rl < RB3 * 16 ? WA + rl * LKLD : WB + (rl - RB3 * 16) * LKLD) + seg;
+            d[0] = pv[it][0].x;
+            d[1] = pv[it][0].y;
+            d[2] = pv[it][1].x;
+            d[3] = pv[it][1].y;
+          }
         }
         __builtin_amdgcn_wave_barrier();
+        if (s0 + LKC < j0) fetch(s0 + LKC);
 #pragma unroll
         for (int b = 0; b < RB3; ++b) {
           if (w + 3 * b < nrb) {
