@@ -244,7 +244,8 @@ int stc_get_batch_factor(stc_handle* h, int32_t member, double* h_Lx, void* stre
    [2] TRSM flops sum |R_mk| n_b^2; [3] their total; [4] exact Cholesky flops
    sum_j c_j^2 (c_j = entries of column j of L); [5] update bytes: operand
    rows read per task plus every output tile read and written once; [6] value
-   load bytes: 20 per input entry plus 8 per stored double; [7] levels;
+   load bytes: 16 per input entry (value and its load entry) plus 8 per
+   stored double (the store written once); [7] levels;
    [8] flops of stc_logdet_backward (tile products of the selected-inverse
    recurrence, 2 per multiply-add); [9] its levels (kernel launches after the
    diagonal-tile inverses). */

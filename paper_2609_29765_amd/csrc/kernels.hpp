@@ -56,6 +56,43 @@ __global__ void k_value_load(const double* __restrict__ vals, const int64_t* __r
   for (; i < qnz; i += step) S[vmap[i]] = V[i];
 }
 
+// One pass over the tile store per value set: block b of LBLK store doubles
+// is assembled in LDS -- zeros, the identity on padded diagonal rows, the
+// caller's values of the entries that land in it (a list per block, built
+// once per pattern: input index, offset in the block; index -1 means 1.0) --
+// and written out with coalesced 16-byte stores.  The values of one block
+// come from short runs of consecutive input entries (rows ascend within a
+// column), so both sides of the copy stay near sequential.  Block 0 of each
+// value set also resets its failure flag to the sentinel `big` (no pivot
+// has failed yet).
+constexpr int LBLK = 4096;
+
+__global__ __launch_bounds__(256) void k_value_gather(const double* __restrict__ vals, int64_t qnz,
+                                                      const int32_t* __restrict__ bptr,
+                                                      const int2* __restrict__ ent, int64_t total,
+                                                      double* __restrict__ store, int64_t mstride,
+                                                      int32_t* __restrict__ info, int32_t big) {
+  __shared__ __align__(16) double buf[LBLK];
+  const int32_t member = blockIdx.y;
+  const double* V = vals + (int64_t)member * qnz;
+  double* S = store + (int64_t)member * mstride;
+  const int64_t b0 = (int64_t)blockIdx.x * LBLK;
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && tid == 0) info[member] = big;
+#pragma unroll
+  for (int x = 2 * tid; x < LBLK; x += 512) *reinterpret_cast<double2*>(buf + x) = make_double2(0.0, 0.0);
+  __syncthreads();
+  const int32_t e0 = bptr[blockIdx.x], e1 = bptr[blockIdx.x + 1];
+  for (int32_t e = e0 + tid; e < e1; e += 256) {
+    const int2 q = ent[e];
+    buf[q.y] = q.x >= 0 ? V[q.x] : 1.0;
+  }
+  __syncthreads();
+  const int64_t n = min<int64_t>(LBLK, total - b0);  // a multiple of 2: the store size is even
+  for (int x = 2 * tid; x < n; x += 512)
+    *reinterpret_cast<double2*>(S + b0 + x) = *reinterpret_cast<const double2*>(buf + x);
+}
+
 // ---------------------------------------------------------------------------
 // operand staging shared by the update kernels: K chunks of 16 doubles per
 // row go from global memory straight into LDS, 16 bytes per lane (the lane's

@@ -84,6 +84,33 @@ struct LevelOffsets {
   int32_t u_off, u_cnt, g_off, g_cnt, p_off, p_cnt, t_off, t_cnt, u_last, g_last;
 };
 
+// arguments of k_value_gather, kept with the graph whose root node it is so
+// that a new values pointer can be written into the instantiated graph
+struct LoadArgs {
+  const double* vals;
+  int64_t qnz;
+  const int32_t* bptr;
+  const int2* ent;
+  int64_t total;
+  double* store;
+  int64_t mstride;
+  int32_t* info;
+  int32_t big;
+  void* ptrs[9];
+  void point() {
+    void* p[9] = {&vals, &qnz, &bptr, &ent, &total, &store, &mstride, &info, &big};
+    for (int i = 0; i < 9; ++i) ptrs[i] = p[i];
+  }
+};
+
+struct GraphRec {
+  hipGraph_t graph = nullptr;  // kept: the root node's handle must stay valid for updates
+  hipGraphExec_t ex = nullptr;
+  hipGraphNode_t load = nullptr;  // root: the value load
+  LoadArgs la;
+  dim3 grid;
+};
+
 }  // namespace
 
 struct stc_handle {
@@ -131,7 +158,13 @@ struct stc_handle {
   double* d_dinv = nullptr;   // inverses of the 32 x 32 diagonal blocks, per member
   int32_t* d_info = nullptr;  // batch
   double* d_ld = nullptr;     // batch
-  std::map<int32_t, hipGraphExec_t> graphs;  // by member count
+  std::map<int32_t, GraphRec> graphs;  // by member count
+  // value load: per block of LBLK store doubles, its entries (input index or
+  // -1 for a padded diagonal one, offset in the block)
+  std::vector<int32_t> ld_ptr;
+  std::vector<int2> ld_ent;
+  int32_t* d_ldptr = nullptr;
+  int2* d_ldent = nullptr;
   // reverse mode of log det
   BackPlan back;
   std::vector<int32_t> back_items;       // flattened per level
@@ -145,7 +178,10 @@ struct stc_handle {
   double* d_ms = nullptr;  // G_k (diagonal slots) and L_mk G_k (off-diagonal slots)
   hipGraphExec_t back_graph = nullptr;
   ~stc_handle() {
-    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto& g : graphs) {
+      (void)hipGraphExecDestroy(g.second.ex);
+      (void)hipGraphDestroy(g.second.graph);
+    }
     for (auto& g : solve_graphs) (void)hipGraphExecDestroy(g.second);
     if (back_graph) (void)hipGraphExecDestroy(back_graph);
   }
@@ -169,6 +205,8 @@ size_t layout(const stc_handle* hc, int32_t batch, char* base) {
     off = align256(off + std::max<size_t>(bytes, 8));
   };
   take(&h->d_vmap, sizeof(int64_t) * p.vmap.size());
+  take(&h->d_ldptr, sizeof(int32_t) * h->ld_ptr.size());
+  take(&h->d_ldent, sizeof(int2) * h->ld_ent.size());
   take(&h->d_maps, sizeof(int32_t) * p.maps.size());
   take(&h->d_upd, sizeof(UpdTaskD) * p.upd.size());
   take(&h->d_contrib, sizeof(ContribD) * p.contribs.size());
@@ -334,12 +372,38 @@ int launch_levels_nb(stc_handle* h, int32_t members, hipStream_t st, Prof* prof)
   return 0;
 }
 
-// the schedule as a HIP graph of its kernel dependency graph: every
-// non-empty kernel of a level is a node that waits only for the kernels whose
-// data it uses (kernel_dag), so the kernels of consecutive levels overlap
-// wherever the data allows
+// the value load's kernel arguments for `members` value sets starting at vals
+void load_args(stc_handle* h, const double* vals, int32_t members, LoadArgs* la, dim3* grid) {
+  la->vals = vals;
+  la->qnz = h->sym.qnz;
+  la->bptr = h->d_ldptr;
+  la->ent = h->d_ldent;
+  la->total = h->plan.store;
+  la->store = h->d_store;
+  la->mstride = h->plan.store;
+  la->info = h->d_info;
+  la->big = kInfoNone;
+  la->point();
+  *grid = dim3((unsigned)(h->ld_ptr.size() - 1), members);
+}
+
+hipKernelNodeParams load_node_params(GraphRec* g) {
+  hipKernelNodeParams kp{};
+  kp.blockDim = dim3(256);
+  kp.gridDim = g->grid;
+  kp.func = reinterpret_cast<void*>(&k_value_gather);
+  kp.kernelParams = g->la.ptrs;
+  kp.extra = nullptr;
+  kp.sharedMemBytes = 0;
+  return kp;
+}
+
+// the factorization as one HIP graph: the value load (root), every non-empty
+// kernel of a level as a node that waits only for the kernels whose data it
+// uses (kernel_dag), so the kernels of consecutive levels overlap wherever
+// the data allows, and the failure-flag finish after the last kernels
 template <int NB>
-int build_graph_nb(stc_handle* h, int32_t members, hipGraphExec_t* ex) {
+int build_graph_nb(stc_handle* h, int32_t members, GraphRec* out) {
   std::vector<KernelNode> dag;
   kernel_dag(h->plan, &dag);
   // the argument blocks stay alive until the graph is instantiated
@@ -347,8 +411,17 @@ int build_graph_nb(stc_handle* h, int32_t members, hipGraphExec_t* ex) {
   std::vector<void*> kargs(dag.size());
   std::vector<hipGraphNode_t> nodes(dag.size());
   std::vector<hipGraphNode_t> deps;
+  std::vector<char> has_dependent(dag.size(), 0);
   hipGraph_t g;
   HIPCHK(hipGraphCreate(&g, 0));
+  auto bail = [&](const char* what, hipError_t e) {
+    (void)hipGraphDestroy(g);
+    return fail(STC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  };
+  load_args(h, nullptr, members, &out->la, &out->grid);
+  hipKernelNodeParams lp = load_node_params(out);
+  hipError_t e = hipGraphAddKernelNode(&out->load, g, nullptr, 0, &lp);
+  if (e != hipSuccess) return bail("hipGraphAddKernelNode", e);
   for (size_t x = 0; x < dag.size(); ++x) {
     args[x] = level_args(h, (size_t)dag[x].level, dag[x].kind);
     const void* fn;
@@ -364,16 +437,38 @@ int build_graph_nb(stc_handle* h, int32_t members, hipGraphExec_t* ex) {
     kp.extra = nullptr;
     kp.sharedMemBytes = (unsigned)lds;
     deps.clear();
-    for (int32_t d : dag[x].deps) deps.push_back(nodes[(size_t)d]);
-    const hipError_t e = hipGraphAddKernelNode(&nodes[x], g, deps.data(), deps.size(), &kp);
-    if (e != hipSuccess) {
-      (void)hipGraphDestroy(g);
-      return fail(STC_ERR_HIP, std::string("hipGraphAddKernelNode: ") + hipGetErrorString(e));
+    for (int32_t d : dag[x].deps) {
+      deps.push_back(nodes[(size_t)d]);
+      has_dependent[(size_t)d] = 1;
     }
+    if (deps.empty()) deps.push_back(out->load);
+    e = hipGraphAddKernelNode(&nodes[x], g, deps.data(), deps.size(), &kp);
+    if (e != hipSuccess) return bail("hipGraphAddKernelNode", e);
   }
-  const hipError_t e = hipGraphInstantiate(ex, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  if (e != hipSuccess) return fail(STC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  deps.clear();
+  for (size_t x = 0; x < dag.size(); ++x)
+    if (!has_dependent[x]) deps.push_back(nodes[x]);
+  if (deps.empty()) deps.push_back(out->load);
+  int32_t* info = h->d_info;
+  int32_t count = members, big = kInfoNone;
+  int32_t* none = nullptr;
+  void* fargs[] = {&info, &count, &big, &none};
+  hipKernelNodeParams fp{};
+  fp.blockDim = dim3(256);
+  fp.gridDim = dim3((unsigned)((members + 255) / 256));
+  fp.func = reinterpret_cast<void*>(&k_info_finish);
+  fp.kernelParams = fargs;
+  fp.extra = nullptr;
+  fp.sharedMemBytes = 0;
+  hipGraphNode_t fin;
+  e = hipGraphAddKernelNode(&fin, g, deps.data(), deps.size(), &fp);
+  if (e != hipSuccess) return bail("hipGraphAddKernelNode", e);
+  e = hipGraphInstantiate(&out->ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(STC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  out->graph = g;
   return 0;
 }
 
@@ -387,7 +482,7 @@ int launch_levels(stc_handle* h, int32_t members, hipStream_t st, Prof* prof) {
   return fail(STC_ERR_ARG, "unsupported tile size");
 }
 
-int build_graph(stc_handle* h, int32_t members, hipGraphExec_t* ex) {
+int build_graph(stc_handle* h, int32_t members, GraphRec* ex) {
   switch (h->plan.nb) {
     case 32: return build_graph_nb<32>(h, members, ex);
     case 64: return build_graph_nb<64>(h, members, ex);
@@ -464,51 +559,45 @@ int get_solve_graph(stc_handle* h, int32_t nr, int32_t g0, hipGraphExec_t* out, 
   return 0;
 }
 
-int get_graph(stc_handle* h, int32_t members, hipGraphExec_t* out) {
+int get_graph(stc_handle* h, int32_t members, GraphRec** out) {
   auto it = h->graphs.find(members);
-  if (it != h->graphs.end()) {
-    *out = it->second;
-    return 0;
+  if (it == h->graphs.end()) {
+    GraphRec rec;
+    const int rc = build_graph(h, members, &rec);
+    if (rc) return rc;
+    it = h->graphs.emplace(members, rec).first;
+    it->second.la.point();  // the record moved: its argument pointers follow it
   }
-  hipGraphExec_t ex;
-  const int rc = build_graph(h, members, &ex);
-  if (rc) return rc;
-  h->graphs[members] = ex;
-  *out = ex;
+  *out = &it->second;
   return 0;
 }
 
-// value load + schedule for `members` value sets starting at vals; with prof,
-// the schedule is launched kernel by kernel with events instead of the graph
+// value load + schedule for `members` value sets starting at vals: one graph
+// launch (the values pointer written into its root node when it changes);
+// with prof, the same kernels launched one by one, each timed
 int run_factor(stc_handle* h, const double* vals, int32_t members, hipStream_t st,
                Prof* prof = nullptr) {
-  const Plan& p = h->plan;
-  const int64_t ms = p.store;
-  hipGraphExec_t ex = nullptr;
-  int rc = prof ? 0 : get_graph(h, members, &ex);
-  if (rc) return rc;
-  hipEvent_t ev = nullptr;
-  hipLaunchKernelGGL(k_info_reset, dim3((members + 255) / 256), dim3(256), 0, st, h->d_info, members,
-                     kInfoNone);
-  const int64_t zgrid = std::min<int64_t>(4096, (ms / 2 + 255) / 256 + 1);
-  if (prof && prof->begin(st, &ev)) return STC_ERR_HIP;
-  hipLaunchKernelGGL(k_zero, dim3((unsigned)zgrid, members), dim3(256), 0, st, h->d_store, ms, ms);
-  const int32_t hlast = p.diag_h[p.NT - 1];
-  if (hlast < p.nb)
-    hipLaunchKernelGGL(k_pad, dim3(1, members), dim3(256), 0, st, h->d_store,
-                       (int64_t)(p.NT - 1) * p.nb * p.nb, p.nb, hlast, ms);
-  const int64_t qnz = h->sym.qnz;
-  const int64_t vgrid = std::min<int64_t>(4096, (qnz + 255) / 256);
-  hipLaunchKernelGGL(k_value_load, dim3((unsigned)vgrid, members), dim3(256), 0, st, vals, h->d_vmap,
-                     qnz, h->d_store, ms);
-  if (prof && prof->end(kKindLoad, 0.0, st, ev)) return STC_ERR_HIP;
-  HIPCHK(hipGetLastError());
-  if (prof) {
-    rc = launch_levels(h, members, st, prof);
+  if (!prof) {
+    GraphRec* g;
+    int rc = get_graph(h, members, &g);
     if (rc) return rc;
-  } else {
-    HIPCHK(hipGraphLaunch(ex, st));
+    if (g->la.vals != vals) {
+      g->la.vals = vals;
+      hipKernelNodeParams kp = load_node_params(g);
+      HIPCHK(hipGraphExecKernelNodeSetParams(g->ex, g->load, &kp));
+    }
+    HIPCHK(hipGraphLaunch(g->ex, st));
+    return 0;
   }
+  LoadArgs la;
+  dim3 grid;
+  load_args(h, vals, members, &la, &grid);
+  hipEvent_t ev = nullptr;
+  if (prof->begin(st, &ev)) return STC_ERR_HIP;
+  HIPCHK(hipLaunchKernel(reinterpret_cast<const void*>(&k_value_gather), grid, dim3(256), la.ptrs, 0, st));
+  if (prof->end(kKindLoad, 0.0, st, ev)) return STC_ERR_HIP;
+  int rc = launch_levels(h, members, st, prof);
+  if (rc) return rc;
   hipLaunchKernelGGL(k_info_finish, dim3((members + 255) / 256), dim3(256), 0, st, h->d_info, members,
                      kInfoNone, (int32_t*)nullptr);
   HIPCHK(hipGetLastError());
@@ -649,6 +738,26 @@ static int check_sweep(const stc_handle* h, bool fwd, const std::vector<int32_t>
 // the host-side lists derived from the symbolic analysis and the plans:
 // flattened level work lists and the solve sweeps' work items
 static void finish_handle(stc_handle* h) {
+  // the value load's per-block entry lists: input entries by store block
+  // (ascending input index within a block), then the padded diagonal ones
+  {
+    const Plan& p = h->plan;
+    const int64_t nblk = (p.store + LBLK - 1) / LBLK;
+    std::vector<int64_t> pad;
+    const int32_t hl = p.diag_h[(size_t)p.NT - 1];
+    for (int32_t r = hl; r < p.nb; ++r) pad.push_back((int64_t)(p.NT - 1) * p.nb * p.nb + (int64_t)r * p.nb + r);
+    h->ld_ptr.assign((size_t)nblk + 1, 0);
+    for (int64_t v : p.vmap) h->ld_ptr[(size_t)(v / LBLK) + 1]++;
+    for (int64_t v : pad) h->ld_ptr[(size_t)(v / LBLK) + 1]++;
+    for (int64_t b = 0; b < nblk; ++b) h->ld_ptr[(size_t)b + 1] += h->ld_ptr[(size_t)b];
+    h->ld_ent.resize((size_t)h->ld_ptr.back());
+    std::vector<int32_t> fill(h->ld_ptr.begin(), h->ld_ptr.end() - 1);
+    for (size_t q = 0; q < p.vmap.size(); ++q) {
+      const int64_t v = p.vmap[q];
+      h->ld_ent[(size_t)fill[(size_t)(v / LBLK)]++] = make_int2((int32_t)q, (int32_t)(v % LBLK));
+    }
+    for (int64_t v : pad) h->ld_ent[(size_t)fill[(size_t)(v / LBLK)]++] = make_int2(-1, (int32_t)(v % LBLK));
+  }
   h->back_level_ptr.push_back(0);
   for (const auto& li : h->back.level_items) {
     h->back_items.insert(h->back_items.end(), li.begin(), li.end());
@@ -771,6 +880,10 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
       delete h;
       return fail(rc, why);
     }
+    if (h->sym.qnz + o.nb >= INT32_MAX) {
+      delete h;
+      return fail(STC_ERR_ARG, "more than 2^31 - 1 input entries");
+    }
     rc = build_plan(h->sym, UB, TR, o.wg_slots, &h->plan, &why);
     if (rc == 0) rc = build_backward(h->sym, &h->plan, &h->back, &why);
     if (rc) {
@@ -801,7 +914,10 @@ int stc_bind(stc_handle* h, void* d_ws, size_t bytes, int32_t batch, void* strea
   stc_workspace_bytes(h, batch, &need);
   if (bytes < need)
     return fail(STC_ERR_ALLOC, "workspace too small: need " + std::to_string(need) + " bytes");
-  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.second);
+  for (auto& g : h->graphs) {
+    (void)hipGraphExecDestroy(g.second.ex);
+    (void)hipGraphDestroy(g.second.graph);
+  }
   h->graphs.clear();
   for (auto& g : h->solve_graphs) (void)hipGraphExecDestroy(g.second);
   h->solve_graphs.clear();
@@ -839,7 +955,8 @@ int stc_bind(stc_handle* h, void* d_ws, size_t bytes, int32_t batch, void* strea
   for (size_t i = 0; i < ftl.size(); ++i) ftl[i] = tl[(size_t)h->sfwd_tl[i]];
   for (size_t i = 0; i < btl.size(); ++i) btl[i] = tl[(size_t)h->sbwd_tl[i]];
   int rc = 0;
-  if ((rc = upload(h->d_vmap, p.vmap)) || (rc = upload(h->d_maps, p.maps)) ||
+  if ((rc = upload(h->d_vmap, p.vmap)) || (rc = upload(h->d_ldptr, h->ld_ptr)) ||
+      (rc = upload(h->d_ldent, h->ld_ent)) || (rc = upload(h->d_maps, p.maps)) ||
       (rc = upload(h->d_upd, upd)) || (rc = upload(h->d_contrib, con)) ||
       (rc = upload(h->d_trsm, tr)) || (rc = upload(h->d_upd_items, h->upd_items)) ||
       (rc = upload(h->d_big_items, h->big_items)) ||
@@ -865,8 +982,8 @@ int stc_bind(stc_handle* h, void* d_ws, size_t bytes, int32_t batch, void* strea
       (rc = upload(h->d_bitems, h->back_items)) || (rc = upload(h->d_trtri, bp.trtri_items)) ||
       (rc = upload(h->d_bdiag, bp.diagflag)))
     return rc;
-  hipGraphExec_t ex;
-  return get_graph(h, 1, &ex);
+  GraphRec* gr;
+  return get_graph(h, 1, &gr);
 }
 
 int stc_factorize(stc_handle* h, const double* d_values, void* stream) {
@@ -1272,7 +1389,7 @@ int stc_get_work(const stc_handle* h, double* w) {
   w[3] = p.flops_tile;
   w[4] = p.flops_exact;
   w[5] = p.bytes_update;
-  w[6] = 20.0 * q + 8.0 * (double)p.store;  // values + map read, value write, store fill
+  w[6] = 16.0 * q + 8.0 * (double)p.store;  // values and their block entries read, the store written once
   w[7] = (double)h->lv.size();
   w[8] = h->back.flops;
   w[9] = (double)(h->back_level_ptr.size() - 1);
