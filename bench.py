@@ -752,7 +752,7 @@ def main():
                     help="with --counters: factorizations each counter run covers per traced one")
     ap.add_argument("--segment", type=int, default=None,
                     help="with --summarize-trace: only the i-th run of dispatches between two marker kernels")
-    ap.add_argument("--segment-marker", default="k_info_reset")
+    ap.add_argument("--segment-marker", default="k_value_gather")
     ap.add_argument("--kernel-filter", default=None, help="comma-separated kernel name prefixes to keep")
     ap.add_argument("--chain", default=None, help="kernel name prefix whose successive launches form a chain")
     args = ap.parse_args()
