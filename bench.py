@@ -702,7 +702,7 @@ def summarize_trace(args):
             by = 0.0
             for c in extra:
                 by += sum(v for kk, _, v in cnt[c] if kk == k) * 1024.0 * scale[c] / args.counter_runs
-            row += [f"{by / 1e6:.1f}", f"{by / (tot * 1e-3) / 1e9:.0f}" if tot > 0 else "-"]
+            row += [f"{by / 1e6:.1f}", f"{by / (tot * 1e-6) / 1e9:.0f}" if tot > 0 else "-"]  # tot: us
         if "SQ_INSTS_VALU_MFMA_MOPS_F64" in cnt:
             mops = sum(v for kk, _, v in cnt["SQ_INSTS_VALU_MFMA_MOPS_F64"] if kk == k) / args.counter_runs
             row += [f"{mops * 512 / 1e9:.2f}"]
@@ -710,6 +710,18 @@ def summarize_trace(args):
     if scale:
         print("\nCounter scale from the plain 1 GiB copy: " +
               ", ".join(f"{c} x {v:.3f}" for c, v in scale.items()))
+    if args.traffic_json and extra:
+        # HBM bytes per launch of each kernel in the selected dispatches, for
+        # the bench's roofline entry (read only while the sources match)
+        out = {"source_hash": kernel_source_hash(), "segment": args.segment,
+               "scale": {c: round(v, 6) for c, v in scale.items()}, "kernels": {}}
+        for k, ts in per.items():
+            by = {c: sum(v for kk, _, v in cnt[c] if kk == k) * 1024.0 * scale[c] / args.counter_runs for c in extra}
+            out["kernels"][k] = {"launches": len(ts), "fetch_bytes": by.get("FETCH_SIZE", 0.0),
+                                 "write_bytes": by.get("WRITE_SIZE", 0.0),
+                                 "bytes_per_launch": sum(by.values()) / len(ts)}
+        with open(args.traffic_json, "w") as fh:
+            json.dump(out, fh, indent=1)
     if args.chain:
         ch = [d for d in disp if d["kernel"].startswith(args.chain)]
         gaps = [(b["start"] - a["end"]) / 1e3 for a, b in zip(ch[:-1], ch[1:])]
@@ -755,6 +767,8 @@ def main():
     ap.add_argument("--segment-marker", default="k_value_gather")
     ap.add_argument("--kernel-filter", default=None, help="comma-separated kernel name prefixes to keep")
     ap.add_argument("--chain", default=None, help="kernel name prefix whose successive launches form a chain")
+    ap.add_argument("--traffic-json", default=None, metavar="FILE",
+                    help="with --counters: write the calibrated HBM bytes per launch of each kernel to FILE")
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(args)
