@@ -273,6 +273,7 @@ class Analysis:
 
     def solve(self, b):
         """Solve A x = b; b device float64 [n] or [n, nrhs] (column-major copy made)."""
+        import torch
         _need_cuda(b)
         self._ws_device()
         one = b.dim() == 1
@@ -280,7 +281,7 @@ class Analysis:
             raise ValueError(f"b must have shape [{self.n}] or [{self.n}, nrhs], got {tuple(b.shape)}")
         B = b.reshape(self.n, 1) if one else b
         nrhs = B.shape[1]
-        X = B.t().contiguous()  # column-major n x nrhs
+        X = B.t().clone(memory_format=torch.contiguous_format)  # column-major n x nrhs, never b itself
         _check(lib().stc_solve(self._h, _dptr(X), int(nrhs), _stream_ptr()))
         X = X.t()
         return X.reshape(-1) if one else X.contiguous()
@@ -288,13 +289,14 @@ class Analysis:
     def solve_batched(self, b):
         """Solve A_b x_b = b_b for every value set b of the last batched
         factorization: b device float64 [B, n] or [B, n, nrhs] (nrhs <= 8)."""
+        import torch
         _need_cuda(b)
         self._ws_device()
         one = b.dim() == 2
         if not (b.dim() in (2, 3) and b.shape[1] == self.n):
             raise ValueError(f"b must have shape [B, {self.n}] or [B, {self.n}, nrhs], got {tuple(b.shape)}")
         Bv = b.reshape(b.shape[0], self.n, 1) if one else b
-        X = Bv.transpose(1, 2).contiguous()  # per value set column-major n x nrhs
+        X = Bv.transpose(1, 2).clone(memory_format=torch.contiguous_format)  # per value set column-major
         _check(lib().stc_solve_batched(self._h, _dptr(X), int(Bv.shape[0]), int(Bv.shape[2]), _stream_ptr()))
         X = X.transpose(1, 2)
         return X.reshape(b.shape[0], self.n) if one else X.contiguous()

@@ -265,3 +265,23 @@ def test_random_large_tiles_semisparse(seed):
     w = W.random_spd(n, float(rng.choice([0.005, 0.02, 0.06])), 40 + seed, dense_rows=int(rng.integers(0, 5)))
     nb = [128, 256][seed % 2]
     run_case(w, ["nd", "rcm"][seed // 2 % 2], nb, "semisparse")
+
+
+def test_solve_leaves_its_input_alone():
+    """The binding solves a column-major copy: b keeps its values for 1-D b,
+    one-column and many-column b, and for batched right-hand sides."""
+    w = W.gmrf_grid2d(16, 16, 0.1, 0)
+    a = S.Analysis(w.n, w.colptr, w.rowind, nb=64, ordering="nd").bind()
+    a.factorize(dev(w.values))
+    for shape in ((w.n,), (w.n, 1), (w.n, 3)):
+        b = torch.randn(*shape, dtype=torch.float64, device="cuda")
+        keep = b.clone()
+        x = a.solve(b)
+        assert torch.equal(b, keep) and not torch.equal(x, b)
+    ab = S.Analysis(w.n, w.colptr, w.rowind, nb=64, ordering="nd").bind(batch=2)
+    ab.factorize_batched(dev(np.stack([w.values, 2 * w.values])))
+    for shape in ((2, w.n), (2, w.n, 1)):
+        b = torch.randn(*shape, dtype=torch.float64, device="cuda")
+        keep = b.clone()
+        ab.solve_batched(b)
+        assert torch.equal(b, keep)
