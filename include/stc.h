@@ -88,6 +88,17 @@ typedef struct {
                             work above which a level's last groups get a
                             launch of their own; 0 = 448 (the best of a sweep
                             on MI355X).  Changes timing only.                  */
+  int32_t align;         /* tile grid: 0 = the uniform n_b grid of Sec. 4.1;
+                            > 0 = a grid aligned to the elimination tree of
+                            P A P^T: every subtree of at least `align` columns
+                            whose columns are consecutive starts on a tile
+                            boundary, the tile before it padded with identity
+                            rows (tiles then follow the tree, as the supernodal
+                            tiles of Sec. 5.4 follow the supernodes, and
+                            independent subtrees no longer share a tile).  The
+                            features, the route and the factor's values are
+                            those of the uniform grid; tiles, tasks and the
+                            schedule follow the aligned grid.                  */
 } stc_opts;
 
 /* Analyse a sparsity pattern once (Sec. 3, Sec. 5.1-5.2).
@@ -226,6 +237,10 @@ int stc_get_L_pattern(const stc_handle* h, int64_t* colptr, int32_t* rowind); /*
 int stc_get_tiles(const stc_handle* h, int32_t* m, int32_t* k, int32_t* cnt, int32_t* true_cnt,
                   int8_t* contig, int64_t* roff, int32_t* rows, int32_t* kd);
 int stc_get_tasks(const stc_handle* h, int32_t* tasks); /* int32[ntasks][4]: op, m, k, n */
+/* grid position of every column of P A P^T (int64[n], ascending); tile t
+   covers positions [t n_b, (t+1) n_b), positions no column takes are padding.
+   The identity on the uniform grid. */
+int stc_get_grid_positions(const stc_handle* h, int64_t* pos);
 
 /* Copy the last single factor to the host, in stc_get_L_pattern order
    (h_Lx double[nnz(L)]); synchronizes the stream. */

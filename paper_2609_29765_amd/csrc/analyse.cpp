@@ -312,20 +312,31 @@ int route_of(double phi, double rho, double sigma) {
   return kRouteSupernodal;
 }
 
-void tiles_and_tasks(Symbolic* s, int nb, int mode) {
+// The tile grid of the analysed pattern: active rows of every off-diagonal
+// tile, kd, and Algorithm 1's task list.  Column j sits at grid position
+// grid_pos(j) (the identity on the uniform grid).  With features set, the
+// features and the route are read off this grid and fix the storage mode;
+// otherwise the ones already in s are kept.
+void build_grid(Symbolic* s, int nb, int mode, bool features) {
   const int64_t n = s->n;
-  const int32_t NT = (int32_t)((n + nb - 1) / nb);
+  const int64_t npad = s->pos.empty() ? n : s->pos[(size_t)n - 1] + 1;
+  const int32_t NT = (int32_t)((npad + nb - 1) / nb);
   s->nb = nb;
   s->NT = NT;
+  s->npad = npad;
   s->kd.assign((size_t)NT, 0);
-  // per block column: the distinct rows (global) below the diagonal block
+  auto P = [&](int64_t j) { return grid_pos(*s, j); };
+  // real columns per block (the rest of a block is padding)
+  std::vector<int32_t> hreal((size_t)NT, 0);
+  for (int64_t j = 0; j < n; ++j) hreal[(size_t)(P(j) / nb)]++;
+  // per block column: the distinct rows below the diagonal block
   std::vector<int32_t> seen((size_t)n, -1);
   std::vector<std::vector<int32_t>> colrows((size_t)NT);
   for (int64_t j = 0; j < n; ++j) {
-    int32_t k = (int32_t)(j / nb);
+    int32_t k = (int32_t)(P(j) / nb);
     for (int64_t p = s->lp[j]; p < s->lp[j + 1]; ++p) {
       int32_t i = s->li[p];
-      if (i / nb == k) {
+      if (P(i) / nb == k) {
         s->kd[k] = std::max<int32_t>(s->kd[k], (int32_t)(i - j));
       } else if (seen[i] != k) {
         seen[i] = k;
@@ -339,14 +350,16 @@ void tiles_and_tasks(Symbolic* s, int nb, int mode) {
   int64_t sum_true = 0;
   for (int32_t k = 0; k < NT; ++k) {
     auto& v = colrows[k];
-    std::sort(v.begin(), v.end());
+    std::sort(v.begin(), v.end());  // ascending columns are ascending positions
     size_t a = 0;
     while (a < v.size()) {
-      int32_t m = v[a] / nb;
+      int32_t m = (int32_t)(P(v[a]) / nb);
       size_t b = a;
-      while (b < v.size() && v[b] / nb == m) ++b;
-      Raw r{m, k, v[a] - m * nb, v[b - 1] - m * nb, (int32_t)(b - a), (int64_t)allrows.size()};
-      for (size_t x = a; x < b; ++x) allrows.push_back(v[x] - m * nb);
+      while (b < v.size() && P(v[b]) / nb == m) ++b;
+      const int64_t base = (int64_t)m * nb;
+      Raw r{m, k, (int32_t)(P(v[a]) - base), (int32_t)(P(v[b - 1]) - base), (int32_t)(b - a),
+            (int64_t)allrows.size()};
+      for (size_t x = a; x < b; ++x) allrows.push_back((int32_t)(P(v[x]) - base));
       raw.push_back(r);
       sum_true += r.cnt;
       a = b;
@@ -354,18 +367,20 @@ void tiles_and_tasks(Symbolic* s, int nb, int mode) {
     std::vector<int32_t>().swap(v);
   }
   const int64_t ntiles = (int64_t)raw.size();
-  // features and route (Sec. 5.1)
-  std::vector<int32_t> rowcount((size_t)n, 0);
-  for (int32_t i : s->li) rowcount[i]++;
-  int64_t maxrc = *std::max_element(rowcount.begin(), rowcount.end());
-  s->phi = (double)s->lnz / (double)s->qnz;
-  s->rho = ntiles ? (double)sum_true / ((double)nb * (double)ntiles) : 1.0;
-  s->sigma = ((double)maxrc * (double)n) / (double)s->lnz;
-  s->tact = ntiles + NT;
-  s->route = route_of(s->phi, s->rho, s->sigma);
-  if (mode == kModeAuto) mode = s->route == kRouteDense ? kModeDense : kModeSemisparse;
-  s->mode = mode;
-  // stored rows: full height on the dense route
+  if (features) {
+    // features and route (Sec. 5.1)
+    std::vector<int32_t> rowcount((size_t)n, 0);
+    for (int32_t i : s->li) rowcount[i]++;
+    int64_t maxrc = *std::max_element(rowcount.begin(), rowcount.end());
+    s->phi = (double)s->lnz / (double)s->qnz;
+    s->rho = ntiles ? (double)sum_true / ((double)nb * (double)ntiles) : 1.0;
+    s->sigma = ((double)maxrc * (double)n) / (double)s->lnz;
+    s->tact = ntiles + NT;
+    s->route = route_of(s->phi, s->rho, s->sigma);
+    if (mode == kModeAuto) mode = s->route == kRouteDense ? kModeDense : kModeSemisparse;
+    s->mode = mode;
+  }
+  // stored rows: full height (the block's real rows) on the dense route
   s->tiles.clear();
   s->rows.clear();
   for (const Raw& r : raw) {
@@ -374,8 +389,8 @@ void tiles_and_tasks(Symbolic* s, int nb, int mode) {
     t.k = r.k;
     t.true_cnt = r.cnt;
     t.roff = (int64_t)s->rows.size();
-    const int32_t hm = (r.m == NT - 1) ? (int32_t)(n - (int64_t)r.m * nb) : nb;
-    if (mode == kModeDense) {
+    const int32_t hm = hreal[(size_t)r.m];
+    if (s->mode == kModeDense) {
       t.cnt = hm;
       t.contig = 1;
       for (int32_t x = 0; x < hm; ++x) s->rows.push_back(x);
@@ -420,7 +435,9 @@ int analyse_perm(Symbolic* s, int nb, int mode) {
   s->iperm.assign((size_t)n, -1);
   for (int64_t a = 0; a < n; ++a) s->iperm[s->perm[a]] = (int32_t)a;
   symbolic(s);
-  tiles_and_tasks(s, nb, mode);
+  s->pos.clear();
+  s->align = 0;
+  build_grid(s, nb, mode, true);
   return 0;
 }
 
@@ -469,16 +486,18 @@ void build_lmap(const Symbolic& s, Plan* p) {
   }
   p->lmap.resize((size_t)s.lnz);
   for (int64_t j = 0; j < s.n; ++j) {
-    const int32_t bj = (int32_t)(j / nb);
+    const int64_t pj = grid_pos(s, j);
+    const int32_t bj = (int32_t)(pj / nb);
     int64_t t = col_first[bj];  // rows ascend, so the tiles of column j are met in order
     for (int64_t q = s.lp[j]; q < s.lp[j + 1]; ++q) {
-      const int32_t i = s.li[q], bi = i / nb;
+      const int64_t pi = grid_pos(s, s.li[q]);
+      const int32_t bi = (int32_t)(pi / nb);
       if (bi == bj) {
-        p->lmap[q] = (int64_t)bj * nb * nb + (int64_t)(i % nb) * nb + (j % nb);
+        p->lmap[q] = (int64_t)bj * nb * nb + (pi % nb) * nb + (pj % nb);
         continue;
       }
       while (s.tiles[t].m < bi) ++t;
-      p->lmap[q] = p->tile_off[t] + (int64_t)inv[(size_t)t * nb + (i % nb)] * nb + (j % nb);
+      p->lmap[q] = p->tile_off[t] + (int64_t)inv[(size_t)t * nb + (pi % nb)] * nb + (pj % nb);
     }
   }
 }
@@ -571,6 +590,36 @@ int analyse(int64_t n, const int64_t* cp, const int32_t* ri, int method, int nb,
   return 0;
 }
 
+void align_tiles(Symbolic* s, int64_t min_subtree) {
+  const int64_t n = s->n;
+  const int32_t nb = s->nb;
+  s->pos.clear();
+  s->align = 0;
+  if (min_subtree > 0) {
+    // subtree sizes and first columns (a child precedes its parent)
+    std::vector<int64_t> size((size_t)n, 1), first((size_t)n);
+    for (int64_t j = 0; j < n; ++j) first[(size_t)j] = j;
+    for (int64_t j = 0; j < n; ++j) {
+      const int32_t q = s->parent[(size_t)j];
+      if (q < 0) continue;
+      size[(size_t)q] += size[(size_t)j];
+      first[(size_t)q] = std::min(first[(size_t)q], first[(size_t)j]);
+    }
+    // a large subtree whose columns are consecutive starts a tile
+    std::vector<char> start((size_t)n, 0);
+    for (int64_t r = 0; r < n; ++r)
+      if (size[(size_t)r] >= min_subtree && first[(size_t)r] == r - size[(size_t)r] + 1) start[(size_t)first[(size_t)r]] = 1;
+    s->pos.resize((size_t)n);
+    int64_t cur = 0;
+    for (int64_t j = 0; j < n; ++j) {
+      if (start[(size_t)j] && cur % nb) cur += nb - cur % nb;
+      s->pos[(size_t)j] = cur++;
+    }
+    s->align = min_subtree;
+  }
+  build_grid(s, nb, s->mode, false);
+}
+
 // ---------------------------------------------------------------------------
 // execution plan
 // ---------------------------------------------------------------------------
@@ -595,8 +644,10 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std
     off += (int64_t)s.tiles[t].cnt * nb;
   }
   p->store = off;
-  p->diag_h.resize((size_t)NT);
-  for (int32_t k = 0; k < NT; ++k) p->diag_h[k] = (int32_t)std::min<int64_t>(nb, n - (int64_t)k * nb);
+  // real columns of each diagonal tile: a prefix of its positions, the
+  // rest padding (identity in the store)
+  p->diag_h.assign((size_t)NT, 0);
+  for (int64_t j = 0; j < n; ++j) p->diag_h[(size_t)(grid_pos(s, j) / nb)]++;
   // tile lookup per block column: (m -> tile index), and inverse row maps
   std::vector<int64_t> col_first((size_t)NT + 1, 0);
   for (const TileInfo& t : s.tiles) col_first[t.k + 1]++;
@@ -615,11 +666,12 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std
     for (int32_t r = 0; r < ti.cnt; ++r) inv[(size_t)t * nb + s.rows[ti.roff + r]] = r;
   }
   auto store_pos = [&](int32_t i, int32_t j) -> int64_t {  // permuted, i >= j
-    int32_t bi = i / nb, bj = j / nb;
-    if (bi == bj) return (int64_t)bj * nb * nb + (int64_t)(i % nb) * nb + (j % nb);
+    const int64_t pi = grid_pos(s, i), pj = grid_pos(s, j);
+    const int32_t bi = (int32_t)(pi / nb), bj = (int32_t)(pj / nb);
+    if (bi == bj) return (int64_t)bj * nb * nb + (pi % nb) * nb + (pj % nb);
     int64_t t = find_tile(bi, bj);
-    int32_t r = inv[(size_t)t * nb + (i % nb)];
-    return p->tile_off[t] + (int64_t)r * nb + (j % nb);
+    int32_t r = inv[(size_t)t * nb + (pi % nb)];
+    return p->tile_off[t] + (int64_t)r * nb + (pj % nb);
   };
   p->vmap.resize((size_t)s.qnz);
   for (int64_t c = 0; c < n; ++c)
@@ -634,7 +686,7 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std
   std::vector<int32_t> colmap_of((size_t)ntiles, -1);
   auto full = [&](int64_t t) {
     const TileInfo& ti = s.tiles[t];
-    int32_t hm = (ti.m == NT - 1) ? (int32_t)(n - (int64_t)ti.m * nb) : nb;
+    const int32_t hm = p->diag_h[(size_t)ti.m];
     return ti.cnt == hm && hm == nb;
   };
   for (int64_t t = 0; t < ntiles; ++t) {

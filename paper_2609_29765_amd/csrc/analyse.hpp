@@ -50,7 +50,16 @@ struct Symbolic {
   double phi = 0, rho = 0, sigma = 0;
   int64_t tact = 0;
   std::vector<int32_t> tasks;        // 4 ints per task: op, m, k, n (-1 unused)
+  // tile grid aligned to the elimination tree (align_tiles): column j of
+  // P A P^T sits at position pos[j] of a padded order npad, tile t covering
+  // positions [t nb, (t + 1) nb); empty pos means position = column
+  int64_t align = 0;                 // minimum subtree size of an aligned start (0: uniform grid)
+  int64_t npad = 0;
+  std::vector<int64_t> pos;
 };
+
+// position of column j in the tile grid
+inline int64_t grid_pos(const Symbolic& s, int64_t j) { return s.pos.empty() ? j : s.pos[(size_t)j]; }
 
 // Validate a lower CSC pattern; returns 0 or a negative STC_ERR_* code.
 int check_pattern(int64_t n, const int64_t* cp, const int32_t* ri, std::string* why);
@@ -58,6 +67,13 @@ int check_pattern(int64_t n, const int64_t* cp, const int32_t* ri, std::string* 
 // Full symbolic analysis. method in Ordering; mode in Mode; perm read for kGiven.
 int analyse(int64_t n, const int64_t* cp, const int32_t* ri, int method, int nb, int mode,
             const int32_t* perm, Symbolic* out, std::string* why);
+
+// Re-tile an analysed pattern on a grid aligned to its elimination tree:
+// every subtree of at least min_subtree columns whose columns are
+// consecutive starts on a tile boundary (the columns before it are padded
+// to the boundary).  Tiles and tasks are rebuilt on that grid; the
+// features, the route and the storage mode stay those of the uniform grid.
+void align_tiles(Symbolic* s, int64_t min_subtree);
 
 // ---------------------------------------------------------------------------
 // execution plan

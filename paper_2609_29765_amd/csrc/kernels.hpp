@@ -1296,14 +1296,14 @@ __global__ void k_logdet_grad(const double* __restrict__ Z, const int64_t* __res
 
 // diag(A^-1) in original numbering from the selected inverse in store
 // layout: out[perm[i]] = Z_ii, NaN when the factorization failed
-__global__ void k_selinv_diag(const double* __restrict__ Z, const int32_t* __restrict__ perm, int64_t n,
+__global__ void k_selinv_diag(const double* __restrict__ Z, const int32_t* __restrict__ perm, int64_t np,
                               int32_t nb, const int32_t* __restrict__ info, double* __restrict__ out) {
   const bool ok = info[0] == 0;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += step) {
+  for (; i < np; i += step) {
     const int64_t k = i / nb, r = i % nb;
-    out[perm[i]] = ok ? Z[k * nb * nb + r * nb + r] : __builtin_nan("");
+    if (perm[i] >= 0) out[perm[i]] = ok ? Z[k * nb * nb + r * nb + r] : __builtin_nan("");
   }
 }
 
@@ -1328,14 +1328,14 @@ __global__ __launch_bounds__(256) void k_mfma_issue(double* __restrict__ out, in
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_logdet(const double* __restrict__ store, int64_t mstride,
-                                                int32_t nb, int64_t n,
+                                                int32_t nb, int64_t np,
                                                 const int32_t* __restrict__ info,
                                                 double* __restrict__ out) {
   __shared__ double part[256];
   const double* S = store + (int64_t)blockIdx.x * mstride;
   const int tid = threadIdx.x;
   double s = 0.0;
-  for (int64_t i = tid; i < n; i += 256) {
+  for (int64_t i = tid; i < np; i += 256) {  // padding positions hold 1: log 1 = 0
     const int64_t k = i / nb, r = i % nb;
     s += log(S[k * nb * nb + r * nb + r]);
   }
@@ -1353,11 +1353,14 @@ __global__ void k_info_reset(int32_t* info, int32_t count, int32_t big) {
   if (i < count) info[i] = big;
 }
 
-// turn "no failure" (still the sentinel) into 0
-__global__ void k_info_finish(int32_t* info, int32_t count, int32_t big, int32_t* out) {
+// turn "no failure" (still the sentinel) into 0, and a failed grid position
+// q + 1 into its column of P A P^T plus one (gcol; identity when null)
+__global__ void k_info_finish(int32_t* info, int32_t count, int32_t big, int32_t* out,
+                              const int32_t* __restrict__ gcol) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) {
     int32_t v = info[i] == big ? 0 : info[i];
+    if (v > 0 && gcol) v = gcol[v - 1] + 1;
     info[i] = v;
     if (out) out[i] = v;
   }
@@ -1379,7 +1382,8 @@ __global__ void k_gather(const double* __restrict__ store, const int64_t* __rest
 // ---------------------------------------------------------------------------
 
 // y = P b for nrhs columns of value set blockIdx.y (y stride ystride per
-// value set, padded rows zero)
+// value set); perm[a] is the original index at grid position a, or -1 at a
+// padding position, which gets zero
 __global__ void k_perm_in(const double* __restrict__ b, const int32_t* __restrict__ perm,
                           int64_t n, int64_t np, int32_t nrhs, double* __restrict__ y, int64_t ystride) {
   b += (int64_t)blockIdx.y * n * nrhs;
@@ -1387,7 +1391,8 @@ __global__ void k_perm_in(const double* __restrict__ b, const int32_t* __restric
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= np * nrhs) return;
   int64_t r = i / np, a = i % np;
-  y[i] = a < n ? b[r * n + perm[a]] : 0.0;
+  const int32_t o = perm[a];
+  y[i] = o >= 0 ? b[r * n + o] : 0.0;
 }
 
 // x = P^T y; NaN throughout when the factorization that the sweeps used
@@ -1398,9 +1403,10 @@ __global__ void k_perm_out(const double* __restrict__ y, const int32_t* __restri
   b += (int64_t)blockIdx.y * n * nrhs;
   y += (int64_t)blockIdx.y * ystride;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n * nrhs) return;
-  int64_t r = i / n, a = i % n;
-  b[r * n + perm[a]] = info[blockIdx.y] != 0 ? __builtin_nan("") : y[r * np + a];
+  if (i >= np * nrhs) return;
+  int64_t r = i / np, a = i % np;
+  const int32_t o = perm[a];
+  if (o >= 0) b[r * n + o] = info[blockIdx.y] != 0 ? __builtin_nan("") : y[i];
 }
 
 // Both sweeps run level by level over the blocks of the tile grid and read L

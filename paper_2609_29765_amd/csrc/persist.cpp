@@ -23,7 +23,7 @@ namespace stc {
 namespace {
 
 constexpr char kMagic[8] = {'S', 'T', 'C', 'P', 'L', 'A', 'N', '\0'};
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 
 // running checksum over a field's bytes: 64-bit words, then the tail
 uint64_t mix(uint64_t h, const char* c, size_t n) {
@@ -46,7 +46,7 @@ template <class A>
 void fields(A& a, Symbolic& s) {
   a(s.n); a(s.qnz); a(s.qp); a(s.qi); a(s.perm); a(s.iperm); a(s.ndense); a(s.method); a(s.parent);
   a(s.lp); a(s.li); a(s.lnz); a(s.nb); a(s.NT); a(s.mode); a(s.route); a(s.tiles); a(s.rows); a(s.kd);
-  a(s.phi); a(s.rho); a(s.sigma); a(s.tact); a(s.tasks);
+  a(s.phi); a(s.rho); a(s.sigma); a(s.tact); a(s.tasks); a(s.align); a(s.npad); a(s.pos);
 }
 
 template <class A>

@@ -150,7 +150,8 @@ struct stc_handle {
   double* d_zrow = nullptr;   // n_b zeros (rows a gather map leaves out)
   int32_t* d_potrf = nullptr;
   int32_t* d_trsm_items = nullptr;
-  int32_t* d_perm = nullptr;
+  int32_t* d_perm = nullptr;  // per grid position: the original index there, or -1 (padding)
+  int32_t* d_gcol = nullptr;  // per grid position: the column of P A P^T there, or -1
   int32_t* d_rows = nullptr;
   double* d_store = nullptr;  // batch stores
   double* d_y = nullptr;      // solve scratch
@@ -163,6 +164,7 @@ struct stc_handle {
   // -1 for a padded diagonal one, offset in the block)
   std::vector<int32_t> ld_ptr;
   std::vector<int2> ld_ent;
+  std::vector<int32_t> gperm, gcol;  // host copies of d_perm and d_gcol
   int32_t* d_ldptr = nullptr;
   int2* d_ldent = nullptr;
   // reverse mode of log det
@@ -215,7 +217,8 @@ size_t layout(const stc_handle* hc, int32_t batch, char* base) {
   take(&h->d_big_items, sizeof(int32_t) * h->big_items.size());
   take(&h->d_potrf, sizeof(int32_t) * h->potrf_list.size());
   take(&h->d_trsm_items, sizeof(int32_t) * h->trsm_items.size());
-  take(&h->d_perm, sizeof(int32_t) * (size_t)s.n);
+  take(&h->d_perm, sizeof(int32_t) * (size_t)padded_n(h));
+  take(&h->d_gcol, sizeof(int32_t) * (size_t)padded_n(h));
   take(&h->d_rows, sizeof(int32_t) * s.rows.size());
   take(&h->d_info, sizeof(int32_t) * (size_t)batch);
   take(&h->d_ld, sizeof(double) * (size_t)batch);
@@ -288,7 +291,7 @@ LevelArgs level_args(const stc_handle* h, size_t li, int kind) {
   a.dinv = h->d_dinv;
   a.dstride = dinv_stride(h);
   a.info = h->d_info;
-  a.nreal = (int32_t)h->sym.n;
+  a.nreal = (int32_t)padded_n(h);  // padding positions hold identity rows and never fail
   a.parts = h->d_parts;
   a.zrow = h->d_zrow;
   a.pstride = h->plan.parts;
@@ -452,7 +455,8 @@ int build_graph_nb(stc_handle* h, int32_t members, GraphRec* out) {
   int32_t* info = h->d_info;
   int32_t count = members, big = kInfoNone;
   int32_t* none = nullptr;
-  void* fargs[] = {&info, &count, &big, &none};
+  const int32_t* gcol = h->d_gcol;
+  void* fargs[] = {&info, &count, &big, &none, &gcol};
   hipKernelNodeParams fp{};
   fp.blockDim = dim3(256);
   fp.gridDim = dim3((unsigned)((members + 255) / 256));
@@ -599,7 +603,7 @@ int run_factor(stc_handle* h, const double* vals, int32_t members, hipStream_t s
   int rc = launch_levels(h, members, st, prof);
   if (rc) return rc;
   hipLaunchKernelGGL(k_info_finish, dim3((members + 255) / 256), dim3(256), 0, st, h->d_info, members,
-                     kInfoNone, (int32_t*)nullptr);
+                     kInfoNone, (int32_t*)nullptr, (const int32_t*)h->d_gcol);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -738,14 +742,25 @@ static int check_sweep(const stc_handle* h, bool fwd, const std::vector<int32_t>
 // the host-side lists derived from the symbolic analysis and the plans:
 // flattened level work lists and the solve sweeps' work items
 static void finish_handle(stc_handle* h) {
+  // grid positions: the original index and the permuted column at each
+  {
+    const int64_t np = padded_n(h);
+    h->gperm.assign((size_t)np, -1);
+    h->gcol.assign((size_t)np, -1);
+    for (int64_t j = 0; j < h->sym.n; ++j) {
+      const int64_t q = grid_pos(h->sym, j);
+      h->gperm[(size_t)q] = h->sym.perm[(size_t)j];
+      h->gcol[(size_t)q] = (int32_t)j;
+    }
+  }
   // the value load's per-block entry lists: input entries by store block
   // (ascending input index within a block), then the padded diagonal ones
   {
     const Plan& p = h->plan;
     const int64_t nblk = (p.store + LBLK - 1) / LBLK;
     std::vector<int64_t> pad;
-    const int32_t hl = p.diag_h[(size_t)p.NT - 1];
-    for (int32_t r = hl; r < p.nb; ++r) pad.push_back((int64_t)(p.NT - 1) * p.nb * p.nb + (int64_t)r * p.nb + r);
+    for (int32_t k = 0; k < p.NT; ++k)
+      for (int32_t r = p.diag_h[(size_t)k]; r < p.nb; ++r) pad.push_back((int64_t)k * p.nb * p.nb + (int64_t)r * p.nb + r);
     h->ld_ptr.assign((size_t)nblk + 1, 0);
     for (int64_t v : p.vmap) h->ld_ptr[(size_t)(v / LBLK) + 1]++;
     for (int64_t v : pad) h->ld_ptr[(size_t)(v / LBLK) + 1]++;
@@ -866,12 +881,13 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
                 stc_handle** out) {
   if (!out) return fail(STC_ERR_ARG, "null output handle");
   *out = nullptr;
-  stc_opts o{64, STC_MODE_AUTO, STC_ORD_AUTO, nullptr, 0};
+  stc_opts o{64, STC_MODE_AUTO, STC_ORD_AUTO, nullptr, 0, 0};
   if (opts) o = *opts;
   if (o.nb == 0) o.nb = 64;
   if (o.nb != 32 && o.nb != 64 && o.nb != 128 && o.nb != 256)
     return fail(STC_ERR_ARG, "nb must be 32, 64, 128 or 256");
   if (o.wg_slots < 0) return fail(STC_ERR_ARG, "wg_slots must be >= 0");
+  if (o.align < 0) return fail(STC_ERR_ARG, "align must be >= 0");
   try {
     auto* h = new stc_handle();
     std::string why;
@@ -880,9 +896,10 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
       delete h;
       return fail(rc, why);
     }
-    if (h->sym.qnz + o.nb >= INT32_MAX) {
+    if (o.align > 0) align_tiles(&h->sym, o.align);
+    if (h->sym.qnz + o.nb >= INT32_MAX || (int64_t)h->sym.NT * o.nb >= INT32_MAX) {
       delete h;
-      return fail(STC_ERR_ARG, "more than 2^31 - 1 input entries");
+      return fail(STC_ERR_ARG, "more than 2^31 - 1 input entries or grid positions");
     }
     rc = build_plan(h->sym, UB, TR, o.wg_slots, &h->plan, &why);
     if (rc == 0) rc = build_backward(h->sym, &h->plan, &h->back, &why);
@@ -961,7 +978,7 @@ int stc_bind(stc_handle* h, void* d_ws, size_t bytes, int32_t batch, void* strea
       (rc = upload(h->d_trsm, tr)) || (rc = upload(h->d_upd_items, h->upd_items)) ||
       (rc = upload(h->d_big_items, h->big_items)) ||
       (rc = upload(h->d_potrf, h->potrf_list)) || (rc = upload(h->d_trsm_items, h->trsm_items)) ||
-      (rc = upload(h->d_perm, s.perm)) ||
+      (rc = upload(h->d_perm, h->gperm)) || (rc = upload(h->d_gcol, h->gcol)) ||
       (rc = upload(h->d_rows, s.rows)) || (rc = upload(h->d_sfwd_items, h->sfwd_items)) ||
       (rc = upload(h->d_sbwd_items, h->sbwd_items)) || (rc = upload(h->d_sfwd_tl, ftl)) ||
       (rc = upload(h->d_sbwd_tl, btl)))
@@ -1010,7 +1027,7 @@ int stc_factorize_batched(stc_handle* h, const double* d_values, int32_t B, doub
   rc = run_factor(h, d_values, B, st);
   if (rc) return rc;
   hipLaunchKernelGGL(k_logdet, dim3(B), dim3(256), 0, st, h->d_store, h->plan.store, h->plan.nb,
-                     h->sym.n, h->d_info, d_logdet);
+                     padded_n(h), h->d_info, d_logdet);
   HIPCHK(hipMemcpyAsync(d_info, h->d_info, sizeof(int32_t) * B, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipGetLastError());
   h->last_stream = st;
@@ -1027,7 +1044,7 @@ int stc_logdet(stc_handle* h, double* d_out, void* stream) {
   if (!h->factored) return fail(STC_ERR_STATE, "logdet before factorize");
   hipStream_t st = (hipStream_t)stream;
   hipLaunchKernelGGL(k_logdet, dim3(1), dim3(256), 0, st, h->d_store, h->plan.store, h->plan.nb,
-                     h->sym.n, h->d_info, d_out);
+                     padded_n(h), h->d_info, d_out);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -1050,7 +1067,7 @@ int stc_solve(stc_handle* h, double* d_b, int32_t nrhs, void* stream) {
     if (rc) return rc;
     HIPCHK(hipGraphLaunch(ex, st));
   }
-  hipLaunchKernelGGL(k_perm_out, dim3((unsigned)((n * nrhs + 255) / 256)), dim3(256), 0, st, h->d_y,
+  hipLaunchKernelGGL(k_perm_out, dim3((unsigned)((np * nrhs + 255) / 256)), dim3(256), 0, st, h->d_y,
                      h->d_perm, h->d_info, n, np, nrhs, d_b, np * nrhs);
   HIPCHK(hipGetLastError());
   return 0;
@@ -1072,7 +1089,7 @@ int stc_solve_batched(stc_handle* h, double* d_b, int32_t B, int32_t nrhs, void*
   rc = get_solve_graph(h, nrhs == 1 ? 1 : SR, 0, &ex, B);
   if (rc) return rc;
   HIPCHK(hipGraphLaunch(ex, st));
-  hipLaunchKernelGGL(k_perm_out, dim3((unsigned)((n * nrhs + 255) / 256), B), dim3(256), 0, st, h->d_y, h->d_perm,
+  hipLaunchKernelGGL(k_perm_out, dim3((unsigned)((np * nrhs + 255) / 256), B), dim3(256), 0, st, h->d_y, h->d_perm,
                      h->d_info, n, np, nrhs, d_b, ys);
   HIPCHK(hipGetLastError());
   return 0;
@@ -1095,7 +1112,7 @@ int stc_solve_noalloc(stc_handle* h, double* d_b, int32_t nrhs, void* stream) {
   hipLaunchKernelGGL(k_perm_in, dim3((unsigned)((np * nrhs + 255) / 256)), dim3(256), 0, st, d_b,
                      h->d_perm, n, np, nrhs, y, np * nrhs);
   for (int32_t g0 = 0; g0 < nrhs; g0 += SR) launch_sweeps(h, y, std::min<int32_t>(SR, nrhs - g0), g0, st);
-  hipLaunchKernelGGL(k_perm_out, dim3((unsigned)((n * nrhs + 255) / 256)), dim3(256), 0, st, y,
+  hipLaunchKernelGGL(k_perm_out, dim3((unsigned)((np * nrhs + 255) / 256)), dim3(256), 0, st, y,
                      h->d_perm, h->d_info, n, np, nrhs, d_b, np * nrhs);
   HIPCHK(hipGetLastError());
   return 0;
@@ -1133,9 +1150,9 @@ int stc_selinv(stc_handle* h, double* d_diag, void* stream) {
   h->zs_ready = true;
   h->last_stream = st;
   if (d_diag) {
-    const int64_t n = h->sym.n;
-    const int64_t grid = std::min<int64_t>(4096, (n + 255) / 256);
-    hipLaunchKernelGGL(k_selinv_diag, dim3((unsigned)grid), dim3(256), 0, st, h->d_zs, h->d_perm, n, h->plan.nb,
+    const int64_t np = padded_n(h);
+    const int64_t grid = std::min<int64_t>(4096, (np + 255) / 256);
+    hipLaunchKernelGGL(k_selinv_diag, dim3((unsigned)grid), dim3(256), 0, st, h->d_zs, h->d_perm, np, h->plan.nb,
                        h->d_info, d_diag);
   }
   HIPCHK(hipGetLastError());
@@ -1207,6 +1224,12 @@ int stc_get_sizes(const stc_handle* h, int64_t* z) {
                    h->plan.store, (int64_t)h->plan.levels.size(),
                    (int64_t)(h->sfwd_nstep.size() + h->sbwd_nstep.size())};
   std::memcpy(z, v, sizeof(v));
+  return 0;
+}
+
+int stc_get_grid_positions(const stc_handle* h, int64_t* pos) {
+  if (!h || !pos) return fail(STC_ERR_ARG, "null argument");
+  for (int64_t j = 0; j < h->sym.n; ++j) pos[j] = grid_pos(h->sym, j);
   return 0;
 }
 

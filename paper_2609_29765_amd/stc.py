@@ -31,7 +31,7 @@ EXPORTS = [
     "stc_analyse", "stc_workspace_bytes", "stc_bind", "stc_factorize", "stc_factorize_batched",
     "stc_logdet", "stc_solve", "stc_solve_noalloc", "stc_solve_batched", "stc_logdet_backward", "stc_selinv", "stc_get_selinv", "stc_info", "stc_get_sizes",
     "stc_get_features", "stc_get_perm", "stc_get_etree", "stc_get_L_pattern", "stc_get_tiles",
-    "stc_get_tasks", "stc_get_factor", "stc_get_batch_factor", "stc_get_work", "stc_get_plan_stats", "stc_check_schedule", "stc_check_solve_schedule", "stc_profile_factorize",
+    "stc_get_tasks", "stc_get_grid_positions", "stc_get_factor", "stc_get_batch_factor", "stc_get_work", "stc_get_plan_stats", "stc_check_schedule", "stc_check_solve_schedule", "stc_profile_factorize",
     "stc_fp64_mfma_peak", "stc_save", "stc_load", "stc_destroy",
     "stc_last_error",
 ]
@@ -47,7 +47,7 @@ class STCError(RuntimeError):
 
 class _opts(C.Structure):
     _fields_ = [("nb", C.c_int32), ("mode", C.c_int32), ("ordering", C.c_int32),
-                ("perm", C.c_void_p), ("wg_slots", C.c_int32)]
+                ("perm", C.c_void_p), ("wg_slots", C.c_int32), ("align", C.c_int32)]
 
 
 def lib():
@@ -79,6 +79,7 @@ def lib():
     L.stc_get_L_pattern.argtypes = [vp, _i64p, _i32p]
     L.stc_get_tiles.argtypes = [vp, _i32p, _i32p, _i32p, _i32p, _i8p, _i64p, _i32p, _i32p]
     L.stc_get_tasks.argtypes = [vp, _i32p]
+    L.stc_get_grid_positions.argtypes = [vp, _i64p]
     L.stc_get_factor.argtypes = [vp, _f64p, vp]
     L.stc_get_batch_factor.argtypes = [vp, C.c_int32, _f64p, vp]
     L.stc_get_work.argtypes = [vp, _f64p]
@@ -129,14 +130,15 @@ class Analysis:
     """Once-per-pattern analysis; factorize / logdet / solve many times."""
 
     def __init__(self, n, colptr, rowind, nb=64, mode="auto", ordering="auto", perm=None,
-                 wg_slots=0, _handle=None):
+                 wg_slots=0, align=0, _handle=None):
         L = lib()
         if _handle is None:
             self.colptr = np.ascontiguousarray(colptr, np.int64)
             self.rowind = np.ascontiguousarray(rowind, np.int32)
             self._perm_in = None if perm is None else np.ascontiguousarray(perm, np.int32)
             o = _opts(int(nb), MODES[mode], ORDERINGS[ordering],
-                      None if self._perm_in is None else self._perm_in.ctypes.data, int(wg_slots))
+                      None if self._perm_in is None else self._perm_in.ctypes.data, int(wg_slots),
+                      int(align))
             h = C.c_void_p()
             _check(L.stc_analyse(int(n), self.colptr, self.rowind, C.byref(o), C.byref(h)))
         else:
@@ -199,6 +201,12 @@ class Analysis:
                                    out["contig"], out["roff"], out["rows"], out["kd"]))
         out["rows"] = out["rows"][:self.nrows]
         return out
+
+    def grid_positions(self):
+        """Tile-grid position of every column of P A P^T (stc_get_grid_positions)."""
+        p = np.zeros(self.n, np.int64)
+        _check(lib().stc_get_grid_positions(self._h, p))
+        return p
 
     def tasks(self):
         t = np.zeros((max(self.ntasks, 1), 4), np.int32)
