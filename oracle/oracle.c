@@ -21,7 +21,11 @@
  *   tiles              uniform n_b grid, active rows of every off-diagonal tile
  *                      (the active columns of the stored transpose), full and
  *                      contiguous flags, diagonal half-width kd (Sec. 4.1-4.3,
- *                      Sec. 5.2 "Per-tile metadata")
+ *                      Sec. 5.2 "Per-tile metadata"); or the same on a grid
+ *                      aligned to the elimination tree (orc_align: large
+ *                      subtrees start on tile boundaries, so the tiling follows
+ *                      the tree as the supernodal tiles of Sec. 5.4 follow the
+ *                      supernodes; the rule is the library's, not the paper's)
  *   features, route    fill ratio, mean tile occupancy, degree skew and the
  *                      fixed precedence of the selector (Sec. 5.1, Table 5)
  *   task list          the ordered SYRK/POTRF/GEMM/TRSM list (Algorithm 1)
@@ -36,8 +40,8 @@
  *
  * Parity status: the factor, logdet, solve and selected inverse are pinned by
  * dense LAPACK, closed forms and spectral identities in the tests; tiles by the
- * worked examples of Sec. 4.1 and Sec. 4.3; the task list by Algorithm 1 on
- * hand-built tile patterns.  The orderings and the AUTO winner rule are
+ * worked examples of Sec. 4.1 and Sec. 4.3, the aligned grid by hand-worked
+ * trees; the task list by Algorithm 1 on hand-built tile patterns.  The orderings and the AUTO winner rule are
  * PARITY UNPINNED by the paper (it names heuristics without parameters): they
  * are pinned only by hand-worked small graphs and by agreement with an
  * independent implementation of the same written rule.
@@ -445,6 +449,10 @@ typedef struct {
   int64_t tact;
   int64_t ntasks;
   int32_t* tasks; /* 4 ints per task: op, m, k, n (-1 = unused slot) */
+  /* tile grid aligned to the elimination tree (orc_align): column j sits at
+     grid position gpos[j]; NULL on the uniform grid (position = column) */
+  int64_t* gpos;
+  int64_t align;
 } orc_t;
 
 void orc_free(orc_t* s);
@@ -553,11 +561,18 @@ static int build_permuted(orc_t* s) {
 }
 
 /* tiles, features, route and Algorithm 1 for block size nb */
-static int build_tiles(orc_t* s, int nb, int mode) {
+#define GPOS(s, j) ((s)->gpos ? (s)->gpos[(j)] : (int64_t)(j))
+
+static int build_tiles(orc_t* s, int nb, int mode, int features) {
   int64_t n = s->n;
-  int NT = (int)((n + nb - 1) / nb);
+  int64_t npad = GPOS(s, n - 1) + 1;
+  int NT = (int)((npad + nb - 1) / nb);
   s->nb = nb;
   s->NT = NT;
+  /* real columns of each block; the block's other positions are padding */
+  int64_t* hreal = (int64_t*)calloc((size_t)NT, sizeof(int64_t));
+  if (!hreal) return ORC_ERR_ALLOC;
+  for (int64_t j = 0; j < n; ++j) hreal[GPOS(s, j) / nb]++;
   /* active-row bitmaps for every (m,k), m>k, stored as bytes per row */
   int64_t npairs = (int64_t)NT * (NT - 1) / 2;
   uint8_t* act = (uint8_t*)calloc((size_t)(npairs > 0 ? npairs : 1) * (size_t)nb, 1);
@@ -566,14 +581,14 @@ static int build_tiles(orc_t* s, int nb, int mode) {
   /* pair index of (m,k), m>k: column-major over k */
 #define PAIR(m, k) ((int64_t)(k) * (2 * (int64_t)NT - (k)-1) / 2 + ((m) - (k)-1))
   for (int64_t j = 0; j < n; ++j) {
-    int k = (int)(j / nb);
+    int k = (int)(GPOS(s, j) / nb);
     for (int64_t p = s->lp[j]; p < s->lp[j + 1]; ++p) {
       int64_t i = s->li[p];
-      int m = (int)(i / nb);
+      int m = (int)(GPOS(s, i) / nb);
       if (m == k) {
         if (i - j > s->kd[k]) s->kd[k] = (int32_t)(i - j);
       } else {
-        act[PAIR(m, k) * nb + (i - (int64_t)m * nb)] = 1;
+        act[PAIR(m, k) * nb + (GPOS(s, i) - (int64_t)m * nb)] = 1;
       }
     }
   }
@@ -588,37 +603,40 @@ static int build_tiles(orc_t* s, int nb, int mode) {
         sum_true += cnt;
       }
     }
-  /* features (Sec. 5.1) */
-  int64_t* rowcount = (int64_t*)calloc((size_t)n, sizeof(int64_t));
-  if (!rowcount) return ORC_ERR_ALLOC;
-  for (int64_t p = 0; p < s->lnz; ++p) rowcount[s->li[p]]++;
-  int64_t maxrc = 0;
-  for (int64_t i = 0; i < n; ++i)
-    if (rowcount[i] > maxrc) maxrc = rowcount[i];
-  free(rowcount);
-  s->phi = (double)s->lnz / (double)s->qnz;
-  s->rho = ntiles ? (double)sum_true / ((double)nb * (double)ntiles) : 1.0;
-  s->sigma = ((double)maxrc * (double)n) / (double)s->lnz;
-  s->tact = ntiles + NT;
-  /* fixed precedence of the selector, cut-offs of Table 5 */
-  if (s->rho >= 0.90)
-    s->route = ROUTE_DENSE;
-  else if (s->phi > 2.0 && s->rho < 0.15)
-    s->route = ROUTE_SUPERNODAL;
-  else if (s->rho >= 0.15 || s->sigma >= 20.0)
-    s->route = ROUTE_SEMISPARSE;
-  else
-    s->route = ROUTE_SUPERNODAL;
-  /* the supernodal decision is reported and runs on the active-column tiles */
-  if (mode == MODE_AUTO) mode = (s->route == ROUTE_DENSE) ? MODE_DENSE : MODE_SEMISPARSE;
-  s->mode = mode;
+  /* features (Sec. 5.1), read off the uniform grid only */
+  if (features) {
+    int64_t* rowcount = (int64_t*)calloc((size_t)n, sizeof(int64_t));
+    if (!rowcount) return ORC_ERR_ALLOC;
+    for (int64_t p = 0; p < s->lnz; ++p) rowcount[s->li[p]]++;
+    int64_t maxrc = 0;
+    for (int64_t i = 0; i < n; ++i)
+      if (rowcount[i] > maxrc) maxrc = rowcount[i];
+    free(rowcount);
+    s->phi = (double)s->lnz / (double)s->qnz;
+    s->rho = ntiles ? (double)sum_true / ((double)nb * (double)ntiles) : 1.0;
+    s->sigma = ((double)maxrc * (double)n) / (double)s->lnz;
+    s->tact = ntiles + NT;
+    /* fixed precedence of the selector, cut-offs of Table 5 */
+    if (s->rho >= 0.90)
+      s->route = ROUTE_DENSE;
+    else if (s->phi > 2.0 && s->rho < 0.15)
+      s->route = ROUTE_SUPERNODAL;
+    else if (s->rho >= 0.15 || s->sigma >= 20.0)
+      s->route = ROUTE_SEMISPARSE;
+    else
+      s->route = ROUTE_SUPERNODAL;
+    /* the supernodal decision is reported and runs on the active-column tiles */
+    if (mode == MODE_AUTO) mode = (s->route == ROUTE_DENSE) ? MODE_DENSE : MODE_SEMISPARSE;
+    s->mode = mode;
+  }
+  mode = s->mode;
   int64_t nrows_stored = 0;
   for (int k = 0; k < NT; ++k)
     for (int m = k + 1; m < NT; ++m) {
       int64_t base = PAIR(m, k) * nb;
       int cnt = 0;
       for (int r = 0; r < nb; ++r) cnt += act[base + r];
-      int hm = (int)((m == NT - 1) ? n - (int64_t)m * nb : nb);
+      int hm = (int)hreal[m];
       if (cnt) nrows_stored += (mode == MODE_DENSE) ? hm : cnt;
     }
   s->ntiles = ntiles;
@@ -644,7 +662,7 @@ static int build_tiles(orc_t* s, int nb, int mode) {
           hi = r;
         }
       if (!cnt) continue;
-      int hm = (int)((m == NT - 1) ? n - (int64_t)m * nb : nb);
+      int hm = (int)hreal[m];
       s->tile_m[t] = m;
       s->tile_k[t] = k;
       s->tile_true[t] = cnt;
@@ -664,6 +682,7 @@ static int build_tiles(orc_t* s, int nb, int mode) {
   s->tile_roff[t] = w;
 #undef PAIR
   free(act);
+  free(hreal);
 
   return ORC_OK;
 }
@@ -773,7 +792,7 @@ static int build_rows_and_cinl(orc_t* s) {
 static int analyse_with_perm(orc_t* s, int nb, int mode) {
   int rc = build_permuted(s);
   if (!rc) rc = symbolic_by_definition(s);
-  if (!rc) rc = build_tiles(s, nb, mode);
+  if (!rc) rc = build_tiles(s, nb, mode, 1);
   if (!rc) rc = build_tasks(s);
   if (!rc) rc = build_rows_and_cinl(s);
   return rc;
@@ -888,7 +907,65 @@ void orc_free(orc_t* s) {
   free(s->tile_m); free(s->tile_k); free(s->tile_cnt); free(s->tile_true);
   free(s->tile_contig); free(s->tile_roff); free(s->rows); free(s->kd);
   free(s->tasks);
+  free(s->gpos);
   free(s);
+}
+
+/* ------------------------------------------------------------------------- */
+/* tile grid aligned to the elimination tree                                 */
+/* ------------------------------------------------------------------------- */
+
+/* Every subtree T(r) of the elimination tree (r and its descendants) with at
+   least min_subtree columns that are consecutive -- its smallest column is
+   r - |T(r)| + 1, since descendants precede r -- starts a tile: the columns
+   before it are padded up to the next multiple of nb.  Sizes and smallest
+   columns come from walking every column's path to its root.  Tiles and
+   tasks are rebuilt on the resulting grid; features, route and storage mode
+   stay those of the uniform grid. */
+int orc_align(orc_t* s, int64_t min_subtree) {
+  int64_t n = s->n;
+  int nb = s->nb;
+  free(s->gpos);
+  s->gpos = NULL;
+  s->align = 0;
+  if (min_subtree > 0) {
+    int64_t* size = (int64_t*)calloc((size_t)n, sizeof(int64_t));
+    int64_t* lo = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    uint8_t* start = (uint8_t*)calloc((size_t)n, 1);
+    s->gpos = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    if (!size || !lo || !start || !s->gpos) {
+      free(size); free(lo); free(start);
+      return ORC_ERR_ALLOC;
+    }
+    for (int64_t r = 0; r < n; ++r) lo[r] = r;
+    for (int64_t j = 0; j < n; ++j)
+      for (int64_t a = j; a >= 0; a = s->parent[a]) {
+        size[a]++;
+        if (j < lo[a]) lo[a] = j;
+      }
+    for (int64_t r = 0; r < n; ++r)
+      if (size[r] >= min_subtree && lo[r] == r - size[r] + 1) start[lo[r]] = 1;
+    int64_t q = 0;
+    for (int64_t j = 0; j < n; ++j) {
+      if (start[j] && q % nb != 0) q = (q / nb + 1) * nb;
+      s->gpos[j] = q;
+      q++;
+    }
+    free(size); free(lo); free(start);
+    s->align = min_subtree;
+  }
+  free(s->tile_m); free(s->tile_k); free(s->tile_cnt); free(s->tile_true);
+  free(s->tile_contig); free(s->tile_roff); free(s->rows); free(s->kd); free(s->tasks);
+  s->tile_m = s->tile_k = s->tile_cnt = s->tile_true = s->rows = s->kd = s->tasks = NULL;
+  s->tile_contig = NULL;
+  s->tile_roff = NULL;
+  int rc = build_tiles(s, nb, s->mode, 0);
+  if (!rc) rc = build_tasks(s);
+  return rc;
+}
+
+void orc_get_positions(const orc_t* s, int64_t* pos) {
+  for (int64_t j = 0; j < s->n; ++j) pos[j] = GPOS(s, j);
 }
 
 /* ------------------------------------------------------------------------- */

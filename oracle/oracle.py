@@ -51,6 +51,9 @@ def lib():
         L.orc_get_value_map.argtypes = [C.c_void_p, _i64p]
         L.orc_get_tiles.argtypes = [C.c_void_p, _i32p, _i32p, _i32p, _i32p, _i8p, _i64p, _i32p, _i32p]
         L.orc_get_tasks.argtypes = [C.c_void_p, _i32p]
+        L.orc_align.argtypes = [C.c_void_p, C.c_int64]
+        L.orc_align.restype = C.c_int
+        L.orc_get_positions.argtypes = [C.c_void_p, _i64p]
         L.orc_factor.argtypes = [C.c_void_p, _f64p, _f64p]
         L.orc_factor.restype = C.c_int64
         L.orc_logdet.argtypes = [C.c_void_p, _f64p]
@@ -90,7 +93,7 @@ class Tiles:
 class Analysis:
     """Symbolic state for one pattern: ordering, L pattern, tiles, tasks."""
 
-    def __init__(self, n, colptr, rowind, ordering="nd", nb=64, mode="auto", perm=None):
+    def __init__(self, n, colptr, rowind, ordering="nd", nb=64, mode="auto", perm=None, align=0):
         self.colptr = np.ascontiguousarray(colptr, np.int64)
         self.rowind = np.ascontiguousarray(rowind, np.int32)
         err = C.c_int(0)
@@ -103,6 +106,10 @@ class Analysis:
         if not h:
             raise ValueError(f"oracle analyse failed with code {err.value}")
         self._h = h
+        if align:
+            rc = lib().orc_align(h, int(align))
+            if rc:
+                raise ValueError(f"oracle alignment failed with code {rc}")
         sz = np.zeros(16, np.int64)
         lib().orc_sizes(h, sz)
         (self.n, self.qnz, self.lnz, self.nb, self.NT, self.ntiles, self.nrows, self.ntasks,
@@ -154,6 +161,12 @@ class Analysis:
         kd = np.zeros(self.NT, np.int32)
         lib().orc_get_tiles(self._h, m, k, cnt, tc, cg, ro, rows, kd)
         return Tiles(m, k, cnt, tc, cg, ro, rows[:self.nrows], kd)
+
+    def positions(self) -> np.ndarray:
+        """Grid position of every column of P A P^T (the identity on the uniform grid)."""
+        p = np.zeros(self.n, np.int64)
+        lib().orc_get_positions(self._h, p)
+        return p
 
     def tasks(self) -> np.ndarray:
         t = np.zeros((max(self.ntasks, 1), 4), np.int32)

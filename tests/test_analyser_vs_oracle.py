@@ -17,9 +17,10 @@ from paper_2609_29765_amd import stc as S  # noqa: E402
 from paper_2609_29765_amd import workloads as W  # noqa: E402
 
 
-def _compare(w, ordering, nb, mode="auto"):
-    o = O.Analysis(w.n, w.colptr, w.rowind, ordering, nb=nb, mode=mode)
-    a = S.Analysis(w.n, w.colptr, w.rowind, nb=nb, mode=mode, ordering=ordering)
+def _compare(w, ordering, nb, mode="auto", align=0):
+    o = O.Analysis(w.n, w.colptr, w.rowind, ordering, nb=nb, mode=mode, align=align)
+    a = S.Analysis(w.n, w.colptr, w.rowind, nb=nb, mode=mode, ordering=ordering, align=align)
+    assert np.array_equal(a.grid_positions(), o.positions())
     assert (a.lnz, a.NT, a.ntiles, a.nrows, a.ntasks, a.ndense, a.method, a.tact) == \
            (o.lnz, o.NT, o.ntiles, o.nrows, o.ntasks, o.ndense, o.method, o.tact)
     assert (a.mode, a.route) == (o.mode, o.route)

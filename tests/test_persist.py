@@ -23,6 +23,7 @@ def exports(a):
     return {"sizes": (a.n, a.qnz, a.lnz, a.nb, a.NT, a.ntiles, a.nrows, a.ntasks, a.mode, a.route, a.ndense,
                       a.method, a.tact, a.store, a.nlevels, a.solve_launches),
             "features": (a.phi, a.rho, a.sigma), "perm": a.perm(), "etree": a.etree(), "lp": lp, "li": li,
+            "positions": a.grid_positions(),
             **{f"tile_{k}": v for k, v in t.items()}, "tasks": a.tasks(), "work": a.work(),
             "plan": a.plan_stats(), "schedule": a.check_schedule(), "solve": a.check_solve_schedule()}
 
@@ -41,6 +42,7 @@ CASES = [
     ("gmrf", lambda: W.gmrf_grid2d(32, 32, 0.1, 0), dict(nb=64, ordering="nd")),
     ("arrowhead", lambda: W.differentiable_arrowhead(20, 25, 8, 0), dict(nb=128, ordering="nd", wg_slots=4)),
     ("dense", lambda: W.dense_spd(700, 0.2, 0), dict(nb=256, ordering="natural", mode="dense")),
+    ("aligned", lambda: W.differentiable_arrowhead(20, 25, 8, 0), dict(nb=128, ordering="nd", align=512)),
 ]
 
 
