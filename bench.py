@@ -39,6 +39,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 matrix peak (published)
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E (published)
+# tile grids the extras' autotuner tries, as multiples of the tile size: the
+# uniform grid and grids aligned to elimination subtrees of 2, 4 and 8 tiles
+GRID_ALIGNS = (0, 2, 4, 8)
 KERNEL_SOURCES = ["paper_2609_29765_amd/csrc/kernels.hpp", "paper_2609_29765_amd/csrc/device_types.hpp",
                   "paper_2609_29765_amd/csrc/runtime.hip", "paper_2609_29765_amd/csrc/analyse.cpp"]
 
@@ -89,9 +92,10 @@ def log(msg):
 # headline: dense route, n = 12288, tile 256
 # ---------------------------------------------------------------------------
 
-def semisparse_pass():
+def semisparse_pass(align):
     """Counter runs over the active-column route: the spatio-temporal
-    arrowhead (n = 101,258, tile 128, ND) factorized once through the graph and
+    arrowhead (n = 101,258, tile 128, ND, grid aligned to subtrees of `align`
+    columns, 0 = uniform) factorized once through the graph and
     once kernel by kernel (one launch per level and kernel kind, the launches
     the per-kind figures charge), then a plain 1 GiB device copy whose counter
     readings calibrate the byte counters.  Prints one JSON line: the per-kind
@@ -101,7 +105,7 @@ def semisparse_pass():
     from paper_2609_29765_amd import workloads
     w = workloads.spatiotemporal_arrowhead()
     v = torch.from_numpy(w.values).cuda()
-    a = stc.Analysis(w.n, w.colptr, w.rowind, nb=128, ordering="nd").bind()
+    a = stc.Analysis(w.n, w.colptr, w.rowind, nb=128, ordering="nd", align=align).bind()
     a.factorize(v)
     torch.cuda.synchronize()
     assert a.info() == 0
@@ -111,14 +115,14 @@ def semisparse_pass():
     x.fill_(1.0)
     y.copy_(x)
     torch.cuda.synchronize()
-    print(json.dumps({"workload": "spatio-temporal arrowhead n=101258, tile 128, ND", "work": a.work(),
+    print(json.dumps({"workload": f"spatio-temporal arrowhead n=101258, tile 128, ND, grid align {align}", "work": a.work(),
                       "kinds": {k: {"ms": ms, "launches": c, "flops": f} for k, (ms, c, f) in prof.items()}}),
           flush=True)
 
 
-def solve_pass():
+def solve_pass(align):
     """Kernel-trace runs over the solve: the spatio-temporal arrowhead
-    (n = 101,258, tile 128, ND) factorized once, then three solves with one
+    (n = 101,258, tile 128, ND, grid alignment `align`) factorized once, then three solves with one
     right-hand side and three with eight, each group's sweeps replayed from
     its graph (the first call of a group captures it).  Prints one JSON line
     with the event-timed solves and the sweeps' launch count."""
@@ -127,7 +131,7 @@ def solve_pass():
     from paper_2609_29765_amd import workloads
     w = workloads.spatiotemporal_arrowhead()
     v = torch.from_numpy(w.values).cuda()
-    a = stc.Analysis(w.n, w.colptr, w.rowind, nb=128, ordering="nd").bind()
+    a = stc.Analysis(w.n, w.colptr, w.rowind, nb=128, ordering="nd", align=align).bind()
     a.factorize(v)
     torch.cuda.synchronize()
     assert a.info() == 0
@@ -145,7 +149,7 @@ def solve_pass():
             torch.cuda.synchronize()
             ms.append(e0.elapsed_time(e1))
         out[f"solve_{nrhs}rhs_ms"] = [round(x, 3) for x in ms]
-    print(json.dumps({"workload": "spatio-temporal arrowhead n=101258, tile 128, ND",
+    print(json.dumps({"workload": f"spatio-temporal arrowhead n=101258, tile 128, ND, grid align {align}",
                       "sweep_launches": a.solve_launches, **out}), flush=True)
 
 
@@ -299,12 +303,14 @@ def headline(args):
 # ---------------------------------------------------------------------------
 
 def extra_gmrf():
-    """Small 2-D GMRF (n = 1024, tile 64, ND): factorize + logdet + solve."""
+    """Small 2-D GMRF (n = 1024, ND): factorize + logdet + solve, tile size
+    and grid tuned."""
     import torch
-    from paper_2609_29765_amd import stc, workloads
+    from paper_2609_29765_amd import workloads
+    from paper_2609_29765_amd.autotune import autotune
     w = workloads.gmrf_grid2d(32, 32, 0.1, 0)
-    a = stc.Analysis(w.n, w.colptr, w.rowind, nb=64, ordering="nd").bind()
     v = torch.from_numpy(w.values).cuda()
+    a, table = autotune(w.n, w.colptr, w.rowind, v, nbs=(32, 64), ordering="nd", trials=20, aligns=GRID_ALIGNS)
     b = torch.from_numpy(w.b).cuda()
     out = torch.empty(1, dtype=torch.float64, device="cuda")
 
@@ -317,9 +323,10 @@ def extra_gmrf():
     us_f = timed(lambda: a.factorize(v), 200) * 1e3
     us = timed(step, 200) * 1e3
     del out
-    return {"workload": "2-D GMRF 32x32 grid, Laplacian + 0.1 I, n=1024, tile 64, ND",
+    return {"workload": "2-D GMRF 32x32 grid, Laplacian + 0.1 I, n=1024, ND",
+            "nb": a.nb, "align": a.align,
             "us_per_factorization": round(us_f, 2), "us_per_factorize_logdet_solve": round(us, 2),
-            "levels": a.nlevels, "mode": a.mode}
+            "levels": a.nlevels, "mode": a.mode, "autotune": table}
 
 
 def extra_semisparse():
@@ -330,7 +337,7 @@ def extra_semisparse():
     w = workloads.spatiotemporal_arrowhead()
     v = torch.from_numpy(w.values).cuda()
     t0 = time.time()
-    a, table = autotune(w.n, w.colptr, w.rowind, v, nbs=(128, 256), ordering="nd", trials=3)
+    a, table = autotune(w.n, w.colptr, w.rowind, v, nbs=(128, 256), ordering="nd", trials=3, aligns=GRID_ALIGNS)
     t_tune = time.time() - t0
     ms = timed(lambda: a.factorize(v), 10)
     assert a.info() == 0
@@ -338,7 +345,7 @@ def extra_semisparse():
     prof = a.profile_factorize(v)
     return {"workload": "spatio-temporal arrowhead n=101258 (50 steps x 45x45 grid, AR1 0.9, kappa 0.5, "
                         "8 dense border rows), ND ordering",
-            "nb": a.nb, "mode": a.mode, "route": a.route, "levels": a.nlevels,
+            "nb": a.nb, "align": a.align, "mode": a.mode, "route": a.route, "levels": a.nlevels,
             "factorizations_per_s": round(1000.0 / ms, 3), "ms_per_factorization": round(ms, 3),
             "gflops_tile": round(wk["flops_tile"] / (ms * 1e-3) / 1e9, 1),
             "gflops_exact": round(wk["flops_exact"] / (ms * 1e-3) / 1e9, 1),
@@ -355,7 +362,8 @@ def extra_batched(B):
     from paper_2609_29765_amd.autotune import autotune
     w = workloads.batched_laplacian3d(m=24, B=B, seed=0)
     V = torch.from_numpy(w.values).cuda()
-    a, table = autotune(w.n, w.colptr, w.rowind, V, nbs=(64, 128), ordering="nd", batched=True, trials=2)
+    a, table = autotune(w.n, w.colptr, w.rowind, V, nbs=(64, 128), ordering="nd", batched=True, trials=2,
+                        aligns=GRID_ALIGNS)
     ms_batched = timed(lambda: a.factorize_batched(V), 3)
     ld_b, info = a.factorize_batched(V)
     assert int(info.abs().sum().item()) == 0
@@ -370,7 +378,7 @@ def extra_batched(B):
     ms_plain = timed(plain, 2)
     dev = float(((ld_s - ld_b).abs() / ld_b.abs()).max().item())
     return {"workload": f"3-D Laplacian 24^3 + 0.05 I, n=13824, B={B} hyperparameter value sets, ND",
-            "nb": a.nb, "mode": a.mode, "levels": a.nlevels, "B": B,
+            "nb": a.nb, "align": a.align, "mode": a.mode, "levels": a.nlevels, "B": B,
             "ms_batched": round(ms_batched, 3), "ms_plain_loop": round(ms_plain, 3),
             "batched_speedup": round(ms_plain / ms_batched, 3),
             "factorizations_per_s_batched": round(B * 1000.0 / ms_batched, 1),
@@ -387,7 +395,7 @@ def extra_backward():
     w = workloads.differentiable_arrowhead(20, 25, 8, 0)
     v = torch.from_numpy(w.values).cuda()
     a, table = autotune(w.n, w.colptr, w.rowind, v, nbs=(32, 64, 128), ordering="nd", trials=3,
-                        objective="logdet_grad")
+                        objective="logdet_grad", aligns=GRID_ALIGNS)
     one = torch.ones(1, dtype=torch.float64, device="cuda")
     dv = torch.from_numpy(w.dvalues).cuda()
 
@@ -426,7 +434,7 @@ def extra_backward():
     wk = a.work()
     return {"workload": "differentiable arrowhead n=12508 (20 steps x 25x25 grid + 8 border rows), "
                         "theta=(log tau, log kappa, atanh rho) seed 0, ND",
-            "nb": a.nb, "levels_forward": a.nlevels, "levels_backward": int(wk["levels_backward"]),
+            "nb": a.nb, "align": a.align, "levels_forward": a.nlevels, "levels_backward": int(wk["levels_backward"]),
             "ms_forward": round(ms_f, 4), "ms_forward_backward": round(ms_fb, 4),
             "backward_ratio": round(ms_fb / ms_f, 3),
             "ms_fd_gradient": round(ms_fd, 4), "speedup_vs_fd": round(ms_fd / ms_fb, 3),
@@ -753,6 +761,8 @@ def main():
     ap.add_argument("--semisparse-pass", action="store_true",
                     help="only: one eager C3 factorization (kernel by kernel) and a 1 GiB copy, "
                          "for counter runs over the active-column route")
+    ap.add_argument("--pass-align", type=int, default=512,
+                    help="tile-grid alignment (columns, 0 = uniform grid) of --solve-pass and --semisparse-pass")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration runs)")
     ap.add_argument("--summarize-trace", default=None, metavar="DIR",
@@ -781,10 +791,10 @@ def main():
         run_extras(args.extras_out, args.batch)
         return
     if args.solve_pass:
-        solve_pass()
+        solve_pass(args.pass_align)
         return
     if args.semisparse_pass:
-        semisparse_pass()
+        semisparse_pass(args.pass_align)
         return
 
     import torch

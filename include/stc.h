@@ -239,8 +239,9 @@ int stc_get_tiles(const stc_handle* h, int32_t* m, int32_t* k, int32_t* cnt, int
 int stc_get_tasks(const stc_handle* h, int32_t* tasks); /* int32[ntasks][4]: op, m, k, n */
 /* grid position of every column of P A P^T (int64[n], ascending); tile t
    covers positions [t n_b, (t+1) n_b), positions no column takes are padding.
-   The identity on the uniform grid. */
-int stc_get_grid_positions(const stc_handle* h, int64_t* pos);
+   The identity on the uniform grid.  *align (if not null) receives the
+   grid's stc_opts.align (0 for the uniform grid). */
+int stc_get_grid_positions(const stc_handle* h, int64_t* pos, int64_t* align);
 
 /* Copy the last single factor to the host, in stc_get_L_pattern order
    (h_Lx double[nnz(L)]); synchronizes the stream. */

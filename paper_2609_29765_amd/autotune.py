@@ -1,4 +1,4 @@
-"""Tile-size / storage-mode autotuner.
+"""Tile-size / storage-mode / tile-grid autotuner.
 
 The paper fixes n_b per regime by hand (80 by default, 120 for structured
 sparse problems on its CPU nodes; 512 and beyond on its GPU, Sec. 6.1 and
@@ -7,13 +7,15 @@ pattern is analysed at every candidate (n_b, storage mode), each candidate's
 captured schedule is replayed on the caller's own values (one value set, or
 the whole batch), and the fastest is kept.  The ordering is computed once, at
 the first candidate, and handed to the others as a given permutation, so the
-candidates differ only in their tiling and schedule.
+candidates differ only in their tiling and schedule.  Besides n_b the grid
+itself is a candidate axis: uniform, or aligned to the elimination tree with
+subtrees of at least a given multiple of n_b starting on tile boundaries.
 """
 from . import stc
 
 
 def autotune(n, colptr, rowind, values, nbs=(64, 128, 256), modes=("auto",), ordering="auto",
-             batched=False, trials=3, warmup=1, objective="factorize", slots=(0,)):
+             batched=False, trials=3, warmup=1, objective="factorize", slots=(0,), aligns=(0,)):
     """Return (best Analysis, bound; table of every candidate).
 
     values: device float64 [nnz] (batched=False) or [B, nnz] (batched=True).
@@ -21,7 +23,10 @@ def autotune(n, colptr, rowind, values, nbs=(64, 128, 256), modes=("auto",), ord
     a factorization followed by the logdet reverse mode (the unit of work of
     a gradient-based fit).
     slots: candidate wg_slots of the schedule (0 = the library default).
-    Each table row: nb, mode, wg_slots, ms per call, levels, tile flops.
+    aligns: candidate tile grids as multiples of n_b (0 = the uniform grid;
+    a > 0 aligns every subtree of at least a * n_b consecutive columns).
+    Each table row: nb, mode, wg_slots, align (columns), ms per call, levels,
+    tile flops.
     Candidates that lose release their workspace.
     """
     import torch
@@ -29,12 +34,13 @@ def autotune(n, colptr, rowind, values, nbs=(64, 128, 256), modes=("auto",), ord
     perm = None
     best = None
     table = []
-    for nb, mode, ws in ((nb, mode, ws) for nb in nbs for mode in modes for ws in slots):
+    for nb, mode, ws, al in ((nb, mode, ws, al) for nb in nbs for mode in modes for ws in slots for al in aligns):
         if perm is None:
-            a = stc.Analysis(n, colptr, rowind, nb=nb, mode=mode, ordering=ordering, wg_slots=ws)
+            a = stc.Analysis(n, colptr, rowind, nb=nb, mode=mode, ordering=ordering, wg_slots=ws, align=al * nb)
             perm = a.perm()
         else:
-            a = stc.Analysis(n, colptr, rowind, nb=nb, mode=mode, ordering="given", perm=perm, wg_slots=ws)
+            a = stc.Analysis(n, colptr, rowind, nb=nb, mode=mode, ordering="given", perm=perm, wg_slots=ws,
+                             align=al * nb)
         a.bind(batch=values.shape[0] if batched else 1)
 
         one = torch.ones(1, dtype=torch.float64, device=values.device)
@@ -58,7 +64,7 @@ def autotune(n, colptr, rowind, values, nbs=(64, 128, 256), modes=("auto",), ord
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / trials
-        table.append(dict(nb=a.nb, mode=a.mode, wg_slots=ws, ms=round(ms, 4), levels=a.nlevels,
+        table.append(dict(nb=a.nb, mode=a.mode, wg_slots=ws, align=al * nb, ms=round(ms, 4), levels=a.nlevels,
                           tile_gflop=round(a.work()["flops_tile"] / 1e9, 3)))
         if best is None or ms < best[0]:
             if best is not None:

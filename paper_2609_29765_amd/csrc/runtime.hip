@@ -1227,9 +1227,10 @@ int stc_get_sizes(const stc_handle* h, int64_t* z) {
   return 0;
 }
 
-int stc_get_grid_positions(const stc_handle* h, int64_t* pos) {
+int stc_get_grid_positions(const stc_handle* h, int64_t* pos, int64_t* align) {
   if (!h || !pos) return fail(STC_ERR_ARG, "null argument");
   for (int64_t j = 0; j < h->sym.n; ++j) pos[j] = grid_pos(h->sym, j);
+  if (align) *align = h->sym.align;
   return 0;
 }
 

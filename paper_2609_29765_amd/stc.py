@@ -79,7 +79,7 @@ def lib():
     L.stc_get_L_pattern.argtypes = [vp, _i64p, _i32p]
     L.stc_get_tiles.argtypes = [vp, _i32p, _i32p, _i32p, _i32p, _i8p, _i64p, _i32p, _i32p]
     L.stc_get_tasks.argtypes = [vp, _i32p]
-    L.stc_get_grid_positions.argtypes = [vp, _i64p]
+    L.stc_get_grid_positions.argtypes = [vp, _i64p, C.POINTER(C.c_int64)]
     L.stc_get_factor.argtypes = [vp, _f64p, vp]
     L.stc_get_batch_factor.argtypes = [vp, C.c_int32, _f64p, vp]
     L.stc_get_work.argtypes = [vp, _f64p]
@@ -205,8 +205,16 @@ class Analysis:
     def grid_positions(self):
         """Tile-grid position of every column of P A P^T (stc_get_grid_positions)."""
         p = np.zeros(self.n, np.int64)
-        _check(lib().stc_get_grid_positions(self._h, p))
+        _check(lib().stc_get_grid_positions(self._h, p, None))
         return p
+
+    @property
+    def align(self):
+        """stc_opts.align of the analysis (0: the uniform grid)."""
+        p = np.zeros(self.n, np.int64)
+        al = C.c_int64(0)
+        _check(lib().stc_get_grid_positions(self._h, p, C.byref(al)))
+        return int(al.value)
 
     def tasks(self):
         t = np.zeros((max(self.ntasks, 1), 4), np.int32)

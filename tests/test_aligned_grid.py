@@ -149,7 +149,7 @@ def test_workloads_full_size_aligned(name, nb, align):
          "c3": lambda: W.spatiotemporal_arrowhead()}[name]()
     a, o = _compare(w, "nd", nb, align=align)
     u = S.Analysis(w.n, w.colptr, w.rowind, nb=nb, ordering="nd")
-    assert a.NT > u.NT  # padded
+    assert a.NT > u.NT and a.align == align and u.align == 0  # padded
     assert (a.phi, a.rho, a.sigma, a.route, a.mode, a.tact) == (u.phi, u.rho, u.sigma, u.route, u.mode, u.tact)
     # the tile DAG is far shallower than on the uniform grid
     assert a.nlevels < u.nlevels / 2

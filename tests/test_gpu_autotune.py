@@ -37,6 +37,24 @@ def test_autotune_tiles_modes_and_slots():
     factor_close(a.factor(), Lo, lp)
 
 
+def test_autotune_tile_grids():
+    """The grid axis: uniform and two aligned grids per tile size; every
+    candidate is reported with its alignment in columns, the winner is the
+    fastest row, and its factorization matches the oracle."""
+    w = W.differentiable_arrowhead(12, 20, 8, 0)
+    v = torch.from_numpy(w.values).cuda()
+    a, table = autotune(w.n, w.colptr, w.rowind, v, nbs=(32, 64), ordering="nd", trials=2, aligns=(0, 2, 4))
+    assert {(r["nb"], r["align"]) for r in table} == {(nb, f * nb) for nb in (32, 64) for f in (0, 2, 4)}
+    best = min(table, key=lambda r: r["ms"])
+    assert (a.nb, a.align, a.nlevels) == (best["nb"], best["align"], best["levels"])
+    a.factorize(v)
+    assert a.info() == 0
+    o = O.Analysis(w.n, w.colptr, w.rowind, "given", nb=a.nb, mode=a.mode, perm=a.perm())
+    Lo, info = o.factor(w.values)
+    assert info == 0
+    factor_close(a.factor(), Lo, o.L_pattern()[0])
+
+
 def test_autotune_batched_objective():
     w = W.batched_laplacian3d(m=10, B=4, seed=0)
     V = torch.from_numpy(w.values).cuda()

@@ -50,10 +50,10 @@ def oracle_factor(key, w, ordering, nb, values=None):
     return _ORACLE[key]
 
 
-def gpu_vs_oracle(w, ordering, nb, key, wg_slots=0, solve=False):
+def gpu_vs_oracle(w, ordering, nb, key, wg_slots=0, solve=False, align=0):
     o, Lo = oracle_factor(key, w, ordering, nb)
-    a = S.Analysis(w.n, w.colptr, w.rowind, nb=nb, ordering=ordering, wg_slots=wg_slots).bind()
-    print(f"[gpu] {key} wg_slots={wg_slots} {a.plan_stats()}", flush=True)
+    a = S.Analysis(w.n, w.colptr, w.rowind, nb=nb, ordering=ordering, wg_slots=wg_slots, align=align).bind()
+    print(f"[gpu] {key} wg_slots={wg_slots} align={align} {a.plan_stats()}", flush=True)
     a.factorize(dev(w.values))
     assert a.info() == 0
     lp, _ = o.L_pattern()
@@ -97,6 +97,15 @@ def test_c3_full_entrywise():
     the bench times (the oracle takes one to two minutes here)."""
     w = W.spatiotemporal_arrowhead()
     gpu_vs_oracle(w, "nd", 128, "c3nb128", solve=True)
+
+
+@pytest.mark.timeout(900)
+def test_c3_full_entrywise_aligned_grid():
+    """The same matrix on the grid aligned to subtrees of 512 columns (the
+    factor's values do not depend on the grid: same oracle factor)."""
+    w = W.spatiotemporal_arrowhead()
+    a = gpu_vs_oracle(w, "nd", 128, "c3nb128", solve=True, align=512)
+    assert a.align == 512 and a.NT > (w.n + 127) // 128
 
 
 def test_c4_members_entrywise():
