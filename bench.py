@@ -40,8 +40,8 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 matrix peak (published)
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E (published)
 # tile grids the extras' autotuner tries, as multiples of the tile size: the
-# uniform grid and grids aligned to elimination subtrees of 2, 4 and 8 tiles
-GRID_ALIGNS = (0, 2, 4, 8)
+# uniform grid and grids aligned to elimination subtrees of 1, 2, 4 and 8 tiles
+GRID_ALIGNS = (0, 1, 2, 4, 8)
 KERNEL_SOURCES = ["paper_2609_29765_amd/csrc/kernels.hpp", "paper_2609_29765_amd/csrc/device_types.hpp",
                   "paper_2609_29765_amd/csrc/runtime.hip", "paper_2609_29765_amd/csrc/analyse.cpp"]
 
@@ -330,14 +330,14 @@ def extra_gmrf():
 
 
 def extra_semisparse():
-    """Spatio-temporal arrowhead, n = 101,258: tile size tuned over 128/256."""
+    """Spatio-temporal arrowhead, n = 101,258: tile size (64, 128, 256) and grid tuned."""
     import torch
     from paper_2609_29765_amd import workloads
     from paper_2609_29765_amd.autotune import autotune
     w = workloads.spatiotemporal_arrowhead()
     v = torch.from_numpy(w.values).cuda()
     t0 = time.time()
-    a, table = autotune(w.n, w.colptr, w.rowind, v, nbs=(128, 256), ordering="nd", trials=3, aligns=GRID_ALIGNS)
+    a, table = autotune(w.n, w.colptr, w.rowind, v, nbs=(64, 128, 256), ordering="nd", trials=3, aligns=GRID_ALIGNS)
     t_tune = time.time() - t0
     ms = timed(lambda: a.factorize(v), 10)
     assert a.info() == 0
