@@ -42,6 +42,9 @@ PEAK_HBM_GBS = 8000.0     # MI355X HBM3E (published)
 # tile grids the extras' autotuner tries, as multiples of the tile size: the
 # uniform grid and grids aligned to elimination subtrees of 1, 2, 4 and 8 tiles
 GRID_ALIGNS = (0, 1, 2, 4, 8)
+# weights of a partial-slot fold in the split-K cost model (percent of the
+# measured one) tried on the best grid
+FOLD_PCTS = (0, 50, 200, 300)
 KERNEL_SOURCES = ["paper_2609_29765_amd/csrc/kernels.hpp", "paper_2609_29765_amd/csrc/device_types.hpp",
                   "paper_2609_29765_amd/csrc/runtime.hip", "paper_2609_29765_amd/csrc/analyse.cpp"]
 
@@ -92,9 +95,9 @@ def log(msg):
 # headline: dense route, n = 12288, tile 256
 # ---------------------------------------------------------------------------
 
-def semisparse_pass(align):
+def semisparse_pass(align, nb=128):
     """Counter runs over the active-column route: the spatio-temporal
-    arrowhead (n = 101,258, tile 128, ND, grid aligned to subtrees of `align`
+    arrowhead (n = 101,258, tile nb, ND, grid aligned to subtrees of `align`
     columns, 0 = uniform) factorized once through the graph and
     once kernel by kernel (one launch per level and kernel kind, the launches
     the per-kind figures charge), then a plain 1 GiB device copy whose counter
@@ -105,7 +108,7 @@ def semisparse_pass(align):
     from paper_2609_29765_amd import workloads
     w = workloads.spatiotemporal_arrowhead()
     v = torch.from_numpy(w.values).cuda()
-    a = stc.Analysis(w.n, w.colptr, w.rowind, nb=128, ordering="nd", align=align).bind()
+    a = stc.Analysis(w.n, w.colptr, w.rowind, nb=nb, ordering="nd", align=align).bind()
     a.factorize(v)
     torch.cuda.synchronize()
     assert a.info() == 0
@@ -115,14 +118,14 @@ def semisparse_pass(align):
     x.fill_(1.0)
     y.copy_(x)
     torch.cuda.synchronize()
-    print(json.dumps({"workload": f"spatio-temporal arrowhead n=101258, tile 128, ND, grid align {align}", "work": a.work(),
+    print(json.dumps({"workload": f"spatio-temporal arrowhead n=101258, tile {nb}, ND, grid align {align}", "work": a.work(),
                       "kinds": {k: {"ms": ms, "launches": c, "flops": f} for k, (ms, c, f) in prof.items()}}),
           flush=True)
 
 
-def solve_pass(align):
+def solve_pass(align, nb=128):
     """Kernel-trace runs over the solve: the spatio-temporal arrowhead
-    (n = 101,258, tile 128, ND, grid alignment `align`) factorized once, then three solves with one
+    (n = 101,258, tile nb, ND, grid alignment `align`) factorized once, then three solves with one
     right-hand side and three with eight, each group's sweeps replayed from
     its graph (the first call of a group captures it).  Prints one JSON line
     with the event-timed solves and the sweeps' launch count."""
@@ -131,7 +134,7 @@ def solve_pass(align):
     from paper_2609_29765_amd import workloads
     w = workloads.spatiotemporal_arrowhead()
     v = torch.from_numpy(w.values).cuda()
-    a = stc.Analysis(w.n, w.colptr, w.rowind, nb=128, ordering="nd", align=align).bind()
+    a = stc.Analysis(w.n, w.colptr, w.rowind, nb=nb, ordering="nd", align=align).bind()
     a.factorize(v)
     torch.cuda.synchronize()
     assert a.info() == 0
@@ -149,7 +152,7 @@ def solve_pass(align):
             torch.cuda.synchronize()
             ms.append(e0.elapsed_time(e1))
         out[f"solve_{nrhs}rhs_ms"] = [round(x, 3) for x in ms]
-    print(json.dumps({"workload": f"spatio-temporal arrowhead n=101258, tile 128, ND, grid align {align}",
+    print(json.dumps({"workload": f"spatio-temporal arrowhead n=101258, tile {nb}, ND, grid align {align}",
                       "sweep_launches": a.solve_launches, **out}), flush=True)
 
 
@@ -337,7 +340,8 @@ def extra_semisparse():
     w = workloads.spatiotemporal_arrowhead()
     v = torch.from_numpy(w.values).cuda()
     t0 = time.time()
-    a, table = autotune(w.n, w.colptr, w.rowind, v, nbs=(64, 128, 256), ordering="nd", trials=3, aligns=GRID_ALIGNS)
+    a, table = autotune(w.n, w.colptr, w.rowind, v, nbs=(64, 128, 256), ordering="nd", trials=3, aligns=GRID_ALIGNS,
+                        folds=FOLD_PCTS)
     t_tune = time.time() - t0
     ms = timed(lambda: a.factorize(v), 10)
     assert a.info() == 0
@@ -363,7 +367,7 @@ def extra_batched(B):
     w = workloads.batched_laplacian3d(m=24, B=B, seed=0)
     V = torch.from_numpy(w.values).cuda()
     a, table = autotune(w.n, w.colptr, w.rowind, V, nbs=(64, 128), ordering="nd", batched=True, trials=2,
-                        aligns=GRID_ALIGNS)
+                        aligns=GRID_ALIGNS, folds=FOLD_PCTS)
     ms_batched = timed(lambda: a.factorize_batched(V), 3)
     ld_b, info = a.factorize_batched(V)
     assert int(info.abs().sum().item()) == 0
@@ -395,7 +399,7 @@ def extra_backward():
     w = workloads.differentiable_arrowhead(20, 25, 8, 0)
     v = torch.from_numpy(w.values).cuda()
     a, table = autotune(w.n, w.colptr, w.rowind, v, nbs=(32, 64, 128), ordering="nd", trials=3,
-                        objective="logdet_grad", aligns=GRID_ALIGNS)
+                        objective="logdet_grad", aligns=GRID_ALIGNS, folds=FOLD_PCTS)
     one = torch.ones(1, dtype=torch.float64, device="cuda")
     dv = torch.from_numpy(w.dvalues).cuda()
 
@@ -763,6 +767,7 @@ def main():
                          "for counter runs over the active-column route")
     ap.add_argument("--pass-align", type=int, default=512,
                     help="tile-grid alignment (columns, 0 = uniform grid) of --solve-pass and --semisparse-pass")
+    ap.add_argument("--pass-nb", type=int, default=128, help="tile size of --solve-pass and --semisparse-pass")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration runs)")
     ap.add_argument("--summarize-trace", default=None, metavar="DIR",
@@ -791,10 +796,10 @@ def main():
         run_extras(args.extras_out, args.batch)
         return
     if args.solve_pass:
-        solve_pass(args.pass_align)
+        solve_pass(args.pass_align, args.pass_nb)
         return
     if args.semisparse_pass:
-        semisparse_pass(args.pass_align)
+        semisparse_pass(args.pass_align, args.pass_nb)
         return
 
     import torch

@@ -99,6 +99,11 @@ typedef struct {
                             features, the route and the factor's values are
                             those of the uniform grid; tiles, tasks and the
                             schedule follow the aligned grid.                  */
+  int32_t max_split;     /* schedule: most work-groups one update task's K
+                            stream is split over (1-64; 0 = 64)               */
+  int32_t fold_pct;      /* schedule: weight, in percent of the measured cost,
+                            that the split's cost model gives to folding one
+                            partial slot (0 = 100).  Both change timing only. */
 } stc_opts;
 
 /* Analyse a sparsity pattern once (Sec. 3, Sec. 5.1-5.2).

@@ -15,7 +15,7 @@ from . import stc
 
 
 def autotune(n, colptr, rowind, values, nbs=(64, 128, 256), modes=("auto",), ordering="auto",
-             batched=False, trials=3, warmup=1, objective="factorize", slots=(0,), aligns=(0,)):
+             batched=False, trials=3, warmup=1, objective="factorize", slots=(0,), aligns=(0,), folds=(0,)):
     """Return (best Analysis, bound; table of every candidate).
 
     values: device float64 [nnz] (batched=False) or [B, nnz] (batched=True).
@@ -25,8 +25,11 @@ def autotune(n, colptr, rowind, values, nbs=(64, 128, 256), modes=("auto",), ord
     slots: candidate wg_slots of the schedule (0 = the library default).
     aligns: candidate tile grids as multiples of n_b (0 = the uniform grid;
     a > 0 aligns every subtree of at least a * n_b consecutive columns).
-    Each table row: nb, mode, wg_slots, align (columns), ms per call, levels,
-    tile flops.
+    folds: fold_pct values (the split-K cost model's weight of a fold, 0 =
+    the library default) tried in a second round on the best candidate of
+    the first.
+    Each table row: nb, mode, wg_slots, align (columns), fold_pct, ms per
+    call, levels, tile flops.
     Candidates that lose release their workspace.
     """
     import torch
@@ -34,13 +37,15 @@ def autotune(n, colptr, rowind, values, nbs=(64, 128, 256), modes=("auto",), ord
     perm = None
     best = None
     table = []
-    for nb, mode, ws, al in ((nb, mode, ws, al) for nb in nbs for mode in modes for ws in slots for al in aligns):
+
+    def trial(nb, mode, ws, al, fp):
+        nonlocal perm, best
+        kw = dict(nb=nb, mode=mode, wg_slots=ws, align=al * nb, fold_pct=fp)
         if perm is None:
-            a = stc.Analysis(n, colptr, rowind, nb=nb, mode=mode, ordering=ordering, wg_slots=ws, align=al * nb)
+            a = stc.Analysis(n, colptr, rowind, ordering=ordering, **kw)
             perm = a.perm()
         else:
-            a = stc.Analysis(n, colptr, rowind, nb=nb, mode=mode, ordering="given", perm=perm, wg_slots=ws,
-                             align=al * nb)
+            a = stc.Analysis(n, colptr, rowind, ordering="given", perm=perm, **kw)
         a.bind(batch=values.shape[0] if batched else 1)
 
         one = torch.ones(1, dtype=torch.float64, device=values.device)
@@ -64,12 +69,18 @@ def autotune(n, colptr, rowind, values, nbs=(64, 128, 256), modes=("auto",), ord
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / trials
-        table.append(dict(nb=a.nb, mode=a.mode, wg_slots=ws, align=al * nb, ms=round(ms, 4), levels=a.nlevels,
-                          tile_gflop=round(a.work()["flops_tile"] / 1e9, 3)))
+        table.append(dict(nb=a.nb, mode=a.mode, wg_slots=ws, align=al * nb, fold_pct=fp, ms=round(ms, 4),
+                          levels=a.nlevels, tile_gflop=round(a.work()["flops_tile"] / 1e9, 3)))
         if best is None or ms < best[0]:
             if best is not None:
                 best[1].release()
-            best = (ms, a)
+            best = (ms, a, (nb, mode, ws, al))
         else:
             a.release()
+
+    for nb, mode, ws, al in ((nb, mode, ws, al) for nb in nbs for mode in modes for ws in slots for al in aligns):
+        trial(nb, mode, ws, al, folds[0])
+    nb, mode, ws, al = best[2]
+    for fp in folds[1:]:
+        trial(nb, mode, ws, al, fp)
     return best[1], table

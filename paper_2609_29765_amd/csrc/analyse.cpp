@@ -624,12 +624,15 @@ void align_tiles(Symbolic* s, int64_t min_subtree) {
 // execution plan
 // ---------------------------------------------------------------------------
 
-int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std::string* why) {
+int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std::string* why, int max_split,
+               int fold_pct) {
   const int32_t nb = s.nb, NT = s.NT;
   const int64_t n = s.n;
   (void)why;
   *p = Plan();
   if (wg_slots > 0) p->wg_slots = wg_slots;
+  if (max_split > 0) p->max_split = max_split;
+  if (fold_pct > 0) p->fold_pct = fold_pct;
   p->nb = nb;
   p->NT = NT;
   p->bm = bm;
@@ -874,7 +877,8 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std
     // kMinPart steps, and parts s > 0 leave partial slots that the task's
     // partner (its tile's next update, at a later level) folds in.  A
     // level's split is chosen among two families -- every splittable task
-    // in s parts (s = 1..16), or every splittable task cut into parts of at
+    // in s parts (s = 1..16, then every 4th up to 32 and every 8th up to
+    // max_split), or every splittable task cut into parts of at
     // most 8 t steps (t = 1..16) -- by the estimated makespan of the level
     // plus those of the levels holding the partners it affects.  Makespans
     // come from simulating longest-first list scheduling of a level's items
@@ -884,16 +888,18 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std
     // contribution is a quarter; the epilogue costs a quarter, and each
     // folded partial slot 0.45 (128-block) or 0.12 (64-block) -- measured
     // on MI355X, where folding a 128-block slot takes about half the time of
-    // one contribution.
+    // one contribution -- times fold_pct percent (a schedule option: how
+    // much a fold costs depends on how loaded the device is around it).
     (void)items;
     const int64_t ksteps = std::max<int64_t>(1, nb / 16);
     constexpr int64_t kMinPart = 8;
     auto steps_of = [&](const UpdTask& u) { return (int64_t)(u.c_end - u.c_begin) * ksteps; };
     auto max_parts = [&](const UpdTask& u) -> int32_t {
-      return u.partner >= 0 ? (int32_t)std::max<int64_t>(1, std::min<int64_t>(16, steps_of(u) / kMinPart)) : 1;
+      return u.partner >= 0 ? (int32_t)std::max<int64_t>(1, std::min<int64_t>(p->max_split, steps_of(u) / kMinPart)) : 1;
     };
     auto dur = [&](const UpdTask& u, int64_t steps_part) {
-      return (u.big ? 1.0 : 0.25) * (double)steps_part / (double)ksteps + 0.25 + (u.big ? 0.45 : 0.12) * u.in_npart;
+      return (u.big ? 1.0 : 0.25) * (double)steps_part / (double)ksteps + 0.25 +
+             (u.big ? 0.45 : 0.12) * 0.01 * p->fold_pct * u.in_npart;
     };
     std::vector<std::vector<int32_t>> lev_tasks((size_t)nlev);
     for (int32_t id = 0; id < (int32_t)p->upd.size(); ++id) lev_tasks[(size_t)p->upd[(size_t)id].level].push_back(id);
@@ -948,7 +954,7 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std
         plev.erase(std::unique(plev.begin(), plev.end()), plev.end());
         double best = 1e300;
         for (int32_t fam = 0; fam < 2; ++fam)
-          for (int32_t c = 1; c <= 16; ++c) {
+          for (int32_t c = 1; c <= (fam == 0 ? std::max<int32_t>(16, p->max_split) : 16); c += (c < 16 ? 1 : c < 32 ? 4 : 8)) {
             cand.assign(ids.size(), 1);
             for (size_t x = 0; x < ids.size(); ++x) {
               const UpdTask& u = p->upd[(size_t)ids[x]];

@@ -126,6 +126,8 @@ struct Level {
 struct Plan {
   int32_t nb = 64, NT = 0;
   int64_t wg_slots = 448;  // concurrent update work-groups the split balances for
+  int32_t max_split = 64;  // most work-groups one early group's K stream is split over
+  int32_t fold_pct = 100;  // weight of folding a partial slot in the split's cost model, percent of the measured
   int32_t bm = 64;          // small update block (rows and columns)
   int64_t parts = 0;        // doubles of partial-sum slots per value set
   int32_t br = 32;          // rows per TRSM work item
@@ -156,7 +158,8 @@ struct Plan {
 
 // wg_slots: concurrent update work-groups the per-level split of long
 // contribution ranges is balanced for (0 = 448, measured best on MI355X)
-int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std::string* why);
+int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std::string* why, int max_split = 0,
+               int fold_pct = 0);
 
 // The kernels of the level schedule as a dependency graph, in place of a
 // barrier between consecutive levels: node (level, kind) with kind 0 POTRF,

@@ -23,7 +23,7 @@ namespace stc {
 namespace {
 
 constexpr char kMagic[8] = {'S', 'T', 'C', 'P', 'L', 'A', 'N', '\0'};
-constexpr uint32_t kVersion = 2;
+constexpr uint32_t kVersion = 3;
 
 // running checksum over a field's bytes: 64-bit words, then the tail
 uint64_t mix(uint64_t h, const char* c, size_t n) {
@@ -73,7 +73,7 @@ void fields(A& a, Level& l) {
 
 template <class A>
 void fields(A& a, Plan& p) {
-  a(p.nb); a(p.NT); a(p.wg_slots); a(p.bm); a(p.parts); a(p.br); a(p.store); a(p.tile_off); a(p.vmap);
+  a(p.nb); a(p.NT); a(p.wg_slots); a(p.max_split); a(p.fold_pct); a(p.bm); a(p.parts); a(p.br); a(p.store); a(p.tile_off); a(p.vmap);
   a(p.maps); a(p.diag_h); a(p.tile_imap); a(p.contribs); a(p.upd); a(p.trsm); a(p.levels);
   a(p.row_tiles_ptr); a(p.row_tiles); a(p.col_tiles_ptr); a(p.col_tiles); a(p.fwd_level_ptr);
   a(p.fwd_level_blk); a(p.bwd_level_ptr); a(p.bwd_level_blk); a(p.flops_tile); a(p.flops_update);

@@ -881,13 +881,15 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
                 stc_handle** out) {
   if (!out) return fail(STC_ERR_ARG, "null output handle");
   *out = nullptr;
-  stc_opts o{64, STC_MODE_AUTO, STC_ORD_AUTO, nullptr, 0, 0};
+  stc_opts o{64, STC_MODE_AUTO, STC_ORD_AUTO, nullptr, 0, 0, 0, 0};
   if (opts) o = *opts;
   if (o.nb == 0) o.nb = 64;
   if (o.nb != 32 && o.nb != 64 && o.nb != 128 && o.nb != 256)
     return fail(STC_ERR_ARG, "nb must be 32, 64, 128 or 256");
   if (o.wg_slots < 0) return fail(STC_ERR_ARG, "wg_slots must be >= 0");
   if (o.align < 0) return fail(STC_ERR_ARG, "align must be >= 0");
+  if (o.max_split < 0 || o.max_split > 64 || o.fold_pct < 0)
+    return fail(STC_ERR_ARG, "max_split must be in [0, 64] and fold_pct >= 0");
   try {
     auto* h = new stc_handle();
     std::string why;
@@ -901,7 +903,7 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
       delete h;
       return fail(STC_ERR_ARG, "more than 2^31 - 1 input entries or grid positions");
     }
-    rc = build_plan(h->sym, UB, TR, o.wg_slots, &h->plan, &why);
+    rc = build_plan(h->sym, UB, TR, o.wg_slots, &h->plan, &why, o.max_split, o.fold_pct);
     if (rc == 0) rc = build_backward(h->sym, &h->plan, &h->back, &why);
     if (rc) {
       delete h;

@@ -55,6 +55,23 @@ def test_autotune_tile_grids():
     factor_close(a.factor(), Lo, o.L_pattern()[0])
 
 
+def test_autotune_fold_weight_round():
+    """The second round tries each fold weight on the first round's winner
+    only; the returned analysis is the fastest row."""
+    w = W.differentiable_arrowhead(12, 20, 8, 0)
+    v = torch.from_numpy(w.values).cuda()
+    a, table = autotune(w.n, w.colptr, w.rowind, v, nbs=(32, 64), ordering="nd", trials=2, aligns=(0, 2),
+                        folds=(0, 50, 300))
+    assert len(table) == 2 * 2 + 2
+    first = min(table[:4], key=lambda r: r["ms"])
+    assert all((r["nb"], r["align"]) == (first["nb"], first["align"]) for r in table[4:])
+    assert [r["fold_pct"] for r in table[4:]] == [50, 300]
+    best = min(table, key=lambda r: r["ms"])
+    assert (a.nb, a.align, a.nlevels) == (best["nb"], best["align"], best["levels"])
+    a.factorize(v)
+    assert a.info() == 0
+
+
 def test_autotune_batched_objective():
     w = W.batched_laplacian3d(m=10, B=4, seed=0)
     V = torch.from_numpy(w.values).cuda()

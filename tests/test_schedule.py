@@ -26,8 +26,8 @@ from paper_2609_29765_amd import stc as S  # noqa: E402
 from paper_2609_29765_amd import workloads as W  # noqa: E402
 
 
-def _check(w, nb, ordering, mode="auto", wg_slots=0):
-    a = S.Analysis(w.n, w.colptr, w.rowind, nb=nb, mode=mode, ordering=ordering, wg_slots=wg_slots)
+def _check(w, nb, ordering, mode="auto", wg_slots=0, **kw):
+    a = S.Analysis(w.n, w.colptr, w.rowind, nb=nb, mode=mode, ordering=ordering, wg_slots=wg_slots, **kw)
     st = a.check_schedule()
     assert st["nodes"] >= 1 and st["objects"] >= 1
     assert st["edges"] >= st["nodes"] - 1 - st["unordered_pairs"] or st["nodes"] == 1
@@ -67,3 +67,30 @@ def test_bordered_and_batched_patterns():
     _check(W.spatiotemporal_arrowhead(T=10, m=20, nborder=8), 64, "nd", wg_slots=8)
     _check(W.differentiable_arrowhead(6, 10, 8, 0), 32, "nd")
     _check(W.batched_laplacian3d(m=10, B=2), 64, "nd", wg_slots=4)
+
+
+@pytest.mark.parametrize("max_split,fold_pct", [(1, 0), (4, 50), (16, 300), (64, 50), (64, 0)])
+def test_split_cap_and_fold_weight(max_split, fold_pct):
+    """The split-K schedule options on aligned and uniform grids: every plan
+    passes both checks; a cap of 1 splits nothing; no split exceeds the cap
+    (partial slots per split task <= cap - 1)."""
+    w = W.spatiotemporal_arrowhead(T=12, m=20, nborder=8)
+    for align in (0, 128):
+        st = _check(w, 64, "nd", wg_slots=16, align=align, max_split=max_split, fold_pct=fold_pct)
+        a = S.Analysis(w.n, w.colptr, w.rowind, nb=64, ordering="nd", wg_slots=16, align=align,
+                       max_split=max_split, fold_pct=fold_pct)
+        ps = a.plan_stats()
+        if max_split == 1:
+            assert ps["split_tasks"] == 0 and ps["partial_doubles"] == 0
+        else:
+            assert ps["split_tasks"] > 0
+        cap = max_split or 64  # each split task holds (parts - 1) slots of at most 64 x 64 doubles
+        assert ps["partial_doubles"] <= ps["split_tasks"] * (cap - 1) * 64 * 64
+        assert st["nodes"] == ps["graph_kernels"]
+
+
+def test_schedule_options_rejected():
+    w = W.gmrf_grid2d(8, 8, 0.1, 0)
+    for kw in (dict(max_split=-1), dict(max_split=65), dict(fold_pct=-5)):
+        with pytest.raises(S.STCError):
+            S.Analysis(w.n, w.colptr, w.rowind, nb=32, ordering="nd", **kw)
