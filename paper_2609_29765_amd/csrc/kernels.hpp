@@ -118,6 +118,7 @@ constexpr int UB = 64;   // output block
 constexpr int UKT = 16;  // K chunk staged in LDS
 constexpr int USTAGE = 2 * UB * DLD;  // A and B rows of one K chunk
 constexpr int UPD_LDS = 2 * USTAGE;   // two stages
+static_assert(UPD_LDS >= 2 * 32 * UB, "the partial-slot fold streams two 32-row chunks through the stages");
 
 template <int NB, bool CULL>
 __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict__ items,
@@ -131,13 +132,54 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
   const UpdTaskD u = tasks[task];
   const int32_t r0 = bx * UB, c0 = by * UB;
   const int32_t ncols = u.diag ? u.c_rows : NB;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: branches on a wave's rows are scalar
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
 
   d4 acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
+  // the partial slots of the split parts first (in slot order): the
+  // accumulators start as their sum, streamed through LDS (before the K
+  // loop uses it) in chunks of 32 rows x 64 columns:
+  // each wave brings two rows per load instruction straight from global
+  // memory, the next chunk's loads fly while the waves owning the current
+  // chunk's rows add it, so a slot costs about one memory round trip
+  // whatever its rows.  Rows past the tile read its last row and columns past
+  // the block's real ones read the slot's own row: neither reaches a stored
+  // value.
+  if (part == 0 && u.in_npart > 0) {
+    const int64_t slot = (int64_t)u.c_rows * NB;
+    const int32_t nch = 2 * u.in_npart;
+    auto load_chunk = [&](int32_t t) {
+      const double* base = parts + u.in_part_off + (int64_t)(t >> 1) * slot;
+      double* buf = smem + (t & 1) * (32 * UB);
+#pragma unroll
+      for (int y = 0; y < 4; ++y) {
+        const int pr = 4 * y + wave;  // rows 2 pr and 2 pr + 1 of the chunk
+        const int32_t i = min(r0 + 32 * (t & 1) + 2 * pr + (lane >> 5), u.c_rows - 1);
+        __builtin_amdgcn_global_load_lds((gvoid_t*)(base + (int64_t)i * NB + c0 + 2 * (lane & 31)),
+                                         (lvoid_t*)(buf + 2 * pr * UB), 16, 0, 0);
+      }
+    };
+    load_chunk(0);
+    for (int32_t t = 0; t < nch; ++t) {
+      __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0): this wave's loads of chunk t are in LDS
+      __syncthreads();  // everyone's are, and chunk t - 1 has been added
+      if (t + 1 < nch) load_chunk(t + 1);
+      if ((t & 1) == (wr >> 5)) {
+        const double* buf = smem + (t & 1) * (32 * UB);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              acc[a][b][e] += buf[(a * 16 + (lane >> 4) + 4 * e) * UB + wc + b * 16 + (lane & 15)];
+      }
+    }
+    __syncthreads();  // every wave has added the last chunk: the stages are free
+  }
   // one stream of (contribution, 16-wide K chunk) steps through two LDS
   // stages: wave w fills rows 16 w + 8 j + lane / 8 (j = 0, 1) of A and of
   // B, lane l bringing the pair (l % 8) ^ key(row); a step's loads are issued
@@ -250,19 +292,6 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
         }
     return;
   }
-  for (int q = 0; q < u.in_npart; ++q) {
-    const double* pq = parts + u.in_part_off + q * slot;
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int32_t i = min(r0 + wr + a * 16 + (lane >> 4) + 4 * e, u.c_rows - 1);
-          const int32_t j = min(c0 + wc + b * 16 + (lane & 15), ncols - 1);
-          acc[a][b][e] += pq[(int64_t)i * NB + j];
-        }
-  }
   double cv[2][2][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -299,6 +328,7 @@ constexpr int UB2 = 128;
 constexpr int UKT2 = 16;
 constexpr int DSTAGE = 2 * UB2 * DLD;      // A and B rows of one K chunk
 constexpr int UPD2_LDS = 2 * DSTAGE;       // two stages
+static_assert(UPD2_LDS >= 2 * 32 * UB2, "the partial-slot fold streams two 32-row chunks through the stages");
 
 template <int NB, bool CULL>
 __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __restrict__ items,
@@ -312,7 +342,7 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
   const UpdTaskD u = tasks[task];
   const int32_t r0 = bx * UB2, c0 = by * UB2;
   const int32_t ncols = u.diag ? u.c_rows : NB;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: branches on a wave's rows are scalar
   const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
 
   d4 acc[4][4];
@@ -321,6 +351,49 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
+  // the partial slots of the split parts first (in slot order): the
+  // accumulators start as their sum, streamed through LDS before the K loop
+  // uses it.  Chunk c of a slot holds row block
+  // a = c of both halves of the block (rows 16 c .. 16 c + 15 and
+  // 64 + 16 c .. 64 + 16 c + 15, 128 columns), so that every wave adds
+  // one row block of its accumulators per chunk.  Each wave brings one row
+  // per load instruction straight from global memory, and the next chunk's
+  // loads fly while the current one is added.  Rows past the tile read its
+  // last row and columns past the block's real ones read the slot's own row:
+  // neither reaches a stored value.
+  if (part == 0 && u.in_npart > 0) {
+    const int64_t slot = (int64_t)u.c_rows * NB;
+    const int32_t nch = 4 * u.in_npart;
+    auto load_chunk = [&](int32_t t) {
+      const double* base = parts + u.in_part_off + (int64_t)(t >> 2) * slot;
+      double* buf = smem + (t & 1) * (32 * UB2);
+#pragma unroll
+      for (int x = 0; x < 8; ++x) {
+        const int lr = 4 * x + wave;  // chunk row: half lr / 16, row lr % 16 of row block t % 4
+        int32_t i = min(r0 + (lr >> 4) * 64 + 16 * (t & 3) + (lr & 15), u.c_rows - 1);
+        asm volatile("" : "+v"(i));  // formed per chunk, not hoisted out of the slot loop into live registers
+        __builtin_amdgcn_global_load_lds((gvoid_t*)(base + (int64_t)i * NB + c0 + 2 * lane),
+                                         (lvoid_t*)(buf + lr * UB2), 16, 0, 0);
+      }
+    };
+    load_chunk(0);
+    for (int32_t q = 0; q < u.in_npart; ++q) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int32_t t = 4 * q + a;
+        __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0): this wave's loads of chunk t are in LDS
+        __syncthreads();  // everyone's are, and chunk t - 1 has been added
+        if (t + 1 < nch) load_chunk(t + 1);
+        const double* buf = smem + (a & 1) * (32 * UB2) + (wr >> 6) * 16 * UB2;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            acc[a][b][e] += buf[((lane >> 4) + 4 * e) * UB2 + wc + b * 16 + (lane & 15)];
+      }
+    }
+    __syncthreads();  // every wave has added the last chunk: the stages are free
+  }
   // One stream of (contribution, 16-wide K chunk) steps.  The operand rows
   // of a step go from global memory straight into one of two LDS stages,
   // 16 bytes per lane: wave w fills rows 32 w + 8 j + lane / 8 (j = 0..3) of
@@ -441,21 +514,10 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
         }
     return;
   }
-  // one 16-row block at a time: its partial slots and C values are read
-  // together (addresses clamped into the tile), then the stores are masked
+  // one 16-row block at a time: its C values are read together (addresses
+  // clamped into the tile), then the stores are masked
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    for (int q = 0; q < u.in_npart; ++q) {
-      const double* pq = parts + u.in_part_off + q * slot;
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int32_t i = min(r0 + wr + a * 16 + (lane >> 4) + 4 * e, u.c_rows - 1);
-          const int32_t j = min(c0 + wc + b * 16 + (lane & 15), ncols - 1);
-          acc[a][b][e] += pq[(int64_t)i * NB + j];
-        }
-    }
     double cv[4][4];
 #pragma unroll
     for (int b = 0; b < 4; ++b)
