@@ -190,7 +190,8 @@ def headline(args):
         from paper_2609_29765_amd.autotune import autotune
         del a
         a, tune_table = autotune(w.n, w.colptr, w.rowind, vals, nbs=(args.nb,), ordering="natural", trials=3,
-                                 slots=tuple(int(x) for x in args.tune_slots.split(",")))
+                                 slots=tuple(int(x) for x in args.tune_slots.split(",")),
+                                 folds=tuple(int(x) for x in args.tune_folds.split(",")) if args.tune_folds else (0,))
         log(f"schedule tuning: {tune_table}")
     else:
         a.bind()
@@ -756,6 +757,8 @@ def main():
     ap.add_argument("--batch", type=int, default=128)
     ap.add_argument("--tune-slots", default="0,320,640",
                     help="wg_slots candidates the headline's schedule is tuned over (empty: no tuning)")
+    ap.add_argument("--tune-folds", default="0,50",
+                    help="fold weights (percent) of the second tuning round on the winning schedule (empty: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras-out", default=None, help=argparse.SUPPRESS)

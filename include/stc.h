@@ -273,12 +273,15 @@ int stc_get_batch_factor(stc_handle* h, int32_t member, double* h_Lx, void* stre
 int stc_get_work(const stc_handle* h, double* work);
 
 /* Shape of the replayed schedule (host, no device work), stats (host)
-   int64[4]: [0] update tasks whose K stream is split over several
+   int64[5]: [0] update tasks whose K stream is split over several
    work-groups (deterministic split-K: parts after the first leave partial
    sums that the tile's next update folds in a fixed order); [1] doubles of
-   partial-sum slots per value set; [2] levels whose last-group updates have
-   a kernel of their own; [3] kernels (graph nodes) of one factorization.
-   All are set by the plan alone (the pattern, n_b, mode and wg_slots). */
+   partial-sum slot memory per value set; [2] levels whose last-group updates
+   have a kernel of their own; [3] kernels (graph nodes) of one
+   factorization; [4] doubles the slots would take without sharing memory
+   (slots share memory where the kernel graph orders the fold of one before
+   the write of the next).  All are set by the plan alone (the pattern, n_b,
+   mode and the schedule options). */
 int stc_get_plan_stats(const stc_handle* h, int64_t* stats);
 
 /* Host check of the factorization schedule, no device work.  The
@@ -289,10 +292,15 @@ int stc_get_plan_stats(const stc_handle* h, int64_t* stats);
    32 x 32 inverses, split-K partial slots) and verifies that the kernels of
    one level touch disjoint data, that every edge points to an earlier node,
    and that every two kernels that both touch one object, at least one of
-   them writing it, are ordered by a path of edges.  stats (host) int64[4]
-   receives: nodes, edges, pairs of kernels the graph leaves unordered (and
-   that may therefore overlap), data objects.  Returns 0, STC_ERR_ARG for a
-   null argument, or STC_ERR_SCHEDULE with stc_last_error naming the pair. */
+   them writing it, are ordered by a path of edges.  Partial slots are
+   checked as ranges of the slot memory, which slots share: every two kernels
+   whose slot ranges overlap, one of them writing, are ordered, no kernel
+   writes a slot range that it also reads, and every range lies inside the
+   slot memory.  stats (host) int64[5] receives: nodes, edges, pairs of
+   kernels the graph leaves unordered (and that may therefore overlap), data
+   objects (tiles), pairs of kernels ordered because they share slot memory.
+   Returns 0, STC_ERR_ARG for a null argument, or STC_ERR_SCHEDULE with
+   stc_last_error naming the pair. */
 int stc_check_schedule(const stc_handle* h, int64_t* stats);
 
 /* Host check of the solve's work items (Sec. 6.7: the sweeps over the

@@ -624,6 +624,107 @@ void align_tiles(Symbolic* s, int64_t min_subtree) {
 // execution plan
 // ---------------------------------------------------------------------------
 
+namespace {
+
+// Memory of the split-K partial slots.  A slot is live from the kernel that
+// writes it (its split task's, level L, early groups) to the kernel that
+// folds it (its partner's, a later level).  Slots share memory: a slot may
+// take memory that earlier slots used once the kernel that folded each of
+// them is an ancestor, in the kernel graph, of the kernel that writes the new
+// slot.  The graph then orders every access to the shared memory with the
+// edges it has anyway, so sharing adds no edge and costs no overlap.  The
+// slots are placed first-fit in the order of their writing kernels; the
+// memory is kept as segments that cover [0, parts), each owned by the last
+// slot placed on it (a slot placed after that one's fold is also placed after
+// the folds of all earlier owners, which precede that slot's writer).
+void place_slots(Plan* p) {
+  std::vector<KernelNode> dag;
+  kernel_dag(*p, &dag);
+  const size_t N = dag.size(), W = N / 64 + 1;
+  std::vector<uint64_t> anc(N * W, 0);
+  for (size_t x = 0; x < N; ++x)
+    for (int32_t d : dag[x].deps) {
+      for (size_t w = 0; w < W; ++w) anc[x * W + w] |= anc[(size_t)d * W + w];
+      anc[x * W + (size_t)d / 64] |= uint64_t(1) << (d % 64);
+    }
+  std::map<std::pair<int32_t, int32_t>, int32_t> node_of;
+  for (size_t x = 0; x < N; ++x) node_of[{dag[x].level, dag[x].kind}] = (int32_t)x;
+  // kernel of each update task: the last groups lead each list of items and
+  // form kind 3 where the level launches them apart, the rest kind 1
+  std::vector<int32_t> node_of_task(p->upd.size(), -1);
+  for (int32_t L = 0; L < (int32_t)p->levels.size(); ++L) {
+    const Level& lv = p->levels[(size_t)L];
+    for (const std::vector<int32_t>* v : {&lv.big_items, &lv.upd_items}) {
+      const size_t nl = 4 * (size_t)(v == &lv.big_items ? lv.big_last : lv.upd_last);
+      for (size_t q = 0; q < v->size(); q += 4) node_of_task[(size_t)(*v)[q]] = node_of.at({L, q < nl ? 3 : 1});
+    }
+  }
+  std::vector<int32_t> split;
+  for (int32_t id = 0; id < (int32_t)p->upd.size(); ++id)
+    if (p->upd[(size_t)id].nsplit > 1) split.push_back(id);
+  std::stable_sort(split.begin(), split.end(), [&](int32_t a, int32_t b) {
+    return node_of_task[(size_t)a] < node_of_task[(size_t)b];
+  });
+  struct Seg {
+    int64_t lo, hi;
+    int32_t task;
+  };
+  std::vector<Seg> segs, next;
+  int64_t end = 0;
+  for (int32_t id : split) {
+    UpdTask& u = p->upd[(size_t)id];
+    const int64_t need = (int64_t)(u.nsplit - 1) * u.c_rows * p->nb;
+    const int32_t wnode = node_of_task[(size_t)id];
+    auto freed = [&](const Seg& g) {
+      const int32_t f = node_of_task[(size_t)p->upd[(size_t)g.task].partner];
+      return (anc[(size_t)wnode * W + (size_t)f / 64] >> (f % 64)) & 1;
+    };
+    // lowest start of a run of freed segments that holds the slot; a run
+    // that reaches the end continues into new memory
+    int64_t start = end;
+    for (size_t i = 0; i < segs.size();) {
+      if (!freed(segs[i])) {
+        ++i;
+        continue;
+      }
+      size_t j = i;
+      while (j < segs.size() && freed(segs[j]) && segs[j].hi - segs[i].lo < need) ++j;
+      if (j == segs.size() || freed(segs[j])) {
+        start = segs[i].lo;
+        break;
+      }
+      i = j + 1;
+    }
+    const int64_t stop = start + need;
+    next.clear();
+    bool placed = false;
+    for (const Seg& g : segs) {
+      if (g.hi <= start || g.lo >= stop) {
+        if (g.lo >= stop && !placed) {
+          next.push_back({start, stop, id});
+          placed = true;
+        }
+        next.push_back(g);
+        continue;
+      }
+      if (g.lo < start) next.push_back({g.lo, start, g.task});
+      if (!placed) {
+        next.push_back({start, stop, id});
+        placed = true;
+      }
+      if (g.hi > stop) next.push_back({stop, g.hi, g.task});
+    }
+    if (!placed) next.push_back({start, stop, id});
+    segs.swap(next);
+    end = std::max(end, stop);
+    u.part_off = start;
+    p->upd[(size_t)u.partner].in_part_off = start;
+  }
+  p->parts = end;
+}
+
+}  // namespace
+
 int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std::string* why, int max_split,
                int fold_pct) {
   const int32_t nb = s.nb, NT = s.NT;
@@ -973,10 +1074,7 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std
       }
     for (UpdTask& u : p->upd) {
       if (u.nsplit < 2) continue;
-      u.part_off = p->parts;
-      p->parts += (int64_t)(u.nsplit - 1) * u.c_rows * nb;
       UpdTask& l = p->upd[(size_t)u.partner];
-      l.in_part_off = u.part_off;
       l.in_npart = u.nsplit - 1;
     }
     for (int32_t id = 0; id < (int32_t)p->upd.size(); ++id) {
@@ -1033,6 +1131,7 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std
       if (w_big_early + w_upd_early < (double)p->wg_slots) L.big_last = L.upd_last = 0;
     }
   }
+  place_slots(p);
   p->flops_tile = flops;
   for (int64_t j = 0; j < n; ++j) {
     double c = (double)(s.lp[j + 1] - s.lp[j]);

@@ -1305,10 +1305,16 @@ int stc_check_schedule(const stc_handle* h, int64_t* stats) {
   std::vector<KernelNode> dag;
   kernel_dag(p, &dag);
   const size_t N = dag.size();
-  // objects: tiles by store offset; partial slots by their offset, negated
-  // minus one; per object the nodes that read and that write it
+  // objects: tiles by store offset, per object the nodes that read and that
+  // write it; partial slots as ranges of the slot memory, which slots share
   std::map<int64_t, std::vector<std::pair<int32_t, bool>>> touch;
   std::vector<std::vector<std::pair<int64_t, bool>>> acc(N);
+  struct SlotUse {
+    int64_t lo, hi;
+    int32_t node;
+    bool write;
+  };
+  std::vector<SlotUse> slot_use;
   for (size_t x = 0; x < N; ++x) {
     const Level& lv = p.levels[(size_t)dag[x].level];
     auto& a = acc[x];
@@ -1331,8 +1337,9 @@ int stc_check_schedule(const stc_handle* h, int64_t* stats) {
             a.emplace_back(p.contribs[(size_t)c].a_off, false);
             a.emplace_back(p.contribs[(size_t)c].b_off, false);
           }
-          if (u.nsplit > 1) a.emplace_back(-1 - u.part_off, true);
-          if (u.in_npart > 0) a.emplace_back(-1 - u.in_part_off, false);
+          const int64_t slot = (int64_t)u.c_rows * p.nb;
+          if (u.nsplit > 1) slot_use.push_back({u.part_off, u.part_off + (u.nsplit - 1) * slot, (int32_t)x, true});
+          if (u.in_npart > 0) slot_use.push_back({u.in_part_off, u.in_part_off + u.in_npart * slot, (int32_t)x, false});
         }
       }
     }
@@ -1360,6 +1367,34 @@ int stc_check_schedule(const stc_handle* h, int64_t* stats) {
   auto ordered = [&](int32_t a, int32_t b) {  // a < b
     return (anc[(size_t)b * W + (size_t)a / 64] >> (a % 64)) & 1;
   };
+  std::sort(slot_use.begin(), slot_use.end(), [](const SlotUse& a, const SlotUse& b) {
+    return std::tie(a.lo, a.hi, a.node, a.write) < std::tie(b.lo, b.hi, b.node, b.write);
+  });
+  slot_use.erase(std::unique(slot_use.begin(), slot_use.end(),
+                             [](const SlotUse& a, const SlotUse& b) {
+                               return a.lo == b.lo && a.hi == b.hi && a.node == b.node && a.write == b.write;
+                             }),
+                 slot_use.end());
+  for (const SlotUse& g : slot_use)
+    if (g.lo < 0 || g.hi > p.parts || g.lo >= g.hi) return fail(STC_ERR_SCHEDULE, "partial slot outside the slot memory");
+  // every two uses of overlapping slot memory, one writing, are ordered
+  int64_t slot_pairs = 0;
+  for (size_t i = 0; i < slot_use.size(); ++i)
+    for (size_t j = i + 1; j < slot_use.size() && slot_use[j].lo < slot_use[i].hi; ++j) {
+      const SlotUse &g = slot_use[i], &k = slot_use[j];
+      if ((!g.write && !k.write) || g.node == k.node) {
+        if (g.node == k.node && (g.write || k.write))
+          return fail(STC_ERR_SCHEDULE, "one kernel writes and reads overlapping partial slots");
+        continue;
+      }
+      ++slot_pairs;
+      const int32_t a = std::min(g.node, k.node), b = std::max(g.node, k.node);
+      if (!ordered(a, b))
+        return fail(STC_ERR_SCHEDULE, "unordered kernels (level " + std::to_string(dag[(size_t)a].level) + ", kind " +
+                                          std::to_string(dag[(size_t)a].kind) + ") and (level " +
+                                          std::to_string(dag[(size_t)b].level) + ", kind " +
+                                          std::to_string(dag[(size_t)b].kind) + ") share partial-slot memory");
+    }
   for (const auto& kv : touch) {
     const auto& v = kv.second;
     for (size_t i = 0; i < v.size(); ++i)
@@ -1384,6 +1419,7 @@ int stc_check_schedule(const stc_handle* h, int64_t* stats) {
   stats[1] = edges;
   stats[2] = unordered;
   stats[3] = (int64_t)touch.size();
+  stats[4] = slot_pairs;
   return 0;
 }
 
@@ -1398,10 +1434,13 @@ int stc_get_plan_stats(const stc_handle* h, int64_t* st) {
   }
   std::vector<KernelNode> dag;
   kernel_dag(p, &dag);
+  int64_t unshared = 0;
+  for (const UpdTask& u : p.upd) unshared += u.nsplit > 1 ? (int64_t)(u.nsplit - 1) * u.c_rows * p.nb : 0;
   st[0] = split;
   st[1] = p.parts;
   st[2] = sep;
   st[3] = (int64_t)dag.size();
+  st[4] = unshared;
   return 0;
 }
 

@@ -350,20 +350,21 @@ class Analysis:
         return dict(zip(keys, (float(x) for x in w)))
 
     def plan_stats(self):
-        """{split_tasks, partial_doubles, separate_last_levels, graph_kernels}
-        of the factorization plan (see stc_get_plan_stats)."""
-        st = np.zeros(4, dtype=np.int64)
+        """{split_tasks, partial_doubles, separate_last_levels, graph_kernels,
+        partial_doubles_unshared} of the factorization plan (see
+        stc_get_plan_stats)."""
+        st = np.zeros(5, dtype=np.int64)
         _check(lib().stc_get_plan_stats(self._h, st))
-        return dict(zip(["split_tasks", "partial_doubles", "separate_last_levels", "graph_kernels"],
-                        (int(x) for x in st)))
+        return dict(zip(["split_tasks", "partial_doubles", "separate_last_levels", "graph_kernels",
+                         "partial_doubles_unshared"], (int(x) for x in st)))
 
     def check_schedule(self):
         """Host check of the kernel dependency graph the factorization replays
         (see stc_check_schedule); raises on a conflicting pair of kernels.
-        Returns {nodes, edges, unordered_pairs, objects}."""
-        st = np.zeros(4, dtype=np.int64)
+        Returns {nodes, edges, unordered_pairs, objects, slot_pairs}."""
+        st = np.zeros(5, dtype=np.int64)
         _check(lib().stc_check_schedule(self._h, st))
-        return dict(zip(["nodes", "edges", "unordered_pairs", "objects"], (int(x) for x in st)))
+        return dict(zip(["nodes", "edges", "unordered_pairs", "objects", "slot_pairs"], (int(x) for x in st)))
 
     def check_solve_schedule(self):
         """Host check of the solve sweeps' work items against the tile

@@ -38,6 +38,9 @@ def _check(w, nb, ordering, mode="auto", wg_slots=0, **kw):
         assert sv["launches"] <= 2 * a.NT
     if a.nb == 256 and a.mode == "dense" and a.NT > 2:  # full 256-row tiles: those levels split
         assert sv["launches"] > 2 * a.NT
+    ps = a.plan_stats()
+    assert ps["partial_doubles"] <= ps["partial_doubles_unshared"]
+    assert (ps["partial_doubles"] == 0) == (ps["split_tasks"] == 0)
     return st
 
 
@@ -87,6 +90,27 @@ def test_split_cap_and_fold_weight(max_split, fold_pct):
         cap = max_split or 64  # each split task holds (parts - 1) slots of at most 64 x 64 doubles
         assert ps["partial_doubles"] <= ps["split_tasks"] * (cap - 1) * 64 * 64
         assert st["nodes"] == ps["graph_kernels"]
+
+
+@pytest.mark.parametrize("case", ["dense", "arrowhead_aligned", "laplacian"])
+def test_slot_memory_shared(case):
+    """Split-K partial slots share memory where the kernel graph orders the
+    fold of one slot before the write of the next.  The checker verifies every
+    pair of kernels whose slot ranges overlap (slot_pairs of them here, each
+    ordered), and the shared memory is a fraction of one slot per split task."""
+    if case == "dense":
+        w, kw = W.dense_spd(2100, 0.3, 2), dict(nb=128, ordering="natural", mode="dense")
+    elif case == "arrowhead_aligned":
+        w, kw = W.spatiotemporal_arrowhead(T=12, m=20, nborder=8), dict(nb=64, ordering="nd", align=128)
+    else:
+        w, kw = W.batched_laplacian3d(m=12, B=2), dict(nb=32, ordering="nd")
+    st = _check(w, wg_slots=16, **kw)
+    a = S.Analysis(w.n, w.colptr, w.rowind, wg_slots=16, **kw)
+    ps = a.plan_stats()
+    print(case, ps, st)
+    assert ps["split_tasks"] > 4
+    assert st["slot_pairs"] > 0
+    assert 2 * ps["partial_doubles"] <= ps["partial_doubles_unshared"]
 
 
 def test_schedule_options_rejected():
