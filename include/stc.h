@@ -86,8 +86,9 @@ typedef struct {
                             level split of long update chains (deterministic
                             split-K) is balanced for, and the early-group
                             work above which a level's last groups get a
-                            launch of their own; 0 = 448 (the best of a sweep
-                            on MI355X).  Changes timing only.                  */
+                            launch of their own; 0 = 448 for n_b >= 128 and
+                            896 for smaller tiles (the best of sweeps on
+                            MI355X).  Changes timing only.                     */
   int32_t align;         /* tile grid: 0 = the uniform n_b grid of Sec. 4.1;
                             > 0 = a grid aligned to the elimination tree of
                             P A P^T: every subtree of at least `align` columns

@@ -731,7 +731,10 @@ int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std
   const int64_t n = s.n;
   (void)why;
   *p = Plan();
-  if (wg_slots > 0) p->wg_slots = wg_slots;
+  // default: 448 for tiles of 128 and 256 (two 128-block work-groups fit a
+  // compute unit), 896 for smaller tiles, whose 64-block work-groups fit
+  // several to a compute unit (both the best of sweeps on MI355X)
+  p->wg_slots = wg_slots > 0 ? wg_slots : nb <= 64 ? 896 : 448;
   if (max_split > 0) p->max_split = max_split;
   if (fold_pct > 0) p->fold_pct = fold_pct;
   p->nb = nb;
