@@ -114,6 +114,17 @@ __device__ __forceinline__ int dkey(int r) { return (r & 7) ^ ((r >> 3) & 1); }
 // fused update: C -= sum_c A_c B_c^T on one 64 x 64 block of an output tile
 // ---------------------------------------------------------------------------
 
+// Entry i of the gather map at `base` (a contribution's row or column map;
+// base < 0: the contribution has none), read whether or not the lane needs
+// it, so that the reads of a contribution's map entries are in flight
+// together instead of one conditional read after another.  A lane that needs
+// no entry reads the first word of the zero row instead and discards it.
+__device__ __forceinline__ int32_t map_entry(const int32_t* __restrict__ maps, int32_t base, int32_t i, bool need,
+                                             const double* __restrict__ zrow) {
+  const int32_t* q = (need && base >= 0) ? maps + base + i : reinterpret_cast<const int32_t*>(zrow);
+  return *q;
+}
+
 constexpr int UB = 64;   // output block
 constexpr int UKT = 16;  // K chunk staged in LDS
 constexpr int USTAGE = 2 * UB * DLD;  // A and B rows of one K chunk
@@ -202,9 +213,10 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
       const int lr = srow + 8 * j;
       const int p2 = 2 * ((lane & 7) ^ dkey(lr));
       const int32_t r = r0 + lr, cc = c0 + lr;
-      int32_t sa = -1, sb = -1;
-      if (r < u.c_rows) sa = c.rowmap < 0 ? (r < c.a_rows ? r : -1) : maps[c.rowmap + r];
-      if (cc < ncols) sb = c.colmap < 0 ? (cc < c.b_rows ? cc : -1) : maps[c.colmap + cc];
+      const bool ir = r < u.c_rows, ic = cc < ncols;
+      const int32_t ma = map_entry(maps, c.rowmap, r, ir, zrow), mb = map_entry(maps, c.colmap, cc, ic, zrow);
+      const int32_t sa = !ir ? -1 : c.rowmap < 0 ? (r < c.a_rows ? r : -1) : ma;
+      const int32_t sb = !ic ? -1 : c.colmap < 0 ? (cc < c.b_rows ? cc : -1) : mb;
       pa[j] = (sa >= 0 ? S + c.a_off + (int64_t)sa * NB : zrow) + p2;
       pb[j] = (sb >= 0 ? S + c.b_off + (int64_t)sb * NB : zrow) + p2;
     }
@@ -212,9 +224,10 @@ __device__ __forceinline__ void dev_update(int32_t it, const int32_t* __restrict
     // fills (lanes 0..31, one row each); products with an empty group are skipped
     if constexpr (CULL) {
       const int32_t r = r0 + wr + lane, cc = c0 + wc + lane;
-      bool ha = false, hb = false;
-      if (lane < 32 && r < u.c_rows) ha = c.rowmap < 0 ? r < c.a_rows : maps[c.rowmap + r] >= 0;
-      if (lane < 32 && cc < ncols) hb = c.colmap < 0 ? cc < c.b_rows : maps[c.colmap + cc] >= 0;
+      const bool ir = lane < 32 && r < u.c_rows, ic = lane < 32 && cc < ncols;
+      const int32_t ma = map_entry(maps, c.rowmap, r, ir, zrow), mb = map_entry(maps, c.colmap, cc, ic, zrow);
+      const bool ha = ir && (c.rowmap < 0 ? r < c.a_rows : ma >= 0);
+      const bool hb = ic && (c.colmap < 0 ? cc < c.b_rows : mb >= 0);
       const uint64_t ba = __ballot(ha), bb = __ballot(hb);
       cmask = ((ba & 0xFFFFull) ? 1u : 0u) | ((ba & 0xFFFF0000ull) ? 2u : 0u) | ((bb & 0xFFFFull) ? 4u : 0u) |
               ((bb & 0xFFFF0000ull) ? 8u : 0u);
@@ -418,9 +431,10 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
       const int lr = srow + 8 * j;
       const int p2 = 2 * ((lane & 7) ^ dkey(lr));
       const int32_t r = r0 + lr, cc = c0 + lr;
-      int32_t sa = -1, sb = -1;
-      if (r < u.c_rows) sa = c.rowmap < 0 ? (r < c.a_rows ? r : -1) : maps[c.rowmap + r];
-      if (cc < ncols) sb = c.colmap < 0 ? (cc < c.b_rows ? cc : -1) : maps[c.colmap + cc];
+      const bool ir = r < u.c_rows, ic = cc < ncols;
+      const int32_t ma = map_entry(maps, c.rowmap, r, ir, zrow), mb = map_entry(maps, c.colmap, cc, ic, zrow);
+      const int32_t sa = !ir ? -1 : c.rowmap < 0 ? (r < c.a_rows ? r : -1) : ma;
+      const int32_t sb = !ic ? -1 : c.colmap < 0 ? (cc < c.b_rows ? cc : -1) : mb;
       pa[j] = (sa >= 0 ? S + c.a_off + (int64_t)sa * NB : zrow) + p2;
       pb[j] = (sb >= 0 ? S + c.b_off + (int64_t)sb * NB : zrow) + p2;
     }
@@ -429,9 +443,10 @@ __device__ __forceinline__ void dev_update_big(int32_t it, const int32_t* __rest
     // of which one is all absent rows are zero and are skipped
     if constexpr (CULL) {
       const int32_t r = r0 + wr + lane, cc = c0 + wc + lane;
-      bool ha = false, hb = false;
-      if (r < u.c_rows) ha = c.rowmap < 0 ? r < c.a_rows : maps[c.rowmap + r] >= 0;
-      if (cc < ncols) hb = c.colmap < 0 ? cc < c.b_rows : maps[c.colmap + cc] >= 0;
+      const bool ir = r < u.c_rows, ic = cc < ncols;
+      const int32_t ma = map_entry(maps, c.rowmap, r, ir, zrow), mb = map_entry(maps, c.colmap, cc, ic, zrow);
+      const bool ha = ir && (c.rowmap < 0 ? r < c.a_rows : ma >= 0);
+      const bool hb = ic && (c.colmap < 0 ? cc < c.b_rows : mb >= 0);
       const uint64_t ba = __ballot(ha), bb = __ballot(hb);
       uint32_t m = 0;
 #pragma unroll
