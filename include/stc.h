@@ -78,7 +78,10 @@ extern "C" {
 typedef struct stc_handle stc_handle;
 
 typedef struct {
-  int32_t nb;            /* tile size n_b: 32, 64, 128 or 256 (0 = 64)          */
+  int32_t nb;            /* tile size n_b: 32, 64, 128 or 256; 0 = automatic:
+                            64, or, when the pattern takes the dense route at
+                            64 (mode AUTO: Sec. 5.1's selector; or mode
+                            DENSE), 256 from n = 2048 and 128 from n = 512     */
   int32_t mode;          /* STC_MODE_*                                           */
   int32_t ordering;      /* STC_ORD_*                                            */
   const int32_t* perm;   /* (host) perm[new] = old, read when ordering == GIVEN  */

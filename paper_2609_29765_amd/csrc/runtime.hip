@@ -881,11 +881,12 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
                 stc_handle** out) {
   if (!out) return fail(STC_ERR_ARG, "null output handle");
   *out = nullptr;
-  stc_opts o{64, STC_MODE_AUTO, STC_ORD_AUTO, nullptr, 0, 0, 0, 0};
+  stc_opts o{0, STC_MODE_AUTO, STC_ORD_AUTO, nullptr, 0, 0, 0, 0};
   if (opts) o = *opts;
-  if (o.nb == 0) o.nb = 64;
+  const bool auto_nb = o.nb == 0;
+  if (auto_nb) o.nb = 64;
   if (o.nb != 32 && o.nb != 64 && o.nb != 128 && o.nb != 256)
-    return fail(STC_ERR_ARG, "nb must be 32, 64, 128 or 256");
+    return fail(STC_ERR_ARG, "nb must be 0, 32, 64, 128 or 256");
   if (o.wg_slots < 0) return fail(STC_ERR_ARG, "wg_slots must be >= 0");
   if (o.align < 0) return fail(STC_ERR_ARG, "align must be >= 0");
   if (o.max_split < 0 || o.max_split > 64 || o.fold_pct < 0)
@@ -894,6 +895,14 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
     auto* h = new stc_handle();
     std::string why;
     int rc = analyse(n, colptr, rowind, o.ordering, o.nb, o.mode, o.perm, &h->sym, &why);
+    // automatic tile size: 64, or larger tiles when the pattern takes the
+    // dense route there (fewer, larger tiles keep the FP64 matrix cores
+    // busy; tile 256 from n = 2048, 128 from n = 512)
+    if (rc == 0 && auto_nb && h->sym.mode == kModeDense && n >= 512) {
+      o.nb = n >= 2048 ? 256 : 128;
+      h->sym = Symbolic();
+      rc = analyse(n, colptr, rowind, o.ordering, o.nb, o.mode, o.perm, &h->sym, &why);
+    }
     if (rc) {
       delete h;
       return fail(rc, why);

@@ -128,7 +128,11 @@ def _need_cuda(t, dtype_name="float64"):
 
 
 class Analysis:
-    """Once-per-pattern analysis; factorize / logdet / solve many times."""
+    """Once-per-pattern analysis; factorize / logdet / solve many times.
+
+    nb: tile size 32, 64, 128 or 256, or 0 for the library's automatic
+    choice (64, larger tiles for patterns on the dense route; see stc_opts).
+    """
 
     def __init__(self, n, colptr, rowind, nb=64, mode="auto", ordering="auto", perm=None,
                  wg_slots=0, align=0, max_split=0, fold_pct=0, _handle=None):

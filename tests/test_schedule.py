@@ -118,3 +118,18 @@ def test_schedule_options_rejected():
     for kw in (dict(max_split=-1), dict(max_split=65), dict(fold_pct=-5)):
         with pytest.raises(S.STCError):
             S.Analysis(w.n, w.colptr, w.rowind, nb=32, ordering="nd", **kw)
+
+
+def test_automatic_tile_size():
+    """nb = 0: tile 64, or 256 (n >= 2048) / 128 (n >= 512) when the pattern
+    takes the dense route at 64; the result equals an explicit analysis at
+    that tile size."""
+    cases = [(W.dense_spd(2100, 0.3, 2), "natural", 256), (W.dense_spd(700, 0.3, 2), "natural", 128),
+             (W.dense_spd(300, 0.3, 2), "natural", 64), (W.gmrf_grid2d(32, 32), "nd", 64),
+             (W.spatiotemporal_arrowhead(T=6, m=20, nborder=8), "nd", 64)]
+    for w, ordering, want in cases:
+        a = S.Analysis(w.n, w.colptr, w.rowind, nb=0, ordering=ordering)
+        assert a.nb == want, (w.n, a.mode, a.nb)
+        b = S.Analysis(w.n, w.colptr, w.rowind, nb=want, ordering=ordering)
+        assert a.mode == b.mode and a.NT == b.NT and np.array_equal(a.perm(), b.perm())
+        assert a.plan_stats() == b.plan_stats()
