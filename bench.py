@@ -333,6 +333,34 @@ def extra_gmrf():
             "levels": a.nlevels, "mode": a.mode, "autotune": table}
 
 
+def extra_supernodal():
+    """2-D GMRF on a 200 x 200 grid (n = 40,000, ND), which the selector
+    routes supernodal at tile 128: the route's tree-aligned grid against the
+    uniform grid (the same tiles forced semisparse), and logdet against its
+    closed form."""
+    import numpy as np
+    import torch
+    from paper_2609_29765_amd import stc, workloads
+    w = workloads.gmrf_grid2d(200, 200, 0.1, 0)
+    v = torch.from_numpy(w.values).cuda()
+    out = {"workload": "2-D GMRF 200x200 grid, Laplacian + 0.1 I, n=40000, ND, tile 128"}
+    for key, mode in (("route", "auto"), ("uniform_grid", "semisparse")):
+        a = stc.Analysis(w.n, w.colptr, w.rowind, nb=128, ordering="nd", mode=mode).bind()
+        ms = timed(lambda: a.factorize(v), 50)
+        ld = float(a.logdet().item())
+        assert a.info() == 0
+        out[key] = {"route": a.route, "align": a.align, "levels": a.nlevels, "ms_per_factorization": round(ms, 4),
+                    "logdet": ld}
+        a.release()
+        del a
+    lam = 2 - 2 * np.cos(np.pi * np.arange(200) / 200)
+    closed = float(np.log(lam[:, None] + lam[None, :] + 0.1).sum())
+    out["rel_logdet_vs_closed_form"] = max(abs(out[k]["logdet"] - closed) / abs(closed) for k in ("route", "uniform_grid"))
+    out["speedup_vs_uniform_grid"] = round(out["uniform_grid"]["ms_per_factorization"] /
+                                          out["route"]["ms_per_factorization"], 2)
+    return out
+
+
 def extra_semisparse():
     """Spatio-temporal arrowhead, n = 101,258: tile size (64, 128, 256) and grid tuned."""
     import torch
@@ -452,7 +480,8 @@ def run_extras(path, batch):
     load_lib()
     out = {}
     for name, fn in [("gmrf_2d", extra_gmrf), ("backward", extra_backward),
-                     ("batched", lambda: extra_batched(batch)), ("semisparse", extra_semisparse)]:
+                     ("batched", lambda: extra_batched(batch)), ("supernodal", extra_supernodal),
+                     ("semisparse", extra_semisparse)]:
         t0 = time.time()
         log(f"extra {name} ...")
         out[name] = fn()
@@ -599,6 +628,9 @@ def cpu_baseline_configs(extras):
                       "gpu_ms_batched": ms_b,
                       "gpu_speedup_vs_oracle": round(per * 128 * 1e3 / ms_b, 1) if ms_b else None}
     log(f"oracle batched: {out['batched']}")
+    w = workloads.gmrf_grid2d(200, 200, 0.1, 0)
+    out["supernodal"] = row("supernodal", w, 128, (ex.get("supernodal", {}).get("route") or {}).get(
+        "ms_per_factorization"))[1]
     w = workloads.spatiotemporal_arrowhead()
     out["semisparse"] = row("semisparse", w, gpu("semisparse", "nb") or 128,
                             gpu("semisparse", "ms_per_factorization"), reps=0)[1]

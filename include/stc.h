@@ -92,7 +92,10 @@ typedef struct {
                             launch of their own; 0 = 448 for n_b >= 128 and
                             896 for smaller tiles (the best of sweeps on
                             MI355X).  Changes timing only.                     */
-  int32_t align;         /* tile grid: 0 = the uniform n_b grid of Sec. 4.1;
+  int32_t align;         /* tile grid: 0 = the uniform n_b grid of Sec. 4.1,
+                            except for patterns the selector routes
+                            supernodal (mode AUTO), whose grid is aligned at
+                            n_b (Sec. 5.4: their tiles follow the fill);
                             > 0 = a grid aligned to the elimination tree of
                             P A P^T: every subtree of at least `align` columns
                             whose columns are consecutive starts on a tile

@@ -106,6 +106,10 @@ class Analysis:
         if not h:
             raise ValueError(f"oracle analyse failed with code {err.value}")
         self._h = h
+        if not align and mode == "auto" and self._route_now() == "supernodal":
+            # the supernodal route's tiles follow the fill (Sec. 5.4): on the
+            # fixed-width tiles, a grid aligned to the elimination tree at n_b
+            align = int(nb)
         if align:
             rc = lib().orc_align(h, int(align))
             if rc:
@@ -119,6 +123,11 @@ class Analysis:
         f = np.zeros(3)
         lib().orc_features(h, f)
         self.phi, self.rho, self.sigma = (float(x) for x in f)
+
+    def _route_now(self):
+        sz = np.zeros(16, np.int64)
+        lib().orc_sizes(self._h, sz)
+        return ROUTES[int(sz[9])]
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -907,7 +907,14 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
       delete h;
       return fail(rc, why);
     }
-    if (o.align > 0) align_tiles(&h->sym, o.align);
+    // the supernodal route (Sec. 5.4) replaces the fixed grid by tiles that
+    // follow the fill; here its patterns keep the fixed-width tiles the
+    // kernels take, on a grid aligned to the elimination tree at n_b columns
+    // (unless the caller fixed the mode or the grid)
+    const int64_t align = o.align > 0 ? o.align
+                          : (o.mode == STC_MODE_AUTO && h->sym.route == kRouteSupernodal) ? o.nb
+                                                                                           : 0;
+    if (align > 0) align_tiles(&h->sym, align);
     if (h->sym.qnz + o.nb >= INT32_MAX || (int64_t)h->sym.NT * o.nb >= INT32_MAX) {
       delete h;
       return fail(STC_ERR_ARG, "more than 2^31 - 1 input entries or grid positions");

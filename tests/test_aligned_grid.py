@@ -159,3 +159,25 @@ def test_rejects_negative_align():
     w = W.gmrf_grid2d(8, 8, 0.1, 0)
     with pytest.raises(S.STCError):
         S.Analysis(w.n, w.colptr, w.rowind, nb=32, ordering="nd", align=-1)
+
+
+def test_supernodal_route_takes_the_tree_aligned_grid():
+    """Patterns the selector routes supernodal (mode AUTO) are factorized on
+    fixed-width tiles aligned to the elimination tree at n_b (their tiles
+    follow the fill, Sec. 5.4); a fixed mode or an explicit grid overrides
+    it.  The 100 x 100 2-D GMRF routes supernodal at tile 128 (rho < 0.15,
+    phi > 2); analyser and oracle apply the rule independently and agree bit
+    for bit."""
+    w = W.gmrf_grid2d(100, 100, 0.1, 0)
+    a, o = _compare(w, "nd", 128)
+    assert a.route == o.route == "supernodal" and a.mode == "semisparse"
+    assert a.align == 128
+    assert not np.array_equal(a.grid_positions(), np.arange(w.n))
+    u = S.Analysis(w.n, w.colptr, w.rowind, nb=128, ordering="nd", mode="semisparse")
+    assert u.route == "supernodal" and u.align == 0
+    assert np.array_equal(u.grid_positions(), np.arange(w.n))
+    e = S.Analysis(w.n, w.colptr, w.rowind, nb=128, ordering="nd", align=512)
+    assert e.align == 512
+    # a semisparse-routed pattern keeps the uniform grid by default
+    s64 = S.Analysis(w.n, w.colptr, w.rowind, nb=64, ordering="nd")
+    assert s64.route == "semisparse" and s64.align == 0

@@ -167,3 +167,40 @@ def test_aligned_solve_noalloc_matches_solve():
     X = b.t().clone(memory_format=torch.contiguous_format)
     S._check(S.lib().stc_solve_noalloc(a._h, S._dptr(X), 2, S._stream_ptr()))
     assert torch.equal(X.t(), x)
+
+
+def test_supernodal_route_gmrf_closed_form():
+    """The 100 x 100 2-D GMRF routes supernodal at tile 128 and is factorized
+    on the grid aligned at n_b: factor, logdet (also against its closed form),
+    solve, selected inverse and gradient against the oracle, which applies
+    the same route rule."""
+    w = W.gmrf_grid2d(100, 100, 0.1, 0)
+    o = O.Analysis(w.n, w.colptr, w.rowind, "nd", nb=128)
+    Lo, info_o = o.factor(w.values)
+    assert info_o == 0 and o.route == "supernodal"
+    a = S.Analysis(w.n, w.colptr, w.rowind, nb=128, ordering="nd").bind()
+    print(f"[gpu] supernodal route gmrf100 nb=128 align={a.align} padding={padded(a)} levels={a.nlevels}", flush=True)
+    assert a.route == "supernodal" and a.align == 128 and padded(a) > 0
+    assert np.array_equal(a.grid_positions(), o.positions())
+    a.factorize(dev(w.values))
+    assert a.info() == 0
+    lp, _ = o.L_pattern()
+    factor_close(a.factor(), Lo, lp)
+    ld = float(a.logdet().item())
+    logdet_close(ld, o.logdet(Lo), Lo[lp[:-1]])
+    lam = 2 - 2 * np.cos(np.pi * np.arange(100) / 100)
+    closed = np.log(lam[:, None] + lam[None, :] + 0.1).sum()
+    assert abs(ld - closed) <= 1e-12 * abs(closed)
+    b = np.random.default_rng(12).standard_normal((w.n, 2))
+    x = a.solve(dev(b)).cpu().numpy()
+    xo = o.solve(Lo, b)
+    assert np.max(np.abs(x - xo)) <= 1e-10 * np.max(np.abs(xo))
+    Zo = o.selinv(Lo)
+    diag = a.selinv().cpu().numpy()
+    factor_close(a.selinv_pattern(), Zo, lp)
+    dref = np.empty(w.n)
+    dref[o.perm()] = Zo[lp[:-1]]
+    assert np.max(np.abs(diag - dref)) <= 1e-10 * np.max(np.abs(dref))
+    go = o.logdet_grad_values(Lo)
+    g = a.logdet_backward(torch.ones(1, dtype=torch.float64, device="cuda")).cpu().numpy()
+    assert np.max(np.abs(g - go)) <= 1e-10 * np.max(np.abs(go))
