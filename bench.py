@@ -123,6 +123,33 @@ def semisparse_pass(align, nb=128):
           flush=True)
 
 
+def batched_pass(batch_hint):
+    """Counter runs over the batched form: the 3-D Laplacian 24^3 with 128
+    value sets (tile 64, ND, grid aligned at 128 columns, split-K schedule for
+    a batch of `batch_hint` value sets, 0 = for one), factorized twice in one
+    batched call each, then a plain 1 GiB device copy whose counter readings
+    calibrate the byte counters.  Prints one JSON line: the plan's work terms
+    and the batch's time."""
+    import torch
+    stc = load_lib()
+    from paper_2609_29765_amd import workloads
+    w = workloads.batched_laplacian3d(m=24, B=128, seed=0)
+    V = torch.from_numpy(w.values).cuda()
+    a = stc.Analysis(w.n, w.colptr, w.rowind, nb=64, ordering="nd", align=128, batch=batch_hint).bind(batch=128)
+    for _ in range(2):
+        _, info = a.factorize_batched(V)
+    torch.cuda.synchronize()
+    assert int(info.abs().sum().item()) == 0
+    ms = timed(lambda: a.factorize_batched(V), 1)
+    x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": f"3-D Laplacian 24^3, B=128, tile 64, ND, grid align 128, batch hint {batch_hint}",
+                      "work": a.work(), "plan": a.plan_stats(), "ms_batched": ms}), flush=True)
+
+
 def solve_pass(align, nb=128):
     """Kernel-trace runs over the solve: the spatio-temporal arrowhead
     (n = 101,258, tile nb, ND, grid alignment `align`) factorized once, then three solves with one
@@ -401,11 +428,15 @@ def extra_batched(B):
     ld_b, info = a.factorize_batched(V)
     assert int(info.abs().sum().item()) == 0
     ld_s = torch.empty(B, dtype=torch.float64, device="cuda")
+    # the plain path on its own schedule: same tiles and grid, split balanced
+    # for one value set
+    from paper_2609_29765_amd import stc
+    p1 = stc.Analysis(w.n, w.colptr, w.rowind, nb=a.nb, ordering="nd", align=a.align).bind()
 
     def plain():
         for i in range(B):
-            a.factorize(V[i])
-            ld_s[i:i + 1].copy_(a.logdet().reshape(1))
+            p1.factorize(V[i])
+            ld_s[i:i + 1].copy_(p1.logdet().reshape(1))
 
     plain()
     ms_plain = timed(plain, 2)
@@ -797,6 +828,9 @@ def main():
     ap.add_argument("--solve-pass", action="store_true",
                     help="factorize the semisparse config, then solve it 3 times with 1 and with 8 "
                          "right-hand sides (for a kernel trace), print one JSON line and exit")
+    ap.add_argument("--batched-pass", type=int, default=None, metavar="HINT",
+                    help="factorize the batched config (B=128) three times with the split-K schedule for a batch of "
+                         "HINT value sets (0: for one), then a 1 GiB copy, for the counter runs; print one JSON line")
     ap.add_argument("--semisparse-pass", action="store_true",
                     help="only: one eager C3 factorization (kernel by kernel) and a 1 GiB copy, "
                          "for counter runs over the active-column route")
@@ -832,6 +866,9 @@ def main():
         return
     if args.solve_pass:
         solve_pass(args.pass_align, args.pass_nb)
+        return
+    if args.batched_pass is not None:
+        batched_pass(args.batched_pass)
         return
     if args.semisparse_pass:
         semisparse_pass(args.pass_align, args.pass_nb)

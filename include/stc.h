@@ -111,6 +111,12 @@ typedef struct {
   int32_t fold_pct;      /* schedule: weight, in percent of the measured cost,
                             that the split's cost model gives to folding one
                             partial slot (0 = 100).  Both change timing only. */
+  int32_t batch;         /* schedule: value sets factorized together (0 or 1:
+                            one).  B > 1 value sets of one pattern already
+                            fill the device B times over, so each set's split
+                            is balanced for max(16, wg_slots / B) work-groups
+                            (wg_slots or its default).  Changes timing only;
+                            any batch size can still be bound.                 */
 } stc_opts;
 
 /* Analyse a sparsity pattern once (Sec. 3, Sec. 5.1-5.2).
@@ -119,7 +125,7 @@ typedef struct {
            triangle of A in CSC form, original numbering, rows ascending within
            each column, the diagonal present and first, no duplicates.  Input
            values passed later to stc_factorize follow this entry order.
-   opts    (host) may be NULL (nb 64, AUTO mode, AUTO ordering).
+   opts    (host) may be NULL (automatic tile size, AUTO mode, AUTO ordering).
    out     (host) receives a new handle; the library copies the pattern.
    Errors: STC_ERR_PATTERN for an invalid pattern, STC_ERR_ARG for bad
    options.  The handle owns only host memory until stc_bind is called. */

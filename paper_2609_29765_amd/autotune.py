@@ -40,7 +40,8 @@ def autotune(n, colptr, rowind, values, nbs=(64, 128, 256), modes=("auto",), ord
 
     def trial(nb, mode, ws, al, fp):
         nonlocal perm, best
-        kw = dict(nb=nb, mode=mode, wg_slots=ws, align=al * nb, fold_pct=fp)
+        kw = dict(nb=nb, mode=mode, wg_slots=ws, align=al * nb, fold_pct=fp,
+                  batch=values.shape[0] if batched else 0)
         if perm is None:
             a = stc.Analysis(n, colptr, rowind, ordering=ordering, **kw)
             perm = a.perm()

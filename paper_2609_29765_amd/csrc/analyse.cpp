@@ -725,16 +725,18 @@ void place_slots(Plan* p) {
 
 }  // namespace
 
+// 448 for tiles of 128 and 256 (two 128-block work-groups fit a compute
+// unit), 896 for smaller tiles, whose 64-block work-groups fit several to a
+// compute unit (both the best of sweeps on MI355X)
+int64_t default_wg_slots(int nb) { return nb <= 64 ? 896 : 448; }
+
 int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std::string* why, int max_split,
                int fold_pct) {
   const int32_t nb = s.nb, NT = s.NT;
   const int64_t n = s.n;
   (void)why;
   *p = Plan();
-  // default: 448 for tiles of 128 and 256 (two 128-block work-groups fit a
-  // compute unit), 896 for smaller tiles, whose 64-block work-groups fit
-  // several to a compute unit (both the best of sweeps on MI355X)
-  p->wg_slots = wg_slots > 0 ? wg_slots : nb <= 64 ? 896 : 448;
+  p->wg_slots = wg_slots > 0 ? wg_slots : default_wg_slots(nb);
   if (max_split > 0) p->max_split = max_split;
   if (fold_pct > 0) p->fold_pct = fold_pct;
   p->nb = nb;

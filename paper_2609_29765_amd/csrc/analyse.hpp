@@ -157,8 +157,8 @@ struct Plan {
 };
 
 // wg_slots: concurrent update work-groups the per-level split of long
-// contribution ranges is balanced for (0 = 448 for n_b >= 128, 896 for
-// smaller tiles, measured best on MI355X)
+// contribution ranges is balanced for (0 = default_wg_slots(n_b))
+int64_t default_wg_slots(int nb);
 int build_plan(const Symbolic& s, int bm, int br, int64_t wg_slots, Plan* p, std::string* why, int max_split = 0,
                int fold_pct = 0);
 

@@ -881,7 +881,7 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
                 stc_handle** out) {
   if (!out) return fail(STC_ERR_ARG, "null output handle");
   *out = nullptr;
-  stc_opts o{0, STC_MODE_AUTO, STC_ORD_AUTO, nullptr, 0, 0, 0, 0};
+  stc_opts o{0, STC_MODE_AUTO, STC_ORD_AUTO, nullptr, 0, 0, 0, 0, 0};
   if (opts) o = *opts;
   const bool auto_nb = o.nb == 0;
   if (auto_nb) o.nb = 64;
@@ -891,6 +891,7 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
   if (o.align < 0) return fail(STC_ERR_ARG, "align must be >= 0");
   if (o.max_split < 0 || o.max_split > 64 || o.fold_pct < 0)
     return fail(STC_ERR_ARG, "max_split must be in [0, 64] and fold_pct >= 0");
+  if (o.batch < 0) return fail(STC_ERR_ARG, "batch must be >= 0");
   try {
     auto* h = new stc_handle();
     std::string why;
@@ -919,7 +920,12 @@ int stc_analyse(int64_t n, const int64_t* colptr, const int32_t* rowind, const s
       delete h;
       return fail(STC_ERR_ARG, "more than 2^31 - 1 input entries or grid positions");
     }
-    rc = build_plan(h->sym, UB, TR, o.wg_slots, &h->plan, &why, o.max_split, o.fold_pct);
+    // a batch of value sets shares the device: each set's split is balanced
+    // for its share of the work-groups (at least 16, the best of a sweep on
+    // the 128-member Laplacian batch)
+    int64_t slots = o.wg_slots;
+    if (o.batch > 1) slots = std::max<int64_t>(16, (slots > 0 ? slots : default_wg_slots(h->sym.nb)) / o.batch);
+    rc = build_plan(h->sym, UB, TR, slots, &h->plan, &why, o.max_split, o.fold_pct);
     if (rc == 0) rc = build_backward(h->sym, &h->plan, &h->back, &why);
     if (rc) {
       delete h;

@@ -48,7 +48,7 @@ class STCError(RuntimeError):
 class _opts(C.Structure):
     _fields_ = [("nb", C.c_int32), ("mode", C.c_int32), ("ordering", C.c_int32),
                 ("perm", C.c_void_p), ("wg_slots", C.c_int32), ("align", C.c_int32),
-                ("max_split", C.c_int32), ("fold_pct", C.c_int32)]
+                ("max_split", C.c_int32), ("fold_pct", C.c_int32), ("batch", C.c_int32)]
 
 
 def lib():
@@ -135,7 +135,7 @@ class Analysis:
     """
 
     def __init__(self, n, colptr, rowind, nb=64, mode="auto", ordering="auto", perm=None,
-                 wg_slots=0, align=0, max_split=0, fold_pct=0, _handle=None):
+                 wg_slots=0, align=0, max_split=0, fold_pct=0, batch=0, _handle=None):
         L = lib()
         if _handle is None:
             self.colptr = np.ascontiguousarray(colptr, np.int64)
@@ -143,7 +143,7 @@ class Analysis:
             self._perm_in = None if perm is None else np.ascontiguousarray(perm, np.int32)
             o = _opts(int(nb), MODES[mode], ORDERINGS[ordering],
                       None if self._perm_in is None else self._perm_in.ctypes.data, int(wg_slots),
-                      int(align), int(max_split), int(fold_pct))
+                      int(align), int(max_split), int(fold_pct), int(batch))
             h = C.c_void_p()
             _check(L.stc_analyse(int(n), self.colptr, self.rowind, C.byref(o), C.byref(h)))
         else:

@@ -131,10 +131,12 @@ def test_aligned_not_spd_reports_the_column():
     assert a.info() == 0
 
 
-def test_aligned_batched_members_and_solves():
+@pytest.mark.parametrize("hint", [0, 4])
+def test_aligned_batched_members_and_solves(hint):
+    """hint: stc_opts.batch, the schedule balanced for B value sets at once."""
     B = 4
     w = W.batched_laplacian3d(m=16, B=B, seed=2)
-    a = S.Analysis(w.n, w.colptr, w.rowind, nb=64, ordering="nd", align=256).bind(batch=B)
+    a = S.Analysis(w.n, w.colptr, w.rowind, nb=64, ordering="nd", align=256, batch=hint).bind(batch=B)
     assert padded(a) > 0
     print(f"[gpu] aligned batched n={w.n} B={B} padding={padded(a)}", flush=True)
     ld, info = a.factorize_batched(dev(w.values))
@@ -151,8 +153,8 @@ def test_aligned_batched_members_and_solves():
         logdet_close(ld[m], o.logdet(Lo), Lo[lp[:-1]])
         xo = o.solve(Lo, b[m])
         assert np.max(np.abs(x[m] - xo)) <= 1e-10 * np.max(np.abs(xo))
-    # one value set alone gives the batched member's logdet bit for bit
-    a1 = S.Analysis(w.n, w.colptr, w.rowind, nb=64, ordering="nd", align=256).bind()
+    # one value set alone, on the same plan, gives the batched member's logdet bit for bit
+    a1 = S.Analysis(w.n, w.colptr, w.rowind, nb=64, ordering="nd", align=256, batch=hint).bind()
     a1.factorize(dev(w.values[2]))
     assert float(a1.logdet().item()) == ld[2]
 

@@ -115,7 +115,7 @@ def test_slot_memory_shared(case):
 
 def test_schedule_options_rejected():
     w = W.gmrf_grid2d(8, 8, 0.1, 0)
-    for kw in (dict(max_split=-1), dict(max_split=65), dict(fold_pct=-5)):
+    for kw in (dict(max_split=-1), dict(max_split=65), dict(fold_pct=-5), dict(batch=-1)):
         with pytest.raises(S.STCError):
             S.Analysis(w.n, w.colptr, w.rowind, nb=32, ordering="nd", **kw)
 
@@ -133,3 +133,20 @@ def test_automatic_tile_size():
         b = S.Analysis(w.n, w.colptr, w.rowind, nb=want, ordering=ordering)
         assert a.mode == b.mode and a.NT == b.NT and np.array_equal(a.perm(), b.perm())
         assert a.plan_stats() == b.plan_stats()
+
+
+def test_batch_hint_balances_each_set_for_its_share():
+    """stc_opts.batch = B > 1: each value set's split is balanced for
+    max(16, wg_slots / B) work-groups, so a 128-member batch splits far less
+    than one value set; the plan equals the one for that budget and passes
+    the schedule checks."""
+    w = W.batched_laplacian3d(m=12, B=2)
+    one = S.Analysis(w.n, w.colptr, w.rowind, nb=64, ordering="nd", align=128)
+    big = S.Analysis(w.n, w.colptr, w.rowind, nb=64, ordering="nd", align=128, batch=128)
+    ref = S.Analysis(w.n, w.colptr, w.rowind, nb=64, ordering="nd", align=128, wg_slots=16)
+    assert big.plan_stats() == ref.plan_stats()
+    assert big.plan_stats()["split_tasks"] < one.plan_stats()["split_tasks"]
+    half = S.Analysis(w.n, w.colptr, w.rowind, nb=64, ordering="nd", align=128, batch=2)
+    assert half.plan_stats() == S.Analysis(w.n, w.colptr, w.rowind, nb=64, ordering="nd", align=128,
+                                           wg_slots=448).plan_stats()
+    _check(w, 64, "nd", align=128, batch=128)
