@@ -1303,6 +1303,103 @@ void kernel_dag(const Plan& p, std::vector<KernelNode>* out) {
   }
 }
 
+namespace {
+
+// The contraction levels run one after another, and a level lasts as long as
+// its longest work item: the task with the most terms.  An item costs its
+// terms' K chunks of 32 plus one per term (its maps) and one (the epilogue).
+// A level whose longest item costs at least 16 and twice the mean load of
+// 1,024 concurrent work-groups splits each task costlier than that target
+// into parts of about the target, cut at term boundaries (at most 16 parts):
+// part 0 keeps the task's output, parts s > 0 write partial slots that a
+// fold kernel adds to it after the level (FoldTask).  Slots are reused from
+// one level to the next, since the levels run in sequence.
+void split_backward(BackPlan* b, int32_t nb) {
+  constexpr int32_t kChunk = 32;
+  constexpr double kWorkGroups = 1024, kMinCost = 16;
+  constexpr int32_t kMaxParts = 16;
+  enum { BUF_P = 4 };
+  auto term_cost = [&](int32_t t) { return (double)((b->terms[(size_t)t].K + kChunk - 1) / kChunk) + 1.0; };
+  auto task_cost = [&](int32_t id) {
+    const ConTask& t = b->tasks[(size_t)id];
+    double c = 1.0;
+    for (int32_t x = t.t_begin; x < t.t_end; ++x) c += term_cost(x);
+    return c;
+  };
+  b->folds.clear();
+  b->fold_items.assign(b->level_items.size(), {});
+  b->slots = 0;
+  for (size_t L = 2; L < b->level_items.size(); ++L) {
+    std::vector<int32_t>& items = b->level_items[L];
+    double total = 0, longest = 0;
+    for (size_t q = 0; q < items.size(); q += 3) {
+      const double c = task_cost(items[q]);
+      total += c;
+      longest = std::max(longest, c);
+    }
+    const double target = std::max(kMinCost, total / kWorkGroups);
+    if (longest < 2 * target) continue;
+    std::map<int32_t, std::vector<int32_t>> parts;  // split task -> its part tasks s > 0
+    std::map<int32_t, int32_t> fold_of;
+    int64_t level_slots = 0;
+    for (size_t q = 0; q < items.size(); q += 3) {
+      const int32_t id = items[q];
+      if (fold_of.count(id) || parts.count(id)) continue;
+      const double c = task_cost(id);
+      ConTask t = b->tasks[(size_t)id];
+      const int32_t nterms = t.t_end - t.t_begin;
+      const int32_t np = std::min<int32_t>({kMaxParts, nterms, (int32_t)std::ceil(c / target)});
+      if (c <= target || np < 2) {
+        parts[id];
+        continue;
+      }
+      // cut points: part k ends at the first term where the running cost
+      // reaches (k + 1) / np of the task's term cost
+      std::vector<int32_t> cut{t.t_begin};
+      double run = 0, tc = c - 1.0;
+      for (int32_t x = t.t_begin; x < t.t_end && (int32_t)cut.size() < np; ++x) {
+        run += term_cost(x);
+        if (run >= tc * (double)cut.size() / np && x + 1 < t.t_end) cut.push_back(x + 1);
+      }
+      cut.push_back(t.t_end);
+      const int32_t nparts = (int32_t)cut.size() - 1;
+      if (nparts < 2) {
+        parts[id];
+        continue;
+      }
+      b->tasks[(size_t)id].t_end = cut[1];
+      const int64_t slot = (int64_t)t.c_rows * nb;
+      std::vector<int32_t>& ps = parts[id];
+      for (int32_t k = 1; k < nparts; ++k) {
+        ConTask pt = t;
+        pt.c_off = level_slots + (int64_t)(k - 1) * slot;
+        pt.c_buf = BUF_P;
+        pt.t_begin = cut[(size_t)k];
+        pt.t_end = cut[(size_t)k + 1];
+        pt.beta = 0;
+        ps.push_back((int32_t)b->tasks.size());
+        b->tasks.push_back(pt);
+      }
+      fold_of[id] = (int32_t)b->folds.size();
+      b->folds.push_back(FoldTask{t.c_off, t.c_buf, t.c_rows, t.ncols, t.diag, level_slots, nparts - 1});
+      level_slots += (int64_t)(nparts - 1) * slot;
+    }
+    std::vector<int32_t> out;
+    std::vector<int32_t>& fi = b->fold_items[L];
+    for (size_t q = 0; q < items.size(); q += 3) {
+      const int32_t id = items[q], x = items[q + 1], y = items[q + 2];
+      out.insert(out.end(), {id, x, y});
+      for (int32_t pid : parts[id]) out.insert(out.end(), {pid, x, y});
+      auto f = fold_of.find(id);
+      if (f != fold_of.end()) fi.insert(fi.end(), {f->second, x, y});
+    }
+    items.swap(out);
+    b->slots = std::max(b->slots, level_slots);
+  }
+}
+
+}  // namespace
+
 int build_backward(const Symbolic& s, Plan* p, BackPlan* b, std::string* why) {
   (void)why;
   *b = BackPlan();
@@ -1457,6 +1554,7 @@ int build_backward(const Symbolic& s, Plan* p, BackPlan* b, std::string* why) {
     add_task(lv, dtask);
   }
   b->level_items.resize((size_t)nlev);
+  split_backward(b, nb);
   // input entries on the diagonal: the first entry of each column
   b->diagflag.assign((size_t)s.qnz, 0);
   for (int64_t j = 0; j < s.n; ++j) b->diagflag[(size_t)s.qp[j]] = 1;

@@ -198,12 +198,27 @@ struct ConTask {
   double alpha;
 };
 
+// A task whose terms are split over several work-group sets: its first part
+// writes the output tile as the task would, part s > 0 writes alpha times its
+// own terms' sum into partial slot s - 1 (c_rows x n_b doubles, row stride
+// n_b, starting at slot_off), and after the level's contraction kernel a fold
+// kernel adds the slots, in slot order, to the output.
+struct FoldTask {
+  int64_t c_off;
+  int32_t c_buf, c_rows, ncols, diag;
+  int64_t slot_off;
+  int32_t nslots;
+};
+
 struct BackPlan {
   std::vector<ConTerm> terms;
   std::vector<ConTask> tasks;
   std::vector<std::vector<int32_t>> level_items;  // per level: task, block row, block col
   std::vector<int32_t> trtri_items;               // level 0: pairs (k, block column)
   std::vector<int8_t> diagflag;                   // input entry is a diagonal entry
+  std::vector<FoldTask> folds;
+  std::vector<std::vector<int32_t>> fold_items;   // per level: fold, block row, block col
+  int64_t slots = 0;  // doubles of partial-slot scratch, reused level after level
   double flops = 0;
 };
 

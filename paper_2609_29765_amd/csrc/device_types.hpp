@@ -47,6 +47,12 @@ struct ConTaskD {
   double alpha;
 };
 
+struct FoldTaskD {     // output of a split reverse-mode task and its partial slots
+  int64_t c_off, slot_off;
+  int32_t c_buf, c_rows, ncols, diag;
+  int32_t nslots, pad;
+};
+
 struct TileD {        // off-diagonal tile as the solve sees it
   int64_t off;        // store offset
   int64_t roff;       // offset of its active rows in the row pool

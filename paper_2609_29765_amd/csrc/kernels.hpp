@@ -1249,6 +1249,7 @@ struct BackArgs {
   const double* L;  // factor store
   double* Z;        // selected-inverse store (same layout)
   double* M;        // L_mk G_k in the off-diagonal slots, G_k in the diagonal slots
+  double* P;        // partial slots of split tasks (output buffer 4)
 };
 
 template <int NB>
@@ -1337,7 +1338,7 @@ __global__ __launch_bounds__(256) void k_backcon(BackArgs g) {
       __syncthreads();
     }
   }
-  double* C = (u.c_buf == 0 ? nullptr : (u.c_buf == 1 ? g.Z : g.M)) + u.c_off;
+  double* C = (u.c_buf == 4 ? g.P : u.c_buf == 1 ? g.Z : g.M) + u.c_off;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -1352,6 +1353,32 @@ __global__ __launch_bounds__(256) void k_backcon(BackArgs g) {
           *cp = u.beta ? *cp + v : v;
         }
       }
+}
+
+// after a contraction level whose long tasks were split: each split task's
+// output block (64 x 64, the contraction's blocking) gets the sum of its
+// partial slots, added in slot order; thread t covers row t / 4 of the block,
+// 16 consecutive columns
+template <int NB>
+__global__ __launch_bounds__(256) void k_backfold(const int32_t* __restrict__ items,
+                                                  const FoldTaskD* __restrict__ folds, double* __restrict__ Z,
+                                                  double* __restrict__ M, const double* __restrict__ P) {
+  const int32_t fi = items[3 * blockIdx.x], bx = items[3 * blockIdx.x + 1], by = items[3 * blockIdx.x + 2];
+  const FoldTaskD f = folds[fi];
+  double* C = (f.c_buf == 1 ? Z : M) + f.c_off;
+  const int32_t i = bx * CB + (int32_t)(threadIdx.x >> 2);
+  const int32_t j0 = by * CB + 16 * (int32_t)(threadIdx.x & 3);
+  if (i >= f.c_rows) return;
+  const int64_t slot = (int64_t)f.c_rows * NB;
+#pragma unroll 4
+  for (int e = 0; e < 16; ++e) {
+    const int32_t j = j0 + e;
+    if (j >= f.ncols || (f.diag && j > i)) continue;
+    const double* p = P + f.slot_off + (int64_t)i * NB + j;
+    double sum = 0.0;
+    for (int32_t s = 0; s < f.nslots; ++s) sum += p[s * slot];
+    C[(int64_t)i * NB + j] += sum;
+  }
 }
 
 // gradient of log det with respect to the input values (lower triangle of a

@@ -23,7 +23,7 @@ namespace stc {
 namespace {
 
 constexpr char kMagic[8] = {'S', 'T', 'C', 'P', 'L', 'A', 'N', '\0'};
-constexpr uint32_t kVersion = 3;
+constexpr uint32_t kVersion = 4;
 
 // running checksum over a field's bytes: 64-bit words, then the tail
 uint64_t mix(uint64_t h, const char* c, size_t n) {
@@ -91,8 +91,14 @@ void fields(A& a, ConTask& t) {
 }
 
 template <class A>
+void fields(A& a, FoldTask& f) {
+  a(f.c_off); a(f.c_buf); a(f.c_rows); a(f.ncols); a(f.diag); a(f.slot_off); a(f.nslots);
+}
+
+template <class A>
 void fields(A& a, BackPlan& b) {
-  a(b.terms); a(b.tasks); a(b.level_items); a(b.trtri_items); a(b.diagflag); a(b.flops);
+  a(b.terms); a(b.tasks); a(b.level_items); a(b.trtri_items); a(b.diagflag); a(b.folds); a(b.fold_items);
+  a(b.slots); a(b.flops);
 }
 
 struct Writer {

@@ -171,6 +171,11 @@ struct stc_handle {
   BackPlan back;
   std::vector<int32_t> back_items;       // flattened per level
   std::vector<int32_t> back_level_ptr;   // items of level L: [ptr[L], ptr[L+1])
+  std::vector<int32_t> fold_items;       // fold items of split tasks, flattened per level
+  std::vector<int32_t> fold_level_ptr;
+  FoldTaskD* d_bfolds = nullptr;
+  int32_t* d_bfitems = nullptr;
+  double* d_bslots = nullptr;  // partial slots of split reverse-mode tasks
   ConTermD* d_bterms = nullptr;
   ConTaskD* d_btasks = nullptr;
   int32_t* d_bitems = nullptr;
@@ -233,6 +238,9 @@ size_t layout(const stc_handle* hc, int32_t batch, char* base) {
   take(&h->d_bterms, sizeof(ConTermD) * h->back.terms.size());
   take(&h->d_btasks, sizeof(ConTaskD) * h->back.tasks.size());
   take(&h->d_bitems, sizeof(int32_t) * h->back_items.size());
+  take(&h->d_bfolds, sizeof(FoldTaskD) * h->back.folds.size());
+  take(&h->d_bfitems, sizeof(int32_t) * h->fold_items.size());
+  take(&h->d_bslots, sizeof(double) * (size_t)h->back.slots);
   take(&h->d_trtri, sizeof(int32_t) * h->back.trtri_items.size());
   take(&h->d_bdiag, sizeof(int8_t) * h->back.diagflag.size());
   take(&h->d_zs, sizeof(double) * (size_t)p.store);
@@ -622,11 +630,16 @@ int launch_backward_nb(stc_handle* h, hipStream_t st) {
   g.L = h->d_store;
   g.Z = h->d_zs;
   g.M = h->d_ms;
+  g.P = h->d_bslots;
   for (size_t L = 0; L + 1 < h->back_level_ptr.size(); ++L) {
     const int32_t a = h->back_level_ptr[L], b = h->back_level_ptr[L + 1];
     if (b == a) continue;
     g.items = h->d_bitems + 3 * (int64_t)a;
     hipLaunchKernelGGL((k_backcon<NB>), dim3(b - a), dim3(256), sizeof(double) * con_lds<NB>(), st, g);
+    const int32_t fa = h->fold_level_ptr[L], fb = h->fold_level_ptr[L + 1];
+    if (fb > fa)
+      hipLaunchKernelGGL((k_backfold<NB>), dim3(fb - fa), dim3(256), 0, st, h->d_bfitems + 3 * (int64_t)fa,
+                         (const FoldTaskD*)h->d_bfolds, h->d_zs, h->d_ms, (const double*)h->d_bslots);
   }
   HIPCHK(hipGetLastError());
   return 0;
@@ -777,6 +790,12 @@ static void finish_handle(stc_handle* h) {
   for (const auto& li : h->back.level_items) {
     h->back_items.insert(h->back_items.end(), li.begin(), li.end());
     h->back_level_ptr.push_back((int32_t)(h->back_items.size() / 3));
+  }
+  h->fold_level_ptr.assign(1, 0);
+  for (size_t L = 0; L < h->back.level_items.size(); ++L) {
+    if (L < h->back.fold_items.size())
+      h->fold_items.insert(h->fold_items.end(), h->back.fold_items[L].begin(), h->back.fold_items[L].end());
+    h->fold_level_ptr.push_back((int32_t)(h->fold_items.size() / 3));
   }
   // flatten the level lists
   for (const Level& L : h->plan.levels) {
@@ -1019,6 +1038,12 @@ int stc_bind(stc_handle* h, void* d_ws, size_t bytes, int32_t batch, void* strea
     const ConTask& t = bp.tasks[i];
     bk[i] = ConTaskD{t.c_off, t.c_buf, t.c_rows, t.ncols, t.diag, t.t_begin, t.t_end, t.beta, 0, t.alpha};
   }
+  std::vector<FoldTaskD> bf(bp.folds.size());
+  for (size_t i = 0; i < bf.size(); ++i) {
+    const FoldTask& f = bp.folds[i];
+    bf[i] = FoldTaskD{f.c_off, f.slot_off, f.c_buf, f.c_rows, f.ncols, f.diag, f.nslots, 0};
+  }
+  if ((rc = upload(h->d_bfolds, bf)) || (rc = upload(h->d_bfitems, h->fold_items))) return rc;
   if ((rc = upload(h->d_bterms, bt)) || (rc = upload(h->d_btasks, bk)) ||
       (rc = upload(h->d_bitems, h->back_items)) || (rc = upload(h->d_trtri, bp.trtri_items)) ||
       (rc = upload(h->d_bdiag, bp.diagflag)))
