@@ -1357,8 +1357,10 @@ __global__ __launch_bounds__(256) void k_backcon(BackArgs g) {
 
 // after a contraction level whose long tasks were split: each split task's
 // output block (64 x 64, the contraction's blocking) gets the sum of its
-// partial slots, added in slot order; thread t covers row t / 4 of the block,
-// 16 consecutive columns
+// partial slots, added in slot order.  Work-group (item, y) covers rows
+// 16 y .. 16 y + 15 of the item's block, thread t four consecutive columns
+// 4 (t % 16) .. of row t / 16; the slots' values are read four slots at a
+// time so that their loads are in flight together.
 template <int NB>
 __global__ __launch_bounds__(256) void k_backfold(const int32_t* __restrict__ items,
                                                   const FoldTaskD* __restrict__ folds, double* __restrict__ Z,
@@ -1366,19 +1368,41 @@ __global__ __launch_bounds__(256) void k_backfold(const int32_t* __restrict__ it
   const int32_t fi = items[3 * blockIdx.x], bx = items[3 * blockIdx.x + 1], by = items[3 * blockIdx.x + 2];
   const FoldTaskD f = folds[fi];
   double* C = (f.c_buf == 1 ? Z : M) + f.c_off;
-  const int32_t i = bx * CB + (int32_t)(threadIdx.x >> 2);
-  const int32_t j0 = by * CB + 16 * (int32_t)(threadIdx.x & 3);
-  if (i >= f.c_rows) return;
+  const int32_t i = bx * CB + 16 * (int32_t)blockIdx.y + (int32_t)(threadIdx.x >> 4);
+  const int32_t j = by * CB + 4 * (int32_t)(threadIdx.x & 15);
+  if (i >= f.c_rows || j >= f.ncols || (f.diag && j > i)) return;
   const int64_t slot = (int64_t)f.c_rows * NB;
-#pragma unroll 4
-  for (int e = 0; e < 16; ++e) {
-    const int32_t j = j0 + e;
-    if (j >= f.ncols || (f.diag && j > i)) continue;
-    const double* p = P + f.slot_off + (int64_t)i * NB + j;
-    double sum = 0.0;
-    for (int32_t s = 0; s < f.nslots; ++s) sum += p[s * slot];
-    C[(int64_t)i * NB + j] += sum;
+  const double* p = P + f.slot_off + (int64_t)i * NB + j;  // j, NB and every offset even: 16-byte aligned pairs
+  double4 sum = {0.0, 0.0, 0.0, 0.0};
+  int32_t s = 0;
+  for (; s + 4 <= f.nslots; s += 4) {
+    double2 v[4][2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q][0] = *reinterpret_cast<const double2*>(p + (s + q) * slot);
+      v[q][1] = *reinterpret_cast<const double2*>(p + (s + q) * slot + 2);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      sum.x += v[q][0].x;
+      sum.y += v[q][0].y;
+      sum.z += v[q][1].x;
+      sum.w += v[q][1].y;
+    }
   }
+  for (; s < f.nslots; ++s) {
+    const double2 a = *reinterpret_cast<const double2*>(p + s * slot);
+    const double2 b = *reinterpret_cast<const double2*>(p + s * slot + 2);
+    sum.x += a.x;
+    sum.y += a.y;
+    sum.z += b.x;
+    sum.w += b.y;
+  }
+  double* c = C + (int64_t)i * NB + j;
+  const double add[4] = {sum.x, sum.y, sum.z, sum.w};
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (j + e < f.ncols && (!f.diag || j + e <= i)) c[e] += add[e];
 }
 
 // gradient of log det with respect to the input values (lower triangle of a

@@ -638,7 +638,7 @@ int launch_backward_nb(stc_handle* h, hipStream_t st) {
     hipLaunchKernelGGL((k_backcon<NB>), dim3(b - a), dim3(256), sizeof(double) * con_lds<NB>(), st, g);
     const int32_t fa = h->fold_level_ptr[L], fb = h->fold_level_ptr[L + 1];
     if (fb > fa)
-      hipLaunchKernelGGL((k_backfold<NB>), dim3(fb - fa), dim3(256), 0, st, h->d_bfitems + 3 * (int64_t)fa,
+      hipLaunchKernelGGL((k_backfold<NB>), dim3(fb - fa, CB / 16), dim3(256), 0, st, h->d_bfitems + 3 * (int64_t)fa,
                          (const FoldTaskD*)h->d_bfolds, h->d_zs, h->d_ms, (const double*)h->d_bslots);
   }
   HIPCHK(hipGetLastError());
