@@ -208,8 +208,11 @@ int stc_solve_noalloc(stc_handle* h, double* d_b, int32_t nrhs, void* stream);
    restricted to the pattern of L is the selected inverse Z = A^-1 on that
    pattern (the selected inversion that consumes the resident factor, Sec.
    6.7), computed on the device by the blocked Takahashi recurrence over the
-   tile DAG in reverse order (one graph launch), from the factor and the 32 x
-   32 diagonal-block inverses the factorization left in the workspace.  Writes
+   tile DAG in reverse order (one graph launch; long tasks of a level are
+   split over several work-groups and their partial results added after the
+   level in a fixed order, so the result is reproducible bit for bit), from
+   the factor and the 32 x 32 diagonal-block inverses the factorization left
+   in the workspace.  Writes
    NaN everywhere when that factorization failed (stc_info != 0).  Overwrites
    the workspace's selected-inverse scratch; the factor is left intact. */
 int stc_logdet_backward(stc_handle* h, const double* d_gbar, double* d_grad_values, void* stream);
@@ -281,8 +284,9 @@ int stc_get_batch_factor(stc_handle* h, int32_t member, double* h_Lx, void* stre
    load bytes: 16 per input entry (value and its load entry) plus 8 per
    stored double (the store written once); [7] levels;
    [8] flops of stc_logdet_backward (tile products of the selected-inverse
-   recurrence, 2 per multiply-add); [9] its levels (kernel launches after the
-   diagonal-tile inverses). */
+   recurrence, 2 per multiply-add); [9] its levels after the diagonal-tile
+   inverses: one contraction launch each, followed by a launch that folds the
+   partial results where the level's long tasks were split. */
 int stc_get_work(const stc_handle* h, double* work);
 
 /* Shape of the replayed schedule (host, no device work), stats (host)
