@@ -164,6 +164,29 @@ def test_backward_leaves_factor_and_repeats():
     assert np.array_equal(a.factor(), L0)
 
 
+@pytest.mark.parametrize("nb,align", [(128, 512), (64, 256)])
+def test_split_reverse_levels_reproducible_and_match_oracle(nb, align):
+    """The differentiable arrowhead's reverse-mode levels hold tasks with many
+    terms, which the plan splits over several work-groups and folds after the
+    level in a fixed order: gradients equal the oracle's to 1e-10 and are bit
+    for bit the same on every call, with refactorizations between calls."""
+    w = W.differentiable_arrowhead(20, 25, 8, 0)
+    o = O.Analysis(w.n, w.colptr, w.rowind, "nd", nb=nb)
+    Lo, info = o.factor(w.values)
+    assert info == 0
+    go = o.logdet_grad_values(Lo)
+    a = S.Analysis(w.n, w.colptr, w.rowind, nb=nb, ordering="nd", align=align).bind()
+    v = dev(w.values)
+    one = torch.ones(1, dtype=torch.float64, device="cuda")
+    print(f"[gpu] split reverse nb={nb} align={align} levels={a.work()['levels_backward']}", flush=True)
+    gs = []
+    for _ in range(3):
+        a.factorize(v)
+        gs.append(a.logdet_backward(one).cpu().numpy())
+    assert np.max(np.abs(gs[0] - go)) <= 1e-10 * np.max(np.abs(go))
+    assert np.array_equal(gs[0], gs[1]) and np.array_equal(gs[0], gs[2])
+
+
 def test_backward_after_failed_factorization_is_nan():
     w = W.random_spd(100, 0.05, 7)
     vals = w.values.copy()
