@@ -333,6 +333,20 @@ int stc_check_schedule(const stc_handle* h, int64_t* stats);
    naming the violation. */
 int stc_check_solve_schedule(const stc_handle* h, int64_t* stats);
 
+/* Host check of the reverse-mode plan (stc_logdet_backward, stc_selinv), no
+   device work.  Its levels run in order: the diagonal-tile inverses G_k,
+   then one contraction launch per level, each followed by a launch that folds
+   the partial results of the level's split tasks.  Verified: every term of
+   the recurrence belongs to exactly one task; every tile a level reads (Z,
+   M = L_mk G_k, G_k) was written at an earlier level; every Z and M tile is
+   written by one task of one level (the diagonal Z_kk accumulating once into
+   H_k); partial slots lie in the slot scratch and the slots of one level are
+   disjoint; each fold adds, to a tile its level wrote, slots that the level's
+   parts wrote.  stats (host) int64[5]: levels, tasks, tile reads checked,
+   folds, partial slots.  Returns 0, STC_ERR_ARG for a null argument, or
+   STC_ERR_SCHEDULE with stc_last_error naming the violation. */
+int stc_check_backward(const stc_handle* h, int64_t* stats);
+
 /* Measurement helper: one factorization of d_values (device) double[nnz]
    with the same kernels as stc_factorize, launched one by one instead of from
    the graph, with a HIP event pair around each launch on `stream`;

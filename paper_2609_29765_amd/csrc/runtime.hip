@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <mutex>
 #include <string>
 #include <type_traits>
@@ -1332,6 +1333,96 @@ int stc_get_tiles(const stc_handle* h, int32_t* m, int32_t* k, int32_t* cnt, int
 int stc_get_tasks(const stc_handle* h, int32_t* tasks) {
   if (!h || !tasks) return fail(STC_ERR_ARG, "null argument");
   std::copy(h->sym.tasks.begin(), h->sym.tasks.end(), tasks);
+  return 0;
+}
+
+// Host check of the reverse-mode plan: levels run in order (one contraction
+// launch each, then a fold launch where tasks were split).
+int stc_check_backward(const stc_handle* h, int64_t* stats) {
+  if (!h || !stats) return fail(STC_ERR_ARG, "null argument");
+  const BackPlan& b = h->back;
+  const int64_t nb = h->plan.nb;
+  enum { BUF_Z = 1, BUF_G = 2, BUF_M = 3, BUF_P = 4 };
+  // every term belongs to exactly one task
+  std::vector<int32_t> owner(b.terms.size(), 0);
+  for (const ConTask& t : b.tasks) {
+    if (t.t_begin < 0 || t.t_end > (int32_t)b.terms.size() || t.t_begin > t.t_end)
+      return fail(STC_ERR_SCHEDULE, "reverse-mode task with a term range outside the terms");
+    for (int32_t x = t.t_begin; x < t.t_end; ++x) owner[(size_t)x]++;
+  }
+  for (int32_t o : owner)
+    if (o != 1) return fail(STC_ERR_SCHEDULE, "a reverse-mode term belongs to no task or to several");
+  // level at which each Z / M tile is written: M tiles and the diagonal H_k
+  // at level 1 (G_k by the inverses before it, level 0), the rest once each
+  std::map<std::pair<int32_t, int64_t>, int32_t> written;  // (buffer, offset) -> level
+  auto key = [](int32_t buf, int64_t off) { return std::make_pair(buf == BUF_G ? (int32_t)BUF_M : buf, off); };
+  for (int32_t k = 0; k < h->plan.NT; ++k) written[key(BUF_G, (int64_t)k * nb * nb)] = 0;
+  int64_t reads = 0, slots_used = 0;
+  for (size_t L = 1; L < b.level_items.size(); ++L) {
+    const std::vector<int32_t>& it = b.level_items[L];
+    std::vector<int32_t> ids;
+    for (size_t q = 0; q < it.size(); q += 3) ids.push_back(it[q]);
+    std::sort(ids.begin(), ids.end());
+    ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+    std::vector<std::pair<int64_t, int64_t>> slot_rng;
+    std::vector<std::pair<int32_t, int64_t>> outs;
+    for (int32_t id : ids) {
+      const ConTask& t = b.tasks[(size_t)id];
+      // inputs: Z tiles written at an earlier level, M and G tiles before the
+      // contraction levels
+      for (int32_t x = t.t_begin; x < t.t_end; ++x) {
+        const ConTerm& c = b.terms[(size_t)x];
+        for (const auto& in : {std::make_pair(c.a_buf, c.a_off), std::make_pair(c.b_buf, c.b_off)}) {
+          if (in.first == 0) continue;  // the factor itself
+          auto w = written.find(key(in.first, in.second));
+          if (w == written.end() || w->second >= (int32_t)L)
+            return fail(STC_ERR_SCHEDULE, "reverse-mode level " + std::to_string(L) +
+                                              " reads a tile not written at an earlier level");
+          ++reads;
+        }
+      }
+      if (t.c_buf == BUF_P) {
+        if (t.c_off < 0 || t.c_off + (int64_t)t.c_rows * nb > b.slots)
+          return fail(STC_ERR_SCHEDULE, "reverse-mode partial slot outside the slot scratch");
+        slot_rng.emplace_back(t.c_off, t.c_off + (int64_t)t.c_rows * nb);
+      } else {
+        outs.push_back(key(t.c_buf, t.c_off));
+      }
+    }
+    std::sort(slot_rng.begin(), slot_rng.end());
+    for (size_t i = 1; i < slot_rng.size(); ++i)
+      if (slot_rng[i].first < slot_rng[i - 1].second)
+        return fail(STC_ERR_SCHEDULE, "reverse-mode partial slots of one level overlap");
+    slots_used += (int64_t)slot_rng.size();
+    for (const auto& o : outs) {
+      auto w = written.find(o);
+      // the diagonal Z_kk accumulates into H_k, written at level 1
+      const bool acc_diag = w != written.end() && w->second == 1 && o.first == BUF_Z && L > 1;
+      if (w != written.end() && !acc_diag)
+        return fail(STC_ERR_SCHEDULE, "a reverse-mode tile is written twice");
+      written[o] = (int32_t)L;
+    }
+    if (outs.size() != std::set<std::pair<int32_t, int64_t>>(outs.begin(), outs.end()).size())
+      return fail(STC_ERR_SCHEDULE, "two tasks of one reverse-mode level write one tile");
+    // folds of this level: each adds slots that this level's parts wrote to
+    // a tile this level wrote
+    if (L < b.fold_items.size())
+      for (size_t q = 0; q < b.fold_items[L].size(); q += 3) {
+        const FoldTask& f = b.folds[(size_t)b.fold_items[L][q]];
+        if (std::find(outs.begin(), outs.end(), key(f.c_buf, f.c_off)) == outs.end())
+          return fail(STC_ERR_SCHEDULE, "a fold adds to a tile its level does not write");
+        for (int32_t x = 0; x < f.nslots; ++x) {
+          const int64_t lo = f.slot_off + (int64_t)x * f.c_rows * nb;
+          if (!std::binary_search(slot_rng.begin(), slot_rng.end(), std::make_pair(lo, lo + (int64_t)f.c_rows * nb)))
+            return fail(STC_ERR_SCHEDULE, "a fold reads a slot no part of its level writes");
+        }
+      }
+  }
+  stats[0] = (int64_t)b.level_items.size();
+  stats[1] = (int64_t)b.tasks.size();
+  stats[2] = reads;
+  stats[3] = (int64_t)b.folds.size();
+  stats[4] = slots_used;
   return 0;
 }
 

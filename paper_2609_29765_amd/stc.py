@@ -31,7 +31,7 @@ EXPORTS = [
     "stc_analyse", "stc_workspace_bytes", "stc_bind", "stc_factorize", "stc_factorize_batched",
     "stc_logdet", "stc_solve", "stc_solve_noalloc", "stc_solve_batched", "stc_logdet_backward", "stc_selinv", "stc_get_selinv", "stc_info", "stc_get_sizes",
     "stc_get_features", "stc_get_perm", "stc_get_etree", "stc_get_L_pattern", "stc_get_tiles",
-    "stc_get_tasks", "stc_get_grid_positions", "stc_get_factor", "stc_get_batch_factor", "stc_get_work", "stc_get_plan_stats", "stc_check_schedule", "stc_check_solve_schedule", "stc_profile_factorize",
+    "stc_get_tasks", "stc_get_grid_positions", "stc_get_factor", "stc_get_batch_factor", "stc_get_work", "stc_get_plan_stats", "stc_check_schedule", "stc_check_solve_schedule", "stc_check_backward", "stc_profile_factorize",
     "stc_fp64_mfma_peak", "stc_save", "stc_load", "stc_destroy",
     "stc_last_error",
 ]
@@ -87,6 +87,7 @@ def lib():
     L.stc_get_plan_stats.argtypes = [vp, _i64p]
     L.stc_check_schedule.argtypes = [vp, _i64p]
     L.stc_check_solve_schedule.argtypes = [vp, _i64p]
+    L.stc_check_backward.argtypes = [vp, _i64p]
     L.stc_profile_factorize.argtypes = [vp, vp, vp, _f64p, _i64p, _f64p]
     L.stc_fp64_mfma_peak.argtypes = [vp, _f64p]
     L.stc_save.argtypes = [vp, C.c_char_p]
@@ -377,6 +378,13 @@ class Analysis:
         st = np.zeros(4, dtype=np.int64)
         _check(lib().stc_check_solve_schedule(self._h, st))
         return dict(zip(["launches", "step_items", "panel_items", "fused_launches"], (int(x) for x in st)))
+
+    def check_backward(self):
+        """Host check of the reverse-mode plan (see stc_check_backward);
+        raises on a violation.  Returns {levels, tasks, reads, folds, slots}."""
+        st = np.zeros(5, dtype=np.int64)
+        _check(lib().stc_check_backward(self._h, st))
+        return dict(zip(["levels", "tasks", "reads", "folds", "slots"], (int(x) for x in st)))
 
     KERNEL_KINDS = ["load", "k_potrf", "k_upd<G>", "k_upd", "k_trsm"]
 

@@ -150,3 +150,31 @@ def test_batch_hint_balances_each_set_for_its_share():
     assert half.plan_stats() == S.Analysis(w.n, w.colptr, w.rowind, nb=64, ordering="nd", align=128,
                                            wg_slots=448).plan_stats()
     _check(w, 64, "nd", align=128, batch=128)
+
+
+@pytest.mark.parametrize("case", ["random", "dense", "gmrf_nd", "arrowhead_aligned", "differentiable_full", "batched_lap"])
+def test_backward_plan(case):
+    """stc_check_backward on the reverse-mode plan: every term in exactly one
+    task, every tile read written at an earlier level, every tile written
+    once, partial slots in bounds and disjoint per level, folds matching the
+    parts of their level.  Long tasks are split (folds > 0) where the levels
+    hold tasks with many terms."""
+    if case == "random":
+        w, kw = W.random_spd(500, 0.02, 3), dict(nb=32, ordering="nd")
+    elif case == "dense":
+        w, kw = W.dense_spd(700, 0.3, 1), dict(nb=128, ordering="natural")
+    elif case == "gmrf_nd":
+        w, kw = W.gmrf_grid2d(40, 40), dict(nb=64, ordering="nd")
+    elif case == "arrowhead_aligned":
+        w, kw = W.spatiotemporal_arrowhead(T=12, m=20, nborder=8), dict(nb=64, ordering="nd", align=128)
+    elif case == "differentiable_full":
+        w, kw = W.differentiable_arrowhead(20, 25, 8, 0), dict(nb=128, ordering="nd", align=512)
+    else:
+        w, kw = W.batched_laplacian3d(m=12, B=2), dict(nb=32, ordering="nd")
+    a = S.Analysis(w.n, w.colptr, w.rowind, **kw)
+    st = a.check_backward()
+    print(case, st)
+    assert st["levels"] >= 3 and st["reads"] > 0
+    assert st["levels"] == a.work()["levels_backward"]
+    if case in ("differentiable_full", "arrowhead_aligned", "random"):
+        assert st["folds"] > 0 and st["slots"] > 0
