@@ -25,7 +25,8 @@ def exports(a):
             "features": (a.phi, a.rho, a.sigma), "perm": a.perm(), "etree": a.etree(), "lp": lp, "li": li,
             "positions": a.grid_positions(),
             **{f"tile_{k}": v for k, v in t.items()}, "tasks": a.tasks(), "work": a.work(),
-            "plan": a.plan_stats(), "schedule": a.check_schedule(), "solve": a.check_solve_schedule()}
+            "plan": a.plan_stats(), "schedule": a.check_schedule(), "solve": a.check_solve_schedule(),
+            "backward": a.check_backward()}
 
 
 def same(x, y):
