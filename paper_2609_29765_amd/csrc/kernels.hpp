@@ -1310,11 +1310,23 @@ __global__ __launch_bounds__(256) void k_backcon(BackArgs g) {
       }
       const int32_t pb = k0 + bp;
       const int32_t qb = pb < c.K ? bq[pb] : -1;
+      if constexpr (NB >= CB) {
+        // the eight columns lie inside the row (c0 + 64 <= NB): four 16-byte
+        // reads of one contiguous run (row and column offsets even)
+        const double* brow = B + (int64_t)max(qb, 0) * NB + c0 + bj;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int32_t j = c0 + bj + e;
-        const double v = B[(int64_t)max(qb, 0) * NB + min(j, NB - 1)];
-        bv[e] = (qb >= 0 && j < NB) ? v : 0.0;
+        for (int e = 0; e < 4; ++e) {
+          const double2 v = *reinterpret_cast<const double2*>(brow + 2 * e);
+          bv[2 * e] = qb >= 0 ? v.x : 0.0;
+          bv[2 * e + 1] = qb >= 0 ? v.y : 0.0;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int32_t j = c0 + bj + e;
+          const double v = B[(int64_t)max(qb, 0) * NB + min(j, NB - 1)];
+          bv[e] = (qb >= 0 && j < NB) ? v : 0.0;
+        }
       }
     };
     fetch(0);
