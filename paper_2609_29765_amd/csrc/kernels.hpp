@@ -1294,19 +1294,37 @@ __global__ __launch_bounds__(256) void k_backcon(BackArgs g) {
     }
     __syncthreads();
     double av[8], bv[8];
+    // A's eight elements are one contiguous run of a stored row when the
+    // index that varies along them is not mapped: p of a stored A with no K
+    // map, r of a transposed A with no row map (tiles of 64 and more, so the
+    // run stays inside the row; offsets even)
+    const bool arun = NB >= CB && ((c.a_mode == CA_NORMAL && c.a_qmap < 0) || (tr && c.a_rmap < 0));
     auto fetch = [&](int32_t k0) {
+      if (arun) {
+        const int32_t rr = tr ? (k0 + apq_t < c.K ? aq[k0 + apq_t] : -1) : arow[arow_n];
+        const int32_t s0 = tr ? r0 + arow_t : k0 + apq_n;  // first index along the run
+        const int32_t lim = tr ? u.c_rows : c.K;
+        const double* arp = A + (int64_t)max(rr, 0) * NB + s0;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int32_t rl = tr ? arow_t + e : arow_n;
-        const int32_t pl = k0 + (tr ? apq_t : apq_n + e);
-        const int32_t rr = arow[rl], qq = pl < c.K ? aq[pl] : -1;
-        const int32_t rc = max(rr, 0), qc = max(qq, 0);
-        int64_t off;
-        if (c.a_mode == CA_NORMAL) off = (int64_t)rc * NB + qc;
-        else if (tr) off = (int64_t)qc * NB + rc;
-        else off = (int64_t)max(rc, qc) * NB + min(rc, qc);
-        const double v = A[off];
-        av[e] = (rr >= 0 && qq >= 0) ? v : 0.0;
+        for (int e = 0; e < 4; ++e) {
+          const double2 v = *reinterpret_cast<const double2*>(arp + 2 * e);
+          av[2 * e] = (rr >= 0 && s0 + 2 * e < lim) ? v.x : 0.0;
+          av[2 * e + 1] = (rr >= 0 && s0 + 2 * e + 1 < lim) ? v.y : 0.0;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int32_t rl = tr ? arow_t + e : arow_n;
+          const int32_t pl = k0 + (tr ? apq_t : apq_n + e);
+          const int32_t rr = arow[rl], qq = pl < c.K ? aq[pl] : -1;
+          const int32_t rc = max(rr, 0), qc = max(qq, 0);
+          int64_t off;
+          if (c.a_mode == CA_NORMAL) off = (int64_t)rc * NB + qc;
+          else if (tr) off = (int64_t)qc * NB + rc;
+          else off = (int64_t)max(rc, qc) * NB + min(rc, qc);
+          const double v = A[off];
+          av[e] = (rr >= 0 && qq >= 0) ? v : 0.0;
+        }
       }
       const int32_t pb = k0 + bp;
       const int32_t qb = pb < c.K ? bq[pb] : -1;
