@@ -1309,15 +1309,17 @@ namespace {
 // its longest work item: the task with the most terms.  An item costs its
 // terms' K chunks of 32 plus one per term (its maps) and one (the epilogue).
 // A level whose longest item costs at least twice the target -- 2, or the
-// mean load of 1,024 concurrent work-groups if larger (the best of a sweep on
-// MI355X) -- splits each task costlier than the target into parts of about
+// mean load of 2,048 work-groups if larger: twice as many as the contraction
+// kernel keeps resident (four per compute unit), so that a level's last
+// round of items is short (the best of 1,024, 2,048 and 4,096 on MI355X) --
+// splits each task costlier than the target into parts of about
 // the target, cut at term boundaries (at most 32 parts):
 // part 0 keeps the task's output, parts s > 0 write partial slots that a
 // fold kernel adds to it after the level (FoldTask).  Slots are reused from
 // one level to the next, since the levels run in sequence.
 void split_backward(BackPlan* b, int32_t nb) {
   constexpr int32_t kChunk = 32;
-  constexpr double kWorkGroups = 1024, kMinCost = 2;
+  constexpr double kWorkGroups = 2048, kMinCost = 2;
   constexpr int32_t kMaxParts = 32;
   enum { BUF_P = 4 };
   auto term_cost = [&](int32_t t) { return (double)((b->terms[(size_t)t].K + kChunk - 1) / kChunk) + 1.0; };

@@ -1234,10 +1234,10 @@ __global__ __launch_bounds__(256) void k_trtri(const int32_t* __restrict__ items
 // task.  A_t(r, p) is read through the term's row map and contraction map in
 // one of three forms (stored tile, transposed tile, symmetric diagonal tile
 // with its lower triangle stored); B_t(p, j) is row p of a tile (through an
-// optional map), j the output column.  K is staged in LDS in chunks of 16.
+// optional map), j the output column.  K is staged in LDS in chunks of 32.
 constexpr int CB = 64;
 constexpr int CKT = 32;
-constexpr int CLD = CKT + 1;
+constexpr int CLD = CKT + 2;  // a staged row: 16 K pairs and one pair of padding
 template <int NB>
 constexpr int con_lds() { return 2 * CB * CLD + (CB + 2 * NB + 1) / 2; }  // As, Bs, row map, two K maps
 
@@ -1253,7 +1253,7 @@ struct BackArgs {
 };
 
 template <int NB>
-__global__ __launch_bounds__(256) void k_backcon(BackArgs g) {
+__global__ __launch_bounds__(256, 4) void k_backcon(BackArgs g) {
   extern __shared__ double smem[];
   double* As = smem;
   double* Bs = smem + CB * CLD;
@@ -1271,13 +1271,16 @@ __global__ __launch_bounds__(256) void k_backcon(BackArgs g) {
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
   // Per term, its row map and both contraction maps go to LDS once; then the
   // 32-wide chunks of K run with the next chunk's values read into registers
-  // while the current one is on MFMA.  Each thread stages eight A elements --
-  // (row tid/4, p = 8 (tid%4) .. +7) for a stored or symmetric A, (rows
-  // 8 (tid%8) .. +7, p = tid/8) for a transposed one -- and eight B elements
-  // (p = tid/8, columns c0 + 8 (tid%8) .. +7).
-  const int arow_n = tid >> 2, apq_n = (tid & 3) * 8;
-  const int arow_t = (tid & 7) * 8, apq_t = tid >> 3;
-  const int bp = tid >> 3, bj = (tid & 7) * 8;
+  // while the current one is on MFMA.  In LDS a row (an output row of A, an
+  // output column of B) holds its chunk as 16 K pairs, padded so that 16
+  // lanes reading one pair of 16 consecutive rows touch every bank once.
+  // Each thread stages eight A and eight B values as four K pairs: a stored
+  // or symmetric A gives row ra, pairs 4 (tid % 4) .. +3 (a run along the
+  // stored row); a transposed A, like B, gives pair kp of rows (A) or
+  // columns (B) jl + 16 x, x = 0..3 (16 lanes cover 16 consecutive values
+  // of the stored row).
+  const int ra = tid >> 2, pa = (tid & 3) * 4;
+  const int kp = tid >> 4, jl = tid & 15;
   for (int32_t t = u.t_begin; t < u.t_end; ++t) {
     const ConTermD c = g.terms[t];
     const double* A = (c.a_buf == 0 ? g.L : (c.a_buf == 1 ? g.Z : g.M)) + c.a_off;
@@ -1293,77 +1296,122 @@ __global__ __launch_bounds__(256) void k_backcon(BackArgs g) {
       bq[p] = c.b_qmap < 0 ? p : g.maps[c.b_qmap + p];
     }
     __syncthreads();
-    double av[8], bv[8];
-    // A's eight elements are one contiguous run of a stored row when the
-    // index that varies along them is not mapped: p of a stored A with no K
-    // map, r of a transposed A with no row map (tiles of 64 and more, so the
-    // run stays inside the row; offsets even)
+    // A's elements along a thread's run are contiguous in a stored row when
+    // the index that varies along it is not mapped: p of a stored A with no
+    // K map, r of a transposed A with no row map (tiles of 64 and more, so
+    // the run stays inside the row; offsets even)
     const bool arun = NB >= CB && ((c.a_mode == CA_NORMAL && c.a_qmap < 0) || (tr && c.a_rmap < 0));
+    double av[8], bv[8];
     auto fetch = [&](int32_t k0) {
-      if (arun) {
-        const int32_t rr = tr ? (k0 + apq_t < c.K ? aq[k0 + apq_t] : -1) : arow[arow_n];
-        const int32_t s0 = tr ? r0 + arow_t : k0 + apq_n;  // first index along the run
-        const int32_t lim = tr ? u.c_rows : c.K;
-        const double* arp = A + (int64_t)max(rr, 0) * NB + s0;
+      if (tr) {  // av[2 x + y] = A(r0 + jl + 16 x, k0 + 2 kp + y)
+        const int32_t p0 = k0 + 2 * kp;
+        const int32_t q0 = p0 < c.K ? aq[p0] : -1, q1 = p0 + 1 < c.K ? aq[p0 + 1] : -1;
+        if (arun) {  // rows r0 + jl + 16 x lie inside the stored row
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const double2 v = *reinterpret_cast<const double2*>(arp + 2 * e);
-          av[2 * e] = (rr >= 0 && s0 + 2 * e < lim) ? v.x : 0.0;
-          av[2 * e + 1] = (rr >= 0 && s0 + 2 * e + 1 < lim) ? v.y : 0.0;
+          for (int y = 0; y < 2; ++y) {
+            const int32_t q = y ? q1 : q0;
+            const double* ap = A + (int64_t)max(q, 0) * NB + r0 + jl;
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+              const double v = ap[16 * x];
+              av[2 * x + y] = (q >= 0 && r0 + jl + 16 * x < u.c_rows) ? v : 0.0;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int x = 0; x < 4; ++x) {
+            const int32_t rr = arow[jl + 16 * x];
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+              const int32_t q = y ? q1 : q0;
+              const double v = A[(int64_t)max(q, 0) * NB + max(rr, 0)];
+              av[2 * x + y] = (rr >= 0 && q >= 0) ? v : 0.0;
+            }
+          }
         }
-      } else {
+      } else {  // av[e] = A(r0 + ra, k0 + 2 pa + e)
+        const int32_t rr = arow[ra];
+        const int32_t s0 = k0 + 2 * pa;
+        if (arun) {
+          const double* ap = A + (int64_t)max(rr, 0) * NB + s0;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int32_t rl = tr ? arow_t + e : arow_n;
-          const int32_t pl = k0 + (tr ? apq_t : apq_n + e);
-          const int32_t rr = arow[rl], qq = pl < c.K ? aq[pl] : -1;
-          const int32_t rc = max(rr, 0), qc = max(qq, 0);
-          int64_t off;
-          if (c.a_mode == CA_NORMAL) off = (int64_t)rc * NB + qc;
-          else if (tr) off = (int64_t)qc * NB + rc;
-          else off = (int64_t)max(rc, qc) * NB + min(rc, qc);
-          const double v = A[off];
-          av[e] = (rr >= 0 && qq >= 0) ? v : 0.0;
+          for (int e = 0; e < 4; ++e) {
+            const double2 v = *reinterpret_cast<const double2*>(ap + 2 * e);
+            av[2 * e] = (rr >= 0 && s0 + 2 * e < c.K) ? v.x : 0.0;
+            av[2 * e + 1] = (rr >= 0 && s0 + 2 * e + 1 < c.K) ? v.y : 0.0;
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int32_t pl = s0 + e;
+            const int32_t qq = pl < c.K ? aq[pl] : -1;
+            const int32_t rc = max(rr, 0), qc = max(qq, 0);
+            const int64_t off = c.a_mode == CA_NORMAL ? (int64_t)rc * NB + qc
+                                                      : (int64_t)max(rc, qc) * NB + min(rc, qc);
+            const double v = A[off];
+            av[e] = (rr >= 0 && qq >= 0) ? v : 0.0;
+          }
         }
       }
-      const int32_t pb = k0 + bp;
-      const int32_t qb = pb < c.K ? bq[pb] : -1;
-      if constexpr (NB >= CB) {
-        // the eight columns lie inside the row (c0 + 64 <= NB): four 16-byte
-        // reads of one contiguous run (row and column offsets even)
-        const double* brow = B + (int64_t)max(qb, 0) * NB + c0 + bj;
+      // bv[2 x + y] = B(k0 + 2 kp + y, c0 + jl + 16 x)
+      const int32_t p0 = k0 + 2 * kp;
+      const int32_t q0 = p0 < c.K ? bq[p0] : -1, q1 = p0 + 1 < c.K ? bq[p0 + 1] : -1;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const double2 v = *reinterpret_cast<const double2*>(brow + 2 * e);
-          bv[2 * e] = qb >= 0 ? v.x : 0.0;
-          bv[2 * e + 1] = qb >= 0 ? v.y : 0.0;
-        }
-      } else {
+      for (int y = 0; y < 2; ++y) {
+        const int32_t q = y ? q1 : q0;
+        const double* bp = B + (int64_t)max(q, 0) * NB;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int32_t j = c0 + bj + e;
-          const double v = B[(int64_t)max(qb, 0) * NB + min(j, NB - 1)];
-          bv[e] = (qb >= 0 && j < NB) ? v : 0.0;
+        for (int x = 0; x < 4; ++x) {
+          const int32_t j = c0 + jl + 16 * x;
+          if constexpr (NB >= CB) {  // the block's columns lie inside the row
+            const double v = bp[j];
+            bv[2 * x + y] = q >= 0 ? v : 0.0;
+          } else {
+            const double v = bp[min(j, NB - 1)];
+            bv[2 * x + y] = (q >= 0 && j < NB) ? v : 0.0;
+          }
         }
       }
     };
     fetch(0);
     for (int32_t k0 = 0; k0 < c.K; k0 += CKT) {
+      if (tr) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        As[(tr ? arow_t + e : arow_n) * CLD + (tr ? apq_t : apq_n + e)] = av[e];
-        Bs[(bj + e) * CLD + bp] = bv[e];
+        for (int x = 0; x < 4; ++x)
+          *reinterpret_cast<double2*>(As + (jl + 16 * x) * CLD + 2 * kp) = double2{av[2 * x], av[2 * x + 1]};
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          *reinterpret_cast<double2*>(As + ra * CLD + 2 * (pa + e)) = double2{av[2 * e], av[2 * e + 1]};
       }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+        *reinterpret_cast<double2*>(Bs + (jl + 16 * x) * CLD + 2 * kp) = double2{bv[2 * x], bv[2 * x + 1]};
       __syncthreads();
       if (k0 + CKT < c.K) fetch(k0 + CKT);
+      // lane group lane / 16 takes pair 4 gq + lane / 16: its first K value
+      // feeds the first product of the pair, its second the second, for A
+      // and B alike
 #pragma unroll
-      for (int kk = 0; kk < CKT; kk += 4) {
-        double af[2], bf[2];
-        for (int a = 0; a < 2; ++a) af[a] = As[(wr + a * 16 + (lane & 15)) * CLD + kk + (lane >> 4)];
-        for (int b = 0; b < 2; ++b) bf[b] = Bs[(wc + b * 16 + (lane & 15)) * CLD + kk + (lane >> 4)];
+      for (int gq = 0; gq < 4; ++gq) {
+        const int sl = 4 * gq + (lane >> 4);
+        double2 af[2], bf[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          af[a] = *reinterpret_cast<const double2*>(As + (wr + a * 16 + (lane & 15)) * CLD + 2 * sl);
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          bf[b] = *reinterpret_cast<const double2*>(Bs + (wc + b * 16 + (lane & 15)) * CLD + 2 * sl);
+        }
+#pragma unroll
         for (int a = 0; a < 2; ++a)
-          for (int b = 0; b < 2; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].x, bf[b].x, acc[a][b], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].y, bf[b].y, acc[a][b], 0, 0, 0);
       }
       __syncthreads();
     }
