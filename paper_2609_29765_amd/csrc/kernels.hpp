@@ -1264,8 +1264,11 @@ __global__ __launch_bounds__(256, 4) void k_backcon(BackArgs g) {
                 by = g.items[3 * blockIdx.x + 2];
   const ConTaskD u = g.tasks[task];
   const int32_t r0 = bx * CB, c0 = by * CB;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  // the wave's 16-row groups that hold output rows (the others are padding
+  // of the block past the task's rows: their products are skipped)
+  const bool row_g[2] = {r0 + wr < u.c_rows, r0 + wr + 16 < u.c_rows};
   d4 acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
@@ -1397,21 +1400,22 @@ __global__ __launch_bounds__(256, 4) void k_backcon(BackArgs g) {
         const int sl = 4 * gq + (lane >> 4);
         double2 af[2], bf[2];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          af[a] = *reinterpret_cast<const double2*>(As + (wr + a * 16 + (lane & 15)) * CLD + 2 * sl);
-        }
+        for (int a = 0; a < 2; ++a)
+          if (row_g[a]) af[a] = *reinterpret_cast<const double2*>(As + (wr + a * 16 + (lane & 15)) * CLD + 2 * sl);
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           bf[b] = *reinterpret_cast<const double2*>(Bs + (wc + b * 16 + (lane & 15)) * CLD + 2 * sl);
         }
 #pragma unroll
         for (int a = 0; a < 2; ++a)
+          if (row_g[a])
 #pragma unroll
-          for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].x, bf[b].x, acc[a][b], 0, 0, 0);
+            for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].x, bf[b].x, acc[a][b], 0, 0, 0);
 #pragma unroll
         for (int a = 0; a < 2; ++a)
+          if (row_g[a])
 #pragma unroll
-          for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].y, bf[b].y, acc[a][b], 0, 0, 0);
+            for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].y, bf[b].y, acc[a][b], 0, 0, 0);
       }
       __syncthreads();
     }
