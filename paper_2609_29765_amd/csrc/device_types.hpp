@@ -47,10 +47,12 @@ struct ConTaskD {
   double alpha;
 };
 
-struct FoldTaskD {     // output of a split reverse-mode task and its partial slots
+struct FoldItemD {     // one 64 x 64 block of a split reverse-mode task's output and its partial slots
   int64_t c_off, slot_off;
   int32_t c_buf, c_rows, ncols, diag;
-  int32_t nslots, pad;
+  int32_t nslots;
+  int32_t bx, by;      // block row and column
+  int32_t pad;
 };
 
 struct TileD {        // off-diagonal tile as the solve sees it

@@ -1441,18 +1441,21 @@ __global__ __launch_bounds__(256, 4) void k_backcon(BackArgs g) {
 // output block (64 x 64, the contraction's blocking) gets the sum of its
 // partial slots, added in slot order.  Work-group (item, y) covers rows
 // 16 y .. 16 y + 15 of the item's block, thread t four consecutive columns
-// 4 (t % 16) .. of row t / 16; the slots' values are read four slots at a
-// time so that their loads are in flight together.
+// 4 (t % 16) .. of row t / 16.  The item carries its whole descriptor, and
+// the output's values are read beside the slots', so that a work-group waits
+// for two rounds of loads; the slots' are read four slots at a time.
 template <int NB>
-__global__ __launch_bounds__(256) void k_backfold(const int32_t* __restrict__ items,
-                                                  const FoldTaskD* __restrict__ folds, double* __restrict__ Z,
+__global__ __launch_bounds__(256) void k_backfold(const FoldItemD* __restrict__ items, double* __restrict__ Z,
                                                   double* __restrict__ M, const double* __restrict__ P) {
-  const int32_t fi = items[3 * blockIdx.x], bx = items[3 * blockIdx.x + 1], by = items[3 * blockIdx.x + 2];
-  const FoldTaskD f = folds[fi];
+  const FoldItemD f = items[blockIdx.x];
   double* C = (f.c_buf == 1 ? Z : M) + f.c_off;
-  const int32_t i = bx * CB + 16 * (int32_t)blockIdx.y + (int32_t)(threadIdx.x >> 4);
-  const int32_t j = by * CB + 4 * (int32_t)(threadIdx.x & 15);
+  const int32_t i = f.bx * CB + 16 * (int32_t)blockIdx.y + (int32_t)(threadIdx.x >> 4);
+  const int32_t j = f.by * CB + 4 * (int32_t)(threadIdx.x & 15);
   if (i >= f.c_rows || j >= f.ncols || (f.diag && j > i)) return;
+  double* c = C + (int64_t)i * NB + j;
+  double cv[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) cv[e] = c[j + e < f.ncols ? e : 0];  // columns past the tile read column j
   const int64_t slot = (int64_t)f.c_rows * NB;
   const double* p = P + f.slot_off + (int64_t)i * NB + j;  // j, NB and every offset even: 16-byte aligned pairs
   double4 sum = {0.0, 0.0, 0.0, 0.0};
@@ -1480,11 +1483,10 @@ __global__ __launch_bounds__(256) void k_backfold(const int32_t* __restrict__ it
     sum.z += b.x;
     sum.w += b.y;
   }
-  double* c = C + (int64_t)i * NB + j;
   const double add[4] = {sum.x, sum.y, sum.z, sum.w};
 #pragma unroll
   for (int e = 0; e < 4; ++e)
-    if (j + e < f.ncols && (!f.diag || j + e <= i)) c[e] += add[e];
+    if (j + e < f.ncols && (!f.diag || j + e <= i)) c[e] = cv[e] + add[e];
 }
 
 // gradient of log det with respect to the input values (lower triangle of a

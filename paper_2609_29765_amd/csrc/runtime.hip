@@ -174,8 +174,7 @@ struct stc_handle {
   std::vector<int32_t> back_level_ptr;   // items of level L: [ptr[L], ptr[L+1])
   std::vector<int32_t> fold_items;       // fold items of split tasks, flattened per level
   std::vector<int32_t> fold_level_ptr;
-  FoldTaskD* d_bfolds = nullptr;
-  int32_t* d_bfitems = nullptr;
+  FoldItemD* d_bfitems = nullptr;
   double* d_bslots = nullptr;  // partial slots of split reverse-mode tasks
   ConTermD* d_bterms = nullptr;
   ConTaskD* d_btasks = nullptr;
@@ -239,8 +238,7 @@ size_t layout(const stc_handle* hc, int32_t batch, char* base) {
   take(&h->d_bterms, sizeof(ConTermD) * h->back.terms.size());
   take(&h->d_btasks, sizeof(ConTaskD) * h->back.tasks.size());
   take(&h->d_bitems, sizeof(int32_t) * h->back_items.size());
-  take(&h->d_bfolds, sizeof(FoldTaskD) * h->back.folds.size());
-  take(&h->d_bfitems, sizeof(int32_t) * h->fold_items.size());
+  take(&h->d_bfitems, sizeof(FoldItemD) * (h->fold_items.size() / 3));
   take(&h->d_bslots, sizeof(double) * (size_t)h->back.slots);
   take(&h->d_trtri, sizeof(int32_t) * h->back.trtri_items.size());
   take(&h->d_bdiag, sizeof(int8_t) * h->back.diagflag.size());
@@ -639,8 +637,8 @@ int launch_backward_nb(stc_handle* h, hipStream_t st) {
     hipLaunchKernelGGL((k_backcon<NB>), dim3(b - a), dim3(256), sizeof(double) * con_lds<NB>(), st, g);
     const int32_t fa = h->fold_level_ptr[L], fb = h->fold_level_ptr[L + 1];
     if (fb > fa)
-      hipLaunchKernelGGL((k_backfold<NB>), dim3(fb - fa, CB / 16), dim3(256), 0, st, h->d_bfitems + 3 * (int64_t)fa,
-                         (const FoldTaskD*)h->d_bfolds, h->d_zs, h->d_ms, (const double*)h->d_bslots);
+      hipLaunchKernelGGL((k_backfold<NB>), dim3(fb - fa, CB / 16), dim3(256), 0, st,
+                         (const FoldItemD*)h->d_bfitems + fa, h->d_zs, h->d_ms, (const double*)h->d_bslots);
   }
   HIPCHK(hipGetLastError());
   return 0;
@@ -1039,12 +1037,13 @@ int stc_bind(stc_handle* h, void* d_ws, size_t bytes, int32_t batch, void* strea
     const ConTask& t = bp.tasks[i];
     bk[i] = ConTaskD{t.c_off, t.c_buf, t.c_rows, t.ncols, t.diag, t.t_begin, t.t_end, t.beta, 0, t.alpha};
   }
-  std::vector<FoldTaskD> bf(bp.folds.size());
+  std::vector<FoldItemD> bf(h->fold_items.size() / 3);
   for (size_t i = 0; i < bf.size(); ++i) {
-    const FoldTask& f = bp.folds[i];
-    bf[i] = FoldTaskD{f.c_off, f.slot_off, f.c_buf, f.c_rows, f.ncols, f.diag, f.nslots, 0};
+    const FoldTask& f = bp.folds[(size_t)h->fold_items[3 * i]];
+    bf[i] = FoldItemD{f.c_off, f.slot_off, f.c_buf, f.c_rows, f.ncols, f.diag, f.nslots,
+                      h->fold_items[3 * i + 1], h->fold_items[3 * i + 2], 0};
   }
-  if ((rc = upload(h->d_bfolds, bf)) || (rc = upload(h->d_bfitems, h->fold_items))) return rc;
+  if ((rc = upload(h->d_bfitems, bf))) return rc;
   if ((rc = upload(h->d_bterms, bt)) || (rc = upload(h->d_btasks, bk)) ||
       (rc = upload(h->d_bitems, h->back_items)) || (rc = upload(h->d_trtri, bp.trtri_items)) ||
       (rc = upload(h->d_bdiag, bp.diagflag)))
