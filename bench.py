@@ -123,6 +123,31 @@ def semisparse_pass(align, nb=128):
           flush=True)
 
 
+def backward_pass(align, nb=128):
+    """Counter runs over the reverse mode: the spatio-temporal arrowhead
+    (n = 101,258, tile nb, ND, grid aligned to subtrees of `align` columns)
+    factorized and differentiated (selected inverse on the factor's pattern,
+    then the logdet gradient) twice, each through its graph; segment 2 of a
+    trace is the second pass.  Prints one JSON line: the plan's reverse-mode
+    flops and levels and the reverse-mode plan checker's counts."""
+    import torch
+    stc = load_lib()
+    from paper_2609_29765_amd import workloads
+    w = workloads.spatiotemporal_arrowhead()
+    v = torch.from_numpy(w.values).cuda()
+    a = stc.Analysis(w.n, w.colptr, w.rowind, nb=nb, ordering="nd", align=align).bind()
+    one = torch.ones(1, dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        a.factorize(v)
+        a.logdet_backward(one)
+    torch.cuda.synchronize()
+    assert a.info() == 0
+    wk = a.work()
+    print(json.dumps({"workload": f"spatio-temporal arrowhead n=101258, tile {nb}, ND, grid align {align}",
+                      "flops_backward": wk["flops_backward"], "levels_backward": wk["levels_backward"],
+                      "check_backward": a.check_backward()}), flush=True)
+
+
 def batched_pass(batch_hint):
     """Counter runs over the batched form: the 3-D Laplacian 24^3 with 128
     value sets (tile 64, ND, grid aligned at 128 columns, split-K schedule for
@@ -834,9 +859,14 @@ def main():
     ap.add_argument("--semisparse-pass", action="store_true",
                     help="only: one eager C3 factorization (kernel by kernel) and a 1 GiB copy, "
                          "for counter runs over the active-column route")
+    ap.add_argument("--backward-pass", action="store_true",
+                    help="only: the C3 factorization and its logdet reverse mode, twice through the graphs, "
+                         "for kernel traces and counter runs over the reverse mode")
     ap.add_argument("--pass-align", type=int, default=512,
-                    help="tile-grid alignment (columns, 0 = uniform grid) of --solve-pass and --semisparse-pass")
-    ap.add_argument("--pass-nb", type=int, default=128, help="tile size of --solve-pass and --semisparse-pass")
+                    help="tile-grid alignment (columns, 0 = uniform grid) of --solve-pass, --semisparse-pass "
+                         "and --backward-pass")
+    ap.add_argument("--pass-nb", type=int, default=128,
+                    help="tile size of --solve-pass, --semisparse-pass and --backward-pass")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration runs)")
     ap.add_argument("--summarize-trace", default=None, metavar="DIR",
@@ -872,6 +902,9 @@ def main():
         return
     if args.semisparse_pass:
         semisparse_pass(args.pass_align, args.pass_nb)
+        return
+    if args.backward_pass:
+        backward_pass(args.pass_align, args.pass_nb)
         return
 
     import torch
