@@ -1284,19 +1284,32 @@ __global__ __launch_bounds__(256, 4) void k_backcon(BackArgs g) {
   // of the stored row).
   const int ra = tid >> 2, pa = (tid & 3) * 4;
   const int kp = tid >> 4, jl = tid & 15;
+  // A term's map entries are read into registers one term ahead (thread tid
+  // holds row map entry tid and contraction map entries tid: K <= n_b <= 256)
+  // and go to LDS when the term starts, so that their global round trip
+  // overlaps the previous term's chunks.
+  ConTermD cn{};
+  int32_t mr = -1, ma = 0, mb = 0;
+  auto map_regs = [&](const ConTermD& c) {
+    const int32_t r = r0 + tid;
+    mr = (tid < CB && r < u.c_rows) ? (c.a_rmap < 0 ? r : g.maps[c.a_rmap + r]) : -1;
+    ma = tid < c.K ? (c.a_qmap < 0 ? tid : g.maps[c.a_qmap + tid]) : 0;
+    mb = tid < c.K ? (c.b_qmap < 0 ? tid : g.maps[c.b_qmap + tid]) : 0;
+  };
+  if (u.t_begin < u.t_end) {
+    cn = g.terms[u.t_begin];
+    map_regs(cn);
+  }
   for (int32_t t = u.t_begin; t < u.t_end; ++t) {
-    const ConTermD c = g.terms[t];
+    const ConTermD c = cn;
     const double* A = (c.a_buf == 0 ? g.L : (c.a_buf == 1 ? g.Z : g.M)) + c.a_off;
     const double* B = (c.b_buf == 0 ? g.L : (c.b_buf == 1 ? g.Z : g.M)) + c.b_off;
     const bool tr = c.a_mode == CA_TRANS;
     __syncthreads();  // previous term's maps and chunks consumed
-    if (tid < CB) {
-      const int32_t r = r0 + tid;
-      arow[tid] = r < u.c_rows ? (c.a_rmap < 0 ? r : g.maps[c.a_rmap + r]) : -1;
-    }
-    for (int p = tid; p < c.K; p += 256) {
-      aq[p] = c.a_qmap < 0 ? p : g.maps[c.a_qmap + p];
-      bq[p] = c.b_qmap < 0 ? p : g.maps[c.b_qmap + p];
+    if (tid < CB) arow[tid] = mr;
+    if (tid < c.K) {
+      aq[tid] = ma;
+      bq[tid] = mb;
     }
     __syncthreads();
     // A's elements along a thread's run are contiguous in a stored row when
@@ -1377,6 +1390,10 @@ __global__ __launch_bounds__(256, 4) void k_backcon(BackArgs g) {
       }
     };
     fetch(0);
+    if (t + 1 < u.t_end) {  // the next term's maps, behind this term's first chunk
+      cn = g.terms[t + 1];
+      map_regs(cn);
+    }
     for (int32_t k0 = 0; k0 < c.K; k0 += CKT) {
       if (tr) {
 #pragma unroll
