@@ -187,6 +187,37 @@ def test_split_reverse_levels_reproducible_and_match_oracle(nb, align):
     assert np.array_equal(gs[0], gs[1]) and np.array_equal(gs[0], gs[2])
 
 
+def test_full_size_arrowhead_reverse_mode_trace_identity_and_solve_columns():
+    """The spatio-temporal arrowhead at full size (n = 101,258, tile 128, grid
+    aligned at 512 columns), whose reverse-mode levels are split most: (1) the
+    derivative of logdet along Q itself is tr(Q^-1 Q) = n, so the gradient
+    dotted with the values is n at any size; (2) on sampled columns j (the
+    border rows among them) the gradient entries of column j equal, up to the
+    factor 2 off the diagonal, the entries of Q^-1 e_j from the library's
+    solve, a separate path (triangular sweeps) checked against the oracle
+    elsewhere.  Tolerances: both sides carry rounding of order cond(Q) eps
+    (cond about 1e4 here); 1e-9 relative leaves a wide margin."""
+    w = W.spatiotemporal_arrowhead()
+    a = S.Analysis(w.n, w.colptr, w.rowind, nb=128, ordering="nd", align=512).bind()
+    print(f"[gpu] full-size reverse n={w.n} levels={a.work()['levels_backward']}", flush=True)
+    a.factorize(dev(w.values))
+    assert a.info() == 0
+    g = a.logdet_backward(torch.ones(1, dtype=torch.float64, device="cuda")).cpu().numpy()
+    assert abs(float(g @ w.values) - w.n) <= 1e-9 * w.n
+    rng = np.random.default_rng(3)
+    cols = [0, w.n // 2, w.n - 9, w.n - 8, w.n - 1] + [int(c) for c in rng.integers(0, w.n, 5)]
+    E = torch.zeros(w.n, len(cols), dtype=torch.float64, device="cuda")
+    for k, j in enumerate(cols):
+        E[j, k] = 1.0
+    X = a.solve(E).cpu().numpy()
+    for k, j in enumerate(cols):
+        lo, hi = w.colptr[j], w.colptr[j + 1]
+        rows = w.rowind[lo:hi]
+        want = np.where(rows == j, 1.0, 2.0) * X[rows, k]
+        err = np.max(np.abs(g[lo:hi] - want))
+        assert err <= 1e-9 * np.max(np.abs(want)), (j, err)
+
+
 def test_backward_after_failed_factorization_is_nan():
     w = W.random_spd(100, 0.05, 7)
     vals = w.values.copy()
