@@ -1239,7 +1239,7 @@ constexpr int CB = 64;
 constexpr int CKT = 32;
 constexpr int CLD = CKT + 2;  // a staged row: 16 K pairs and one pair of padding
 template <int NB>
-constexpr int con_lds() { return 2 * CB * CLD + (CB + 2 * NB + 1) / 2; }  // As, Bs, row map, two K maps
+constexpr int con_lds() { return 2 * CB * CLD + (2 * (CB + 2 * NB) + 1) / 2; }  // As, Bs, two sets of maps (row map, two K maps)
 
 struct BackArgs {
   const int32_t* items;  // triples: task, block row, block column
@@ -1257,9 +1257,8 @@ __global__ __launch_bounds__(256, 4) void k_backcon(BackArgs g) {
   extern __shared__ double smem[];
   double* As = smem;
   double* Bs = smem + CB * CLD;
-  int32_t* arow = reinterpret_cast<int32_t*>(smem + 2 * CB * CLD);  // CB
-  int32_t* aq = arow + CB;                                           // NB
-  int32_t* bq = aq + NB;                                             // NB
+  int32_t* mapsets = reinterpret_cast<int32_t*>(smem + 2 * CB * CLD);  // two sets: row map (CB), two K maps (NB each)
+  constexpr int MSET = CB + 2 * NB;
   const int32_t task = g.items[3 * blockIdx.x], bx = g.items[3 * blockIdx.x + 1],
                 by = g.items[3 * blockIdx.x + 2];
   const ConTaskD u = g.tasks[task];
@@ -1272,23 +1271,43 @@ __global__ __launch_bounds__(256, 4) void k_backcon(BackArgs g) {
   d4 acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-  // Per term, its row map and both contraction maps go to LDS once; then the
-  // 32-wide chunks of K run with the next chunk's values read into registers
-  // while the current one is on MFMA.  In LDS a row (an output row of A, an
-  // output column of B) holds its chunk as 16 K pairs, padded so that 16
-  // lanes reading one pair of 16 consecutive rows touch every bank once.
-  // Each thread stages eight A and eight B values as four K pairs: a stored
-  // or symmetric A gives row ra, pairs 4 (tid % 4) .. +3 (a run along the
-  // stored row); a transposed A, like B, gives pair kp of rows (A) or
-  // columns (B) jl + 16 x, x = 0..3 (16 lanes cover 16 consecutive values
-  // of the stored row).
+  // The task's terms run as one stream of 32-wide K chunks, the next chunk's
+  // values read into registers while the current one is on MFMA, across term
+  // boundaries too: a term's row map and both contraction maps sit in one of
+  // two LDS sets (terms alternate), written from registers read a term
+  // ahead, so that the first chunk of the next term is read during the last
+  // chunk of the current one.  In LDS a row (an output row of A, an output
+  // column of B) holds its chunk as 16 K pairs, padded so that 16 lanes
+  // reading one pair of 16 consecutive rows touch every bank once.  Each
+  // thread stages eight A and eight B values as four K pairs: a stored or
+  // symmetric A gives row ra, pairs 4 (tid % 4) .. +3 (a run along the stored
+  // row); a transposed A, like B, gives pair kp of rows (A) or columns (B)
+  // jl + 16 x, x = 0..3 (16 lanes cover 16 consecutive values of the stored
+  // row).
   const int ra = tid >> 2, pa = (tid & 3) * 4;
   const int kp = tid >> 4, jl = tid & 15;
-  // A term's map entries are read into registers one term ahead (thread tid
-  // holds row map entry tid and contraction map entries tid: K <= n_b <= 256)
-  // and go to LDS when the term starts, so that their global round trip
-  // overlaps the previous term's chunks.
-  ConTermD cn{};
+  struct Term {  // what the fetches of a term need
+    const double* A;
+    const double* B;
+    int32_t K, mode;
+    bool tr, arun;
+  };
+  auto make_term = [&](const ConTermD& c) {
+    Term s;
+    s.K = c.K;
+    s.mode = c.a_mode;
+    s.A = (c.a_buf == 0 ? g.L : (c.a_buf == 1 ? g.Z : g.M)) + c.a_off;
+    s.B = (c.b_buf == 0 ? g.L : (c.b_buf == 1 ? g.Z : g.M)) + c.b_off;
+    s.tr = c.a_mode == CA_TRANS;
+    // A's elements along a thread's run are contiguous in a stored row when
+    // the index that varies along it is not mapped: p of a stored A with no
+    // K map, r of a transposed A with no row map (tiles of 64 and more, so
+    // the run stays inside the row; offsets even)
+    s.arun = NB >= CB && ((c.a_mode == CA_NORMAL && c.a_qmap < 0) || (s.tr && c.a_rmap < 0));
+    return s;
+  };
+  // thread tid's entries of a term's maps (row map entry tid, contraction map
+  // entries tid: K <= n_b <= 256), read into registers, then put in a set
   int32_t mr = -1, ma = 0, mb = 0;
   auto map_regs = [&](const ConTermD& c) {
     const int32_t r = r0 + tid;
@@ -1296,145 +1315,160 @@ __global__ __launch_bounds__(256, 4) void k_backcon(BackArgs g) {
     ma = tid < c.K ? (c.a_qmap < 0 ? tid : g.maps[c.a_qmap + tid]) : 0;
     mb = tid < c.K ? (c.b_qmap < 0 ? tid : g.maps[c.b_qmap + tid]) : 0;
   };
-  if (u.t_begin < u.t_end) {
-    cn = g.terms[u.t_begin];
-    map_regs(cn);
-  }
-  for (int32_t t = u.t_begin; t < u.t_end; ++t) {
-    const ConTermD c = cn;
-    const double* A = (c.a_buf == 0 ? g.L : (c.a_buf == 1 ? g.Z : g.M)) + c.a_off;
-    const double* B = (c.b_buf == 0 ? g.L : (c.b_buf == 1 ? g.Z : g.M)) + c.b_off;
-    const bool tr = c.a_mode == CA_TRANS;
-    __syncthreads();  // previous term's maps and chunks consumed
-    if (tid < CB) arow[tid] = mr;
-    if (tid < c.K) {
-      aq[tid] = ma;
-      bq[tid] = mb;
+  auto put_maps = [&](int set, int32_t K) {
+    int32_t* m = mapsets + set * MSET;
+    if (tid < CB) m[tid] = mr;
+    if (tid < K) {
+      m[CB + tid] = ma;
+      m[CB + NB + tid] = mb;
     }
-    __syncthreads();
-    // A's elements along a thread's run are contiguous in a stored row when
-    // the index that varies along it is not mapped: p of a stored A with no
-    // K map, r of a transposed A with no row map (tiles of 64 and more, so
-    // the run stays inside the row; offsets even)
-    const bool arun = NB >= CB && ((c.a_mode == CA_NORMAL && c.a_qmap < 0) || (tr && c.a_rmap < 0));
-    double av[8], bv[8];
-    auto fetch = [&](int32_t k0) {
-      if (tr) {  // av[2 x + y] = A(r0 + jl + 16 x, k0 + 2 kp + y)
-        const int32_t p0 = k0 + 2 * kp;
-        const int32_t q0 = p0 < c.K ? aq[p0] : -1, q1 = p0 + 1 < c.K ? aq[p0 + 1] : -1;
-        if (arun) {  // rows r0 + jl + 16 x lie inside the stored row
+  };
+  double av[8], bv[8];
+  auto fetch = [&](const Term& s, int set, int32_t k0) {
+    const int32_t K = s.K;
+    const double* A = s.A;
+    const int32_t* arow = mapsets + set * MSET;
+    const int32_t* aq = arow + CB;
+    const int32_t* bq = aq + NB;
+    if (s.tr) {  // av[2 x + y] = A(r0 + jl + 16 x, k0 + 2 kp + y)
+      const int32_t p0 = k0 + 2 * kp;
+      const int32_t q0 = p0 < K ? aq[p0] : -1, q1 = p0 + 1 < K ? aq[p0 + 1] : -1;
+      if (s.arun) {  // rows r0 + jl + 16 x lie inside the stored row
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          const int32_t q = y ? q1 : q0;
+          const double* ap = A + (int64_t)max(q, 0) * NB + r0 + jl;
+#pragma unroll
+          for (int x = 0; x < 4; ++x) {
+            const double v = ap[16 * x];
+            av[2 * x + y] = (q >= 0 && r0 + jl + 16 * x < u.c_rows) ? v : 0.0;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          const int32_t rr = arow[jl + 16 * x];
 #pragma unroll
           for (int y = 0; y < 2; ++y) {
             const int32_t q = y ? q1 : q0;
-            const double* ap = A + (int64_t)max(q, 0) * NB + r0 + jl;
-#pragma unroll
-            for (int x = 0; x < 4; ++x) {
-              const double v = ap[16 * x];
-              av[2 * x + y] = (q >= 0 && r0 + jl + 16 * x < u.c_rows) ? v : 0.0;
-            }
-          }
-        } else {
-#pragma unroll
-          for (int x = 0; x < 4; ++x) {
-            const int32_t rr = arow[jl + 16 * x];
-#pragma unroll
-            for (int y = 0; y < 2; ++y) {
-              const int32_t q = y ? q1 : q0;
-              const double v = A[(int64_t)max(q, 0) * NB + max(rr, 0)];
-              av[2 * x + y] = (rr >= 0 && q >= 0) ? v : 0.0;
-            }
-          }
-        }
-      } else {  // av[e] = A(r0 + ra, k0 + 2 pa + e)
-        const int32_t rr = arow[ra];
-        const int32_t s0 = k0 + 2 * pa;
-        if (arun) {
-          const double* ap = A + (int64_t)max(rr, 0) * NB + s0;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const double2 v = *reinterpret_cast<const double2*>(ap + 2 * e);
-            av[2 * e] = (rr >= 0 && s0 + 2 * e < c.K) ? v.x : 0.0;
-            av[2 * e + 1] = (rr >= 0 && s0 + 2 * e + 1 < c.K) ? v.y : 0.0;
-          }
-        } else {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int32_t pl = s0 + e;
-            const int32_t qq = pl < c.K ? aq[pl] : -1;
-            const int32_t rc = max(rr, 0), qc = max(qq, 0);
-            const int64_t off = c.a_mode == CA_NORMAL ? (int64_t)rc * NB + qc
-                                                      : (int64_t)max(rc, qc) * NB + min(rc, qc);
-            const double v = A[off];
-            av[e] = (rr >= 0 && qq >= 0) ? v : 0.0;
+            const double v = A[(int64_t)max(q, 0) * NB + max(rr, 0)];
+            av[2 * x + y] = (rr >= 0 && q >= 0) ? v : 0.0;
           }
         }
       }
-      // bv[2 x + y] = B(k0 + 2 kp + y, c0 + jl + 16 x)
-      const int32_t p0 = k0 + 2 * kp;
-      const int32_t q0 = p0 < c.K ? bq[p0] : -1, q1 = p0 + 1 < c.K ? bq[p0 + 1] : -1;
+    } else {  // av[e] = A(r0 + ra, k0 + 2 pa + e)
+      const int32_t rr = arow[ra];
+      const int32_t s0 = k0 + 2 * pa;
+      if (s.arun) {
+        const double* ap = A + (int64_t)max(rr, 0) * NB + s0;
 #pragma unroll
-      for (int y = 0; y < 2; ++y) {
-        const int32_t q = y ? q1 : q0;
-        const double* bp = B + (int64_t)max(q, 0) * NB;
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-          const int32_t j = c0 + jl + 16 * x;
-          if constexpr (NB >= CB) {  // the block's columns lie inside the row
-            const double v = bp[j];
-            bv[2 * x + y] = q >= 0 ? v : 0.0;
-          } else {
-            const double v = bp[min(j, NB - 1)];
-            bv[2 * x + y] = (q >= 0 && j < NB) ? v : 0.0;
-          }
+        for (int e = 0; e < 4; ++e) {
+          const double2 v = *reinterpret_cast<const double2*>(ap + 2 * e);
+          av[2 * e] = (rr >= 0 && s0 + 2 * e < K) ? v.x : 0.0;
+          av[2 * e + 1] = (rr >= 0 && s0 + 2 * e + 1 < K) ? v.y : 0.0;
         }
-      }
-    };
-    fetch(0);
-    if (t + 1 < u.t_end) {  // the next term's maps, behind this term's first chunk
-      cn = g.terms[t + 1];
-      map_regs(cn);
-    }
-    for (int32_t k0 = 0; k0 < c.K; k0 += CKT) {
-      if (tr) {
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-          *reinterpret_cast<double2*>(As + (jl + 16 * x) * CLD + 2 * kp) = double2{av[2 * x], av[2 * x + 1]};
       } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          *reinterpret_cast<double2*>(As + ra * CLD + 2 * (pa + e)) = double2{av[2 * e], av[2 * e + 1]};
+        for (int e = 0; e < 8; ++e) {
+          const int32_t pl = s0 + e;
+          const int32_t qq = pl < K ? aq[pl] : -1;
+          const int32_t rc = max(rr, 0), qc = max(qq, 0);
+          const int64_t off = s.mode == CA_NORMAL ? (int64_t)rc * NB + qc
+                                                    : (int64_t)max(rc, qc) * NB + min(rc, qc);
+          const double v = A[off];
+          av[e] = (rr >= 0 && qq >= 0) ? v : 0.0;
+        }
       }
+    }
+    // bv[2 x + y] = B(k0 + 2 kp + y, c0 + jl + 16 x)
+    const int32_t p0 = k0 + 2 * kp;
+    const int32_t q0 = p0 < K ? bq[p0] : -1, q1 = p0 + 1 < K ? bq[p0 + 1] : -1;
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
-        *reinterpret_cast<double2*>(Bs + (jl + 16 * x) * CLD + 2 * kp) = double2{bv[2 * x], bv[2 * x + 1]};
-      __syncthreads();
-      if (k0 + CKT < c.K) fetch(k0 + CKT);
-      // lane group lane / 16 takes pair 4 gq + lane / 16: its first K value
-      // feeds the first product of the pair, its second the second, for A
-      // and B alike
+    for (int y = 0; y < 2; ++y) {
+      const int32_t q = y ? q1 : q0;
+      const double* bp = s.B + (int64_t)max(q, 0) * NB;
 #pragma unroll
-      for (int gq = 0; gq < 4; ++gq) {
-        const int sl = 4 * gq + (lane >> 4);
-        double2 af[2], bf[2];
+      for (int x = 0; x < 4; ++x) {
+        const int32_t j = c0 + jl + 16 * x;
+        if constexpr (NB >= CB) {  // the block's columns lie inside the row
+          const double v = bp[j];
+          bv[2 * x + y] = q >= 0 ? v : 0.0;
+        } else {
+          const double v = bp[min(j, NB - 1)];
+          bv[2 * x + y] = (q >= 0 && j < NB) ? v : 0.0;
+        }
+      }
+    }
+  };
+  if (u.t_begin < u.t_end) {
+    const ConTermD first = g.terms[u.t_begin];
+    map_regs(first);
+    put_maps(0, first.K);
+    __syncthreads();
+    Term cur = make_term(first);
+    int set = 0;
+    fetch(cur, set, 0);
+    for (int32_t t = u.t_begin; t < u.t_end; ++t) {
+      const bool more = t + 1 < u.t_end;
+      Term nxt{};
+      if (more) {  // the next term's maps, behind this term's first chunk
+        const ConTermD c = g.terms[t + 1];
+        map_regs(c);
+        nxt = make_term(c);
+      }
+      for (int32_t k0 = 0; k0 < cur.K; k0 += CKT) {
+        const bool last = k0 + CKT >= cur.K;
+        if (cur.tr) {
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
-          if (row_g[a]) af[a] = *reinterpret_cast<const double2*>(As + (wr + a * 16 + (lane & 15)) * CLD + 2 * sl);
+          for (int x = 0; x < 4; ++x)
+            *reinterpret_cast<double2*>(As + (jl + 16 * x) * CLD + 2 * kp) = double2{av[2 * x], av[2 * x + 1]};
+        } else {
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          bf[b] = *reinterpret_cast<const double2*>(Bs + (wc + b * 16 + (lane & 15)) * CLD + 2 * sl);
+          for (int e = 0; e < 4; ++e)
+            *reinterpret_cast<double2*>(As + ra * CLD + 2 * (pa + e)) = double2{av[2 * e], av[2 * e + 1]};
         }
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
-          if (row_g[a])
+        for (int x = 0; x < 4; ++x)
+          *reinterpret_cast<double2*>(Bs + (jl + 16 * x) * CLD + 2 * kp) = double2{bv[2 * x], bv[2 * x + 1]};
+        // the other set was last read by the fetches of the previous term,
+        // before the barrier that closed its chunk
+        if (last && more) put_maps(set ^ 1, nxt.K);
+        __syncthreads();
+        if (!last || more) {  // one call site: the next chunk of this term or the first of the next
+          const Term& ft = last ? nxt : cur;
+          fetch(ft, last ? set ^ 1 : set, last ? 0 : k0 + CKT);
+        }
+        // lane group lane / 16 takes pair 4 gq + lane / 16: its first K value
+        // feeds the first product of the pair, its second the second, for A
+        // and B alike
 #pragma unroll
-            for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].x, bf[b].x, acc[a][b], 0, 0, 0);
+        for (int gq = 0; gq < 4; ++gq) {
+          const int sl = 4 * gq + (lane >> 4);
+          double2 af[2], bf[2];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
-          if (row_g[a])
+          for (int a = 0; a < 2; ++a)
+            if (row_g[a]) af[a] = *reinterpret_cast<const double2*>(As + (wr + a * 16 + (lane & 15)) * CLD + 2 * sl);
 #pragma unroll
-            for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].y, bf[b].y, acc[a][b], 0, 0, 0);
+          for (int b = 0; b < 2; ++b) {
+            bf[b] = *reinterpret_cast<const double2*>(Bs + (wc + b * 16 + (lane & 15)) * CLD + 2 * sl);
+          }
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+            if (row_g[a])
+#pragma unroll
+              for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].x, bf[b].x, acc[a][b], 0, 0, 0);
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+            if (row_g[a])
+#pragma unroll
+              for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a].y, bf[b].y, acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
       }
-      __syncthreads();
+      if (more) {
+        cur = nxt;
+        set ^= 1;
+      }
     }
   }
   double* C = (u.c_buf == 4 ? g.P : u.c_buf == 1 ? g.Z : g.M) + u.c_off;

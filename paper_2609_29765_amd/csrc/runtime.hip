@@ -1351,6 +1351,10 @@ int stc_check_backward(const stc_handle* h, int64_t* stats) {
   }
   for (int32_t o : owner)
     if (o != 1) return fail(STC_ERR_SCHEDULE, "a reverse-mode term belongs to no task or to several");
+  // the contraction kernel streams K chunks across a task's terms and reads
+  // the next term's first chunk during a term's last: every term has one
+  for (const ConTerm& c : b.terms)
+    if (c.K < 1 || c.K > nb) return fail(STC_ERR_SCHEDULE, "a reverse-mode term's contraction length is outside 1..n_b");
   // level at which each Z / M tile is written: M tiles and the diagonal H_k
   // at level 1 (G_k by the inverses before it, level 0), the rest once each
   std::map<std::pair<int32_t, int64_t>, int32_t> written;  // (buffer, offset) -> level
