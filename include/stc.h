@@ -337,7 +337,9 @@ int stc_check_solve_schedule(const stc_handle* h, int64_t* stats);
    device work.  Its levels run in order: the diagonal-tile inverses G_k,
    then one contraction launch per level, each followed by a launch that folds
    the partial results of the level's split tasks.  Verified: every term of
-   the recurrence belongs to exactly one task; every tile a level reads (Z,
+   the recurrence belongs to exactly one task and contracts over 1..n_b
+   entries (the contraction kernel streams a task's terms and reads a term's
+   first chunk during the previous term's last); every tile a level reads (Z,
    M = L_mk G_k, G_k) was written at an earlier level; every Z and M tile is
    written by one task of one level (the diagonal Z_kk accumulating once into
    H_k); partial slots lie in the slot scratch and the slots of one level are
