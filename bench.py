@@ -532,12 +532,45 @@ def extra_backward():
             "backward_gflop": round(wk["flops_backward"] / 1e9, 3), "autotune": table}
 
 
+def extra_backward_semisparse():
+    """Spatio-temporal arrowhead n = 101,258 (tile 128, ND, grid aligned at
+    512 columns): logdet and its gradient with respect to the input values
+    against the factorization alone, and the gradient's trace identity
+    (gradient . values = tr(Q^-1 Q) = n)."""
+    import torch
+    stc = load_lib()
+    from paper_2609_29765_amd import workloads
+    w = workloads.spatiotemporal_arrowhead()
+    v = torch.from_numpy(w.values).cuda()
+    a = stc.Analysis(w.n, w.colptr, w.rowind, nb=128, ordering="nd", align=512).bind()
+    one = torch.ones(1, dtype=torch.float64, device="cuda")
+
+    def fwd():
+        a.factorize(v)
+        return a.logdet()
+
+    def fwd_bwd():
+        a.factorize(v)
+        a.logdet()
+        return a.logdet_backward(one)
+
+    g = fwd_bwd()
+    ms_f = timed(fwd, 10)
+    ms_fb = timed(fwd_bwd, 10)
+    wk = a.work()
+    return {"workload": "spatio-temporal arrowhead n=101258, tile 128, ND, grid aligned at 512 columns",
+            "levels_forward": a.nlevels, "levels_backward": int(wk["levels_backward"]),
+            "ms_forward": round(ms_f, 3), "ms_forward_backward": round(ms_fb, 3),
+            "backward_ratio": round(ms_fb / ms_f, 3), "backward_gflop": round(wk["flops_backward"] / 1e9, 1),
+            "rel_trace_identity": abs(float(g @ v) - w.n) / w.n}
+
+
 def run_extras(path, batch):
     load_lib()
     out = {}
     for name, fn in [("gmrf_2d", extra_gmrf), ("backward", extra_backward),
                      ("batched", lambda: extra_batched(batch)), ("supernodal", extra_supernodal),
-                     ("semisparse", extra_semisparse)]:
+                     ("semisparse", extra_semisparse), ("backward_semisparse", extra_backward_semisparse)]:
         t0 = time.time()
         log(f"extra {name} ...")
         out[name] = fn()
